@@ -1,0 +1,332 @@
+"""Oracle for the Monte Carlo KBC lattice Boltzmann hot path.
+
+TEST INFRASTRUCTURE ONLY. Plain, slow, double-precision statements of what
+the GPU library computes. Only the tests, the smoke check and the benchmark's
+CPU-baseline leg may import this package. It shares no code with the GPU
+library; its inputs come from ``mc_inputs`` (random parameters only).
+
+Contents and the passage each part follows:
+  * parameter map (Table 1's omega from the viscosity; section "Randomized
+    Taylor-Green vortex flow" for Re; Tables 2 and 3 for the paper's own
+    Mach-number convention);
+  * initial velocity, eqs. (tgv_init_velo), (alpha_perturbation),
+    (initialRTGV), with the optional Leray projection done spectrally on
+    the grid (a library FFT), and equilibrium populations,
+    eq. (initialPopulations);
+  * time stepping by the C++ part (``lbm_oracle.cpp``): eqs. (equilibrium),
+    (bgkCollisionOp)-(momentDefin), (kbcCollision), (entropyControl),
+    (kbc_entropy), (lbIteration);
+  * moments rho = sum f, rho u = sum c f; kinetic energy per unit volume;
+  * complex-step derivative of the ensemble-mean kinetic energy with
+    respect to the 24 random parameters (Squire and Trapp 1998);
+  * observables: energy spectrum, eqs. (dftCoeff), (energySpecDisc);
+    structure function, Lemma (structureFunctionSpectral) / eq.
+    (SF_single_spec2); 1-point Wasserstein distance between equal-size
+    empirical laws by sorted rearrangement, eq. (wassersteinPermutations).
+
+Array conventions: fields are C-ordered [z][y][x] (x fastest); populations
+f[cell][27] with i = 9*(cx+1) + 3*(cy+1) + (cz+1); velocities u[3][z][y][x].
+"""
+import ctypes
+import math
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB = None
+
+_dp = ctypes.POINTER(ctypes.c_double)
+_ip = ctypes.POINTER(ctypes.c_int32)
+
+
+def _ptr(a, t=_dp):
+    return a.ctypes.data_as(t)
+
+
+def lib():
+    """Load liboracle.so, building it with g++ first if it is missing."""
+    global _LIB
+    if _LIB is None:
+        path = os.path.join(HERE, "liboracle.so")
+        if not os.path.exists(path):
+            from . import build as _b
+            _b.build()
+        L = ctypes.CDLL(path)
+        L.oracle_velocity_set.argtypes = [_ip, _dp]
+        L.oracle_moment_basis.argtypes = [_dp, _dp, _ip]
+        L.oracle_equilibrium.argtypes = [ctypes.c_double, _dp, _dp]
+        L.oracle_collide.argtypes = [_dp, ctypes.c_double, ctypes.c_int32, _dp, _dp, _dp, _dp]
+        L.oracle_collide_z.argtypes = [_dp, ctypes.c_double, _dp, _dp]
+        L.oracle_run.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_double, ctypes.c_int32, _dp, _dp,
+                                 ctypes.c_int32]
+        L.oracle_run_z.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_double, _dp, ctypes.c_int32]
+        L.oracle_init_field.argtypes = [ctypes.c_int64, _dp, _dp]
+        L.oracle_init_field_z.argtypes = [ctypes.c_int64, _dp, _dp]
+        L.oracle_max_threads.restype = ctypes.c_int32
+        _LIB = L
+    return _LIB
+
+
+# ---------------------------------------------------------------- lattice
+def velocity_set():
+    c = np.zeros((27, 3), dtype=np.int32)
+    w = np.zeros(27)
+    lib().oracle_velocity_set(_ptr(c, _ip), _ptr(w))
+    return c, w
+
+
+def moment_basis():
+    M = np.zeros((27, 27))
+    Minv = np.zeros((27, 27))
+    g = np.zeros(27, dtype=np.int32)
+    lib().oracle_moment_basis(_ptr(M), _ptr(Minv), _ptr(g, _ip))
+    return M, Minv, g
+
+
+def equilibrium(rho, u):
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    feq = np.zeros(27)
+    lib().oracle_equilibrium(float(rho), _ptr(u), _ptr(feq))
+    return feq
+
+
+MODE_KBC, MODE_BGK, MODE_EXACT = 0, 1, 2
+
+
+def collide(f, omega, mode=MODE_KBC):
+    """One collision at one node. Returns (f*, gamma, ds, dh)."""
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    fs = np.zeros(27)
+    ds = np.zeros(27)
+    dh = np.zeros(27)
+    g = np.zeros(1)
+    lib().oracle_collide(_ptr(f), float(omega), int(mode), _ptr(fs), _ptr(g), _ptr(ds), _ptr(dh))
+    return fs, float(g[0]), ds, dh
+
+
+def collide_complex(f, omega):
+    f = np.ascontiguousarray(f, dtype=np.complex128)
+    fs = np.zeros(27, dtype=np.complex128)
+    g = np.zeros(1, dtype=np.complex128)
+    lib().oracle_collide_z(_ptr(f), float(omega), _ptr(fs), _ptr(g))
+    return fs, g[0]
+
+
+# ---------------------------------------------------------------- parameters
+def lattice_viscosity(n, u0, re):
+    """nu in lattice units for Re = U0 L / nu with L = n / (2 pi) lattice units."""
+    return u0 * (n / (2.0 * math.pi)) / re
+
+
+def omega_shear(nu):
+    """Table 1: omega = 2 c_s^2 / (2 nu + c_s^2), c_s^2 = 1/3."""
+    cs2 = 1.0 / 3.0
+    return 2.0 * cs2 / (2.0 * nu + cs2)
+
+
+def paper_table_row(n, ma, re, dx):
+    """Relaxation time and physical time step of a row of Tables 2 and 3.
+
+    Ma is relative to the lattice speed of sound, so the lattice velocity is
+    Ma * c_s; the reference length 1 is 1/dx lattice units; the reference
+    velocity is 1, so dt = dx * (lattice velocity)."""
+    u_lu = ma * math.sqrt(1.0 / 3.0)
+    nu = u_lu * (1.0 / dx) / re
+    tau = 1.0 / omega_shear(nu)
+    dt = dx * u_lu
+    return tau, dt
+
+
+# ---------------------------------------------------------------- initial data
+def grid(n):
+    x = 2.0 * math.pi * np.arange(n) / n
+    Z, Y, X = np.meshgrid(x, x, x, indexing="ij")
+    return X, Y, Z
+
+
+def taylor_green(n):
+    """eq. (tgv_init_velo) with unit amplitude, as [3][z][y][x]."""
+    X, Y, Z = grid(n)
+    return np.stack([np.sin(X) * np.cos(Y) * np.cos(Z), -np.cos(X) * np.sin(Y) * np.cos(Z), np.zeros_like(X)])
+
+
+def perturbation(n, y):
+    """eq. (alpha_perturbation) with coefficients y[24] (real or complex)."""
+    X, Y, Z = grid(n)
+    a = (np.sin, np.cos)
+    y = np.asarray(y)
+    s = np.zeros((3, n, n, n), dtype=np.result_type(y.dtype, np.float64))
+    for al in range(3):
+        for i in range(2):
+            for j in range(2):
+                for k in range(2):
+                    s[al] += y[8 * al + 4 * i + 2 * j + k] * a[i](2 * X) * a[j](2 * Y) * a[k](2 * Z)
+    return s / 8.0
+
+
+def leray_project(v):
+    """Remove the gradient part of a periodic field on the grid, spectrally.
+
+    The projection is real-linear, so a complex field (complex-step input) is
+    projected part by part: the FFT's own complex arithmetic must not mix the
+    rounding of the real part into the imaginary part."""
+    if np.iscomplexobj(v):
+        return leray_project(np.ascontiguousarray(v.real)) + 1j * leray_project(np.ascontiguousarray(v.imag))
+    n = v.shape[1]
+    k = np.fft.fftfreq(n) * n
+    KZ, KY, KX = np.meshgrid(k, k, k, indexing="ij")
+    K = (KX, KY, KZ)
+    k2 = KX ** 2 + KY ** 2 + KZ ** 2
+    k2[0, 0, 0] = 1.0
+    vh = [np.fft.fftn(v[a]) for a in range(3)]
+    div = K[0] * vh[0] + K[1] * vh[1] + K[2] * vh[2]
+    return np.stack([np.fft.ifftn(vh[a] - K[a] * div / k2).real for a in range(3)])
+
+
+def initial_velocity(n, u0, amp, y, project):
+    """u0 = U0 [TGV + amp * P s(Y)] (section "Discretization and well-prepared
+    initial data"; the projection P is optional as in the numerics section)."""
+    s = perturbation(n, y)
+    if project:
+        s = leray_project(s)
+    return u0 * (taylor_green(n) + amp * s)
+
+
+def equilibrium_field(u):
+    """eq. (initialPopulations): f = f^eq(1, u) at every node -> f[ncell][27]."""
+    n = u.shape[1]
+    ncell = n ** 3
+    if np.iscomplexobj(u):
+        uu = np.ascontiguousarray(u.reshape(3, ncell), dtype=np.complex128)
+        f = np.zeros((ncell, 27), dtype=np.complex128)
+        lib().oracle_init_field_z(ncell, _ptr(uu), _ptr(f))
+    else:
+        uu = np.ascontiguousarray(u.reshape(3, ncell), dtype=np.float64)
+        f = np.zeros((ncell, 27))
+        lib().oracle_init_field(ncell, _ptr(uu), _ptr(f))
+    return f
+
+
+def init_populations(n, u0, amp, y, project):
+    return equilibrium_field(initial_velocity(n, u0, amp, y, project))
+
+
+# ---------------------------------------------------------------- time stepping
+def run(f, n, steps, omega, mode=MODE_KBC, threads=0, gamma_stats=False):
+    """Advance f[ncell][27] in place by `steps` steps; optionally return the
+    per-step (min, max, mean) of gamma."""
+    assert f.shape == (n ** 3, 27) and f.flags.c_contiguous
+    gs = np.zeros((max(steps, 1), 3)) if gamma_stats else None
+    if np.iscomplexobj(f):
+        assert mode == MODE_KBC
+        lib().oracle_run_z(n, steps, float(omega), _ptr(f), int(threads))
+    else:
+        lib().oracle_run(n, steps, float(omega), int(mode), _ptr(f), _ptr(gs) if gs is not None else None,
+                         int(threads))
+    return gs[:steps] if gs is not None else None
+
+
+def max_threads():
+    return int(lib().oracle_max_threads())
+
+
+# ---------------------------------------------------------------- moments and reductions
+def moments(f, n):
+    """rho[z][y][x], u[3][z][y][x] with rho = sum f, rho u = sum c f."""
+    c, _ = velocity_set()
+    rho = f.sum(axis=1)
+    j = f @ c.astype(np.float64)
+    u = (j / rho[:, None]).T
+    return rho.reshape(n, n, n), u.reshape(3, n, n, n)
+
+
+def kinetic_energy(u):
+    """Mean of |u|^2 / 2 over the nodes (energy per unit volume of u).
+    Uses u.u without conjugation so that complex steps carry derivatives."""
+    return 0.5 * np.mean(u[0] * u[0] + u[1] * u[1] + u[2] * u[2])
+
+
+def reductions(f, n):
+    """mass, jx, jy, jz (sums over nodes), kinetic energy."""
+    c, _ = velocity_set()
+    rho, u = moments(f, n)
+    j = f @ c.astype(np.float64)
+    return np.array([rho.sum(), j[:, 0].sum(), j[:, 1].sum(), j[:, 2].sum(), kinetic_energy(u)])
+
+
+# ---------------------------------------------------------------- gradient reference
+def ke_gradient_complex_step(n, u0, re, amp, y, project, steps, h=1e-30, threads=0, params=None):
+    """d KE(T) / d Y_p for one sample by the complex step Im KE(Y + i h e_p) / h."""
+    omega = omega_shear(lattice_viscosity(n, u0, re))
+    params = range(24) if params is None else params
+    grad = np.zeros(24)
+    for p in params:
+        yc = np.asarray(y, dtype=np.complex128).copy()
+        yc[p] += 1j * h
+        f = init_populations(n, u0, amp, yc, project)
+        run(f, n, steps, omega, threads=threads)
+        _, u = moments(f, n)
+        grad[p] = kinetic_energy(u).imag / h
+    return grad
+
+
+def ke_after(n, u0, re, amp, y, project, steps, threads=0):
+    omega = omega_shear(lattice_viscosity(n, u0, re))
+    f = init_populations(n, u0, amp, np.asarray(y, dtype=np.float64), project)
+    run(f, n, steps, omega, threads=threads)
+    _, u = moments(f, n)
+    return float(kinetic_energy(u))
+
+
+# ---------------------------------------------------------------- observables
+def energy_spectrum(u):
+    """eq. (energySpecDisc): E(kappa) for kappa = 0..N/2 from eq. (dftCoeff)
+    coefficients; modes whose rounded |k| exceeds N/2 are not counted."""
+    n = u.shape[1]
+    uh = np.stack([np.fft.fftn(u[a]) / n ** 3 for a in range(3)])
+    phi = np.sum(np.abs(uh) ** 2, axis=0)
+    k = np.fft.fftfreq(n) * n
+    k[k == -n // 2] = n // 2   # index set {-N/2+1, ..., N/2}
+    KZ, KY, KX = np.meshgrid(k, k, k, indexing="ij")
+    kmag2 = KX ** 2 + KY ** 2 + KZ ** 2
+    shell = np.floor(np.sqrt(kmag2) + 0.5).astype(np.int64)
+    E = np.zeros(n // 2 + 1)
+    for kap in range(n // 2 + 1):
+        sel = shell == kap
+        cnt = np.count_nonzero(sel)
+        if cnt:
+            E[kap] = 4.0 * math.pi / cnt * np.sum(0.5 * kmag2[sel] * phi[sel])
+    return E
+
+
+def autocorrelation(u):
+    """eq. (SF_approx_spec5): R_h = N^-d F^-1(sum_i |F u_i|^2)_h."""
+    n = u.shape[1]
+    psd = sum(np.abs(np.fft.fftn(u[a])) ** 2 for a in range(3))
+    return np.fft.ifftn(psd).real / n ** 3
+
+
+def structure_function(u):
+    """eq. (SF_single_spec2): S2(r) for r = 1..N/2 over the shells C_r of lags
+    (minimum image) whose Euclidean length rounds to r."""
+    n = u.shape[1]
+    R = autocorrelation(u)
+    h = np.fft.fftfreq(n) * n
+    h[h == -n // 2] = n // 2
+    HZ, HY, HX = np.meshgrid(h, h, h, indexing="ij")
+    rr = np.floor(np.sqrt(HX ** 2 + HY ** 2 + HZ ** 2) + 0.5).astype(np.int64)
+    S = np.zeros(n // 2)
+    for r in range(1, n // 2 + 1):
+        sel = rr == r
+        S[r - 1] = np.mean(2.0 * (R[0, 0, 0] - R[sel]))
+    return S
+
+
+def wasserstein1_equal_weights(a, b):
+    """W1 between two empirical laws with the same number of equal-weight
+    atoms on the real line: mean |sorted(a) - sorted(b)|."""
+    a = np.sort(np.asarray(a, dtype=np.float64))
+    b = np.sort(np.asarray(b, dtype=np.float64))
+    assert a.shape == b.shape
+    return float(np.mean(np.abs(a - b)))

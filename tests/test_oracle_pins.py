@@ -1,0 +1,509 @@
+"""Pins of the oracle against facts fixed by the paper and by mathematics.
+
+Each test checks the oracle against something other than itself: moment
+identities of the lattice, the textbook BGK collision, stated invariants,
+special cases, closed forms, brute force and the printed parameter tables.
+"""
+import itertools
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import mc_inputs
+import oracle
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def random_state(seed, n, amp_u=0.05, amp_noise=1e-3, rho_noise=1e-3):
+    """Non-equilibrium populations: equilibrium of a random (rho, u) field plus noise."""
+    rng = np.random.default_rng(seed)
+    ncell = n ** 3
+    f = np.zeros((ncell, 27))
+    rho = 1.0 + rng.uniform(-rho_noise, rho_noise, ncell)
+    u = rng.uniform(-amp_u, amp_u, (ncell, 3))
+    c, w = oracle.velocity_set()
+    cu = u @ c.T
+    usq = np.sum(u * u, axis=1)[:, None]
+    f = rho[:, None] * w[None, :] * (1 + 3 * cu + 4.5 * cu ** 2 - 1.5 * usq)
+    f *= 1.0 + rng.uniform(-amp_noise, amp_noise, f.shape)
+    return np.ascontiguousarray(f)
+
+
+def textbook_feq(rho, u):
+    """Second-order Maxwellian truncation written from the textbook form with
+    c_s^2 = 1/3 and the D3Q27 weights (8/27, 2/27, 1/54, 1/216 by number of
+    non-zero velocity components)."""
+    wclass = {0: 8 / 27, 1: 2 / 27, 2: 1 / 54, 3: 1 / 216}
+    out = np.zeros(27)
+    for i, (cx, cy, cz) in enumerate(itertools.product((-1, 0, 1), repeat=3)):
+        cvec = np.array([cx, cy, cz], float)
+        w = wclass[int(np.count_nonzero(cvec))]
+        cu = cvec @ u
+        out[i] = rho * w * (1 + cu / (1 / 3) + (cu ** 2 - np.dot(u, u) / 3) / (2 / 9))
+    return out
+
+
+# ---------------------------------------------------------------- lattice
+def test_velocity_set_index_convention_and_weights():
+    c, w = oracle.velocity_set()
+    for i, (cx, cy, cz) in enumerate(itertools.product((-1, 0, 1), repeat=3)):
+        assert tuple(c[i]) == (cx, cy, cz)
+        assert tuple(c[26 - i]) == (-cx, -cy, -cz)
+    # the weights are fixed by the isotropy conditions of a 27-velocity set
+    # with symmetric classes: sum w = 1, sum w cx^2 = 1/3, sum w cx^2 cy^2 = 1/9,
+    # sum w cx^2 cy^2 cz^2 = 1/27
+    cf = c.astype(float)
+    assert abs(w.sum() - 1) < 1e-15
+    assert abs(np.sum(w * cf[:, 0] ** 2) - 1 / 3) < 1e-15
+    assert abs(np.sum(w * cf[:, 0] ** 2 * cf[:, 1] ** 2) - 1 / 9) < 1e-15
+    assert abs(np.sum(w * cf[:, 0] ** 2 * cf[:, 1] ** 2 * cf[:, 2] ** 2) - 1 / 27) < 1e-15
+    # isotropy through fourth order
+    for a, b in itertools.product(range(3), repeat=2):
+        assert abs(np.sum(w * cf[:, a] * cf[:, b]) - (a == b) / 3) < 1e-15
+    for a, b, g, d in itertools.product(range(3), repeat=4):
+        iso = ((a == b) * (g == d) + (a == g) * (b == d) + (a == d) * (b == g)) / 9
+        assert abs(np.sum(w * cf[:, a] * cf[:, b] * cf[:, g] * cf[:, d]) - iso) < 1e-15
+    for a, b, g in itertools.product(range(3), repeat=3):
+        assert abs(np.sum(w * cf[:, a] * cf[:, b] * cf[:, g])) < 1e-15
+
+
+def test_moment_basis_invertible_and_grouped():
+    M, Minv, g = oracle.moment_basis()
+    assert np.max(np.abs(M @ Minv - np.eye(27))) < 1e-13
+    assert list(np.bincount(g)) == [4, 5, 18]
+
+
+def test_equilibrium_moments():
+    """The truncated Maxwellian reproduces rho, rho u and rho/3 I + rho u u."""
+    c, _ = oracle.velocity_set()
+    cf = c.astype(float)
+    rng = np.random.default_rng(1)
+    for _ in range(10):
+        rho = 1 + rng.uniform(-0.1, 0.1)
+        u = rng.uniform(-0.1, 0.1, 3)
+        feq = oracle.equilibrium(rho, u)
+        assert np.max(np.abs(feq - textbook_feq(rho, u))) < 1e-16
+        assert abs(feq.sum() - rho) < 1e-15
+        assert np.max(np.abs(cf.T @ feq - rho * u)) < 1e-16
+        P = (cf.T * feq) @ cf
+        assert np.max(np.abs(P - (rho / 3 * np.eye(3) + rho * np.outer(u, u)))) < 1e-15
+
+
+# ---------------------------------------------------------------- collision pins
+def test_equilibrium_is_fixed_point():
+    rng = np.random.default_rng(2)
+    for omega in (0.7, 1.3, 1.99):
+        for _ in range(5):
+            feq = oracle.equilibrium(1 + rng.uniform(-0.05, 0.05), rng.uniform(-0.08, 0.08, 3))
+            fs, gamma, ds, dh = oracle.collide(feq, omega)
+            assert np.max(np.abs(fs - feq)) < 5e-16
+            assert np.max(np.abs(ds)) < 5e-16 and np.max(np.abs(dh)) < 5e-16
+
+
+def test_uniform_state_stays_bitwise_uniform():
+    n = 6
+    feq = oracle.equilibrium(1.01, np.array([0.03, -0.02, 0.01]))
+    f = np.ascontiguousarray(np.tile(feq, (n ** 3, 1)))
+    oracle.run(f, n, 3, 1.9)
+    assert np.all(f == f[0:1, :])
+    assert np.max(np.abs(f[0] - feq)) < 5e-16
+
+
+def test_collision_conserves_mass_and_momentum():
+    c, _ = oracle.velocity_set()
+    cf = c.astype(float)
+    f = random_state(3, 3, amp_noise=5e-2)
+    for omega in (0.5, 1.0, 1.5, 1.999):
+        for cell in range(f.shape[0]):
+            fs, *_ = oracle.collide(f[cell], omega)
+            assert abs(fs.sum() - f[cell].sum()) < 1e-15
+            assert np.max(np.abs(cf.T @ (fs - f[cell]))) < 1e-15
+
+
+def test_step_conserves_totals():
+    n = 8
+    c, _ = oracle.velocity_set()
+    f = random_state(4, n, amp_noise=1e-2)
+    mass0 = f.sum()
+    j0 = (f @ c.astype(float)).sum(axis=0)
+    oracle.run(f, n, 5, 1.95)
+    assert abs(f.sum() - mass0) / mass0 < 1e-14
+    assert np.max(np.abs((f @ c.astype(float)).sum(axis=0) - j0)) < 1e-14 * mass0
+
+
+def test_bgk_special_cases():
+    """gamma = 2 gives the textbook BGK collision; at omega = 1 the closed-form
+    gamma is exactly 2, so KBC collapses to BGK with f* = f^eq."""
+    f = random_state(5, 2, amp_noise=2e-2)
+    c, _ = oracle.velocity_set()
+    for cell in range(f.shape[0]):
+        rho = f[cell].sum()
+        u = (c.astype(float).T @ f[cell]) / rho
+        feq = textbook_feq(rho, u)
+        for omega in (0.8, 1.6, 1.97):
+            fs, gamma, *_ = oracle.collide(f[cell], omega, oracle.MODE_BGK)
+            assert gamma == 2.0
+            assert np.max(np.abs(fs - (f[cell] - omega * (f[cell] - feq)))) < 1e-15
+        fs, gamma, *_ = oracle.collide(f[cell], 1.0)
+        assert abs(gamma - 2.0) < 1e-14
+        assert np.max(np.abs(fs - feq)) < 1e-15
+
+
+def test_shear_hom_split():
+    """ds carries exactly the traceless and off-diagonal second moments of
+    f^neq and no other raw moment; ds + dh = f^neq; closed form of ds."""
+    c, w = oracle.velocity_set()
+    cf = c.astype(float)
+    f = random_state(6, 2, amp_noise=3e-2)
+    for cell in range(f.shape[0]):
+        fc = f[cell]
+        rho = fc.sum()
+        u = (cf.T @ fc) / rho
+        fneq = fc - textbook_feq(rho, u)
+        _, _, ds, dh = oracle.collide(fc, 1.7)
+        assert np.max(np.abs(ds + dh - fneq)) < 1e-15
+
+        def mom(v, p, q, r):
+            return np.sum(v * cf[:, 0] ** p * cf[:, 1] ** q * cf[:, 2] ** r)
+
+        nxz = mom(fneq, 2, 0, 0) - mom(fneq, 0, 0, 2)
+        nyz = mom(fneq, 0, 2, 0) - mom(fneq, 0, 0, 2)
+        assert abs(mom(ds, 2, 0, 0) - mom(ds, 0, 0, 2) - nxz) < 1e-16
+        assert abs(mom(ds, 0, 2, 0) - mom(ds, 0, 0, 2) - nyz) < 1e-16
+        for (p, q, r) in ((1, 1, 0), (1, 0, 1), (0, 1, 1)):
+            assert abs(mom(ds, p, q, r) - mom(fneq, p, q, r)) < 1e-16
+        assert abs(mom(ds, 2, 0, 0) + mom(ds, 0, 2, 0) + mom(ds, 0, 0, 2)) < 1e-16
+        for p, q, r in itertools.product(range(3), repeat=3):
+            if p + q + r <= 1 or p + q + r >= 3:
+                assert abs(mom(ds, p, q, r)) < 1e-16
+        # closed form per velocity class
+        exp = np.zeros(27)
+        pxy, pxz, pyz = mom(fneq, 1, 1, 0), mom(fneq, 1, 0, 1), mom(fneq, 0, 1, 1)
+        for i in range(27):
+            cx, cy, cz = c[i]
+            nz = np.count_nonzero(c[i])
+            if nz == 1:
+                exp[i] = ((2 * nxz - nyz) / 6 if cx else (2 * nyz - nxz) / 6 if cy else -(nxz + nyz) / 6)
+            elif nz == 2:
+                exp[i] = (cx * cy * pxy + cx * cz * pxz + cy * cz * pyz) / 4
+        assert np.max(np.abs(exp - ds)) < 1e-16
+
+
+def test_closed_form_gamma_minimises_quadratic_entropy():
+    """The closed form makes the quadratic expansion of H around f^eq,
+    sum (f* - f^eq)^2 / f^eq, stationary in gamma."""
+    c, _ = oracle.velocity_set()
+    f = random_state(7, 2, amp_noise=2e-2)
+    for cell in range(f.shape[0]):
+        fc = f[cell]
+        rho = fc.sum()
+        u = (c.astype(float).T @ fc) / rho
+        feq = textbook_feq(rho, u)
+        omega = 1.93
+        _, gamma, ds, dh = oracle.collide(fc, omega)
+
+        def hq(g):
+            fs = fc - omega * ds - omega * g / 2 * dh
+            return np.sum((fs - feq) ** 2 / feq)
+
+        d = 1e-3 * max(1.0, abs(gamma))
+        assert hq(gamma) <= hq(gamma + d) and hq(gamma) <= hq(gamma - d)
+        slope = (hq(gamma + d) - hq(gamma - d)) / (2 * d)
+        curv = (hq(gamma + d) - 2 * hq(gamma) + hq(gamma - d)) / d ** 2
+        assert abs(slope) < 1e-6 * curv * d + 1e-30
+
+
+def test_exact_entropic_gamma_limit():
+    """Near equilibrium and at rest the closed form approaches the exact
+    minimiser of the discrete H-function, and the exact minimiser never
+    increases H."""
+    rng = np.random.default_rng(8)
+    c, w = oracle.velocity_set()
+    omega = 1.98
+    diffs = []
+    for amp in (1e-2, 1e-3, 1e-4):
+        dd = []
+        for _ in range(10):
+            feq = oracle.equilibrium(1.0, np.zeros(3))
+            f = feq * (1 + amp * rng.uniform(-1, 1, 27))
+            # restore the mass and momentum of the rest state so that u = 0
+            f = f - w * (f.sum() - 1.0)
+            jx = c.astype(float).T @ f
+            for a in range(3):
+                sel_p = c[:, a] == 1
+                sel_m = c[:, a] == -1
+                f[sel_p] -= jx[a] / 2 * w[sel_p] / w[sel_p].sum()
+                f[sel_m] += jx[a] / 2 * w[sel_m] / w[sel_m].sum()
+            assert np.max(np.abs(c.astype(float).T @ f)) < 1e-15
+            _, g_cf, _, _ = oracle.collide(f, omega, oracle.MODE_KBC)
+            fs_ex, g_ex, _, _ = oracle.collide(f, omega, oracle.MODE_EXACT)
+            H = lambda v: np.sum(v * np.log(v / w))
+            assert H(fs_ex) <= H(f) + 1e-15
+            dd.append(abs(g_cf - g_ex))
+        diffs.append(np.median(dd))
+    assert diffs[1] < diffs[0] / 2 and diffs[2] < diffs[1] / 2
+    assert diffs[2] < diffs[0] / 20 and diffs[2] < 1e-5
+
+
+@pytest.mark.slow
+def test_gamma_approaches_bgk_value_under_refinement():
+    """For a resolved flow the mean stabiliser tends to the BGK value 2 as the
+    resolution grows (remark on the convergence of the deterministic scheme)."""
+    dev = []
+    for n in (16, 32):
+        u0 = 0.05 * 32 / n
+        omega = oracle.omega_shear(oracle.lattice_viscosity(n, u0, 100.0))
+        f = oracle.init_populations(n, u0, 0.0, np.zeros(24), False)
+        gs = oracle.run(f, n, 20 * (n // 16) ** 2, omega, gamma_stats=True)
+        dev.append(abs(gs[-1, 2] - 2.0))
+    assert dev[1] < dev[0] / 3
+
+
+# ---------------------------------------------------------------- lattice symmetry
+def _cube_symmetries():
+    mats = []
+    for perm in itertools.permutations(range(3)):
+        for signs in itertools.product((1, -1), repeat=3):
+            R = np.zeros((3, 3), int)
+            for r in range(3):
+                R[r, perm[r]] = signs[r]
+            mats.append(R)
+    return mats
+
+
+def _apply_symmetry(f, n, R):
+    c, _ = oracle.velocity_set()
+    sigma = np.zeros(27, int)
+    for i in range(27):
+        rc = R @ c[i]
+        sigma[i] = [k for k in range(27) if tuple(c[k]) == tuple(rc)][0]
+    fz = f.reshape(n, n, n, 27)
+    out = np.zeros_like(fz)
+    idx = np.arange(n)
+    Z, Yg, X = np.meshgrid(idx, idx, idx, indexing="ij")
+    P = np.stack([X, Yg, Z], axis=-1)
+    Pn = np.einsum("ab,zyxb->zyxa", R, P) % n
+    for i in range(27):
+        out[Pn[..., 2], Pn[..., 1], Pn[..., 0], sigma[i]] = fz[..., i]
+    return np.ascontiguousarray(out.reshape(n ** 3, 27))
+
+
+def test_cube_symmetry_equivariance():
+    n = 6
+    f0 = random_state(9, n, amp_noise=5e-3)
+    rng = np.random.default_rng(10)
+    syms = _cube_symmetries()
+    assert len(syms) == 48
+    for k in rng.choice(48, size=6, replace=False):
+        R = syms[k]
+        a = f0.copy()
+        b = _apply_symmetry(f0, n, R)
+        oracle.run(a, n, 3, 1.97)
+        oracle.run(b, n, 3, 1.97)
+        assert np.max(np.abs(_apply_symmetry(a, n, R) - b)) < 1e-15
+
+
+# ---------------------------------------------------------------- streaming
+def test_streaming_is_a_permutation_and_keeps_relative_entropy():
+    n = 6
+    c, w = oracle.velocity_set()
+    f = random_state(11, n, amp_noise=1e-2)
+    g = f.copy()
+    oracle.run(g, n, 1, 0.0, mode=oracle.MODE_BGK)   # zero frequency: streaming only
+    for i in range(27):
+        assert np.array_equal(np.sort(f[:, i]), np.sort(g[:, i]))
+    # single-velocity shift check
+    fz = f.reshape(n, n, n, 27)
+    gz = g.reshape(n, n, n, 27)
+    for i in range(27):
+        cx, cy, cz = c[i]
+        assert np.array_equal(gz[..., i], np.roll(fz[..., i], shift=(cz, cy, cx), axis=(0, 1, 2)))
+    hrel = lambda v: np.sum(v * np.log(v / w) - v + w)
+    assert abs(hrel(f) - hrel(g)) <= 1e-12 * hrel(f)
+
+
+def test_initial_relative_entropy_scales_with_dx_squared():
+    """Lemma (well-prepared initialisation): H_rel(0) = O(eps^2) when the lattice
+    velocity shrinks with eps (diffusive scaling)."""
+    _, w = oracle.velocity_set()
+    y = mc_inputs.draw_y(5, 1)[0]
+    vals = []
+    for n in (8, 16, 32):
+        eps = 2 * math.pi / n
+        f = oracle.init_populations(n, 0.05 * 8 / n, 0.05, y, True)
+        vals.append(eps ** 3 * np.sum(f * np.log(f / w) - f + w))
+    r1, r2 = vals[0] / vals[1], vals[1] / vals[2]
+    assert 3.8 < r1 < 4.2 and 3.9 < r2 < 4.1
+
+
+# ---------------------------------------------------------------- initial data
+def test_initial_kinetic_energy_closed_form():
+    """Discrete orthogonality: KE(0) = U0^2 (1/8 + amp^2 sum Y^2 / 1024)
+    without projection."""
+    for n, seed in ((8, 1), (12, 2), (16, 3)):
+        y = mc_inputs.draw_y(seed, 1)[0]
+        u0, amp = 0.05, 0.3
+        f = oracle.init_populations(n, u0, amp, y, False)
+        rho, u = oracle.moments(f, n)
+        ke = oracle.kinetic_energy(u)
+        assert abs(ke - u0 ** 2 * (1 / 8 + amp ** 2 * np.sum(y ** 2) / 1024)) < 1e-15
+        assert np.max(np.abs(rho - 1)) < 1e-15
+
+
+def test_leray_projection_properties():
+    """The projection is idempotent, leaves a spectrally divergence-free field,
+    removes a pure gradient, has rank 16 on the 24 perturbation fields, and
+    matches the closed form s + grad(div s)/12 (all fields are Laplacian
+    eigenfunctions with eigenvalue -12)."""
+    n = 8
+    X, Y, Z = oracle.grid(n)
+    k = np.fft.fftfreq(n) * n
+    KZ, KY, KX = np.meshgrid(k, k, k, indexing="ij")
+    cols = []
+    for p in range(24):
+        e = np.zeros(24)
+        e[p] = 1
+        s = oracle.perturbation(n, e)
+        ps = oracle.leray_project(s)
+        assert np.max(np.abs(oracle.leray_project(ps) - ps)) < 1e-14
+        div = KX * np.fft.fftn(ps[0]) + KY * np.fft.fftn(ps[1]) + KZ * np.fft.fftn(ps[2])
+        assert np.max(np.abs(div)) < 1e-11
+        # residual is curl-free
+        r = [np.fft.fftn(s[a] - ps[a]) for a in range(3)]
+        curl = (KY * r[2] - KZ * r[1], KZ * r[0] - KX * r[2], KX * r[1] - KY * r[0])
+        assert max(np.max(np.abs(cc)) for cc in curl) < 1e-11
+        # closed form by analytic derivatives
+        al, i, j, kk = p // 8, (p // 4) % 2, (p // 2) % 2, p % 2
+        fn = (np.sin, np.cos)
+        dfn = (lambda t: 2 * np.cos(t), lambda t: -2 * np.sin(t))
+        d2fn = (lambda t: -4 * np.sin(t), lambda t: -4 * np.cos(t))
+        idxs = (i, j, kk)
+        coords = (2 * X, 2 * Y, 2 * Z)
+        grad_div = np.zeros((3, n, n, n))
+        for b in range(3):
+            term = np.ones((n, n, n)) / 8
+            for ax in range(3):
+                if ax == al and ax == b:
+                    term = term * d2fn[idxs[ax]](coords[ax])
+                elif ax == al or ax == b:
+                    term = term * dfn[idxs[ax]](coords[ax])
+                else:
+                    term = term * fn[idxs[ax]](coords[ax])
+            grad_div[b] = term
+        assert np.max(np.abs(ps - (s + grad_div / 12))) < 1e-14
+        cols.append(ps.ravel())
+    assert np.linalg.matrix_rank(np.array(cols), tol=1e-9) == 16
+
+
+# ---------------------------------------------------------------- analytic decay
+@pytest.mark.slow
+def test_two_dimensional_taylor_green_decay_rate():
+    """A z-independent 2-D Taylor-Green mode decays like exp(-2 nu k^2 t), so
+    its kinetic energy like exp(-4 nu k^2 t), k = 2 pi / n per lattice unit."""
+    n = 24
+    u0 = 0.01
+    nu = 0.05
+    omega = oracle.omega_shear(nu)
+    X, Y, Z = oracle.grid(n)
+    u = u0 * np.stack([np.sin(X) * np.cos(Y), -np.cos(X) * np.sin(Y), np.zeros_like(X)])
+    f = oracle.equilibrium_field(u)
+    steps = 120
+    oracle.run(f, n, 20, omega)      # let the initial pressure transient pass
+    _, ua = oracle.moments(f, n)
+    ke_a = oracle.kinetic_energy(ua)
+    oracle.run(f, n, steps, omega)
+    _, ub = oracle.moments(f, n)
+    ke_b = oracle.kinetic_energy(ub)
+    rate = -math.log(ke_b / ke_a) / steps
+    k = 2 * math.pi / n
+    assert abs(rate / (4 * nu * k ** 2) - 1) < 0.01
+
+
+# ---------------------------------------------------------------- parameter tables
+def test_unit_conversion_reproduces_paper_tables():
+    with open(os.path.join(GOLDEN, "paper_parameter_tables.json")) as fh:
+        tab = json.load(fh)
+    for row in tab["rows"]:
+        n = row["N"]
+        dx = 2 * math.pi / (n - 1) if row["dx"] == "2pi/(N-1)" else 2 * math.pi / n
+        tau, dt = oracle.paper_table_row(n, row["Ma"], row["Re"], dx)
+        assert round(tau, 6) == pytest.approx(row["tau"], abs=0), row
+        mant, ex = row["dt"]
+        # three printed digits: within one unit of the last one
+        assert abs(dt / 10 ** ex - mant) < 0.01, row
+
+
+# ---------------------------------------------------------------- complex step
+def test_complex_step_matches_central_differences():
+    n, steps = 8, 6
+    y = mc_inputs.draw_y(3, 1)[0]
+    g = oracle.ke_gradient_complex_step(n, 0.05, 100.0, 0.5, y, True, steps, params=[0, 5, 13, 23])
+    h = 1e-4
+    for p in (0, 5, 13, 23):
+        yp, ym = y.copy(), y.copy()
+        yp[p] += h
+        ym[p] -= h
+        fd = (oracle.ke_after(n, 0.05, 100.0, 0.5, yp, True, steps) -
+              oracle.ke_after(n, 0.05, 100.0, 0.5, ym, True, steps)) / (2 * h)
+        assert abs(fd - g[p]) <= 1e-6 * abs(g).max() + 1e-14
+
+
+# ---------------------------------------------------------------- observables
+def test_spectrum_of_taylor_green_sits_in_shell_two():
+    n = 16
+    u = oracle.taylor_green(n)
+    E = oracle.energy_spectrum(u)
+    # the 8 wave vectors (+-1, +-1, +-1) have |k| = sqrt 3 -> shell 2;
+    # shell 2 holds |k|^2 in {3, 4, 5, 6}: 8 + 6 + 24 + 24 = 62 modes
+    phi_total = 2 * oracle.kinetic_energy(u)
+    assert abs(E[2] - 4 * math.pi / 62 * 0.5 * 3 * phi_total) < 1e-14
+    assert np.max(np.abs(np.delete(E, 2))) < 1e-14
+
+
+def test_structure_function_matches_direct_sum():
+    n = 8
+    rng = np.random.default_rng(12)
+    u = rng.normal(size=(3, n, n, n))
+    S = oracle.structure_function(u)
+    # direct O(N^6) evaluation of the shell-averaged squared increment
+    h = np.arange(n)
+    hm = np.where(h > n // 2, h - n, h)
+    acc = np.zeros(n // 2)
+    cnt = np.zeros(n // 2)
+    for hz in range(n):
+        for hy in range(n):
+            for hx in range(n):
+                r = int(math.floor(math.sqrt(hm[hx] ** 2 + hm[hy] ** 2 + hm[hz] ** 2) + 0.5))
+                if 1 <= r <= n // 2:
+                    sh = np.roll(u, shift=(-hz, -hy, -hx), axis=(1, 2, 3))
+                    acc[r - 1] += np.mean(np.sum((sh - u) ** 2, axis=0))
+                    cnt[r - 1] += 1
+    assert np.max(np.abs(S - acc / cnt)) < 1e-12
+
+
+def test_wasserstein_sorted_matches_permutation_brute_force():
+    rng = np.random.default_rng(13)
+    for m in range(1, 8):
+        a = rng.normal(size=m)
+        b = rng.normal(size=m) + 0.3
+        brute = min(np.mean(np.abs(a - b[list(p)])) for p in itertools.permutations(range(m)))
+        assert abs(oracle.wasserstein1_equal_weights(a, b) - brute) < 1e-15
+
+
+def test_taylor_green_field():
+    """eq. (tgv_init_velo): divergence-free, and its values at sample nodes."""
+    n = 8
+    u = oracle.taylor_green(n)
+    k = np.fft.fftfreq(n) * n
+    KZ, KY, KX = np.meshgrid(k, k, k, indexing="ij")
+    div = KX * np.fft.fftn(u[0]) + KY * np.fft.fftn(u[1]) + KZ * np.fft.fftn(u[2])
+    assert np.max(np.abs(div)) < 1e-12
+    # node (x, y, z) = (2, 1, 0) * 2 pi / 8
+    x, y, z = 2 * math.pi * 2 / 8, 2 * math.pi * 1 / 8, 0.0
+    assert abs(u[0, 0, 1, 2] - math.sin(x) * math.cos(y) * math.cos(z)) < 1e-15
+    assert abs(u[1, 0, 1, 2] + math.cos(x) * math.sin(y) * math.cos(z)) < 1e-15
+    assert u[2].max() == 0.0 and u[2].min() == 0.0
