@@ -1,0 +1,193 @@
+"""Benchmark of the Monte Carlo KBC lattice Boltzmann hot path on one MI355X.
+
+A step is one tick of the whole ensemble: one fused collide-and-stream
+launch over every sample (with the double-precision per-sample reductions
+fused in on the saved ticks), inputs resident in HBM. The default workload is
+the randomized Taylor-Green ensemble of 64 samples at 64^3 in FP32 shifted
+populations (Re 1600, projected perturbation, reductions every 50 steps).
+
+Prints one JSON line: aggregate MLUPS, the roofline of the collide-and-stream
+kernel (HBM bytes of the algorithm / measured launch time), the measured
+bandwidth of a plain copy kernel, the single-sample FP64 step on the same GPU,
+and the oracle timed on the host cores.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0     # MI355X HBM3E
+BYTES_PER_LUP = {"f32s": 216, "f64": 432}   # 27 loads + 27 stores per node update
+
+
+def build_ensemble(wl, mc, torch):
+    samples = []
+    for g in wl.groups:
+        samples += [mc.Sample(g.n, g.u0, g.re, g.amp, g.project, g.stride)] * g.count
+    ens = mc.Ensemble(samples, wl.precision)
+    ens.init(wl.seed)
+    return ens
+
+
+def cells_per_tick(ens, tick):
+    return sum(s.n ** 3 for s in ens.samples if tick % s.stride == 0)
+
+
+def timed_ticks(ens, torch, ticks, record_every):
+    """Run `ticks` ticks from the current state; return (seconds, lattice updates)."""
+    t0 = ens.ticks
+    lups = sum(cells_per_tick(ens, t0 + k) for k in range(ticks))
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ens.synchronize()
+    ev0.record(ens.stream)
+    ens.step(ticks, record_every=record_every)
+    ev1.record(ens.stream)
+    ens.synchronize()
+    return ev0.elapsed_time(ev1) / 1e3, lups
+
+
+def stream_bandwidth(mc, torch, nbytes=4 << 30, reps=5):
+    src = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    dst = torch.empty_like(src)
+    s = torch.cuda.current_stream()
+    mc.stream_copy(dst, src, s)
+    torch.cuda.synchronize()
+    best = 0.0
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        mc.stream_copy(dst, src, s)
+        e1.record(s)
+        torch.cuda.synchronize()
+        best = max(best, 2 * nbytes / (e0.elapsed_time(e1) / 1e3) / 1e9)
+    del src, dst
+    torch.cuda.empty_cache()
+    return best
+
+
+def kernel_roofline(ens, wl, torch, ticks):
+    """Average duration of the collide-and-stream launches (HIP events on the
+    ensemble's stream, one pair per launch) and the algorithmic bandwidth."""
+    ens.use_graphs(False)
+    ens.time_launches(True)
+    t0 = ens.ticks
+    lups = sum(cells_per_tick(ens, t0 + k) for k in range(ticks))
+    ens.step(ticks)
+    avg_ms, launches = ens.launch_time()
+    ens.time_launches(False)
+    ens.use_graphs(True)
+    bytes_per_launch = BYTES_PER_LUP[wl.precision] * lups / launches
+    achieved = bytes_per_launch / (avg_ms / 1e3) / 1e9
+    return avg_ms, launches, bytes_per_launch, achieved
+
+
+def fp64_single(mc, torch, n, u0, re, ticks=200):
+    ens = mc.Ensemble([mc.Sample(n, u0, re)], "f64")
+    ens.init(0)
+    ens.step(20)
+    sec, lups = timed_ticks(ens, torch, ticks, 0)
+    return lups / sec / 1e6
+
+
+def cpu_baseline(seconds_target=15.0):
+    """The oracle on one 64^3 RTGV sample of the workload, on all host cores."""
+    import mc_inputs
+    import oracle
+    wl = mc_inputs.WORKLOADS["rtgv64x64_f32"]
+    g = wl.groups[0]
+    y = mc_inputs.draw_y(wl.seed, 1)[0]
+    om = oracle.omega_shear(oracle.lattice_viscosity(g.n, g.u0, g.re))
+    f = oracle.init_populations(g.n, g.u0, g.amp, y, g.project)
+    threads = len(os.sched_getaffinity(0))
+    t = time.perf_counter()
+    oracle.run(f, g.n, 2, om, threads=threads)
+    probe = time.perf_counter() - t
+    steps = max(2, min(200, int(seconds_target / max(probe / 2, 1e-6))))
+    t = time.perf_counter()
+    oracle.run(f, g.n, steps, om, threads=threads)
+    sec = time.perf_counter() - t
+    return {"value": g.n ** 3 * steps / sec / 1e6, "unit": "MLUPS", "cores": threads, "kind": "oracle",
+            "sample": f"1 RTGV sample at {g.n}^3 of the 64x64^3 workload, {steps} steps, FP64 moment-space "
+                      f"KBC collision, two-lattice pull streaming ({sec:.1f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="rtgv64x64_f32")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--roofline-ticks", type=int, default=40)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (this build has no multi-GPU path); got --gpus {args.gpus}",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import mc_inputs
+    import paper_2608_23786_amd as mc
+
+    wl = mc_inputs.WORKLOADS[args.workload]
+    print(f"[bench] workload {wl.name}: {wl.m} samples, precision {wl.precision}", file=sys.stderr, flush=True)
+    b_meas = stream_bandwidth(mc, torch)
+    print(f"[bench] copy kernel: {b_meas:.0f} GB/s", file=sys.stderr, flush=True)
+    ens = build_ensemble(wl, mc, torch)
+    tuned = None
+    if not args.no_autotune:
+        tuned = ens.autotune(reps=2)
+        print(f"[bench] autotuned launch: block {tuned[0]}, xcd remap {tuned[1]}", file=sys.stderr, flush=True)
+    ens.step(args.warmup)
+    rec_every = wl.save_every if wl.save_every and args.steps >= wl.save_every else 0
+    sec, lups = timed_ticks(ens, torch, args.steps, rec_every)
+    mlups = lups / sec / 1e6
+    bad = ens.check()
+    if bad >= 0:
+        raise SystemExit(f"sample {bad} became unstable")
+    print(f"[bench] {args.steps} ticks in {sec:.3f} s: {mlups:.0f} MLUPS", file=sys.stderr, flush=True)
+    avg_ms, launches, bpl, achieved = kernel_roofline(ens, wl, torch, args.roofline_ticks)
+    print(f"[bench] collide-stream: {launches} launches, {avg_ms:.4f} ms avg, {achieved:.0f} GB/s algorithmic",
+          file=sys.stderr, flush=True)
+    f64_32 = fp64_single(mc, torch, 32, 0.05, 100.0)
+    f64_64 = fp64_single(mc, torch, 64, 0.025, 1600.0)
+    out = {
+        "metric": "aggregate MLUPS & % HBM roofline, batched FP32 vs plain FP64, at stated rel. error",
+        "value": round(mlups, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(sec / args.steps * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if wl.precision == "f32s" else "f64",
+        "data": "synthetic",
+        "config": {"workload": wl.name, "samples": wl.m,
+                   "lattices": [f"{g.count}x{g.n}^3 stride {g.stride}" for g in wl.groups],
+                   "precision": "FP32 shifted populations (f - w), FP64 reductions" if wl.precision == "f32s"
+                   else "FP64", "reduce_every": rec_every, "launch": {"block": ens.get_launch()[0],
+                                                                      "xcd_remap": ens.get_launch()[1]},
+                   "rel_error_bound_vs_oracle": 1e-5 if wl.precision == "f32s" else 1e-12},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": "kbc_step_kernel", "bytes_per_lup": BYTES_PER_LUP[wl.precision],
+                     "avg_launch_ms": round(avg_ms, 5), "launches_timed": launches,
+                     "measured_copy_GBps": round(b_meas, 1), "frac_of_measured_copy": round(achieved / b_meas, 4)},
+        "fp64_single_sample": {"32^3 TGV Re 100 MLUPS": round(f64_32, 1), "64^3 Re 1600 MLUPS": round(f64_64, 1)},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,232 @@
+/* mclbm.h - C ABI of the MI355X Monte Carlo KBC lattice Boltzmann library.
+ *
+ * The library evolves an ensemble of M independent samples of the randomized
+ * Taylor-Green vortex (RTGV) with a D3Q27 lattice Boltzmann scheme whose
+ * collision is the entropic multi-relaxation (KBC) operator: the
+ * non-equilibrium part of the populations is split into a shear part and a
+ * higher-order part, the shear part relaxes with omega (fixed by the
+ * viscosity), the higher-order part with omega*gamma/2, and gamma is chosen
+ * per node and time step by the closed-form entropic condition. The
+ * ensemble is the empirical measure of the paper's Monte Carlo method.
+ *
+ * Paper passages (arXiv 2608.23786):
+ *   equilibrium, moments ........ eq. (equilibrium) and the density/momentum
+ *                                  definitions that follow it
+ *   collide-and-stream .......... eq. (lbIteration)
+ *   KBC collision ............... eqs. (kbcCollision), (entropyControl),
+ *                                 Table 1 (relaxation groups and omega)
+ *   random initial data ......... eqs. (alpha_perturbation), (tgv_init_velo),
+ *                                 (initialRTGV), (initialPopulations)
+ *   Monte Carlo ensemble ........ eq. (statSolDisc) and the push-forward
+ *                                 construction of section 4.1
+ *   kinetic energy .............. eq. (dftCoeff) normalisation (energy per
+ *                                 unit volume of u)
+ *
+ * Conventions shared by every call
+ *   - Velocities: index i = 9*(cx+1) + 3*(cy+1) + (cz+1), c in {-1,0,1}^3;
+ *     the opposite velocity of i is 26 - i.
+ *   - Nodes: x_n = 2*pi*n/N, n = 0..N-1 per axis (periodic box [0, 2pi)^3).
+ *     Fields are C-ordered [z][y][x] (x fastest); cell = (z*N + y)*N + x.
+ *   - Random parameters: Y[m][24] in [-1, 1]; Y[m][p] multiplies the product
+ *     a_i(2x) a_j(2y) a_k(2z) in velocity component alpha, with
+ *     p = 8*alpha + 4*i + 2*j + k, a_0 = sin, a_1 = cos. The physical
+ *     coefficients are X = amp * u0 * Y.
+ *   - Units: lattice units. Re = u0 * L / nu with L = N / (2 pi) lattice
+ *     units, so nu = u0 * N / (2 pi Re) and omega = 1 / (3 nu + 1/2).
+ *   - Time: one tick advances every sample whose stride divides the tick
+ *     index by one lattice Boltzmann step. "State at step n" is the
+ *     post-stream population field after n steps; step 0 is the initial
+ *     equilibrium.
+ *
+ * Memory and streams
+ *   The caller owns all device memory (the workspace, outputs, checkpoint and
+ *   backward buffers) and the HIP stream; the library borrows them. A context
+ *   holds host-side metadata only; mclbm_destroy frees no device memory.
+ *   All device work is enqueued on the context's stream; device outputs are
+ *   valid once that stream has been synchronised. Calls that take host
+ *   pointers for output synchronise the stream themselves.
+ *   One context per stream; contexts are not thread-safe.
+ *
+ * Errors
+ *   Every call returns an mclbm_status. Arguments are validated before any
+ *   work is enqueued (MCLBM_ERR_ARG). HIP runtime failures give
+ *   MCLBM_ERR_HIP. Calls out of order (e.g. step before init) give
+ *   MCLBM_ERR_STATE. A non-finite density or velocity, or a non-positive
+ *   equilibrium population, met by a collision sets a sticky per-sample flag
+ *   that the next mclbm_reduce / mclbm_moments / mclbm_check reports as
+ *   MCLBM_ERR_UNSTABLE. mclbm_last_error() returns a message for the last
+ *   failing call of the calling thread.
+ */
+#ifndef MCLBM_H
+#define MCLBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mclbm_ctx mclbm_ctx;
+
+typedef enum {
+  MCLBM_OK = 0,
+  MCLBM_ERR_ARG = 1,
+  MCLBM_ERR_OOM = 2,         /* a caller-provided buffer is too small */
+  MCLBM_ERR_HIP = 3,
+  MCLBM_ERR_STATE = 4,
+  MCLBM_ERR_UNSTABLE = 5,
+  MCLBM_ERR_UNSUPPORTED = 6
+} mclbm_status;
+
+typedef enum {
+  MCLBM_FP64 = 0,            /* populations stored and computed in double */
+  MCLBM_FP32_SHIFTED = 1     /* g = f - w stored and computed in float */
+} mclbm_precision;
+
+/* One sample of the ensemble. */
+typedef struct {
+  int32_t n;        /* lattice points per axis: a power of two, 8 <= n <= 1024 */
+  double u0;        /* Taylor-Green amplitude in lattice units, 0 < u0 <= 0.2 */
+  double re;        /* Reynolds number u0 * (n / 2pi) / nu, > 0 */
+  double amp;       /* perturbation amplitude relative to u0, >= 0 */
+  int32_t project;  /* 1: Leray-project the perturbation; 0: use it as drawn */
+  int32_t stride;   /* the sample steps on every stride-th tick, a power of two >= 1 */
+} mclbm_sample_desc;
+
+/* Shear relaxation frequency of a sample (Table 1):
+ * omega = 2 c_s^2 / (2 nu + c_s^2) = 1 / (3 nu + 1/2), nu = u0 * n / (2 pi re).
+ * Returns 0 for invalid arguments. */
+double mclbm_omega(int32_t n, double u0, double re);
+
+/* Bytes of device workspace mclbm_create needs for this ensemble (0 if the
+ * descriptors are invalid). Population storage is one in-place buffer of
+ * 27 * n^3 values per sample, plus small tables. */
+size_t mclbm_workspace_bytes(int32_t m, const mclbm_sample_desc* desc, int32_t precision);
+
+/* Create a context for m samples (1 <= m <= 256). `workspace` is device memory
+ * of at least mclbm_workspace_bytes() bytes, 256-byte aligned; `hip_stream` is
+ * a hipStream_t (NULL for the null stream). The descriptors are copied. */
+mclbm_status mclbm_create(mclbm_ctx** out, int32_t m, const mclbm_sample_desc* desc, int32_t precision,
+                          void* workspace, size_t workspace_bytes, void* hip_stream);
+
+mclbm_status mclbm_destroy(mclbm_ctx* ctx);
+
+/* Draw or take the random parameters and set every sample to step 0:
+ * u0(x) = u0 [TGV(x) + amp * P s(Y)(x)], f = f^eq(1, u0(x)).
+ * y_host: host array Y[m][24], or NULL to draw Y with SplitMix64 from `seed`
+ * (state = seed; per draw: state += 0x9E3779B97F4A7C15, then the
+ * 30/27/31-bit xor-shift-multiply finaliser; Y = 2*(draw >> 11)*2^-53 - 1,
+ * sample by sample, parameter by parameter). Resets the tick counter. */
+mclbm_status mclbm_init(mclbm_ctx* ctx, uint64_t seed, const double* y_host);
+
+/* Copy the random parameters in use to the host: Y[m][24]. */
+mclbm_status mclbm_get_y(const mclbm_ctx* ctx, double* y_host);
+
+/* Set the physical viscosity eps of every sample (host array of m values,
+ * eps = 1/Re with unit reference length and velocity); nu = u0 * n * eps / (2 pi). */
+mclbm_status mclbm_set_viscosity(mclbm_ctx* ctx, const double* eps_host);
+
+/* Advance `ticks` ticks. If record_every > 0, the reductions of
+ * mclbm_reduce are taken of the state at the start of every tick t of this
+ * call with t % record_every == 0 (t counted from the start of the call),
+ * fused into that tick's collide-and-stream, and written as consecutive
+ * records of m*8 doubles to records_dev (device); max_records bounds how
+ * many fit. record_every must then be a multiple of every sample's stride
+ * and of the tick counter's phase. */
+mclbm_status mclbm_step(mclbm_ctx* ctx, int64_t ticks, int32_t record_every, double* records_dev,
+                        int64_t max_records);
+
+/* Density and velocity of one sample at its current step, in double:
+ * rho_dev[n^3], u_dev[3][n^3] (device, may be NULL to skip). */
+mclbm_status mclbm_moments(mclbm_ctx* ctx, int32_t sample, double* rho_dev, double* u_dev);
+
+/* Per-sample reductions of the current state into red_dev[m][8] (device):
+ * total mass sum(rho), total momentum sum(rho u) (3), kinetic energy
+ * mean(|u|^2 / 2), and min / max / mean of the stabiliser gamma that the
+ * next collision computes from this state. Accumulated in double. */
+mclbm_status mclbm_reduce(mclbm_ctx* ctx, double* red_dev);
+
+/* Report the sticky instability flags: *first_bad = lowest unstable sample
+ * or -1. Returns MCLBM_ERR_UNSTABLE if any. */
+mclbm_status mclbm_check(mclbm_ctx* ctx, int32_t* first_bad);
+
+/* Populations f (not shifted) of one sample at its current step, in double,
+ * layout [27][n^3] (device). get copies out; set replaces the state (the
+ * sample's step count is kept). */
+mclbm_status mclbm_get_state(mclbm_ctx* ctx, int32_t sample, double* f_dev);
+mclbm_status mclbm_set_state(mclbm_ctx* ctx, int32_t sample, const double* f_dev);
+
+/* Write NaN into population i of cell `cell` of one sample (failure-path
+ * tests). */
+mclbm_status mclbm_poison(mclbm_ctx* ctx, int32_t sample, int64_t cell, int32_t i);
+
+/* Checkpoint: a device copy of the whole ensemble state and its step
+ * counters. mclbm_checkpoint_bytes gives the size; restore puts the context
+ * back to exactly that state. */
+size_t mclbm_checkpoint_bytes(const mclbm_ctx* ctx);
+mclbm_status mclbm_checkpoint(mclbm_ctx* ctx, void* dst_dev, size_t bytes);
+mclbm_status mclbm_restore(mclbm_ctx* ctx, const void* src_dev, size_t bytes);
+
+/* Gradient of J = (1/m) sum_m KE_m(T) with respect to Y (discrete adjoint).
+ * Requires every stride to be 1 and the context to be at tick 0 (just
+ * initialised).
+ *   mclbm_forward_ckpt runs `ticks` steps from step 0 and stores a copy of
+ *     the state every `ckpt_every` steps in ckpt_dev;
+ *   mclbm_backward then computes dJdY_dev[m][24] (device, double) and
+ *     ke_dev[m] = KE_m(T) (device, may be NULL), recomputing each segment
+ *     of ckpt_every steps from its checkpoint into work_dev.
+ * Sizes come from mclbm_ckpt_bytes / mclbm_backward_work_bytes. The state
+ * after backward is the forward state at T. */
+size_t mclbm_ckpt_bytes(const mclbm_ctx* ctx, int64_t ticks, int32_t ckpt_every);
+size_t mclbm_backward_work_bytes(const mclbm_ctx* ctx, int32_t ckpt_every);
+mclbm_status mclbm_forward_ckpt(mclbm_ctx* ctx, int64_t ticks, int32_t ckpt_every, void* ckpt_dev,
+                                size_t ckpt_bytes);
+mclbm_status mclbm_backward(mclbm_ctx* ctx, int64_t ticks, int32_t ckpt_every, const void* ckpt_dev,
+                            size_t ckpt_bytes, void* work_dev, size_t work_bytes, double* dJdY_dev,
+                            double* ke_dev);
+
+/* Launch shape of the collide-and-stream kernel, one for the whole ensemble
+ * launch: threads (= lattice nodes) per block, 128, 256, 512 or 1024 (1024:
+ * FP32 only), not above any sample's n^3; xcd_remap = 1 renumbers blocks so
+ * that each of the 8 XCDs works on one contiguous range of nodes.
+ * Invalidates cached graphs. */
+mclbm_status mclbm_set_launch(mclbm_ctx* ctx, int32_t block_threads, int32_t xcd_remap);
+mclbm_status mclbm_get_launch(const mclbm_ctx* ctx, int32_t* block_threads, int32_t* xcd_remap);
+
+/* Time every launch shape on the current state (`reps` periods of
+ * 2 * max stride ticks each, after one warm-up period), keep the fastest,
+ * and restore the state from a checkpoint written to scratch_dev
+ * (mclbm_checkpoint_bytes). best_block / best_xcd (may be NULL) receive the
+ * choice. */
+mclbm_status mclbm_autotune(mclbm_ctx* ctx, int32_t reps, void* scratch_dev, size_t scratch_bytes,
+                            int32_t* best_block, int32_t* best_xcd);
+
+/* Capture the tick loop into HIP graphs (1, the default) or launch kernel by
+ * kernel (0). Graphs are used only on a non-NULL stream, for runs of at
+ * least one graph length (a whole number of activity/parity periods). */
+mclbm_status mclbm_use_graphs(mclbm_ctx* ctx, int32_t enable);
+
+/* Current tick counter and the number of steps sample s has taken. */
+int64_t mclbm_ticks(const mclbm_ctx* ctx);
+int64_t mclbm_steps(const mclbm_ctx* ctx, int32_t sample);
+
+/* Average duration in milliseconds, measured with HIP events on the
+ * context's stream, of the collide-and-stream launches enqueued since the
+ * last call (timing must be switched on with mclbm_time_launches(ctx, 1);
+ * it brackets every tick launch with events). *launches gets the count. */
+mclbm_status mclbm_time_launches(mclbm_ctx* ctx, int32_t enable);
+mclbm_status mclbm_launch_time(mclbm_ctx* ctx, double* avg_ms, int64_t* launches);
+
+/* Device-to-device copy of `bytes` (a multiple of 16) with a plain vector
+ * copy kernel on `hip_stream`: the measured HBM bandwidth reference. */
+mclbm_status mclbm_stream_copy(void* dst_dev, const void* src_dev, size_t bytes, void* hip_stream);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char* mclbm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MCLBM_H */

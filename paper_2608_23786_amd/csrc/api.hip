@@ -1,0 +1,942 @@
+// Host side of the C ABI declared in include/mclbm.h: context, workspace
+// layout, tick scheduling of mixed-resolution ensembles, HIP graph capture,
+// launch-shape autotuning, checkpoints and the adjoint driver.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/mclbm.h"
+#include "kernels.h"
+#include "lattice.h"
+
+using namespace mclbm;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+mclbm_status fail(mclbm_status st, const std::string& msg) {
+  g_last_error = msg;
+  return st;
+}
+
+#define HIP_TRY(expr)                                                                                \
+  do {                                                                                               \
+    hipError_t e_ = (expr);                                                                          \
+    if (e_ != hipSuccess)                                                                            \
+      return fail(MCLBM_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_));                \
+  } while (0)
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+int ilog2(int v) {
+  int l = 0;
+  while ((1 << l) < v) ++l;
+  return l;
+}
+bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
+
+constexpr int kMinBlock = 128;        // smallest collide-and-stream block
+constexpr int kAuxBlock = 256;        // block of the auxiliary kernels
+constexpr int kMaxTables = 128;       // launch tables kept in the workspace
+constexpr size_t kHeaderBytes = 4096; // checkpoint header
+constexpr uint64_t kCkptMagic = 0x4d434c424d434b50ull;
+
+// Leray projection on the 24 perturbation coefficients.
+// Every basis field a_i(2x) a_j(2y) a_k(2z) e_alpha is a Laplacian eigenfunction
+// (eigenvalue -12), so P s = s + grad(div s) / 12 exactly, and grad div maps the
+// family into itself: d/dx a_0(2x) = 2 a_1(2x), d/dx a_1(2x) = -2 a_0(2x).
+// Returns P[24][24] with Y' = P Y.
+std::vector<double> projection_matrix() {
+  std::vector<double> P(24 * 24, 0.0);
+  for (int p = 0; p < 24; ++p) {
+    const int al = p / 8;
+    const int idx[3] = {(p >> 2) & 1, (p >> 1) & 1, p & 1};
+    for (int be = 0; be < 3; ++be) {
+      int out[3] = {idx[0], idx[1], idx[2]};
+      double coef;
+      if (be == al) {
+        coef = 1.0 - 4.0 / 12.0;  // s_alpha + d^2/dx_alpha^2 s_alpha / 12
+      } else {
+        const double sa = idx[al] == 0 ? 2.0 : -2.0;
+        const double sb = idx[be] == 0 ? 2.0 : -2.0;
+        out[al] = 1 - idx[al];
+        out[be] = 1 - idx[be];
+        coef = sa * sb / 12.0;
+      }
+      const int q = 8 * be + 4 * out[0] + 2 * out[1] + out[2];
+      P[q * 24 + p] += coef;
+    }
+  }
+  return P;
+}
+
+struct Table {
+  size_t offset = 0;         // byte offset of the Seg array in the table pool
+  int nseg = 0;
+  int total_blocks = 0;
+  std::vector<Seg> host;     // persistent host copy (source of the upload)
+};
+
+}  // namespace
+
+struct mclbm_ctx {
+  int m = 0;
+  int precision = 0;
+  size_t elem = 8;
+  std::vector<mclbm_sample_desc> desc;
+  hipStream_t stream = nullptr;
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+
+  // workspace carve
+  DevSample* d_samples = nullptr;
+  int32_t* d_flags = nullptr;
+  double* d_ycoef = nullptr;
+  double* d_pmat = nullptr;
+  Seg* d_tables = nullptr;
+  size_t table_pool_bytes = 0;
+  double* d_partials = nullptr;
+  size_t partial_blocks = 0;
+  char* pop = nullptr;
+  size_t state_bytes = 0;
+
+  std::vector<DevSample> h_samples;
+  std::vector<double> y;     // drawn or given parameters, m x 24
+  std::vector<double> pmat;
+  bool initialized = false;
+  int64_t tick = 0;
+  std::vector<int64_t> steps;
+  int max_stride = 1;
+
+  // launch shape
+  int block = 256;
+  int xcd_remap = 0;
+
+  // launch tables by key
+  std::map<std::string, Table> tables;
+  size_t table_next = 0;
+
+  // graphs keyed by the tick phase
+  bool use_graphs = true;
+  std::map<int64_t, hipGraphExec_t> graphs;
+  int64_t graph_ticks = 0;
+
+  // launch timing
+  bool timing = false;
+  std::vector<hipEvent_t> ev_pool;
+  size_t ev_used = 0;
+
+  std::vector<char> ckpt_header;
+
+  int64_t cells(int s) const { return int64_t(desc[s].n) * desc[s].n * desc[s].n; }
+};
+
+namespace {
+
+void drop_graphs(mclbm_ctx* c) {
+  for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
+  c->graphs.clear();
+}
+
+mclbm_status validate_desc(int32_t m, const mclbm_sample_desc* d, int32_t precision) {
+  if (m < 1 || m > kMaxSamples) return fail(MCLBM_ERR_ARG, "m must be in [1, 256]");
+  if (!d) return fail(MCLBM_ERR_ARG, "descriptor array is NULL");
+  if (precision != MCLBM_FP64 && precision != MCLBM_FP32_SHIFTED) return fail(MCLBM_ERR_ARG, "unknown precision");
+  for (int s = 0; s < m; ++s) {
+    const mclbm_sample_desc& e = d[s];
+    const int nmax = precision == MCLBM_FP64 ? 512 : 1024;
+    if (!is_pow2(e.n) || e.n < 8 || e.n > nmax)
+      return fail(MCLBM_ERR_ARG, "sample " + std::to_string(s) + ": n must be a power of two in [8, " +
+                                     std::to_string(nmax) + "]");
+    if (!(e.u0 > 0.0) || !(e.u0 <= 0.2)) return fail(MCLBM_ERR_ARG, "sample " + std::to_string(s) + ": u0 out of (0, 0.2]");
+    if (!(e.re > 0.0) || !std::isfinite(e.re)) return fail(MCLBM_ERR_ARG, "sample " + std::to_string(s) + ": re must be > 0");
+    if (!(e.amp >= 0.0) || !std::isfinite(e.amp)) return fail(MCLBM_ERR_ARG, "sample " + std::to_string(s) + ": amp must be >= 0");
+    if (e.project != 0 && e.project != 1) return fail(MCLBM_ERR_ARG, "sample " + std::to_string(s) + ": project must be 0 or 1");
+    if (!is_pow2(e.stride) || e.stride > 1024)
+      return fail(MCLBM_ERR_ARG, "sample " + std::to_string(s) + ": stride must be a power of two <= 1024");
+  }
+  return MCLBM_OK;
+}
+
+struct Layout {
+  size_t samples, flags, ycoef, pmat, tables, table_bytes, partials, partial_blocks, pop, state_bytes, total;
+};
+
+Layout layout_of(int32_t m, const mclbm_sample_desc* d, int32_t precision) {
+  Layout L{};
+  const size_t elem = precision == MCLBM_FP64 ? 8 : 4;
+  size_t off = 0;
+  L.samples = off;
+  off = align_up(off + sizeof(DevSample) * kMaxSamples);
+  L.flags = off;
+  off = align_up(off + sizeof(int32_t) * kMaxSamples);
+  L.ycoef = off;
+  off = align_up(off + sizeof(double) * 24 * kMaxSamples);
+  L.pmat = off;
+  off = align_up(off + sizeof(double) * 24 * 24);
+  L.tables = off;
+  L.table_bytes = size_t(kMaxTables) * align_up(sizeof(Seg) * m);
+  off = align_up(off + L.table_bytes);
+  size_t cells = 0;
+  for (int s = 0; s < m; ++s) cells += size_t(d[s].n) * d[s].n * d[s].n;
+  L.partial_blocks = cells / kMinBlock;
+  L.partials = off;
+  off = align_up(off + L.partial_blocks * kRecord * sizeof(double));
+  L.pop = off;
+  size_t st = 0;
+  for (int s = 0; s < m; ++s) st = align_up(st + size_t(Q) * d[s].n * d[s].n * d[s].n * elem);
+  L.state_bytes = st;
+  off += st;
+  L.total = off;
+  return L;
+}
+
+double omega_of(double nu);
+
+void fill_sample(mclbm_ctx* c, int s, double nu) {
+  DevSample& h = c->h_samples[s];
+  const double omega = omega_of(nu);
+  h.omega = omega;
+  h.two_over_omega = 2.0 / omega;
+  h.kappa = 2.0 - 2.0 / omega;
+  h.omega_f = float(h.omega);
+  h.two_over_omega_f = float(h.two_over_omega);
+  h.kappa_f = float(h.kappa);
+}
+
+// Re = u0 L / nu with L = n / (2 pi) lattice units (the box is 2 pi reference lengths)
+double lattice_nu(int32_t n, double u0, double re) { return u0 * (double(n) / (2.0 * M_PI)) / re; }
+double lattice_nu(const mclbm_sample_desc& d) { return lattice_nu(d.n, d.u0, d.re); }
+double omega_of(double nu) { return 1.0 / (3.0 * nu + 0.5); }  // Table 1: 2 c_s^2 / (2 nu + c_s^2), c_s^2 = 1/3
+
+// Launch table for the samples active at `tick` (stride divides tick), with
+// their AA parities; `all` forces every sample (init, reductions, adjoint).
+mclbm_status get_table(mclbm_ctx* c, int64_t tick, bool all, int block, bool parity_zero, const Table** out) {
+  std::string key = std::to_string(block) + (all ? "A" : "T") + (parity_zero ? "0" : "P") + ":";
+  std::vector<Seg> segs;
+  int first = 0;
+  for (int s = 0; s < c->m; ++s) {
+    const bool active = all || (tick % c->desc[s].stride == 0);
+    if (!active) continue;
+    Seg g;
+    g.sample = s;
+    g.first_block = first;
+    g.nblocks = int32_t(c->cells(s) / block);
+    g.parity = parity_zero ? 0 : int32_t(c->steps[s] & 1);
+    first += g.nblocks;
+    segs.push_back(g);
+    key += std::to_string(s) + (g.parity ? "o" : "e") + ",";
+  }
+  auto it = c->tables.find(key);
+  if (it != c->tables.end()) {
+    *out = &it->second;
+    return MCLBM_OK;
+  }
+  const size_t slot = align_up(sizeof(Seg) * c->m);
+  if (c->table_next + slot > c->table_pool_bytes) {
+    // pool full: wait until no launch reads a table, then start over
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    drop_graphs(c);
+    c->tables.clear();
+    c->table_next = 0;
+  }
+  Table t;
+  t.offset = c->table_next;
+  t.nseg = int(segs.size());
+  t.total_blocks = first;
+  t.host = segs;
+  c->table_next += slot;
+  if (!segs.empty()) {
+    HIP_TRY(hipMemcpy(reinterpret_cast<char*>(c->d_tables) + t.offset, t.host.data(), sizeof(Seg) * segs.size(),
+                      hipMemcpyHostToDevice));
+  }
+  auto res = c->tables.emplace(key, std::move(t));
+  *out = &res.first->second;
+  return MCLBM_OK;
+}
+
+const Seg* table_ptr(mclbm_ctx* c, const Table* t) {
+  return reinterpret_cast<const Seg*>(reinterpret_cast<const char*>(c->d_tables) + t->offset);
+}
+
+StepLaunch make_launch(mclbm_ctx* c, const Table* t, void* pop, void* dst) {
+  StepLaunch L;
+  L.pop = pop;
+  L.dst = dst;
+  L.samples = c->d_samples;
+  L.segs = table_ptr(c, t);
+  L.nseg = t->nseg;
+  L.total_blocks = t->total_blocks;
+  L.block = c->block;
+  L.xcd_remap = c->xcd_remap;
+  L.flags = c->d_flags;
+  L.partials = c->d_partials;
+  return L;
+}
+
+hipEvent_t next_event(mclbm_ctx* c) {
+  if (c->ev_used == c->ev_pool.size()) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    c->ev_pool.push_back(e);
+  }
+  return c->ev_pool[c->ev_used++];
+}
+
+// One tick: every active sample takes one step; optionally fused reductions.
+mclbm_status run_tick(mclbm_ctx* c, double* record_out) {
+  const Table* t = nullptr;
+  mclbm_status st = get_table(c, c->tick, false, c->block, false, &t);
+  if (st != MCLBM_OK) return st;
+  if (t->nseg > 0) {
+    StepLaunch L = make_launch(c, t, c->pop, nullptr);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (c->timing) {
+      e0 = next_event(c);
+      e1 = next_event(c);
+      if (!e0 || !e1) return fail(MCLBM_ERR_HIP, "hipEventCreate failed");
+      HIP_TRY(hipEventRecord(e0, c->stream));
+    }
+    HIP_TRY(launch_step(c->precision, record_out ? kStepRecord : kStep, L, c->stream));
+    if (c->timing) HIP_TRY(hipEventRecord(e1, c->stream));
+    if (record_out)
+      HIP_TRY(launch_record_finalize(c->d_partials, L.segs, t->nseg, c->d_samples, record_out, c->stream));
+    for (const Seg& g : t->host) c->steps[g.sample] += 1;
+  }
+  c->tick += 1;
+  return MCLBM_OK;
+}
+
+// Length of one graph: a whole number of periods of the parity/activity
+// pattern (2 * max stride ticks), at least 32 ticks.
+int64_t graph_length(const mclbm_ctx* c) {
+  const int64_t period = 2 * int64_t(c->max_stride);
+  return period * std::max<int64_t>(1, (32 + period - 1) / period);
+}
+
+// Graphs are used when one period needs few enough launch tables that all of
+// them stay resident in the table pool while the graph exists.
+bool graphs_possible(const mclbm_ctx* c) { return 2 * int64_t(c->max_stride) <= kMaxTables / 4; }
+
+mclbm_status run_graph(mclbm_ctx* c) {
+  const int64_t len = graph_length(c);
+  const int64_t phase = c->tick % (2 * int64_t(c->max_stride));
+  auto it = c->graphs.find(phase);
+  if (it == c->graphs.end()) {
+    // leave room for every table of the period so that none is evicted
+    // between building the tables and capturing the launches that read them
+    const size_t slot = align_up(sizeof(Seg) * c->m);
+    if (c->table_next + size_t(kMaxTables / 4 + 8) * slot > c->table_pool_bytes) {
+      HIP_TRY(hipStreamSynchronize(c->stream));
+      drop_graphs(c);
+      c->tables.clear();
+      c->table_next = 0;
+      it = c->graphs.end();
+    }
+    // make sure every table of the period exists before capturing
+    const int64_t tick0 = c->tick;
+    std::vector<int64_t> steps0 = c->steps;
+    for (int64_t k = 0; k < len; ++k) {
+      const Table* t = nullptr;
+      mclbm_status st = get_table(c, c->tick, false, c->block, false, &t);
+      if (st != MCLBM_OK) return st;
+      for (const Seg& g : t->host) c->steps[g.sample] += 1;
+      c->tick += 1;
+    }
+    c->tick = tick0;
+    c->steps = steps0;
+    HIP_TRY(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+    mclbm_status st = MCLBM_OK;
+    for (int64_t k = 0; k < len && st == MCLBM_OK; ++k) st = run_tick(c, nullptr);
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamEndCapture(c->stream, &graph);
+    c->tick = tick0;
+    c->steps = steps0;
+    if (st != MCLBM_OK) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return st;
+    }
+    if (e != hipSuccess) return fail(MCLBM_ERR_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return fail(MCLBM_ERR_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+    it = c->graphs.emplace(phase, exec).first;
+  }
+  HIP_TRY(hipGraphLaunch(it->second, c->stream));
+  // bookkeeping of the ticks the graph ran
+  for (int64_t k = 0; k < len; ++k) {
+    for (int s = 0; s < c->m; ++s)
+      if (c->tick % c->desc[s].stride == 0) c->steps[s] += 1;
+    c->tick += 1;
+  }
+  return MCLBM_OK;
+}
+
+mclbm_status run_plain_ticks(mclbm_ctx* c, int64_t ticks) {
+  int64_t left = ticks;
+  const int64_t len = graph_length(c);
+  while (left > 0) {
+    if (c->use_graphs && c->stream && !c->timing && graphs_possible(c) && left >= len) {
+      mclbm_status st = run_graph(c);
+      if (st != MCLBM_OK) return st;
+      left -= len;
+    } else {
+      mclbm_status st = run_tick(c, nullptr);
+      if (st != MCLBM_OK) return st;
+      left -= 1;
+    }
+  }
+  return MCLBM_OK;
+}
+
+mclbm_status check_ctx(const mclbm_ctx* c, bool need_init) {
+  if (!c) return fail(MCLBM_ERR_ARG, "context is NULL");
+  if (need_init && !c->initialized) return fail(MCLBM_ERR_STATE, "mclbm_init has not been called");
+  return MCLBM_OK;
+}
+
+mclbm_status check_flags(mclbm_ctx* c, int32_t* first_bad) {
+  std::vector<int32_t> flags(c->m);
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  HIP_TRY(hipMemcpy(flags.data(), c->d_flags, sizeof(int32_t) * c->m, hipMemcpyDeviceToHost));
+  for (int s = 0; s < c->m; ++s)
+    if (flags[s]) {
+      if (first_bad) *first_bad = s;
+      return fail(MCLBM_ERR_UNSTABLE, "sample " + std::to_string(s) + " became unstable (non-finite density or "
+                                      "velocity, or a non-positive equilibrium population)");
+    }
+  if (first_bad) *first_bad = -1;
+  return MCLBM_OK;
+}
+
+uint64_t splitmix64_next(uint64_t& state) {
+  state += 0x9E3779B97F4A7C15ull;
+  uint64_t z = state;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+}  // namespace
+
+extern "C" {
+
+double mclbm_omega(int32_t n, double u0, double re) {
+  if (n < 1 || !(u0 > 0.0) || !(re > 0.0)) return 0.0;
+  return omega_of(lattice_nu(n, u0, re));
+}
+
+size_t mclbm_workspace_bytes(int32_t m, const mclbm_sample_desc* desc, int32_t precision) {
+  if (validate_desc(m, desc, precision) != MCLBM_OK) return 0;
+  return layout_of(m, desc, precision).total;
+}
+
+mclbm_status mclbm_create(mclbm_ctx** out, int32_t m, const mclbm_sample_desc* desc, int32_t precision,
+                          void* workspace, size_t workspace_bytes, void* hip_stream) {
+  if (!out) return fail(MCLBM_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  mclbm_status st = validate_desc(m, desc, precision);
+  if (st != MCLBM_OK) return st;
+  const Layout L = layout_of(m, desc, precision);
+  if (!workspace) return fail(MCLBM_ERR_ARG, "workspace is NULL");
+  if (reinterpret_cast<uintptr_t>(workspace) % kAlign) return fail(MCLBM_ERR_ARG, "workspace must be 256-byte aligned");
+  if (workspace_bytes < L.total)
+    return fail(MCLBM_ERR_OOM, "workspace too small: need " + std::to_string(L.total) + " bytes");
+
+  mclbm_ctx* c = new mclbm_ctx();
+  c->m = m;
+  c->precision = precision;
+  c->elem = precision == MCLBM_FP64 ? 8 : 4;
+  c->desc.assign(desc, desc + m);
+  c->stream = static_cast<hipStream_t>(hip_stream);
+  c->ws = static_cast<char*>(workspace);
+  c->ws_bytes = workspace_bytes;
+  c->d_samples = reinterpret_cast<DevSample*>(c->ws + L.samples);
+  c->d_flags = reinterpret_cast<int32_t*>(c->ws + L.flags);
+  c->d_ycoef = reinterpret_cast<double*>(c->ws + L.ycoef);
+  c->d_pmat = reinterpret_cast<double*>(c->ws + L.pmat);
+  c->d_tables = reinterpret_cast<Seg*>(c->ws + L.tables);
+  c->table_pool_bytes = L.table_bytes;
+  c->d_partials = reinterpret_cast<double*>(c->ws + L.partials);
+  c->partial_blocks = L.partial_blocks;
+  c->pop = c->ws + L.pop;
+  c->state_bytes = L.state_bytes;
+  c->steps.assign(m, 0);
+  c->y.assign(size_t(m) * 24, 0.0);
+  c->pmat = projection_matrix();
+  c->h_samples.resize(m);
+  size_t off = 0;
+  for (int s = 0; s < m; ++s) {
+    DevSample& h = c->h_samples[s];
+    std::memset(&h, 0, sizeof(h));
+    h.offset = off / c->elem;
+    h.n = desc[s].n;
+    h.log2n = ilog2(desc[s].n);
+    h.u0 = desc[s].u0;
+    h.amp = desc[s].amp;
+    h.project = desc[s].project;
+    fill_sample(c, s, lattice_nu(desc[s]));
+    off = align_up(off + size_t(Q) * c->cells(s) * c->elem);
+    c->max_stride = std::max(c->max_stride, desc[s].stride);
+  }
+  hipError_t e = hipMemcpy(c->d_samples, c->h_samples.data(), sizeof(DevSample) * m, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(c->d_pmat, c->pmat.data(), sizeof(double) * 24 * 24, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemset(c->d_flags, 0, sizeof(int32_t) * kMaxSamples);
+  if (e != hipSuccess) {
+    delete c;
+    return fail(MCLBM_ERR_HIP, std::string("context upload: ") + hipGetErrorString(e));
+  }
+  c->ckpt_header.assign(kHeaderBytes, 0);
+  *out = c;
+  return MCLBM_OK;
+}
+
+mclbm_status mclbm_destroy(mclbm_ctx* c) {
+  if (!c) return MCLBM_OK;
+  (void)hipStreamSynchronize(c->stream);
+  drop_graphs(c);
+  for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+  delete c;
+  return MCLBM_OK;
+}
+
+mclbm_status mclbm_init(mclbm_ctx* c, uint64_t seed, const double* y_host) {
+  mclbm_status st = check_ctx(c, false);
+  if (st != MCLBM_OK) return st;
+  if (y_host) {
+    for (size_t k = 0; k < size_t(c->m) * 24; ++k) {
+      if (!std::isfinite(y_host[k])) return fail(MCLBM_ERR_ARG, "Y contains a non-finite value");
+      c->y[k] = y_host[k];
+    }
+  } else {
+    uint64_t state = seed;
+    for (size_t k = 0; k < size_t(c->m) * 24; ++k)
+      c->y[k] = 2.0 * (double(splitmix64_next(state) >> 11) * 0x1.0p-53) - 1.0;
+  }
+  // coefficients of the (projected) perturbation per sample
+  std::vector<double> yc(size_t(c->m) * 24);
+  for (int s = 0; s < c->m; ++s) {
+    const double* ys = &c->y[size_t(s) * 24];
+    for (int q = 0; q < 24; ++q) {
+      double v = ys[q];
+      if (c->desc[s].project) {
+        v = 0.0;
+        for (int p = 0; p < 24; ++p) v += c->pmat[q * 24 + p] * ys[p];
+      }
+      yc[size_t(s) * 24 + q] = v;
+    }
+  }
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  HIP_TRY(hipMemcpy(c->d_ycoef, yc.data(), sizeof(double) * yc.size(), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemset(c->d_flags, 0, sizeof(int32_t) * kMaxSamples));
+  std::fill(c->steps.begin(), c->steps.end(), 0);
+  c->tick = 0;
+  const Table* t = nullptr;
+  st = get_table(c, 0, true, kAuxBlock, true, &t);
+  if (st != MCLBM_OK) return st;
+  HIP_TRY(launch_init(c->precision, c->pop, c->d_samples, table_ptr(c, t), t->nseg, t->total_blocks, c->d_ycoef,
+                      c->stream));
+  c->initialized = true;
+  return MCLBM_OK;
+}
+
+mclbm_status mclbm_get_y(const mclbm_ctx* c, double* y_host) {
+  mclbm_status st = check_ctx(c, true);
+  if (st != MCLBM_OK) return st;
+  if (!y_host) return fail(MCLBM_ERR_ARG, "y_host is NULL");
+  std::memcpy(y_host, c->y.data(), sizeof(double) * c->y.size());
+  return MCLBM_OK;
+}
+
+mclbm_status mclbm_set_viscosity(mclbm_ctx* c, const double* eps_host) {
+  mclbm_status st = check_ctx(c, false);
+  if (st != MCLBM_OK) return st;
+  if (!eps_host) return fail(MCLBM_ERR_ARG, "eps_host is NULL");
+  for (int s = 0; s < c->m; ++s)
+    if (!(eps_host[s] > 0.0) || !std::isfinite(eps_host[s])) return fail(MCLBM_ERR_ARG, "viscosity must be > 0");
+  for (int s = 0; s < c->m; ++s) {
+    c->desc[s].re = 1.0 / eps_host[s];
+    fill_sample(c, s, lattice_nu(c->desc[s]));
+  }
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  HIP_TRY(hipMemcpy(c->d_samples, c->h_samples.data(), sizeof(DevSample) * c->m, hipMemcpyHostToDevice));
+  return MCLBM_OK;
+}
+
+mclbm_status mclbm_step(mclbm_ctx* c, int64_t ticks, int32_t record_every, double* records_dev,
+                        int64_t max_records) {
+  mclbm_status st = check_ctx(c, true);
+  if (st != MCLBM_OK) return st;
+  if (ticks < 0) return fail(MCLBM_ERR_ARG, "ticks must be >= 0");
+  if (record_every < 0) return fail(MCLBM_ERR_ARG, "record_every must be >= 0");
+  if (record_every > 0) {
+    if (!records_dev) return fail(MCLBM_ERR_ARG, "records_dev is NULL");
+    for (int s = 0; s < c->m; ++s)
+      if (record_every % c->desc[s].stride) return fail(MCLBM_ERR_ARG, "record_every must be a multiple of every stride");
+    if (c->tick % c->max_stride) return fail(MCLBM_ERR_ARG, "recording must start on a tick where every sample steps");
+    const int64_t need = (ticks + record_every - 1) / record_every;
+    if (need > max_records) return fail(MCLBM_ERR_OOM, "records_dev holds " + std::to_string(max_records) +
+                                                           " records, " + std::to_string(need) + " needed");
+    int64_t k = 0;
+    for (int64_t t = 0; t < ticks;) {
+      st = run_tick(c, records_dev + size_t(k) * c->m * kRecord);
+      if (st != MCLBM_OK) return st;
+      ++k;
+      ++t;
+      const int64_t plain = std::min<int64_t>(record_every - 1, ticks - t);
+      st = run_plain_ticks(c, plain);
+      if (st != MCLBM_OK) return st;
+      t += plain;
+    }
+    return MCLBM_OK;
+  }
+  return run_plain_ticks(c, ticks);
+}
+
+mclbm_status mclbm_moments(mclbm_ctx* c, int32_t sample, double* rho_dev, double* u_dev) {
+  mclbm_status st = check_ctx(c, true);
+  if (st != MCLBM_OK) return st;
+  if (sample < 0 || sample >= c->m) return fail(MCLBM_ERR_ARG, "sample out of range");
+  HIP_TRY(launch_moments(c->precision, c->pop, c->d_samples, sample, c->desc[sample].n, int32_t(c->steps[sample] & 1),
+                         rho_dev, u_dev, c->stream));
+  return check_flags(c, nullptr);
+}
+
+mclbm_status mclbm_reduce(mclbm_ctx* c, double* red_dev) {
+  mclbm_status st = check_ctx(c, true);
+  if (st != MCLBM_OK) return st;
+  if (!red_dev) return fail(MCLBM_ERR_ARG, "red_dev is NULL");
+  const Table* t = nullptr;
+  st = get_table(c, c->tick, true, c->block, false, &t);
+  if (st != MCLBM_OK) return st;
+  StepLaunch L = make_launch(c, t, c->pop, nullptr);
+  HIP_TRY(launch_step(c->precision, kReduceOnly, L, c->stream));
+  HIP_TRY(launch_record_finalize(c->d_partials, L.segs, t->nseg, c->d_samples, red_dev, c->stream));
+  return check_flags(c, nullptr);
+}
+
+mclbm_status mclbm_check(mclbm_ctx* c, int32_t* first_bad) {
+  mclbm_status st = check_ctx(c, false);
+  if (st != MCLBM_OK) return st;
+  return check_flags(c, first_bad);
+}
+
+mclbm_status mclbm_get_state(mclbm_ctx* c, int32_t sample, double* f_dev) {
+  mclbm_status st = check_ctx(c, true);
+  if (st != MCLBM_OK) return st;
+  if (sample < 0 || sample >= c->m || !f_dev) return fail(MCLBM_ERR_ARG, "bad sample or NULL buffer");
+  HIP_TRY(launch_get_state(c->precision, c->pop, c->d_samples, sample, c->desc[sample].n,
+                           int32_t(c->steps[sample] & 1), f_dev, c->stream));
+  return MCLBM_OK;
+}
+
+mclbm_status mclbm_set_state(mclbm_ctx* c, int32_t sample, const double* f_dev) {
+  mclbm_status st = check_ctx(c, true);
+  if (st != MCLBM_OK) return st;
+  if (sample < 0 || sample >= c->m || !f_dev) return fail(MCLBM_ERR_ARG, "bad sample or NULL buffer");
+  HIP_TRY(launch_set_state(c->precision, c->pop, c->d_samples, sample, c->desc[sample].n,
+                           int32_t(c->steps[sample] & 1), f_dev, c->stream));
+  return MCLBM_OK;
+}
+
+mclbm_status mclbm_poison(mclbm_ctx* c, int32_t sample, int64_t cell, int32_t i) {
+  mclbm_status st = check_ctx(c, true);
+  if (st != MCLBM_OK) return st;
+  if (sample < 0 || sample >= c->m) return fail(MCLBM_ERR_ARG, "sample out of range");
+  if (cell < 0 || cell >= c->cells(sample) || i < 0 || i >= Q) return fail(MCLBM_ERR_ARG, "cell or velocity out of range");
+  HIP_TRY(launch_poison(c->precision, c->pop, c->d_samples, sample, int32_t(c->steps[sample] & 1), cell, i, c->stream));
+  return MCLBM_OK;
+}
+
+size_t mclbm_checkpoint_bytes(const mclbm_ctx* c) { return c ? kHeaderBytes + c->state_bytes : 0; }
+
+mclbm_status mclbm_checkpoint(mclbm_ctx* c, void* dst_dev, size_t bytes) {
+  mclbm_status st = check_ctx(c, true);
+  if (st != MCLBM_OK) return st;
+  if (!dst_dev) return fail(MCLBM_ERR_ARG, "dst_dev is NULL");
+  if (bytes < mclbm_checkpoint_bytes(c)) return fail(MCLBM_ERR_OOM, "checkpoint buffer too small");
+  // header: magic, m, precision, tick, steps[m]
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  std::vector<int64_t> h(4 + c->m);
+  h[0] = int64_t(kCkptMagic);
+  h[1] = c->m;
+  h[2] = c->precision;
+  h[3] = c->tick;
+  for (int s = 0; s < c->m; ++s) h[4 + s] = c->steps[s];
+  HIP_TRY(hipMemcpy(dst_dev, h.data(), sizeof(int64_t) * h.size(), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpyAsync(static_cast<char*>(dst_dev) + kHeaderBytes, c->pop, c->state_bytes, hipMemcpyDeviceToDevice,
+                         c->stream));
+  return MCLBM_OK;
+}
+
+mclbm_status mclbm_restore(mclbm_ctx* c, const void* src_dev, size_t bytes) {
+  mclbm_status st = check_ctx(c, true);
+  if (st != MCLBM_OK) return st;
+  if (!src_dev) return fail(MCLBM_ERR_ARG, "src_dev is NULL");
+  if (bytes < mclbm_checkpoint_bytes(c)) return fail(MCLBM_ERR_OOM, "checkpoint buffer too small");
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  std::vector<int64_t> h(4 + c->m);
+  HIP_TRY(hipMemcpy(h.data(), src_dev, sizeof(int64_t) * h.size(), hipMemcpyDeviceToHost));
+  if (h[0] != int64_t(kCkptMagic) || h[1] != c->m || h[2] != c->precision)
+    return fail(MCLBM_ERR_ARG, "checkpoint does not belong to this ensemble");
+  HIP_TRY(hipMemcpyAsync(c->pop, static_cast<const char*>(src_dev) + kHeaderBytes, c->state_bytes,
+                         hipMemcpyDeviceToDevice, c->stream));
+  c->tick = h[3];
+  for (int s = 0; s < c->m; ++s) c->steps[s] = h[4 + s];
+  HIP_TRY(hipMemsetAsync(c->d_flags, 0, sizeof(int32_t) * kMaxSamples, c->stream));
+  return MCLBM_OK;
+}
+
+// ------------------------------------------------------------------ adjoint
+size_t mclbm_ckpt_bytes(const mclbm_ctx* c, int64_t ticks, int32_t ckpt_every) {
+  if (!c || ticks < 1 || ckpt_every < 1) return 0;
+  const int64_t nck = (ticks + ckpt_every - 1) / ckpt_every;
+  return size_t(nck) * c->state_bytes;
+}
+
+size_t mclbm_backward_work_bytes(const mclbm_ctx* c, int32_t ckpt_every) {
+  if (!c || ckpt_every < 1) return 0;
+  size_t cells = 0;
+  for (int s = 0; s < c->m; ++s) cells += size_t(c->cells(s));
+  const size_t partials = align_up(cells / kAuxBlock * 24 * sizeof(double));
+  const size_t records = align_up(size_t(c->m) * kRecord * sizeof(double));
+  return size_t(ckpt_every) * c->state_bytes + 2 * c->state_bytes + partials + records;
+}
+
+static mclbm_status check_adjoint(mclbm_ctx* c, int64_t ticks, int32_t ckpt_every) {
+  mclbm_status st = check_ctx(c, true);
+  if (st != MCLBM_OK) return st;
+  if (ticks < 1 || ckpt_every < 1) return fail(MCLBM_ERR_ARG, "ticks and ckpt_every must be >= 1");
+  for (int s = 0; s < c->m; ++s)
+    if (c->desc[s].stride != 1) return fail(MCLBM_ERR_UNSUPPORTED, "the adjoint needs every stride to be 1");
+  return MCLBM_OK;
+}
+
+mclbm_status mclbm_forward_ckpt(mclbm_ctx* c, int64_t ticks, int32_t ckpt_every, void* ckpt_dev, size_t ckpt_bytes) {
+  mclbm_status st = check_adjoint(c, ticks, ckpt_every);
+  if (st != MCLBM_OK) return st;
+  if (c->tick != 0) return fail(MCLBM_ERR_STATE, "forward_ckpt must start from step 0 (call mclbm_init first)");
+  if (!ckpt_dev || ckpt_bytes < mclbm_ckpt_bytes(c, ticks, ckpt_every))
+    return fail(MCLBM_ERR_OOM, "checkpoint buffer too small");
+  for (int64_t k = 0; k * ckpt_every < ticks; ++k) {
+    const Table* t = nullptr;
+    st = get_table(c, c->tick, true, kAuxBlock, false, &t);
+    if (st != MCLBM_OK) return st;
+    HIP_TRY(launch_canonical_copy(c->precision, c->pop, static_cast<char*>(ckpt_dev) + size_t(k) * c->state_bytes,
+                                  c->d_samples, table_ptr(c, t), t->nseg, t->total_blocks, c->stream));
+    st = run_plain_ticks(c, std::min<int64_t>(ckpt_every, ticks - k * ckpt_every));
+    if (st != MCLBM_OK) return st;
+  }
+  return MCLBM_OK;
+}
+
+mclbm_status mclbm_backward(mclbm_ctx* c, int64_t ticks, int32_t ckpt_every, const void* ckpt_dev,
+                            size_t ckpt_bytes, void* work_dev, size_t work_bytes, double* dJdY_dev,
+                            double* ke_dev) {
+  mclbm_status st = check_adjoint(c, ticks, ckpt_every);
+  if (st != MCLBM_OK) return st;
+  if (c->tick != ticks) return fail(MCLBM_ERR_STATE, "backward must follow forward_ckpt over the same ticks");
+  if (!ckpt_dev || ckpt_bytes < mclbm_ckpt_bytes(c, ticks, ckpt_every))
+    return fail(MCLBM_ERR_OOM, "checkpoint buffer too small");
+  if (!work_dev || work_bytes < mclbm_backward_work_bytes(c, ckpt_every))
+    return fail(MCLBM_ERR_OOM, "backward work buffer too small");
+  if (!dJdY_dev) return fail(MCLBM_ERR_ARG, "dJdY_dev is NULL");
+
+  char* w = static_cast<char*>(work_dev);
+  char* seg_states = w;
+  char* lam[2] = {w + size_t(ckpt_every) * c->state_bytes, w + size_t(ckpt_every + 1) * c->state_bytes};
+  double* partials = reinterpret_cast<double*>(w + size_t(ckpt_every + 2) * c->state_bytes);
+  size_t cells = 0;
+  for (int s = 0; s < c->m; ++s) cells += size_t(c->cells(s));
+  double* records = reinterpret_cast<double*>(reinterpret_cast<char*>(partials) +
+                                              align_up(cells / kAuxBlock * 24 * sizeof(double)));
+
+  if (ke_dev) {
+    const Table* t = nullptr;
+    st = get_table(c, c->tick, true, c->block, false, &t);
+    if (st != MCLBM_OK) return st;
+    StepLaunch L = make_launch(c, t, c->pop, nullptr);
+    HIP_TRY(launch_step(c->precision, kReduceOnly, L, c->stream));
+    HIP_TRY(launch_record_finalize(c->d_partials, L.segs, t->nseg, c->d_samples, records, c->stream));
+    HIP_TRY(launch_extract(records, c->m, 4, ke_dev, c->stream));
+  }
+
+  const Table* aux = nullptr;      // every sample, live parities (seed)
+  st = get_table(c, c->tick, true, kAuxBlock, false, &aux);
+  if (st != MCLBM_OK) return st;
+  HIP_TRY(launch_adjoint_seed(c->precision, c->pop, lam[0], c->d_samples, table_ptr(c, aux), aux->nseg,
+                              aux->total_blocks, 1.0 / c->m, c->stream));
+  const Table* nat = nullptr;      // every sample, natural layout
+  st = get_table(c, 0, true, kAuxBlock, true, &nat);
+  if (st != MCLBM_OK) return st;
+  const Table* push = nullptr;     // push steps use the collide kernel's block
+  st = get_table(c, 0, true, c->block, true, &push);
+  if (st != MCLBM_OK) return st;
+
+  int cur = 0;
+  const int64_t nseg = (ticks + ckpt_every - 1) / ckpt_every;
+  for (int64_t k = nseg - 1; k >= 0; --k) {
+    const int64_t n0 = k * ckpt_every;
+    const int64_t n1 = std::min<int64_t>(ticks, n0 + ckpt_every);
+    const char* ck = static_cast<const char*>(ckpt_dev) + size_t(k) * c->state_bytes;
+    auto state_at = [&](int64_t n) -> const char* {
+      return n == n0 ? ck : seg_states + size_t(n - n0) * c->state_bytes;
+    };
+    for (int64_t n = n0 + 1; n < n1; ++n) {
+      StepLaunch L = make_launch(c, push, const_cast<char*>(state_at(n - 1)), const_cast<char*>(state_at(n)));
+      HIP_TRY(launch_step(c->precision, kPush, L, c->stream));
+    }
+    for (int64_t n = n1 - 1; n >= n0; --n) {
+      HIP_TRY(launch_adjoint_step(c->precision, state_at(n), lam[cur], lam[1 - cur], c->d_samples, table_ptr(c, nat),
+                                  nat->nseg, nat->total_blocks, c->stream));
+      cur = 1 - cur;
+    }
+  }
+  HIP_TRY(launch_init_adjoint(c->precision, lam[cur], c->d_samples, table_ptr(c, nat), nat->nseg, nat->total_blocks,
+                              c->d_ycoef, partials, c->stream));
+  HIP_TRY(launch_init_adjoint_finalize(partials, table_ptr(c, nat), nat->nseg, c->d_samples, c->d_pmat, dJdY_dev,
+                                       c->stream));
+  return MCLBM_OK;
+}
+
+// ------------------------------------------------------------------ launch shape
+mclbm_status mclbm_set_launch(mclbm_ctx* c, int32_t block_threads, int32_t xcd_remap) {
+  mclbm_status st = check_ctx(c, false);
+  if (st != MCLBM_OK) return st;
+  if (block_threads != 128 && block_threads != 256 && block_threads != 512 && block_threads != 1024)
+    return fail(MCLBM_ERR_ARG, "block_threads must be 128, 256, 512 or 1024");
+  if (block_threads == 1024 && c->precision == MCLBM_FP64)
+    return fail(MCLBM_ERR_UNSUPPORTED, "1024-thread blocks are built for the FP32 path only");
+  for (int s = 0; s < c->m; ++s)
+    if (c->cells(s) < block_threads) return fail(MCLBM_ERR_ARG, "block larger than a sample's lattice");
+  if (xcd_remap != 0 && xcd_remap != 1) return fail(MCLBM_ERR_ARG, "xcd_remap must be 0 or 1");
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  c->block = block_threads;
+  c->xcd_remap = xcd_remap;
+  drop_graphs(c);
+  return MCLBM_OK;
+}
+
+mclbm_status mclbm_get_launch(const mclbm_ctx* c, int32_t* block_threads, int32_t* xcd_remap) {
+  if (!c) return fail(MCLBM_ERR_ARG, "context is NULL");
+  if (block_threads) *block_threads = c->block;
+  if (xcd_remap) *xcd_remap = c->xcd_remap;
+  return MCLBM_OK;
+}
+
+mclbm_status mclbm_autotune(mclbm_ctx* c, int32_t reps, void* scratch_dev, size_t scratch_bytes, int32_t* best_block,
+                            int32_t* best_xcd) {
+  mclbm_status st = check_ctx(c, true);
+  if (st != MCLBM_OK) return st;
+  if (reps < 1) return fail(MCLBM_ERR_ARG, "reps must be >= 1");
+  st = mclbm_checkpoint(c, scratch_dev, scratch_bytes);
+  if (st != MCLBM_OK) return st;
+  const bool timing0 = c->timing, graphs0 = c->use_graphs;
+  c->use_graphs = false;
+  c->timing = false;
+  const int blocks[4] = {128, 256, 512, 1024};
+  float best = 1e30f;
+  int bb = c->block, bx = c->xcd_remap;
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  const int64_t per = 2 * int64_t(c->max_stride) * reps;
+  for (int b : blocks) {
+    bool fits = !(b == 1024 && c->precision == MCLBM_FP64);
+    for (int s = 0; s < c->m; ++s) fits = fits && c->cells(s) >= b;
+    if (!fits) continue;
+    for (int x = 0; x < 2; ++x) {
+      c->block = b;
+      c->xcd_remap = x;
+      st = run_plain_ticks(c, 2 * int64_t(c->max_stride));  // warm-up
+      if (st != MCLBM_OK) break;
+      HIP_TRY(hipEventRecord(e0, c->stream));
+      st = run_plain_ticks(c, per);
+      if (st != MCLBM_OK) break;
+      HIP_TRY(hipEventRecord(e1, c->stream));
+      HIP_TRY(hipEventSynchronize(e1));
+      float ms = 0.f;
+      HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+      if (ms < best) {
+        best = ms;
+        bb = b;
+        bx = x;
+      }
+      mclbm_status rs = mclbm_restore(c, scratch_dev, scratch_bytes);
+      if (rs != MCLBM_OK) return rs;
+    }
+    if (st != MCLBM_OK) break;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  c->use_graphs = graphs0;
+  c->timing = timing0;
+  if (st != MCLBM_OK) {
+    (void)mclbm_restore(c, scratch_dev, scratch_bytes);
+    return st;
+  }
+  c->block = bb;
+  c->xcd_remap = bx;
+  drop_graphs(c);
+  if (best_block) *best_block = bb;
+  if (best_xcd) *best_xcd = bx;
+  return mclbm_restore(c, scratch_dev, scratch_bytes);
+}
+
+mclbm_status mclbm_use_graphs(mclbm_ctx* c, int32_t enable) {
+  mclbm_status st = check_ctx(c, false);
+  if (st != MCLBM_OK) return st;
+  c->use_graphs = enable != 0;
+  return MCLBM_OK;
+}
+
+int64_t mclbm_ticks(const mclbm_ctx* c) { return c ? c->tick : -1; }
+int64_t mclbm_steps(const mclbm_ctx* c, int32_t sample) {
+  return (c && sample >= 0 && sample < c->m) ? c->steps[sample] : -1;
+}
+
+mclbm_status mclbm_time_launches(mclbm_ctx* c, int32_t enable) {
+  mclbm_status st = check_ctx(c, false);
+  if (st != MCLBM_OK) return st;
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  c->timing = enable != 0;
+  c->ev_used = 0;
+  return MCLBM_OK;
+}
+
+mclbm_status mclbm_launch_time(mclbm_ctx* c, double* avg_ms, int64_t* launches) {
+  mclbm_status st = check_ctx(c, false);
+  if (st != MCLBM_OK) return st;
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  double total = 0.0;
+  const size_t pairs = c->ev_used / 2;
+  for (size_t k = 0; k < pairs; ++k) {
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, c->ev_pool[2 * k], c->ev_pool[2 * k + 1]));
+    total += ms;
+  }
+  if (avg_ms) *avg_ms = pairs ? total / double(pairs) : 0.0;
+  if (launches) *launches = int64_t(pairs);
+  c->ev_used = 0;
+  return MCLBM_OK;
+}
+
+mclbm_status mclbm_stream_copy(void* dst_dev, const void* src_dev, size_t bytes, void* hip_stream) {
+  if (!dst_dev || !src_dev) return fail(MCLBM_ERR_ARG, "NULL buffer");
+  if (bytes % 16) return fail(MCLBM_ERR_ARG, "bytes must be a multiple of 16");
+  HIP_TRY(launch_stream_copy(dst_dev, src_dev, bytes, static_cast<hipStream_t>(hip_stream)));
+  return MCLBM_OK;
+}
+
+const char* mclbm_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,72 @@
+// Launch interface between the host side of the library and its HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "lattice.h"
+
+namespace mclbm {
+
+// One collide-and-stream launch over the blocks described by `segs`.
+struct StepLaunch {
+  void* pop;                 // population storage (AA in place), or the source in push mode
+  void* dst;                 // push mode: destination storage (natural layout)
+  const DevSample* samples;
+  const Seg* segs;
+  int32_t nseg;
+  int32_t total_blocks;
+  int32_t block;             // threads per block (cells per block)
+  int32_t xcd_remap;
+  int32_t* flags;            // per-sample instability flags
+  double* partials;          // record mode: kRecord doubles per block
+};
+
+enum StepKind { kStep = 0, kStepRecord = 1, kReduceOnly = 2, kPush = 3 };
+
+hipError_t launch_step(int precision, StepKind kind, const StepLaunch& L, hipStream_t s);
+
+// Records from block partials: one block per segment, writes out[sample*kRecord + k].
+hipError_t launch_record_finalize(const double* partials, const Seg* segs, int32_t nseg, const DevSample* samples,
+                                  double* out, hipStream_t s);
+
+// Initial equilibrium populations of every sample in `segs` (blocks of 256 cells).
+hipError_t launch_init(int precision, void* pop, const DevSample* samples, const Seg* segs, int32_t nseg,
+                       int32_t total_blocks, const double* ycoef, hipStream_t s);
+
+// Density and velocity (double) of one sample; parity selects the AA layout.
+hipError_t launch_moments(int precision, const void* pop, const DevSample* samples, int32_t sample, int32_t n,
+                          int32_t parity, double* rho, double* u, hipStream_t s);
+
+// Unshifted populations f[27][n^3] in double, out of or into the state.
+hipError_t launch_get_state(int precision, const void* pop, const DevSample* samples, int32_t sample, int32_t n,
+                            int32_t parity, double* f, hipStream_t s);
+hipError_t launch_set_state(int precision, void* pop, const DevSample* samples, int32_t sample, int32_t n,
+                            int32_t parity, const double* f, hipStream_t s);
+hipError_t launch_poison(int precision, void* pop, const DevSample* samples, int32_t sample, int32_t parity,
+                         int64_t cell, int32_t i, hipStream_t s);
+
+// Copy the state of every sample in `segs` into natural layout at dst (same offsets).
+hipError_t launch_canonical_copy(int precision, const void* pop, void* dst, const DevSample* samples, const Seg* segs,
+                                 int32_t nseg, int32_t total_blocks, hipStream_t s);
+
+// Adjoint: seed lambda_T from the state (parity-aware), one reverse step, and the
+// initial-data adjoint with its per-sample projection onto the 24 parameters.
+hipError_t launch_adjoint_seed(int precision, const void* pop, void* lam, const DevSample* samples, const Seg* segs,
+                               int32_t nseg, int32_t total_blocks, double inv_m, hipStream_t s);
+hipError_t launch_adjoint_step(int precision, const void* state, const void* lam_in, void* lam_out,
+                               const DevSample* samples, const Seg* segs, int32_t nseg, int32_t total_blocks,
+                               hipStream_t s);
+hipError_t launch_init_adjoint(int precision, const void* lam, const DevSample* samples, const Seg* segs,
+                               int32_t nseg, int32_t total_blocks, const double* ycoef, double* partials,
+                               hipStream_t s);
+hipError_t launch_init_adjoint_finalize(const double* partials, const Seg* segs, int32_t nseg,
+                                        const DevSample* samples, const double* pmat, double* dJdY,
+                                        hipStream_t s);
+hipError_t launch_extract(const double* records, int32_t m, int32_t field, double* out, hipStream_t s);
+
+hipError_t launch_stream_copy(void* dst, const void* src, size_t bytes, hipStream_t s);
+
+}  // namespace mclbm

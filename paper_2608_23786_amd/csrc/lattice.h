@@ -1,0 +1,52 @@
+// D3Q27 lattice constants and the per-sample / per-launch tables shared by
+// the kernels and the host side of the library.
+//
+// Velocity set: c_i in {-1,0,1}^3 with i = 9*(cx+1) + 3*(cy+1) + (cz+1); the
+// opposite velocity is 26 - i. Weights are the tensor product of the 1-D
+// weights (1/6, 2/3, 1/6), i.e. 8/27 (rest), 2/27 (6 faces), 1/54 (12 edges),
+// 1/216 (8 corners); c_s^2 = 1/3 (the usual D3Q27 set used with the
+// equilibrium of eq. (equilibrium)).
+#pragma once
+
+#include <cstdint>
+
+namespace mclbm {
+
+constexpr int Q = 27;
+constexpr int kMaxSamples = 256;
+
+__host__ __device__ constexpr int cx(int i) { return i / 9 - 1; }
+__host__ __device__ constexpr int cy(int i) { return (i / 3) % 3 - 1; }
+__host__ __device__ constexpr int cz(int i) { return i % 3 - 1; }
+__host__ __device__ constexpr int opposite(int i) { return 26 - i; }
+__host__ __device__ constexpr int nonzeros(int i) { return (cx(i) != 0) + (cy(i) != 0) + (cz(i) != 0); }
+__host__ __device__ constexpr double weight(int i) {
+  return nonzeros(i) == 0 ? 8.0 / 27.0 : nonzeros(i) == 1 ? 2.0 / 27.0 : nonzeros(i) == 2 ? 1.0 / 54.0 : 1.0 / 216.0;
+}
+
+// Per-sample table in device memory.
+struct DevSample {
+  uint64_t offset;        // element offset of population plane 0 of this sample
+  int32_t n;              // points per axis
+  int32_t log2n;
+  double omega;           // shear relaxation frequency
+  double two_over_omega;  // 2 / omega
+  double kappa;           // 2 - 2 / omega
+  float omega_f, two_over_omega_f, kappa_f;
+  int32_t project;        // 1: the perturbation coefficients were Leray-projected
+  double u0;              // Taylor-Green amplitude
+  double amp;             // perturbation amplitude relative to u0
+};
+
+// One run of consecutive blocks of a launch that belong to one sample.
+struct Seg {
+  int32_t sample;
+  int32_t first_block;
+  int32_t nblocks;
+  int32_t parity;         // steps taken so far, modulo 2 (AA layout of the state)
+};
+
+// Reduction record layout (doubles per sample).
+constexpr int kRecord = 8;  // mass, jx, jy, jz, ke, gamma_min, gamma_max, gamma_mean
+
+}  // namespace mclbm

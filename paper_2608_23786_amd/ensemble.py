@@ -1,0 +1,279 @@
+"""Python face of the MI355X Monte Carlo KBC lattice Boltzmann library.
+
+PyTorch supplies device memory (uint8 tensors the library borrows) and the
+HIP stream; every step of the method runs in the library's kernels.
+"""
+import ctypes
+from dataclasses import dataclass
+from typing import List, Optional, Sequence
+
+import torch
+
+from . import _lib
+from ._lib import MclbmError, SampleDesc, check, lib
+
+PRECISIONS = {"f64": _lib.FP64, "f32s": _lib.FP32_SHIFTED}
+RECORD_FIELDS = ("mass", "jx", "jy", "jz", "ke", "gamma_min", "gamma_max", "gamma_mean")
+
+
+@dataclass
+class Sample:
+    n: int
+    u0: float
+    re: float
+    amp: float = 0.0
+    project: bool = False
+    stride: int = 1
+
+    def desc(self) -> SampleDesc:
+        return SampleDesc(self.n, self.u0, self.re, self.amp, int(self.project), self.stride)
+
+
+def omega(n: int, u0: float, re: float) -> float:
+    """Shear relaxation frequency the library uses for a sample."""
+    return lib().mclbm_omega(n, u0, re)
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _require_cuda(t: torch.Tensor, dtype=None, numel=None, name="tensor"):
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise ValueError(f"{name} must have dtype {dtype}")
+    if numel is not None and t.numel() < numel:
+        raise ValueError(f"{name} needs at least {numel} elements")
+
+
+class Ensemble:
+    """An ensemble of RTGV samples evolved in one in-place population buffer."""
+
+    def __init__(self, samples: Sequence[Sample], precision: str = "f32s", device="cuda:0",
+                 stream: Optional[torch.cuda.Stream] = None):
+        if precision not in PRECISIONS:
+            raise ValueError(f"precision must be one of {list(PRECISIONS)}")
+        self.samples: List[Sample] = list(samples)
+        self.m = len(self.samples)
+        self.precision = precision
+        self.device = torch.device(device)
+        L = lib()
+        self._desc = (SampleDesc * self.m)(*[s.desc() for s in self.samples])
+        nbytes = L.mclbm_workspace_bytes(self.m, self._desc, PRECISIONS[precision])
+        if nbytes == 0:
+            # the library reports the reason of invalid descriptors on create
+            nbytes = 256
+        self.stream = stream if stream is not None else torch.cuda.Stream(device=self.device)
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        base = self.workspace.data_ptr()
+        self._ws_ptr = (base + 255) // 256 * 256
+        self._ctx = ctypes.c_void_p()
+        check(L.mclbm_create(ctypes.byref(self._ctx), self.m, self._desc, PRECISIONS[precision],
+                             ctypes.c_void_p(self._ws_ptr), nbytes, ctypes.c_void_p(self.stream.cuda_stream)))
+
+    def __del__(self):
+        ctx = getattr(self, "_ctx", None)
+        if ctx is not None and ctx.value:
+            try:
+                lib().mclbm_destroy(ctx)
+            except Exception:
+                pass
+            self._ctx = None
+
+    # ------------------------------------------------------------ helpers
+    def _dev_empty(self, shape, dtype=torch.float64):
+        with torch.cuda.stream(self.stream):
+            return torch.empty(shape, dtype=dtype, device=self.device)
+
+    def synchronize(self):
+        self.stream.synchronize()
+
+    def _consume(self):
+        """The library's stream waits for work the caller queued on its current stream."""
+        self.stream.wait_stream(torch.cuda.current_stream(self.device))
+
+    def _produce(self):
+        """The caller's current stream waits for the library's outputs."""
+        torch.cuda.current_stream(self.device).wait_stream(self.stream)
+
+    # ------------------------------------------------------------ lifecycle
+    def init(self, seed: int = 0, y: Optional[torch.Tensor] = None):
+        if y is not None:
+            yh = torch.as_tensor(y, dtype=torch.float64).contiguous().cpu()
+            if yh.numel() != self.m * 24:
+                raise ValueError("y must have m x 24 values")
+            check(lib().mclbm_init(self._ctx, seed, ctypes.cast(yh.data_ptr(), _lib._dp)))
+        else:
+            check(lib().mclbm_init(self._ctx, seed, None))
+
+    def y(self) -> torch.Tensor:
+        out = torch.empty((self.m, 24), dtype=torch.float64)
+        check(lib().mclbm_get_y(self._ctx, ctypes.cast(out.data_ptr(), _lib._dp)))
+        return out
+
+    def set_viscosity(self, eps: Sequence[float]):
+        arr = (ctypes.c_double * self.m)(*eps)
+        check(lib().mclbm_set_viscosity(self._ctx, arr))
+
+    def step(self, ticks: int, record_every: int = 0) -> Optional[torch.Tensor]:
+        if record_every > 0:
+            nrec = (ticks + record_every - 1) // record_every
+            rec = self._dev_empty((max(nrec, 1), self.m, 8))
+            check(lib().mclbm_step(self._ctx, ticks, record_every, _ptr(rec), nrec))
+            self._produce()
+            return rec[:nrec]
+        check(lib().mclbm_step(self._ctx, ticks, 0, None, 0))
+        return None
+
+    @property
+    def ticks(self) -> int:
+        return int(lib().mclbm_ticks(self._ctx))
+
+    def steps(self, sample: int) -> int:
+        return int(lib().mclbm_steps(self._ctx, sample))
+
+    # ------------------------------------------------------------ read-out
+    def _check_sample(self, sample: int):
+        if not 0 <= sample < self.m:
+            # let the library report the error
+            check(lib().mclbm_moments(self._ctx, sample, None, None))
+
+    def moments(self, sample: int):
+        self._check_sample(sample)
+        n = self.samples[sample].n
+        rho = self._dev_empty((n, n, n))
+        u = self._dev_empty((3, n, n, n))
+        check(lib().mclbm_moments(self._ctx, sample, _ptr(rho), _ptr(u)))
+        self._produce()
+        return rho, u
+
+    def reduce(self) -> torch.Tensor:
+        red = self._dev_empty((self.m, 8))
+        check(lib().mclbm_reduce(self._ctx, _ptr(red)))
+        self._produce()
+        return red
+
+    def check(self) -> int:
+        bad = ctypes.c_int32(-1)
+        st = lib().mclbm_check(self._ctx, ctypes.byref(bad))
+        if st not in (_lib.OK, _lib.ERR_UNSTABLE):
+            check(st)
+        return bad.value
+
+    def get_state(self, sample: int) -> torch.Tensor:
+        self._check_sample(sample)
+        n = self.samples[sample].n
+        f = self._dev_empty((27, n, n, n))
+        check(lib().mclbm_get_state(self._ctx, sample, _ptr(f)))
+        self._produce()
+        return f
+
+    def set_state(self, sample: int, f: torch.Tensor):
+        self._check_sample(sample)
+        n = self.samples[sample].n
+        _require_cuda(f, torch.float64, 27 * n ** 3, "f")
+        self._consume()
+        check(lib().mclbm_set_state(self._ctx, sample, _ptr(f)))
+        f.record_stream(self.stream)
+
+    def poison(self, sample: int, cell: int, i: int):
+        check(lib().mclbm_poison(self._ctx, sample, cell, i))
+
+    # ------------------------------------------------------------ checkpoints
+    def checkpoint_bytes(self) -> int:
+        return int(lib().mclbm_checkpoint_bytes(self._ctx))
+
+    def checkpoint(self, buf: Optional[torch.Tensor] = None) -> torch.Tensor:
+        nb = self.checkpoint_bytes()
+        if buf is None:
+            buf = self._dev_empty((nb,), torch.uint8)
+        self._consume()
+        check(lib().mclbm_checkpoint(self._ctx, _ptr(buf), buf.numel()))
+        self._produce()
+        return buf
+
+    def restore(self, buf: torch.Tensor):
+        self._consume()
+        check(lib().mclbm_restore(self._ctx, _ptr(buf), buf.numel()))
+
+    # ------------------------------------------------------------ launch shape
+    def set_launch(self, block: int, xcd_remap: int = 0):
+        check(lib().mclbm_set_launch(self._ctx, block, xcd_remap))
+
+    def get_launch(self):
+        b, x = ctypes.c_int32(), ctypes.c_int32()
+        check(lib().mclbm_get_launch(self._ctx, ctypes.byref(b), ctypes.byref(x)))
+        return b.value, x.value
+
+    def autotune(self, reps: int = 2):
+        scratch = self._dev_empty((self.checkpoint_bytes(),), torch.uint8)
+        b, x = ctypes.c_int32(), ctypes.c_int32()
+        check(lib().mclbm_autotune(self._ctx, reps, _ptr(scratch), scratch.numel(), ctypes.byref(b),
+                                   ctypes.byref(x)))
+        return b.value, x.value
+
+    def use_graphs(self, enable: bool):
+        check(lib().mclbm_use_graphs(self._ctx, int(enable)))
+
+    def time_launches(self, enable: bool):
+        check(lib().mclbm_time_launches(self._ctx, int(enable)))
+
+    def launch_time(self):
+        avg = ctypes.c_double()
+        cnt = ctypes.c_int64()
+        check(lib().mclbm_launch_time(self._ctx, ctypes.byref(avg), ctypes.byref(cnt)))
+        return avg.value, cnt.value
+
+    # ------------------------------------------------------------ adjoint
+    def forward_ckpt(self, ticks: int, ckpt_every: int) -> torch.Tensor:
+        nb = int(lib().mclbm_ckpt_bytes(self._ctx, ticks, ckpt_every))
+        if nb == 0:
+            raise MclbmError(_lib.ERR_ARG, "invalid ticks / ckpt_every")
+        ck = self._dev_empty((nb,), torch.uint8)
+        check(lib().mclbm_forward_ckpt(self._ctx, ticks, ckpt_every, _ptr(ck), nb))
+        return ck
+
+    def backward(self, ticks: int, ckpt_every: int, ckpt: torch.Tensor):
+        wb = int(lib().mclbm_backward_work_bytes(self._ctx, ckpt_every))
+        work = self._dev_empty((wb,), torch.uint8)
+        dj = self._dev_empty((self.m, 24))
+        ke = self._dev_empty((self.m,))
+        check(lib().mclbm_backward(self._ctx, ticks, ckpt_every, _ptr(ckpt), ckpt.numel(), _ptr(work), wb,
+                                   _ptr(dj), _ptr(ke)))
+        self._produce()
+        return dj, ke
+
+
+def stream_copy(dst: torch.Tensor, src: torch.Tensor, stream: Optional[torch.cuda.Stream] = None):
+    nbytes = min(dst.numel() * dst.element_size(), src.numel() * src.element_size()) // 16 * 16
+    s = stream if stream is not None else torch.cuda.current_stream()
+    check(lib().mclbm_stream_copy(_ptr(dst), _ptr(src), nbytes, ctypes.c_void_p(s.cuda_stream)))
+
+
+class EnsembleKE(torch.autograd.Function):
+    """J(Y) = (1/M) sum_m KE_m(T) for an ensemble started from Y.
+
+    forward(Y, ensemble, ticks, ckpt_every) -> J (0-d float64 tensor);
+    backward gives dJ/dY from the library's discrete adjoint."""
+
+    @staticmethod
+    def forward(ctx, y, ensemble: Ensemble, ticks: int, ckpt_every: int):
+        ensemble.init(0, y.detach().cpu())
+        ck = ensemble.forward_ckpt(ticks, ckpt_every)
+        ctx.ensemble = ensemble
+        ctx.ticks = ticks
+        ctx.ckpt_every = ckpt_every
+        ctx.ckpt = ck
+        red = ensemble.reduce()
+        ensemble.synchronize()
+        return red[:, 4].mean().to(y.device)
+
+    @staticmethod
+    def backward(ctx, gJ):
+        dj, _ = ctx.ensemble.backward(ctx.ticks, ctx.ckpt_every, ctx.ckpt)
+        ctx.ensemble.synchronize()
+        ctx.ckpt = None
+        return gJ.to(dj.device) * dj, None, None, None

@@ -1,0 +1,100 @@
+"""Host-side checks of the C-ABI library (no GPU needed): it loads, exports
+every entry point its header declares, and its host logic (argument
+validation, parameter map, workspace sizing) behaves as documented."""
+import ctypes
+import json
+import math
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mclbm.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"\b(mclbm_[a-z0-9_]+)\s*\(", text)
+    return sorted(set(names))
+
+
+def test_library_loads_and_exports_every_declared_symbol():
+    import paper_2608_23786_amd as mc
+    L = mc.lib()
+    names = declared_functions()
+    assert len(names) >= 30
+    for name in names:
+        assert hasattr(L, name), name
+    from paper_2608_23786_amd import _lib
+    assert set(names) == set(_lib.SIGNATURES), set(names) ^ set(_lib.SIGNATURES)
+
+
+def test_omega_reproduces_paper_tables_with_unit_spacing_convention():
+    """The library's parameter map uses dx = 2 pi / N: it reproduces the rows of
+    Table 3 that use this convention (N >= 32) to every printed digit of tau."""
+    import paper_2608_23786_amd as mc
+    tab = json.load(open(os.path.join(ROOT, "tests", "golden", "paper_parameter_tables.json")))
+    rows = [r for r in tab["rows"] if r["dx"] == "2pi/N"]
+    assert len(rows) == 5
+    for r in rows:
+        u0 = r["Ma"] / math.sqrt(3.0)
+        tau = 1.0 / mc.omega(r["N"], u0, r["Re"])
+        assert round(tau, 6) == r["tau"], r
+
+
+def test_omega_of_documented_configs():
+    import paper_2608_23786_amd as mc
+    # 32^3, U0 = 0.05, Re = 100: nu = 0.05 * 32 / (2 pi 100)
+    nu = 0.05 * 32 / (2 * math.pi * 100)
+    assert abs(mc.omega(32, 0.05, 100.0) - 1 / (3 * nu + 0.5)) < 1e-15
+    assert abs(1 / mc.omega(64, 0.025, 1600.0) - 0.5004775) < 1e-7
+    assert mc.omega(0, 0.05, 100.0) == 0.0
+
+
+def test_workspace_sizing_and_validation():
+    import paper_2608_23786_amd as mc
+    from paper_2608_23786_amd import _lib
+    L = mc.lib()
+    good = (mc.SampleDesc * 2)(mc.Sample(32, 0.05, 100.0).desc(), mc.Sample(64, 0.025, 1600.0, 0.05, True, 2).desc())
+    nb32 = L.mclbm_workspace_bytes(2, good, _lib.FP32_SHIFTED)
+    nb64 = L.mclbm_workspace_bytes(2, good, _lib.FP64)
+    assert nb32 >= 27 * (32 ** 3 + 64 ** 3) * 4
+    assert nb64 >= 27 * (32 ** 3 + 64 ** 3) * 8
+    assert nb64 > nb32
+    for bad in (mc.Sample(48, 0.05, 100.0), mc.Sample(4, 0.05, 100.0), mc.Sample(32, 0.0, 100.0),
+                mc.Sample(32, 0.05, -1.0), mc.Sample(32, 0.05, 100.0, stride=3),
+                mc.Sample(32, 0.05, 100.0, amp=float("nan"))):
+        arr = (mc.SampleDesc * 1)(bad.desc())
+        assert L.mclbm_workspace_bytes(1, arr, _lib.FP32_SHIFTED) == 0
+    arr = (mc.SampleDesc * 1)(mc.Sample(1024, 0.05, 100.0).desc())
+    assert L.mclbm_workspace_bytes(1, arr, _lib.FP64) == 0          # FP64 limited to n <= 512
+    assert L.mclbm_workspace_bytes(1, arr, _lib.FP32_SHIFTED) > 0
+    assert L.mclbm_workspace_bytes(0, arr, _lib.FP32_SHIFTED) == 0
+    assert L.mclbm_workspace_bytes(1, arr, 7) == 0
+
+
+def test_create_rejects_bad_arguments_before_touching_the_device():
+    import paper_2608_23786_amd as mc
+    from paper_2608_23786_amd import _lib
+    L = mc.lib()
+    arr = (mc.SampleDesc * 1)(mc.Sample(16, 0.05, 100.0).desc())
+    ctx = ctypes.c_void_p()
+    assert L.mclbm_create(ctypes.byref(ctx), 1, arr, _lib.FP64, None, 1 << 20, None) == _lib.ERR_ARG
+    assert "workspace" in L.mclbm_last_error().decode()
+    assert L.mclbm_create(ctypes.byref(ctx), 1, arr, _lib.FP64, ctypes.c_void_p(256), 16, None) == _lib.ERR_OOM
+    assert L.mclbm_create(ctypes.byref(ctx), 1, arr, _lib.FP64, ctypes.c_void_p(100), 1 << 30, None) == _lib.ERR_ARG
+    assert L.mclbm_create(None, 1, arr, _lib.FP64, ctypes.c_void_p(256), 1 << 30, None) == _lib.ERR_ARG
+    assert L.mclbm_stream_copy(None, None, 16, None) == _lib.ERR_ARG
+    assert L.mclbm_ticks(None) == -1
+
+
+def test_inputs_generator_is_splitmix64():
+    """Published SplitMix64 output for seed 0 (first draws of the reference
+    implementation by Vigna: 0xe220a8397b1dcdaf, 0x6e789e6aa1b965f4)."""
+    import mc_inputs
+    out = mc_inputs.splitmix64_stream(0, 2)
+    assert out == [0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4]
+    y = mc_inputs.draw_y(2608, 3)
+    assert y.shape == (3, 24) and y.min() >= -1 and y.max() < 1
