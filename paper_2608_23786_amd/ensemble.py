@@ -264,6 +264,7 @@ class EnsembleKE(torch.autograd.Function):
         ensemble.init(0, y.detach().cpu())
         ck = ensemble.forward_ckpt(ticks, ckpt_every)
         ctx.ensemble = ensemble
+        ctx.y_device = y.device
         ctx.ticks = ticks
         ctx.ckpt_every = ckpt_every
         ctx.ckpt = ck
@@ -276,4 +277,4 @@ class EnsembleKE(torch.autograd.Function):
         dj, _ = ctx.ensemble.backward(ctx.ticks, ctx.ckpt_every, ctx.ckpt)
         ctx.ensemble.synchronize()
         ctx.ckpt = None
-        return gJ.to(dj.device) * dj, None, None, None
+        return (gJ.to(dj.device) * dj).to(ctx.y_device), None, None, None

@@ -1,0 +1,157 @@
+"""Gradient of the ensemble-mean kinetic energy with respect to the 24 random
+parameters per sample: the library's discrete adjoint against the oracle's
+complex-step derivative, central finite differences of the GPU FP64 forward,
+and structural properties.
+
+Tolerances: FP64 adjoint vs complex step 1e-8 of max|dJ/dY| (both are exact
+to rounding; the closed-form stabiliser is a ratio of small inner products,
+which amplifies rounding). FP32 adjoint: stated per test, from the float
+rounding of the forward states and of the reverse sweep.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import mc_inputs
+import oracle
+
+pytestmark = pytest.mark.gpu
+mc = pytest.importorskip("paper_2608_23786_amd")
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def gpu_gradient(samples, precision, y, steps, every):
+    ens = mc.Ensemble(samples, precision)
+    ens.init(0, torch.from_numpy(y))
+    ck = ens.forward_ckpt(steps, every)
+    dj, ke = ens.backward(steps, every, ck)
+    return dj.cpu().numpy(), ke.cpu().numpy(), ens
+
+
+def oracle_gradient(samples, y, steps):
+    m = len(samples)
+    g = np.zeros((m, 24))
+    ke = np.zeros(m)
+    for s, smp in enumerate(samples):
+        g[s] = oracle.ke_gradient_complex_step(smp.n, smp.u0, smp.re, smp.amp, y[s], smp.project, steps) / m
+        ke[s] = oracle.ke_after(smp.n, smp.u0, smp.re, smp.amp, y[s], smp.project, steps)
+    return g, ke
+
+
+@pytest.mark.parametrize("steps,every", [(20, 6), (20, 20), (7, 1)])
+def test_fp64_adjoint_matches_complex_step(steps, every):
+    samples = [mc.Sample(8, 0.05, 100.0, 0.5, True), mc.Sample(8, 0.04, 60.0, 0.5, False)]
+    y = mc_inputs.draw_y(21, 2)
+    dj, ke, _ = gpu_gradient(samples, "f64", y, steps, every)
+    g, ke_o = oracle_gradient(samples, y, steps)
+    err = np.max(np.abs(dj - g)) / np.max(np.abs(g))
+    print(f"steps {steps} every {every}: max |adjoint - complex step| / max = {err:.3e}")
+    assert err < 1e-8
+    assert np.max(np.abs(ke - ke_o) / ke_o) < 1e-12
+
+
+def test_fp64_adjoint_16cubed():
+    samples = [mc.Sample(16, 0.05, 200.0, 0.2, True)] * 2
+    y = mc_inputs.draw_y(22, 2)
+    dj, _, _ = gpu_gradient(samples, "f64", y, 40, 16)
+    g, _ = oracle_gradient(samples, y, 40)
+    assert np.max(np.abs(dj - g)) / np.max(np.abs(g)) < 1e-8
+
+
+def test_fp32_adjoint_close_to_fp64_reference():
+    samples = [mc.Sample(16, 0.05, 200.0, 0.2, True)] * 2
+    y = mc_inputs.draw_y(22, 2)
+    dj32, _, _ = gpu_gradient(samples, "f32s", y, 40, 10)
+    g, _ = oracle_gradient(samples, y, 40)
+    err = np.max(np.abs(dj32 - g)) / np.max(np.abs(g))
+    print(f"fp32 adjoint: max rel err vs complex step = {err:.3e}")
+    assert err < 1e-4
+
+
+def test_central_differences_of_gpu_forward():
+    """Central differences (h = 1e-3 on Y) of the GPU FP64 forward."""
+    samples = [mc.Sample(16, 0.05, 200.0, 0.3, True), mc.Sample(16, 0.05, 200.0, 0.3, False)]
+    steps, h = 30, 1e-3
+    y = mc_inputs.draw_y(23, 2)
+    dj, _, _ = gpu_gradient(samples, "f64", y, steps, 10)
+
+    def J(yy):
+        ens = mc.Ensemble(samples, "f64")
+        ens.init(0, torch.from_numpy(yy))
+        ens.step(steps)
+        return float(ens.reduce()[:, 4].mean())
+
+    for s, p in ((0, 0), (0, 11), (1, 5), (1, 23)):
+        yp, ym = y.copy(), y.copy()
+        yp[s, p] += h
+        ym[s, p] -= h
+        fd = (J(yp) - J(ym)) / (2 * h)
+        assert abs(fd - dj[s, p]) <= 1e-6 * np.max(np.abs(dj)), (s, p, fd, dj[s, p])
+
+
+def test_projected_gradient_lies_in_the_range_of_the_projection():
+    """With the Leray projection on, J depends on Y only through P Y, so dJ/dY
+    is annihilated by I - P (P symmetric idempotent on the coefficients)."""
+    n = 8
+    basis = np.stack([oracle.perturbation(n, np.eye(24)[p]).ravel() for p in range(24)], axis=1)
+    proj = np.stack([oracle.leray_project(oracle.perturbation(n, np.eye(24)[p])).ravel() for p in range(24)], axis=1)
+    P = np.linalg.lstsq(basis, proj, rcond=None)[0]
+    assert np.max(np.abs(P @ P - P)) < 1e-12 and np.max(np.abs(P - P.T)) < 1e-12
+    samples = [mc.Sample(n, 0.05, 100.0, 0.5, True)]
+    y = mc_inputs.draw_y(24, 1)
+    dj, _, _ = gpu_gradient(samples, "f64", y, 10, 5)
+    assert np.max(np.abs((np.eye(24) - P) @ dj[0])) < 1e-10 * np.max(np.abs(dj))
+
+
+def test_autograd_function():
+    samples = [mc.Sample(8, 0.05, 100.0, 0.5, True)] * 3
+    ens = mc.Ensemble(samples, "f64")
+    y = torch.from_numpy(mc_inputs.draw_y(25, 3)).requires_grad_(True)
+    J = mc.EnsembleKE.apply(y, ens, 12, 5)
+    J.backward()
+    g, ke = oracle_gradient(samples, y.detach().numpy(), 12)
+    assert abs(float(J) - ke.mean()) / ke.mean() < 1e-12
+    assert np.max(np.abs(y.grad.numpy() - g)) / np.max(np.abs(g)) < 1e-8
+
+
+def test_backward_leaves_the_final_forward_state():
+    samples = [mc.Sample(8, 0.05, 100.0, 0.5, True)]
+    y = mc_inputs.draw_y(26, 1)
+    _, ke, ens = gpu_gradient(samples, "f64", y, 9, 4)
+    assert ens.ticks == 9
+    assert abs(float(ens.reduce()[0, 4]) - ke[0]) < 1e-15
+
+
+def test_adjoint_argument_errors():
+    ens = mc.Ensemble([mc.Sample(8, 0.05, 100.0, 0.5, True, 2)], "f64")
+    ens.init(0)
+    with pytest.raises(mc.MclbmError, match="ERR_UNSUPPORTED"):
+        ens.forward_ckpt(4, 2)
+    ens2 = mc.Ensemble([mc.Sample(8, 0.05, 100.0, 0.5, True)], "f64")
+    ens2.init(0)
+    ens2.step(1)
+    with pytest.raises(mc.MclbmError, match="ERR_STATE"):
+        ens2.forward_ckpt(4, 2)
+
+
+@pytest.mark.parametrize("precision,tol", [("f64", 1e-8), ("f32s", 2e-2)])
+def test_gradient_reference_32cubed_1000_steps(precision, tol):
+    """2 RTGV samples at 32^3 over 1000 steps (the small reference case of the
+    adjoint workload): GPU adjoint against the stored complex-step gradient."""
+    path = os.path.join(GOLDEN, "gradient_rtgv32_T1000.json")
+    if not os.path.exists(path):
+        pytest.skip("reference gradient not generated")
+    ref = json.load(open(path))
+    y = np.array(ref["y"])
+    samples = [mc.Sample(ref["n"], ref["u0"], ref["re"], ref["amp"], ref["project"])] * ref["m"]
+    assert np.array_equal(y, mc_inputs.draw_y(ref["seed"], ref["m"]))
+    dj, ke, _ = gpu_gradient(samples, precision, y, ref["steps"], 50)
+    g = np.array(ref["dJdY"])
+    err = np.max(np.abs(dj - g)) / np.max(np.abs(g))
+    print(f"{precision}: max |adjoint - reference| / max|reference| = {err:.3e}")
+    assert err < tol
+    assert np.max(np.abs(ke - np.array(ref["ke"])) / np.array(ref["ke"])) < (1e-12 if precision == "f64" else 1e-5)
