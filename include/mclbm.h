@@ -186,6 +186,41 @@ mclbm_status mclbm_backward(mclbm_ctx* ctx, int64_t ticks, int32_t ckpt_every, c
                             size_t ckpt_bytes, void* work_dev, size_t work_bytes, double* dJdY_dev,
                             double* ke_dev);
 
+/* Observables of one sample's current velocity field, in double:
+ *   s2_dev[n/2]: second-order structure function S2(r), r = 1..n/2, by the
+ *     discrete Wiener-Khinchin route of Lemma (structureFunctionSpectral) /
+ *     Algorithm 1: R_h = N^-3 F^-1(sum_a |F u_a|^2)_h (F unnormalised, F^-1
+ *     with 1/N^3), S2(r) = 1/|C_r| sum_{h in C_r} 2 (R_0 - R_h), C_r = lags
+ *     (minimum image, components in {-n/2+1..n/2}) whose length rounds to r;
+ *   ek_dev[n/2+1]: energy spectrum E(kappa), kappa = 0..n/2, eq.
+ *     (energySpecDisc) with the coefficients of eq. (dftCoeff); modes whose
+ *     length rounds above n/2 are not counted.
+ * Either output may be NULL. work_dev: device scratch of
+ * mclbm_observables_work_bytes(ctx, sample) bytes, owned by the caller.
+ * Supported n: 8..512. Lattice units (divide by u0^2 for physical units). */
+size_t mclbm_observables_work_bytes(const mclbm_ctx* ctx, int32_t sample);
+mclbm_status mclbm_observables(mclbm_ctx* ctx, int32_t sample, double* s2_dev, double* ek_dev, void* work_dev,
+                               size_t work_bytes);
+
+/* Velocity of every sample at the q^3 nodes common to all resolutions
+ * (node j = (jx, jy, jz) at lattice index (n/q) j, i.e. x = 2 pi j / q):
+ * out_dev[m][3][q^3], double, component-major per sample (appendix on the
+ * Wasserstein distances: exact restriction to the common downsampled grid).
+ * q must divide every sample's n. */
+mclbm_status mclbm_point_values(mclbm_ctx* ctx, int32_t q, double* out_dev);
+
+/* 1-point Wasserstein distance W_{1,1} between two ensembles (Algorithm 2 with
+ * eq. (wassersteinPermutations)): for each node and component, W1 of the two
+ * empirical laws of m equal-weight values (sorted rearrangement), summed over
+ * the q^3 nodes and divided by q^3. a_dev, b_dev: point values
+ * [m][3][q^3] (as written by mclbm_point_values); out_dev[3] receives the
+ * per-component terms D_c / q^3 (their sum is W_{1,1}). m <= 4096, q <= 64.
+ * work_dev: mclbm_w1_work_bytes(q) bytes of device scratch. Runs on
+ * hip_stream. */
+size_t mclbm_w1_work_bytes(int32_t q);
+mclbm_status mclbm_w1_1pt(const double* a_dev, const double* b_dev, int32_t m, int32_t q, double* out_dev,
+                          void* work_dev, size_t work_bytes, void* hip_stream);
+
 /* Launch shape of the collide-and-stream kernel, one for the whole ensemble
  * launch: threads (= lattice nodes) per block, 128, 256, 512 or 1024 (1024:
  * FP32 only), not above any sample's n^3; xcd_remap = 1 renumbers blocks so

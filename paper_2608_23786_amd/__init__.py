@@ -4,4 +4,4 @@ The compute path is the HIP library ``libmclbm.so`` behind the C ABI in
 ``include/mclbm.h``; this package only marshals arguments to it.
 """
 from ._lib import MclbmError, SampleDesc, lib  # noqa: F401
-from .ensemble import RECORD_FIELDS, Ensemble, EnsembleKE, Sample, omega, stream_copy  # noqa: F401
+from .ensemble import RECORD_FIELDS, Ensemble, EnsembleKE, Sample, omega, stream_copy, w1_1pt  # noqa: F401

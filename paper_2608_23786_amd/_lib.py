@@ -61,6 +61,11 @@ SIGNATURES = {
     "mclbm_backward_work_bytes": (_sz, [_ctxp, _i32]),
     "mclbm_forward_ckpt": (_i32, [_ctxp, _i64, _i32, _vp, _sz]),
     "mclbm_backward": (_i32, [_ctxp, _i64, _i32, _vp, _sz, _vp, _sz, _vp, _vp]),
+    "mclbm_observables_work_bytes": (_sz, [_ctxp, _i32]),
+    "mclbm_observables": (_i32, [_ctxp, _i32, _vp, _vp, _vp, _sz]),
+    "mclbm_point_values": (_i32, [_ctxp, _i32, _vp]),
+    "mclbm_w1_work_bytes": (_sz, [_i32]),
+    "mclbm_w1_1pt": (_i32, [_vp, _vp, _i32, _i32, _vp, _vp, _sz, _vp]),
     "mclbm_set_launch": (_i32, [_ctxp, _i32, _i32]),
     "mclbm_get_launch": (_i32, [_ctxp, _ip, _ip]),
     "mclbm_autotune": (_i32, [_ctxp, _i32, _vp, _sz, _ip, _ip]),

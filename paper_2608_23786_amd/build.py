@@ -8,7 +8,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmclbm.so")
 
-SOURCES = ["kernels.hip", "api.hip"]
+SOURCES = ["kernels.hip", "observables.hip", "api.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

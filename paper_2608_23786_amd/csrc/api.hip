@@ -808,6 +808,62 @@ mclbm_status mclbm_backward(mclbm_ctx* c, int64_t ticks, int32_t ckpt_every, con
   return MCLBM_OK;
 }
 
+// ------------------------------------------------------------------ observables
+size_t mclbm_observables_work_bytes(const mclbm_ctx* c, int32_t sample) {
+  if (!c || sample < 0 || sample >= c->m) return 0;
+  const size_t n3 = size_t(c->cells(sample));
+  return align_up(3 * n3 * sizeof(double)) + 3 * n3 * 2 * sizeof(double);
+}
+
+mclbm_status mclbm_observables(mclbm_ctx* c, int32_t sample, double* s2_dev, double* ek_dev, void* work_dev,
+                               size_t work_bytes) {
+  mclbm_status st = check_ctx(c, true);
+  if (st != MCLBM_OK) return st;
+  if (sample < 0 || sample >= c->m) return fail(MCLBM_ERR_ARG, "sample out of range");
+  if (!work_dev || work_bytes < mclbm_observables_work_bytes(c, sample))
+    return fail(MCLBM_ERR_OOM, "observables work buffer too small");
+  const int n = c->desc[sample].n;
+  const size_t n3 = size_t(c->cells(sample));
+  double* u = static_cast<double*>(work_dev);
+  double2* x = reinterpret_cast<double2*>(static_cast<char*>(work_dev) + align_up(3 * n3 * sizeof(double)));
+  HIP_TRY(launch_moments(c->precision, c->pop, c->d_samples, sample, n, int32_t(c->steps[sample] & 1), nullptr, u,
+                         c->stream));
+  HIP_TRY(launch_fft3(n, x, u, 3, -1, c->stream));
+  HIP_TRY(launch_psd(x, n3, x, c->stream));
+  if (ek_dev) HIP_TRY(launch_shells(x, n, 0, ek_dev, c->stream));
+  if (s2_dev) {
+    HIP_TRY(launch_fft3(n, x, nullptr, 1, +1, c->stream));
+    HIP_TRY(launch_shells(x, n, 1, s2_dev, c->stream));
+  }
+  return MCLBM_OK;
+}
+
+mclbm_status mclbm_point_values(mclbm_ctx* c, int32_t q, double* out_dev) {
+  mclbm_status st = check_ctx(c, true);
+  if (st != MCLBM_OK) return st;
+  if (!out_dev) return fail(MCLBM_ERR_ARG, "out_dev is NULL");
+  if (q < 1) return fail(MCLBM_ERR_ARG, "q must be >= 1");
+  for (int s = 0; s < c->m; ++s)
+    if (c->desc[s].n % q) return fail(MCLBM_ERR_ARG, "q must divide every sample's n");
+  const Table* t = nullptr;
+  st = get_table(c, c->tick, true, kAuxBlock, false, &t);
+  if (st != MCLBM_OK) return st;
+  HIP_TRY(launch_point_values(c->precision, c->pop, c->d_samples, table_ptr(c, t), t->nseg, q, out_dev, c->stream));
+  return MCLBM_OK;
+}
+
+size_t mclbm_w1_work_bytes(int32_t q) { return q > 0 ? size_t(3) * q * q * q * sizeof(double) : 0; }
+
+mclbm_status mclbm_w1_1pt(const double* a_dev, const double* b_dev, int32_t m, int32_t q, double* out_dev,
+                          void* work_dev, size_t work_bytes, void* hip_stream) {
+  if (!a_dev || !b_dev || !out_dev || !work_dev) return fail(MCLBM_ERR_ARG, "NULL buffer");
+  if (m < 1 || m > 4096) return fail(MCLBM_ERR_ARG, "m must be in [1, 4096]");
+  if (q < 1 || q > 64) return fail(MCLBM_ERR_ARG, "q must be in [1, 64]");
+  if (work_bytes < mclbm_w1_work_bytes(q)) return fail(MCLBM_ERR_OOM, "w1 work buffer too small");
+  HIP_TRY(launch_w1(a_dev, b_dev, m, q, static_cast<double*>(work_dev), out_dev, static_cast<hipStream_t>(hip_stream)));
+  return MCLBM_OK;
+}
+
 // ------------------------------------------------------------------ launch shape
 mclbm_status mclbm_set_launch(mclbm_ctx* c, int32_t block_threads, int32_t xcd_remap) {
   mclbm_status st = check_ctx(c, false);

@@ -179,6 +179,27 @@ class Ensemble:
         check(lib().mclbm_set_state(self._ctx, sample, _ptr(f)))
         f.record_stream(self.stream)
 
+    def observables(self, sample: int, work: Optional[torch.Tensor] = None):
+        """(S2[r = 1..n/2], E[kappa = 0..n/2]) of one sample's current state, float64 on the device."""
+        self._check_sample(sample)
+        n = self.samples[sample].n
+        wb = int(lib().mclbm_observables_work_bytes(self._ctx, sample))
+        if work is None or work.numel() < wb:
+            work = self._dev_empty((wb,), torch.uint8)
+        s2 = self._dev_empty((n // 2,))
+        ek = self._dev_empty((n // 2 + 1,))
+        self._consume()
+        check(lib().mclbm_observables(self._ctx, sample, _ptr(s2), _ptr(ek), _ptr(work), work.numel()))
+        self._produce()
+        return s2, ek
+
+    def point_values(self, q: int = 8) -> torch.Tensor:
+        """Velocity at the q^3 nodes common to all resolutions: [m, 3, q^3] float64."""
+        out = self._dev_empty((self.m, 3, q ** 3))
+        check(lib().mclbm_point_values(self._ctx, q, _ptr(out)))
+        self._produce()
+        return out
+
     def poison(self, sample: int, cell: int, i: int):
         check(lib().mclbm_poison(self._ctx, sample, cell, i))
 
@@ -245,6 +266,22 @@ class Ensemble:
                                    _ptr(dj), _ptr(ke)))
         self._produce()
         return dj, ke
+
+
+def w1_1pt(a: torch.Tensor, b: torch.Tensor, q: int = 8, stream: Optional[torch.cuda.Stream] = None):
+    """Per-component terms of W_{1,1} between two ensembles' point values
+    ([m, 3, q^3] float64 each); their sum is W_{1,1}."""
+    _require_cuda(a, torch.float64, name="a")
+    _require_cuda(b, torch.float64, name="b")
+    if a.shape != b.shape or a.dim() != 3 or a.shape[1] != 3 or a.shape[2] != q ** 3:
+        raise ValueError("a and b must both have shape [m, 3, q^3]")
+    s = stream if stream is not None else torch.cuda.current_stream()
+    wb = int(lib().mclbm_w1_work_bytes(q))
+    work = torch.empty(wb, dtype=torch.uint8, device=a.device)
+    out = torch.empty(3, dtype=torch.float64, device=a.device)
+    check(lib().mclbm_w1_1pt(_ptr(a), _ptr(b), a.shape[0], q, _ptr(out), _ptr(work), wb,
+                             ctypes.c_void_p(s.cuda_stream)))
+    return out
 
 
 def stream_copy(dst: torch.Tensor, src: torch.Tensor, stream: Optional[torch.cuda.Stream] = None):
