@@ -101,6 +101,30 @@ def kernel_roofline(ens, wl, torch, ticks):
     return avg_ms, launches, bytes_per_launch, achieved
 
 
+def launch_sweep(ens, wl, torch, ticks=20):
+    """Algorithmic GB/s of the collide-and-stream kernel for every launch shape
+    (state is checkpointed and restored around the sweep)."""
+    ck = ens.checkpoint()
+    keep = ens.get_launch()
+    rows = []
+    for block in (128, 256, 512, 1024):
+        if wl.precision == "f64" and block == 1024:
+            continue
+        for xcd in (0, 1):
+            for buf in (0, 1):
+                for nt in (0, 1):
+                    ens.set_launch(block, xcd, buf, nt)
+                    ens.step(2)
+                    avg_ms, _, _, gbs = kernel_roofline(ens, wl, torch, ticks)
+                    rows.append({"block": block, "xcd_remap": xcd, "buffer_addressing": buf, "nontemporal": nt,
+                                 "avg_ms": round(avg_ms, 5), "GBps": round(gbs, 1)})
+                    print(f"[sweep] block {block:4d} xcd {xcd} buf {buf} nt {nt}: {avg_ms:.4f} ms {gbs:.0f} GB/s",
+                          file=sys.stderr, flush=True)
+    ens.set_launch(*keep)
+    ens.restore(ck)
+    return rows
+
+
 def fp64_single(mc, torch, n, u0, re, ticks=200):
     ens = mc.Ensemble([mc.Sample(n, u0, re)], "f64")
     ens.init(0)
@@ -142,6 +166,7 @@ def main():
     ap.add_argument("--roofline-ticks", type=int, default=40)
     ap.add_argument("--skip-fp64", action="store_true", help="skip the single-sample FP64 reference runs")
     ap.add_argument("--copy-gib", type=float, default=4.0, help="size of the copy-kernel bandwidth probe")
+    ap.add_argument("--sweep", action="store_true", help="time every launch shape and report the table")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (this build has no multi-GPU path); got --gpus {args.gpus}",
@@ -159,8 +184,10 @@ def main():
     ens = build_ensemble(wl, mc, torch)
     tuned = None
     if not args.no_autotune:
-        tuned = ens.autotune(reps=2)
-        print(f"[bench] autotuned launch: block {tuned[0]}, xcd remap {tuned[1]}", file=sys.stderr, flush=True)
+        tuned = ens.autotune(reps=5)
+        print(f"[bench] autotuned launch: block {tuned[0]}, xcd remap {tuned[1]}, buffer addressing {tuned[2]}, "
+              f"non-temporal {tuned[3]}", file=sys.stderr, flush=True)
+    sweep = launch_sweep(ens, wl, torch) if args.sweep else None
     ens.step(args.warmup)
     rec_every = wl.save_every if wl.save_every and args.steps >= wl.save_every else 0
     sec, lups = timed_ticks(ens, torch, args.steps, rec_every)
@@ -192,8 +219,8 @@ def main():
         "config": {"workload": wl.name, "samples": wl.m,
                    "lattices": [f"{g.count}x{g.n}^3 stride {g.stride}" for g in wl.groups],
                    "precision": "FP32 shifted populations (f - w), FP64 reductions" if wl.precision == "f32s"
-                   else "FP64", "reduce_every": rec_every, "launch": {"block": ens.get_launch()[0],
-                                                                      "xcd_remap": ens.get_launch()[1]},
+                   else "FP64", "reduce_every": rec_every, "launch": dict(zip(("block", "xcd_remap", "buffer_addressing", "nontemporal"),
+                                                                          ens.get_launch())),
                    "rel_error_bound_vs_oracle": 1e-5 if wl.precision == "f32s" else 1e-12},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": counter_traffic(wl.name),
@@ -202,6 +229,7 @@ def main():
                      "avg_launch_ms": round(avg_ms, 5), "launches_timed": launches,
                      "measured_copy_GBps": round(b_meas, 1), "frac_of_measured_copy": round(achieved / b_meas, 4)},
         "fp64_single_sample": f64,
+        **({"launch_sweep": sweep} if sweep else {}),
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()

@@ -224,18 +224,23 @@ mclbm_status mclbm_w1_1pt(const double* a_dev, const double* b_dev, int32_t m, i
 /* Launch shape of the collide-and-stream kernel, one for the whole ensemble
  * launch: threads (= lattice nodes) per block, 128, 256, 512 or 1024 (1024:
  * FP32 only), not above any sample's n^3; xcd_remap = 1 renumbers blocks so
- * that each of the 8 XCDs works on one contiguous range of nodes.
- * Invalidates cached graphs. */
-mclbm_status mclbm_set_launch(mclbm_ctx* ctx, int32_t block_threads, int32_t xcd_remap);
-mclbm_status mclbm_get_launch(const mclbm_ctx* ctx, int32_t* block_threads, int32_t* xcd_remap);
+ * that each of the 8 XCDs works on one contiguous range of nodes;
+ * buffer_addressing = 1 addresses the population planes through one buffer
+ * resource per sample (scalar plane offsets, 32-bit lane offsets), used only
+ * while every sample's populations span less than 2 GiB, else plain 64-bit
+ * pointers; nontemporal = 1 marks the population loads and stores
+ * non-temporal. None of these changes a result. Invalidates cached graphs. */
+mclbm_status mclbm_set_launch(mclbm_ctx* ctx, int32_t block_threads, int32_t xcd_remap, int32_t buffer_addressing,
+                              int32_t nontemporal);
+mclbm_status mclbm_get_launch(const mclbm_ctx* ctx, int32_t* block_threads, int32_t* xcd_remap,
+                              int32_t* buffer_addressing, int32_t* nontemporal);
 
 /* Time every launch shape on the current state (`reps` periods of
  * 2 * max stride ticks each, after one warm-up period), keep the fastest,
  * and restore the state from a checkpoint written to scratch_dev
- * (mclbm_checkpoint_bytes). best_block / best_xcd (may be NULL) receive the
- * choice. */
+ * (mclbm_checkpoint_bytes). best_* (may be NULL) receive the choice. */
 mclbm_status mclbm_autotune(mclbm_ctx* ctx, int32_t reps, void* scratch_dev, size_t scratch_bytes,
-                            int32_t* best_block, int32_t* best_xcd);
+                            int32_t* best_block, int32_t* best_xcd, int32_t* best_buffer, int32_t* best_nt);
 
 /* Capture the tick loop into HIP graphs (1, the default) or launch kernel by
  * kernel (0). Graphs are used only on a non-NULL stream, for runs of at

@@ -119,6 +119,8 @@ struct mclbm_ctx {
   // launch shape
   int block = 256;
   int xcd_remap = 0;
+  int buffer_addr = 1;       // buffer-resource addressing where every sample fits
+  int nontemporal = 1;       // non-temporal population loads and stores
 
   // launch tables by key
   std::map<std::string, Table> tables;
@@ -207,7 +209,9 @@ void fill_sample(mclbm_ctx* c, int s, double nu) {
   h.omega = omega;
   h.two_over_omega = 2.0 / omega;
   h.kappa = 2.0 - 2.0 / omega;
+  h.eps = 6.0 * nu / (3.0 * nu + 0.5);  // 2 - omega = 2 - 1/(3 nu + 1/2) without cancellation
   h.omega_f = float(h.omega);
+  h.eps_f = float(h.eps);
   h.two_over_omega_f = float(h.two_over_omega);
   h.kappa_f = float(h.kappa);
 }
@@ -279,6 +283,10 @@ StepLaunch make_launch(mclbm_ctx* c, const Table* t, void* pop, void* dst) {
   L.xcd_remap = c->xcd_remap;
   L.flags = c->d_flags;
   L.partials = c->d_partials;
+  L.buffer_ok = c->buffer_addr;
+  L.nontemporal = c->nontemporal;
+  for (int s = 0; s < c->m; ++s)
+    if (uint64_t(Q) * uint64_t(c->cells(s)) * c->elem >= (uint64_t(1) << 31)) L.buffer_ok = 0;
   return L;
 }
 
@@ -865,7 +873,8 @@ mclbm_status mclbm_w1_1pt(const double* a_dev, const double* b_dev, int32_t m, i
 }
 
 // ------------------------------------------------------------------ launch shape
-mclbm_status mclbm_set_launch(mclbm_ctx* c, int32_t block_threads, int32_t xcd_remap) {
+mclbm_status mclbm_set_launch(mclbm_ctx* c, int32_t block_threads, int32_t xcd_remap, int32_t buffer_addressing,
+                              int32_t nontemporal) {
   mclbm_status st = check_ctx(c, false);
   if (st != MCLBM_OK) return st;
   if (block_threads != 128 && block_threads != 256 && block_threads != 512 && block_threads != 1024)
@@ -875,22 +884,29 @@ mclbm_status mclbm_set_launch(mclbm_ctx* c, int32_t block_threads, int32_t xcd_r
   for (int s = 0; s < c->m; ++s)
     if (c->cells(s) < block_threads) return fail(MCLBM_ERR_ARG, "block larger than a sample's lattice");
   if (xcd_remap != 0 && xcd_remap != 1) return fail(MCLBM_ERR_ARG, "xcd_remap must be 0 or 1");
+  if (buffer_addressing != 0 && buffer_addressing != 1) return fail(MCLBM_ERR_ARG, "buffer_addressing must be 0 or 1");
+  if (nontemporal != 0 && nontemporal != 1) return fail(MCLBM_ERR_ARG, "nontemporal must be 0 or 1");
   HIP_TRY(hipStreamSynchronize(c->stream));
   c->block = block_threads;
   c->xcd_remap = xcd_remap;
+  c->buffer_addr = buffer_addressing;
+  c->nontemporal = nontemporal;
   drop_graphs(c);
   return MCLBM_OK;
 }
 
-mclbm_status mclbm_get_launch(const mclbm_ctx* c, int32_t* block_threads, int32_t* xcd_remap) {
+mclbm_status mclbm_get_launch(const mclbm_ctx* c, int32_t* block_threads, int32_t* xcd_remap,
+                              int32_t* buffer_addressing, int32_t* nontemporal) {
   if (!c) return fail(MCLBM_ERR_ARG, "context is NULL");
   if (block_threads) *block_threads = c->block;
   if (xcd_remap) *xcd_remap = c->xcd_remap;
+  if (buffer_addressing) *buffer_addressing = c->buffer_addr;
+  if (nontemporal) *nontemporal = c->nontemporal;
   return MCLBM_OK;
 }
 
 mclbm_status mclbm_autotune(mclbm_ctx* c, int32_t reps, void* scratch_dev, size_t scratch_bytes, int32_t* best_block,
-                            int32_t* best_xcd) {
+                            int32_t* best_xcd, int32_t* best_buffer, int32_t* best_nt) {
   mclbm_status st = check_ctx(c, true);
   if (st != MCLBM_OK) return st;
   if (reps < 1) return fail(MCLBM_ERR_ARG, "reps must be >= 1");
@@ -901,7 +917,7 @@ mclbm_status mclbm_autotune(mclbm_ctx* c, int32_t reps, void* scratch_dev, size_
   c->timing = false;
   const int blocks[4] = {128, 256, 512, 1024};
   float best = 1e30f;
-  int bb = c->block, bx = c->xcd_remap;
+  int bb = c->block, bx = c->xcd_remap, bf = c->buffer_addr, bn = c->nontemporal;
   hipEvent_t e0, e1;
   HIP_TRY(hipEventCreate(&e0));
   HIP_TRY(hipEventCreate(&e1));
@@ -910,9 +926,12 @@ mclbm_status mclbm_autotune(mclbm_ctx* c, int32_t reps, void* scratch_dev, size_
     bool fits = !(b == 1024 && c->precision == MCLBM_FP64);
     for (int s = 0; s < c->m; ++s) fits = fits && c->cells(s) >= b;
     if (!fits) continue;
-    for (int x = 0; x < 2; ++x) {
+    for (int v = 0; v < 8; ++v) {
+      const int x = v & 1, f = (v >> 1) & 1, nt = v >> 2;
       c->block = b;
       c->xcd_remap = x;
+      c->buffer_addr = f;
+      c->nontemporal = nt;
       st = run_plain_ticks(c, 2 * int64_t(c->max_stride));  // warm-up
       if (st != MCLBM_OK) break;
       HIP_TRY(hipEventRecord(e0, c->stream));
@@ -926,6 +945,8 @@ mclbm_status mclbm_autotune(mclbm_ctx* c, int32_t reps, void* scratch_dev, size_
         best = ms;
         bb = b;
         bx = x;
+        bf = f;
+        bn = nt;
       }
       mclbm_status rs = mclbm_restore(c, scratch_dev, scratch_bytes);
       if (rs != MCLBM_OK) return rs;
@@ -942,9 +963,13 @@ mclbm_status mclbm_autotune(mclbm_ctx* c, int32_t reps, void* scratch_dev, size_
   }
   c->block = bb;
   c->xcd_remap = bx;
+  c->buffer_addr = bf;
+  c->nontemporal = bn;
   drop_graphs(c);
   if (best_block) *best_block = bb;
   if (best_xcd) *best_xcd = bx;
+  if (best_buffer) *best_buffer = bf;
+  if (best_nt) *best_nt = bn;
   return mclbm_restore(c, scratch_dev, scratch_bytes);
 }
 

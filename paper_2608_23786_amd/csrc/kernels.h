@@ -22,6 +22,8 @@ struct StepLaunch {
   int32_t xcd_remap;
   int32_t* flags;            // per-sample instability flags
   double* partials;          // record mode: kRecord doubles per block
+  int32_t buffer_ok;         // buffer-resource addressing (every sample's populations span < 2 GiB)
+  int32_t nontemporal;       // non-temporal loads and stores of the populations
 };
 
 enum StepKind { kStep = 0, kStepRecord = 1, kReduceOnly = 2, kPush = 3 };

@@ -124,7 +124,19 @@ __device__ __forceinline__ T geq(const Macro<T>& m) {
   } else {
     const T cu = cdot<i>(m.ux, m.uy, m.uz);
     const T cj = cdot<i>(m.jx, m.jy, m.jz);
-    return w * (m.drho + T(3) * cj + m.rho * (T(4.5) * cu * cu - m.usq15));
+    if constexpr (std::is_same<T, float>::value) {
+      // 3 w_i c_i.j with 3 w_i split into a float head and tail: with the
+      // rounded weights alone, sum_i 3 w_i c_i c_i = (1 + 7.5e-9) I, a
+      // systematic momentum gain in every collision that accumulates over
+      // thousands of steps; with the tail the first moment of g^eq is j up
+      // to unbiased rounding.
+      constexpr double w3 = 3.0 * weight(i);
+      constexpr float w3_hi = float(w3);
+      constexpr float w3_lo = float(w3 - double(w3_hi));
+      return w * (m.drho + m.rho * (T(4.5) * cu * cu - m.usq15)) + (w3_hi * cj + w3_lo * cj);
+    } else {
+      return w * (m.drho + T(3) * cj + m.rho * (T(4.5) * cu * cu - m.usq15));
+    }
   }
 }
 
@@ -179,7 +191,7 @@ __device__ __forceinline__ Shear<T> shear_coefficients(const T (&fneq)[Q]) {
 
 template <typename T>
 struct Relax {
-  T omega, two_over_omega, kappa;
+  T omega, two_over_omega, kappa, eps;
 };
 
 template <typename T>
@@ -189,10 +201,12 @@ __device__ __forceinline__ Relax<T> relax_of(const DevSample& sp) {
     r.omega = sp.omega_f;
     r.two_over_omega = sp.two_over_omega_f;
     r.kappa = sp.kappa_f;
+    r.eps = sp.eps_f;
   } else {
     r.omega = sp.omega;
     r.two_over_omega = sp.two_over_omega;
     r.kappa = sp.kappa;
+    r.eps = sp.eps;
   }
   return r;
 }
@@ -204,7 +218,8 @@ struct CellResult {
   bool bad;
 };
 
-// KBC collision of one node in place: g <- g*.
+// KBC collision of one node in place: g <- g*. Between the passes g[] holds
+// the shifted equilibrium, so every g^eq_i is evaluated once.
 template <typename T>
 __device__ __forceinline__ CellResult<T> kbc_collide(T (&g)[Q], const Relax<T>& rp) {
   CellResult<T> res;
@@ -213,13 +228,15 @@ __device__ __forceinline__ CellResult<T> kbc_collide(T (&g)[Q], const Relax<T>& 
   T fneq[Q];
   static_for<0, Q>([&](auto ic) {
     constexpr int i = decltype(ic)::value;
-    fneq[i] = g[i] - geq<i>(m);
+    const T ge = geq<i>(m);
+    fneq[i] = g[i] - ge;
+    g[i] = ge;
   });
   const Shear<T> s = shear_coefficients(fneq);
   T A = T(0), B = T(0), fmin = T(1);
   static_for<0, Q>([&](auto ic) {
     constexpr int i = decltype(ic)::value;
-    const T feq = T(weight(i)) + geq<i>(m);
+    const T feq = T(weight(i)) + g[i];
     const T r = recip(feq);
     fmin = vmin(fmin, feq);
     if constexpr (nonzeros(i) == 1 || nonzeros(i) == 2) {
@@ -234,14 +251,18 @@ __device__ __forceinline__ CellResult<T> kbc_collide(T (&g)[Q], const Relax<T>& 
   T gamma = T(2);
   if (B > T(1e-30)) gamma = rp.two_over_omega - rp.kappa * (A / B);
   const T t = T(0.5) * rp.omega * gamma;
+  // g* = g - omega ds - t dh = (g^eq - ds) + (2 - omega) ds + (1 - t) dh.
+  // The shear relaxation enters through eps = 2 - omega, which keeps the
+  // viscosity (proportional to eps for omega near 2) at full relative
+  // precision even in float.
+  const T one_t = T(1) - t;
   static_for<0, Q>([&](auto ic) {
     constexpr int i = decltype(ic)::value;
     if constexpr (nonzeros(i) == 1 || nonzeros(i) == 2) {
       const T ds = shear_part<i>(s);
-      const T dh = fneq[i] - ds;
-      g[i] = g[i] - rp.omega * ds - t * dh;
+      g[i] = (g[i] - ds) + rp.eps * ds + one_t * (fneq[i] - ds);
     } else {
-      g[i] = g[i] - t * fneq[i];
+      g[i] = g[i] + one_t * fneq[i];
     }
   });
   res.gamma = gamma;
@@ -287,6 +308,57 @@ template <typename T>
 __device__ __forceinline__ void st(T* plane, uint32_t idx, T v) {
   *reinterpret_cast<T*>(reinterpret_cast<char*>(plane) + idx * uint32_t(sizeof(T))) = v;
 }
+
+// The 27 planes of one sample through one buffer resource: the per-plane
+// offset is a scalar (SGPR) operand and each lane supplies a 32-bit byte
+// offset, so an access costs one VGPR of address. Used when the sample's
+// populations occupy less than 4 GiB.
+constexpr int kBufferFlags = 0x00020000;  // 32-bit raw data format (gfx9 family)
+
+// NT: non-temporal loads and stores (each population is read once and written
+// once per step, so nothing is gained by keeping it in the caches).
+constexpr int kAuxNontemporal = 2;  // cache-policy operand of buffer instructions: nt
+
+template <typename T, bool NT>
+struct BufPlanes {
+  static constexpr int aux = NT ? kAuxNontemporal : 0;
+  __amdgpu_buffer_rsrc_t rsrc;
+  uint32_t plane_bytes;
+  __device__ __forceinline__ BufPlanes(T* base, uint32_t ncell)
+      : rsrc(__builtin_amdgcn_make_buffer_rsrc(base, 0, int(uint32_t(Q) * ncell * uint32_t(sizeof(T))), kBufferFlags)),
+        plane_bytes(ncell * uint32_t(sizeof(T))) {}
+  __device__ __forceinline__ T load(int plane, uint32_t idx) const {
+    if constexpr (sizeof(T) == 4)
+      return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(rsrc, int(idx * 4u), int(plane * plane_bytes), aux));
+    else
+      return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(rsrc, int(idx * 8u), int(plane * plane_bytes), aux));
+  }
+  __device__ __forceinline__ void store(int plane, uint32_t idx, T v) const {
+    if constexpr (sizeof(T) == 4)
+      __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), rsrc, int(idx * 4u),
+                                            int(plane * plane_bytes), aux);
+    else
+      __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(decltype(__builtin_amdgcn_raw_buffer_load_b64(
+                                                                   rsrc, 0, 0, 0)), v),
+                                            rsrc, int(idx * 8u), int(plane * plane_bytes), aux);
+  }
+};
+
+// The same access through plain pointers (any sample size).
+template <typename T, bool NT>
+struct PtrPlanes {
+  T* base;
+  uint32_t ncell;
+  __device__ __forceinline__ PtrPlanes(T* b, uint32_t n) : base(b), ncell(n) {}
+  __device__ __forceinline__ T load(int plane, uint32_t idx) const {
+    if constexpr (NT) return __builtin_nontemporal_load(base + size_t(plane) * ncell + idx);
+    else return ld(base + size_t(plane) * ncell, idx);
+  }
+  __device__ __forceinline__ void store(int plane, uint32_t idx, T v) const {
+    if constexpr (NT) __builtin_nontemporal_store(v, base + size_t(plane) * ncell + idx);
+    else st(base + size_t(plane) * ncell, idx, v);
+  }
+};
 
 // populations of the post-stream state at a node, for either AA parity
 template <typename T>
@@ -398,7 +470,7 @@ struct StepArgs {
   double* partials;
 };
 
-template <typename T, int BLOCK, StepKind KIND>
+template <typename T, int BLOCK, StepKind KIND, bool BUF, bool NT>
 __global__ void __launch_bounds__(BLOCK) kbc_step_kernel(StepArgs<T> a) {
   const int b = remap_block(blockIdx.x, a.total_blocks, a.xcd_remap);
   const Seg sg = a.segs[find_segment(a.segs, a.nseg, b)];
@@ -406,11 +478,22 @@ __global__ void __launch_bounds__(BLOCK) kbc_step_kernel(StepArgs<T> a) {
   const int l = sp.log2n;
   const uint32_t ncell = 1u << (3 * l);
   const Cell c = make_cell(uint32_t(b - sg.first_block) * BLOCK + threadIdx.x, l);
-  T* base = a.pop + sp.offset;
+  using Planes = typename std::conditional<BUF, BufPlanes<T, NT>, PtrPlanes<T, NT>>::type;
+  const Planes src(a.pop + sp.offset, ncell);
   const bool odd = (KIND != kPush) && (sg.parity & 1);
 
   T g[Q];
-  load_state(base, ncell, c, odd, g);
+  if (!odd) {
+    static_for<0, Q>([&](auto ic) {
+      constexpr int i = decltype(ic)::value;
+      g[i] = src.load(i, c.cell);
+    });
+  } else {
+    static_for<0, Q>([&](auto ic) {
+      constexpr int i = decltype(ic)::value;
+      g[i] = src.load(opposite(i), neighbour<i, -1>(c));
+    });
+  }
   const CellResult<T> res = kbc_collide(g, relax_of<T>(sp));
   if (res.bad) a.flags[sg.sample] = 1;
 
@@ -418,19 +501,19 @@ __global__ void __launch_bounds__(BLOCK) kbc_step_kernel(StepArgs<T> a) {
     if (!odd) {
       static_for<0, Q>([&](auto ic) {
         constexpr int i = decltype(ic)::value;
-        st(base + size_t(opposite(i)) * ncell, c.cell, g[i]);
+        src.store(opposite(i), c.cell, g[i]);
       });
     } else {
       static_for<0, Q>([&](auto ic) {
         constexpr int i = decltype(ic)::value;
-        st(base + size_t(i) * ncell, neighbour<i, +1>(c), g[i]);
+        src.store(i, neighbour<i, +1>(c), g[i]);
       });
     }
   } else if constexpr (KIND == kPush) {
-    T* dbase = a.dst + sp.offset;
+    const Planes dst(a.dst + sp.offset, ncell);
     static_for<0, Q>([&](auto ic) {
       constexpr int i = decltype(ic)::value;
-      st(dbase + size_t(i) * ncell, neighbour<i, +1>(c), g[i]);
+      dst.store(i, neighbour<i, +1>(c), g[i]);
     });
   }
 
@@ -710,7 +793,7 @@ __global__ void __launch_bounds__(256) adjoint_step_kernel(const T* state, const
   if (active) {
     const T gbar = T(0.5) * rp.omega * tbar;
     Abar = -rp.kappa * gbar / B;
-    Bbar = rp.kappa * gbar * A / (B * B);
+    Bbar = rp.kappa * gbar * (A / B) / B;  // B * B would underflow in float
   }
   // adjoints of fneq (through dh and the weights) and of the shear coefficients
   T fbar[Q], geqbar[Q];
@@ -873,15 +956,16 @@ __global__ void extract_kernel(const double* records, int m, int field, double* 
   if (s < m) out[s] = records[size_t(s) * kRecord + field];
 }
 
+// One 16-byte element per thread (the fastest plain copy measured on gfx950).
 __global__ void __launch_bounds__(256) stream_copy_kernel(const float4* __restrict__ src, float4* __restrict__ dst,
                                                           size_t n4) {
-  size_t i = size_t(blockIdx.x) * 256 + threadIdx.x;
-  const size_t stride = size_t(gridDim.x) * 256;
-  for (; i < n4; i += stride) dst[i] = src[i];
+  const size_t i = size_t(blockIdx.x) * 256 + threadIdx.x;
+  if (i < n4) dst[i] = src[i];
 }
 
 template <typename T, int BLOCK, StepKind KIND>
 hipError_t launch_step_t(const StepLaunch& L, hipStream_t s) {
+  const bool buf = L.buffer_ok;
   StepArgs<T> a;
   a.pop = static_cast<T*>(L.pop);
   a.dst = static_cast<T*>(L.dst);
@@ -892,7 +976,15 @@ hipError_t launch_step_t(const StepLaunch& L, hipStream_t s) {
   a.xcd_remap = L.xcd_remap;
   a.flags = L.flags;
   a.partials = L.partials;
-  hipLaunchKernelGGL((kbc_step_kernel<T, BLOCK, KIND>), dim3(L.total_blocks), dim3(BLOCK), 0, s, a);
+  const dim3 grid(L.total_blocks), blk(BLOCK);
+  if (buf && L.nontemporal)
+    hipLaunchKernelGGL((kbc_step_kernel<T, BLOCK, KIND, true, true>), grid, blk, 0, s, a);
+  else if (buf)
+    hipLaunchKernelGGL((kbc_step_kernel<T, BLOCK, KIND, true, false>), grid, blk, 0, s, a);
+  else if (L.nontemporal)
+    hipLaunchKernelGGL((kbc_step_kernel<T, BLOCK, KIND, false, true>), grid, blk, 0, s, a);
+  else
+    hipLaunchKernelGGL((kbc_step_kernel<T, BLOCK, KIND, false, false>), grid, blk, 0, s, a);
   return hipGetLastError();
 }
 
@@ -1052,9 +1144,9 @@ hipError_t launch_extract(const double* records, int32_t m, int32_t field, doubl
 
 hipError_t launch_stream_copy(void* dst, const void* src, size_t bytes, hipStream_t s) {
   const size_t n4 = bytes / 16;
-  size_t blocks = (n4 + 255) / 256;
-  if (blocks > 256 * 1024) blocks = 256 * 1024;
+  const size_t blocks = (n4 + 255) / 256;
   if (blocks == 0) return hipSuccess;
+  if (blocks > 0x7fffffffull) return hipErrorInvalidValue;
   hipLaunchKernelGGL(stream_copy_kernel, dim3(unsigned(blocks)), dim3(256), 0, s, static_cast<const float4*>(src),
                      static_cast<float4*>(dst), n4);
   return hipGetLastError();

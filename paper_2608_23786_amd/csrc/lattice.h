@@ -32,7 +32,8 @@ struct DevSample {
   double omega;           // shear relaxation frequency
   double two_over_omega;  // 2 / omega
   double kappa;           // 2 - 2 / omega
-  float omega_f, two_over_omega_f, kappa_f;
+  double eps;             // 2 - omega (carries the viscosity: nu = eps / (6 - 3 eps))
+  float omega_f, two_over_omega_f, kappa_f, eps_f;
   int32_t project;        // 1: the perturbation coefficients were Leray-projected
   double u0;              // Taylor-Green amplitude
   double amp;             // perturbation amplitude relative to u0

@@ -221,20 +221,20 @@ class Ensemble:
         check(lib().mclbm_restore(self._ctx, _ptr(buf), buf.numel()))
 
     # ------------------------------------------------------------ launch shape
-    def set_launch(self, block: int, xcd_remap: int = 0):
-        check(lib().mclbm_set_launch(self._ctx, block, xcd_remap))
+    def set_launch(self, block: int, xcd_remap: int = 0, buffer_addressing: int = 1, nontemporal: int = 1):
+        check(lib().mclbm_set_launch(self._ctx, block, xcd_remap, buffer_addressing, nontemporal))
 
     def get_launch(self):
-        b, x = ctypes.c_int32(), ctypes.c_int32()
-        check(lib().mclbm_get_launch(self._ctx, ctypes.byref(b), ctypes.byref(x)))
-        return b.value, x.value
+        v = [ctypes.c_int32() for _ in range(4)]
+        check(lib().mclbm_get_launch(self._ctx, *[ctypes.byref(x) for x in v]))
+        return tuple(x.value for x in v)
 
     def autotune(self, reps: int = 2):
+        """Time every launch shape; returns (block, xcd_remap, buffer_addressing, nontemporal) chosen."""
         scratch = self._dev_empty((self.checkpoint_bytes(),), torch.uint8)
-        b, x = ctypes.c_int32(), ctypes.c_int32()
-        check(lib().mclbm_autotune(self._ctx, reps, _ptr(scratch), scratch.numel(), ctypes.byref(b),
-                                   ctypes.byref(x)))
-        return b.value, x.value
+        v = [ctypes.c_int32() for _ in range(4)]
+        check(lib().mclbm_autotune(self._ctx, reps, _ptr(scratch), scratch.numel(), *[ctypes.byref(x) for x in v]))
+        return tuple(x.value for x in v)
 
     def use_graphs(self, enable: bool):
         check(lib().mclbm_use_graphs(self._ctx, int(enable)))

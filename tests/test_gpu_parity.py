@@ -123,6 +123,23 @@ def test_rtgv_fp32_ensemble_matches_oracle():
         assert err < 1e-5
 
 
+@pytest.mark.slow
+def test_rtgv64_fp32_1000_steps_within_target():
+    """The 64^3 RTGV sample of the 64-sample workload (U0 0.025, Re 1600,
+    projected, seed 2608, sample 0) after 1000 steps: FP32 shifted
+    populations against the FP64 oracle, relative L2 of u <= 1e-5."""
+    n, u0, re, amp, steps = 64, 0.025, 1600.0, 0.05, 1000
+    y = mc_inputs.draw_y(2608, 2)
+    ens = mc.Ensemble([mc.Sample(n, u0, re, amp, True)] * 2, "f32s")
+    ens.init(0, torch.from_numpy(y))
+    ens.step(steps)
+    _, u_g = gpu_velocity(ens, 0)
+    _, u_o, _ = oracle_velocity(n, u0, re, amp, y[0], True, steps)
+    err = rel_l2(u_g, u_o)
+    print(f"64^3 RTGV, 1000 steps, FP32: rel L2(u) = {err:.3e}, max rel = {np.max(np.abs(u_g - u_o)) / np.max(np.abs(u_o)):.3e}")
+    assert err < 1e-5
+
+
 def test_fp64_rtgv_unprojected_matches_oracle():
     n, u0, re, amp, steps = 16, 0.05, 200.0, 0.4, 60
     y = mc_inputs.draw_y(11, 2)
@@ -194,12 +211,12 @@ def test_records_match_reduce_and_oracle():
 
 
 # ------------------------------------------------------------------ scheduling invariants
-def run_state(precision, block, xcd, graphs, ticks=40):
+def run_state(precision, block, xcd, graphs, ticks=40, buf=1, nt=1):
     y = mc_inputs.draw_y(9, 3)
     ens = mc.Ensemble([mc.Sample(16, 0.05, 100.0, 0.2, True, 2), mc.Sample(32, 0.05, 100.0, 0.2, True, 1),
                        mc.Sample(16, 0.05, 100.0, 0.2, True, 1)], precision)
     ens.init(0, torch.from_numpy(y))
-    ens.set_launch(block, xcd)
+    ens.set_launch(block, xcd, buf, nt)
     ens.use_graphs(graphs)
     ens.step(ticks)
     return [ens.get_state(s).cpu().numpy() for s in range(3)]
@@ -207,11 +224,12 @@ def run_state(precision, block, xcd, graphs, ticks=40):
 
 @pytest.mark.parametrize("precision", ["f64", "f32s"])
 def test_results_do_not_depend_on_launch_shape_or_graphs(precision):
-    ref = run_state(precision, 256, 0, False)
-    for block, xcd, graphs in ((128, 1, False), (512, 0, True), (256, 1, True)):
-        out = run_state(precision, block, xcd, graphs)
+    ref = run_state(precision, 256, 0, False, buf=0, nt=0)
+    for block, xcd, graphs, buf, nt in ((128, 1, False, 1, 0), (512, 0, True, 0, 1), (256, 1, True, 1, 1),
+                                        (256, 0, False, 1, 0)):
+        out = run_state(precision, block, xcd, graphs, buf=buf, nt=nt)
         for a, b in zip(ref, out):
-            assert np.array_equal(a, b), (block, xcd, graphs)
+            assert np.array_equal(a, b), (block, xcd, graphs, buf, nt)
 
 
 def test_checkpoint_restore_is_exact():
