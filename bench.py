@@ -133,6 +133,88 @@ def fp64_single(mc, torch, n, u0, re, ticks=200):
     return lups / sec / 1e6
 
 
+def bench_mixed(mc, torch, with_sf=True):
+    """Uneven batch 32 x 64^3 + 12 x 128^3 + 4 x 256^3 (strides 16:4:1), 1000
+    ticks, FP64 reductions fused every 16 ticks (all samples at equal physical
+    time) and, when with_sf, the FP64 structure function of every sample per
+    saved tick. Returns a dict of throughput figures."""
+    import mc_inputs
+    wl = mc_inputs.WORKLOADS["mixed48_f32"]
+    ens = build_ensemble(wl, mc, torch)
+    tuned = ens.autotune(reps=1)
+    ens.step(32)
+    ticks, every = wl.ticks, wl.save_every
+    work = ens._dev_empty((max(int(mc.lib().mclbm_observables_work_bytes(ens._ctx, s)) for s in range(ens.m)),),
+                          torch.uint8)
+    t0 = ens.ticks
+    lups = sum(cells_per_tick(ens, t0 + k) for k in range(ticks))
+    ens.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    sf_sec = 0.0
+    e0.record(ens.stream)
+    saves = 0
+    for k in range(0, ticks, every):
+        ens.step(min(every, ticks - k), record_every=every)
+        saves += 1
+        if with_sf:
+            for s in range(ens.m):
+                ens.observables(s, work, structure=True, spectrum=False)
+    e1.record(ens.stream)
+    ens.synchronize()
+    sec = e0.elapsed_time(e1) / 1e3
+    out = {"workload": wl.name, "ticks": ticks, "saves": saves, "lattice_updates": lups,
+           "seconds": round(sec, 4), "MLUPS_including_observables": round(lups / sec / 1e6, 1),
+           "launch": dict(zip(("block", "xcd_remap", "buffer_addressing", "nontemporal"), tuned))}
+    # the same ticks without the structure functions (first realign to a tick
+    # where every sample steps)
+    ens.step((-ens.ticks) % every)
+    ens.synchronize()
+    e0.record(ens.stream)
+    for k in range(0, ticks, every):
+        ens.step(min(every, ticks - k), record_every=every)
+    e1.record(ens.stream)
+    ens.synchronize()
+    sec2 = e0.elapsed_time(e1) / 1e3
+    out["MLUPS_lbm_and_reductions"] = round(lups / sec2 / 1e6, 1)
+    out["structure_function_share"] = round(max(0.0, 1 - sec2 / sec), 4) if with_sf else 0.0
+    if ens.check() >= 0:
+        raise SystemExit("mixed workload became unstable")
+    del ens, work
+    torch.cuda.empty_cache()
+    return out
+
+
+def bench_adjoint(mc, torch):
+    """8 x 128^3 FP32: forward 1000 steps with checkpoints every 50, then the
+    discrete adjoint (recompute per segment + reverse collide-and-stream) to
+    d(mean KE)/dY."""
+    import mc_inputs
+    wl = mc_inputs.WORKLOADS["adjoint128x8_f32"]
+    ens = build_ensemble(wl, mc, torch)
+    cells = sum(s.n ** 3 for s in ens.samples)
+    ticks, every = wl.ticks, wl.save_every
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    ens.synchronize()
+    e[0].record(ens.stream)
+    ck = ens.forward_ckpt(ticks, every)
+    e[1].record(ens.stream)
+    dj, ke = ens.backward(ticks, every, ck)
+    e[2].record(ens.stream)
+    ens.synchronize()
+    fwd = e[0].elapsed_time(e[1]) / 1e3
+    bwd = e[1].elapsed_time(e[2]) / 1e3
+    out = {"workload": wl.name, "steps": ticks, "ckpt_every": every,
+           "forward_seconds": round(fwd, 4), "backward_seconds": round(bwd, 4),
+           "forward_MLUPS": round(cells * ticks / fwd / 1e6, 1),
+           "backward_MLUPS": round(cells * ticks / bwd / 1e6, 1),
+           "backward_bytes_per_lup": 324 + 216 * (ticks - (ticks + every - 1) // every) / ticks,
+           "dJdY_norm": float(dj.norm()), "J": float(ke.mean())}
+    out["backward_GBps_algorithmic"] = round(out["backward_bytes_per_lup"] * cells * ticks / bwd / 1e9, 1)
+    del ens, ck
+    torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(seconds_target=15.0):
     """The oracle on one 64^3 RTGV sample of the workload, on all host cores."""
     import mc_inputs
@@ -167,6 +249,7 @@ def main():
     ap.add_argument("--skip-fp64", action="store_true", help="skip the single-sample FP64 reference runs")
     ap.add_argument("--copy-gib", type=float, default=4.0, help="size of the copy-kernel bandwidth probe")
     ap.add_argument("--sweep", action="store_true", help="time every launch shape and report the table")
+    ap.add_argument("--no-extra", action="store_true", help="skip the mixed-resolution and adjoint workloads")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (this build has no multi-GPU path); got --gpus {args.gpus}",
@@ -203,6 +286,14 @@ def main():
     if not args.skip_fp64:
         f64 = {"32^3 TGV Re 100 MLUPS": round(fp64_single(mc, torch, 32, 0.05, 100.0), 1),
                "64^3 Re 1600 MLUPS": round(fp64_single(mc, torch, 64, 0.025, 1600.0), 1)}
+    extra = {}
+    if not args.no_extra:
+        del ens
+        torch.cuda.empty_cache()
+        extra["mixed48"] = bench_mixed(mc, torch)
+        print(f"[bench] mixed48: {extra['mixed48']}", file=sys.stderr, flush=True)
+        extra["adjoint128x8"] = bench_adjoint(mc, torch)
+        print(f"[bench] adjoint128x8: {extra['adjoint128x8']}", file=sys.stderr, flush=True)
     out = {
         "metric": "aggregate MLUPS & % HBM roofline, batched FP32 vs plain FP64, at stated rel. error",
         "value": round(mlups, 1),
@@ -220,7 +311,7 @@ def main():
                    "lattices": [f"{g.count}x{g.n}^3 stride {g.stride}" for g in wl.groups],
                    "precision": "FP32 shifted populations (f - w), FP64 reductions" if wl.precision == "f32s"
                    else "FP64", "reduce_every": rec_every, "launch": dict(zip(("block", "xcd_remap", "buffer_addressing", "nontemporal"),
-                                                                          ens.get_launch())),
+                                                                          tuned or (256, 0, 1, 1))),
                    "rel_error_bound_vs_oracle": 1e-5 if wl.precision == "f32s" else 1e-12},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": counter_traffic(wl.name),
@@ -230,6 +321,7 @@ def main():
                      "measured_copy_GBps": round(b_meas, 1), "frac_of_measured_copy": round(achieved / b_meas, 4)},
         "fp64_single_sample": f64,
         **({"launch_sweep": sweep} if sweep else {}),
+        **extra,
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()

@@ -820,7 +820,8 @@ mclbm_status mclbm_backward(mclbm_ctx* c, int64_t ticks, int32_t ckpt_every, con
 size_t mclbm_observables_work_bytes(const mclbm_ctx* c, int32_t sample) {
   if (!c || sample < 0 || sample >= c->m) return 0;
   const size_t n3 = size_t(c->cells(sample));
-  return align_up(3 * n3 * sizeof(double)) + 3 * n3 * 2 * sizeof(double);
+  return align_up(3 * n3 * sizeof(double)) + align_up(3 * n3 * 2 * sizeof(double)) +
+         shell_scratch_doubles(c->desc[sample].n) * sizeof(double);
 }
 
 mclbm_status mclbm_observables(mclbm_ctx* c, int32_t sample, double* s2_dev, double* ek_dev, void* work_dev,
@@ -834,14 +835,15 @@ mclbm_status mclbm_observables(mclbm_ctx* c, int32_t sample, double* s2_dev, dou
   const size_t n3 = size_t(c->cells(sample));
   double* u = static_cast<double*>(work_dev);
   double2* x = reinterpret_cast<double2*>(static_cast<char*>(work_dev) + align_up(3 * n3 * sizeof(double)));
+  double* scratch = reinterpret_cast<double*>(reinterpret_cast<char*>(x) + align_up(3 * n3 * 2 * sizeof(double)));
   HIP_TRY(launch_moments(c->precision, c->pop, c->d_samples, sample, n, int32_t(c->steps[sample] & 1), nullptr, u,
                          c->stream));
   HIP_TRY(launch_fft3(n, x, u, 3, -1, c->stream));
   HIP_TRY(launch_psd(x, n3, x, c->stream));
-  if (ek_dev) HIP_TRY(launch_shells(x, n, 0, ek_dev, c->stream));
+  if (ek_dev) HIP_TRY(launch_shells(x, n, 0, scratch, ek_dev, c->stream));
   if (s2_dev) {
     HIP_TRY(launch_fft3(n, x, nullptr, 1, +1, c->stream));
-    HIP_TRY(launch_shells(x, n, 1, s2_dev, c->stream));
+    HIP_TRY(launch_shells(x, n, 1, scratch, s2_dev, c->stream));
   }
   return MCLBM_OK;
 }

@@ -76,8 +76,10 @@ hipError_t launch_stream_copy(void* dst, const void* src, size_t bytes, hipStrea
 // supplies real input for the first pass. sign -1 forward, +1 unnormalised inverse.
 hipError_t launch_fft3(int n, double2* data, const double* rin, int ncomp, int sign, hipStream_t s);
 hipError_t launch_psd(const double2* x, size_t n3, double2* out, hipStream_t s);
-// mode 0: energy spectrum bins kappa = 0..n/2; mode 1: structure function r = 1..n/2
-hipError_t launch_shells(const double2* data, int n, int mode, double* out, hipStream_t s);
+// mode 0: energy spectrum bins kappa = 0..n/2; mode 1: structure function r = 1..n/2.
+// scratch: shell_scratch_doubles(n) doubles.
+size_t shell_scratch_doubles(int n);
+hipError_t launch_shells(const double2* data, int n, int mode, double* scratch, double* out, hipStream_t s);
 hipError_t launch_point_values(int precision, const void* pop, const DevSample* samples, const Seg* segs,
                                int32_t nseg, int q, double* out, hipStream_t s);
 hipError_t launch_w1(const double* a, const double* b, int m, int q, double* col, double* out, hipStream_t s);

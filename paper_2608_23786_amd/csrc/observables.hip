@@ -11,9 +11,10 @@
 //     resolution, and the 1-point Wasserstein distance between two such
 //     ensembles by sorting (Algorithm 2, eq. (wassersteinPermutations)).
 // Shells hold the integer vectors (minimum image, components in
-// {-N/2+1, ..., N/2}) whose length rounds to the shell index; a block per
-// shell enumerates its (z, y) rows and the one or two x-intervals of each row,
-// so every sum runs in a fixed order (results do not depend on scheduling).
+// {-N/2+1, ..., N/2}) whose length rounds to the shell index; blocks
+// enumerate the (z, y) rows of a shell and the one or two x-intervals of each
+// row, so every sum runs in a fixed order (results do not depend on
+// scheduling).
 #include <hip/hip_runtime.h>
 
 #include "kernels.h"
@@ -115,48 +116,80 @@ __device__ __forceinline__ int64_t isqrt_floor(int64_t v) {
   return r;
 }
 
-// Shell sums over the real parts of data (N^3, minimum-image index vectors).
-// mode 0 (spectrum): out[kappa] = 4 pi / |S| sum |k|^2/2 * v / N^6, kappa = 0..N/2
-// mode 1 (structure function): out[r-1] = 1/|C| sum 2 (v(0) - v(h)) / N^6, r = 1..N/2
-__global__ void __launch_bounds__(256) shell_kernel(const double2* data, int n, int mode, double* out) {
-  const int shell = mode == 0 ? int(blockIdx.x) : int(blockIdx.x) + 1;
-  const int64_t lo2 = int64_t(2 * shell - 1) * (2 * shell - 1);  // 4|h|^2 >= (2r-1)^2
-  const int64_t hi2 = int64_t(2 * shell + 1) * (2 * shell + 1);  // 4|h|^2 <  (2r+1)^2
+// Shell sums over the real parts of data (N^3, minimum-image index vectors),
+// in two passes.
+// Pass 1 (one wave per (z, y) row, s = hz^2 + hy^2): the row is folded by
+// |hx| = m into LDS, v[m] = value(+m) + value(-m) (one term at m = 0 and
+// m = N/2), then lane r sums v over the m-interval whose |h| rounds to r and
+// writes rowbins[r][row] (and the number of lags, rowcnt[r][row]).
+// Pass 2 (one block per shell): sums its rowbins column in a fixed order.
+// mode 0 (spectrum): value = |k|^2/2 * v; mode 1 (structure function):
+// value = 2 (v(0) - v(h)).
+__global__ void __launch_bounds__(256) shell_rows_kernel(const double2* data, int n, int mode, double* rowbins,
+                                                         double* rowcnt) {
+  __shared__ double sh[4][513];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int rows = n * n;
+  const int row = blockIdx.x * 4 + wave;
   const int half = n / 2;
-  const double v0 = data[0].x;
-  const double norm = 1.0 / (double(n) * n * n) / (double(n) * n * n);
-  double acc = 0.0;
-  double cnt = 0.0;
-  for (int row = threadIdx.x; row < n * n; row += 256) {
-    const int hz = row / n - half + 1, hy = row % n - half + 1;  // in {-N/2+1, ..., N/2}
+  if (row < rows) {
+    const int iz = row / n, iy = row % n;
+    const int hz = iz <= half ? iz : iz - n, hy = iy <= half ? iy : iy - n;
     const int64_t s = int64_t(hz) * hz + int64_t(hy) * hy;
-    // hx^2 in [ceil((lo2 - 4s)/4), floor((hi2 - 1 - 4s)/4)]
-    const int64_t top = hi2 - 1 - 4 * s;
-    if (top < 0) continue;
-    const int64_t hx2_max = top / 4;
-    const int64_t bot = lo2 - 4 * s;
-    const int64_t hx2_min = bot <= 0 ? 0 : (bot + 3) / 4;
-    if (hx2_min > hx2_max) continue;
-    int64_t a = isqrt_floor(hx2_min);
-    if (a * a < hx2_min) ++a;
-    const int64_t b = isqrt_floor(hx2_max);
-    if (a > b) continue;
-    const size_t rowbase = (size_t((hz + n) % n) * n + size_t((hy + n) % n)) * n;
-    const double w2 = double(s);
-    // hx in [a, b] and [-b, -a], clipped to {-N/2+1, ..., N/2}
-    for (int64_t hx = -b; hx <= b; ++hx) {
-      if (hx > -a && hx < a) {
-        hx = a - 1;
-        continue;
+    const size_t base = size_t(row) * n;
+    const double v0 = data[0].x;
+    for (int m = lane; m <= half; m += 64) {
+      const double k2 = double(s) + double(m) * m;
+      const double a = data[base + m].x;
+      double v = mode == 0 ? 0.5 * k2 * a : 2.0 * (v0 - a);
+      if (m >= 1 && m <= half - 1) {
+        const double b = data[base + (n - m)].x;
+        v += mode == 0 ? 0.5 * k2 * b : 2.0 * (v0 - b);
       }
-      if (hx < -half + 1 || hx > half) continue;
-      const double v = data[rowbase + size_t((hx + n) % n)].x;
-      if (mode == 0) acc += 0.5 * (w2 + double(hx) * hx) * v;
-      else acc += 2.0 * (v0 - v);
-      cnt += 1.0;
+      sh[wave][m] = v;
     }
   }
+  __syncthreads();
+  if (row < rows) {
+    const int iz = row / n, iy = row % n;
+    const int hz = iz <= half ? iz : iz - n, hy = iy <= half ? iy : iy - n;
+    const int64_t s = int64_t(hz) * hz + int64_t(hy) * hy;
+    for (int r = lane; r <= half; r += 64) {
+      // m^2 in [ceil(((2r-1)^2 - 4s)/4), floor(((2r+1)^2 - 1 - 4s)/4)], m in [0, N/2]
+      double sum = 0.0, cnt = 0.0;
+      const int64_t lo2 = r == 0 ? 0 : int64_t(2 * r - 1) * (2 * r - 1);
+      const int64_t top = int64_t(2 * r + 1) * (2 * r + 1) - 1 - 4 * s;
+      if (top >= 0) {
+        const int64_t m2max = top / 4;
+        const int64_t bot = lo2 - 4 * s;
+        const int64_t m2min = bot <= 0 ? 0 : (bot + 3) / 4;
+        if (m2min <= m2max) {
+          int64_t a = isqrt_floor(m2min);
+          if (a * a < m2min) ++a;
+          int64_t b = isqrt_floor(m2max);
+          if (b > half) b = half;
+          for (int64_t m = a; m <= b; ++m) {
+            sum += sh[wave][m];
+            cnt += (m == 0 || m == half) ? 1.0 : 2.0;
+          }
+        }
+      }
+      rowbins[size_t(r) * rows + row] = sum;
+      rowcnt[size_t(r) * rows + row] = cnt;
+    }
+  }
+}
+
+__global__ void __launch_bounds__(256) shell_sum_kernel(const double* rowbins, const double* rowcnt, int n, int mode,
+                                                        double* out) {
+  const int rows = n * n;
+  const int r = mode == 0 ? int(blockIdx.x) : int(blockIdx.x) + 1;
   __shared__ double sa[256], sc[256];
+  double acc = 0.0, cnt = 0.0;
+  for (int k = threadIdx.x; k < rows; k += 256) {
+    acc += rowbins[size_t(r) * rows + k];
+    cnt += rowcnt[size_t(r) * rows + k];
+  }
   sa[threadIdx.x] = acc;
   sc[threadIdx.x] = cnt;
   __syncthreads();
@@ -168,8 +201,8 @@ __global__ void __launch_bounds__(256) shell_kernel(const double2* data, int n, 
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    const double sum = sa[0] * norm;
-    const double c = sc[0];
+    const double norm = 1.0 / (double(n) * n * n) / (double(n) * n * n);
+    const double sum = sa[0] * norm, c = sc[0];
     if (mode == 0) out[blockIdx.x] = c > 0 ? 4.0 * M_PI / c * sum : 0.0;
     else out[blockIdx.x] = c > 0 ? sum / c : 0.0;
   }
@@ -312,9 +345,18 @@ hipError_t launch_psd(const double2* x, size_t n3, double2* out, hipStream_t s) 
   return hipGetLastError();
 }
 
-hipError_t launch_shells(const double2* data, int n, int mode, double* out, hipStream_t s) {
+size_t shell_scratch_doubles(int n) { return size_t(2) * (n / 2 + 1) * size_t(n) * n; }
+
+hipError_t launch_shells(const double2* data, int n, int mode, double* scratch, double* out, hipStream_t s) {
+  const size_t table = size_t(n / 2 + 1) * size_t(n) * n;
+  double* rowbins = scratch;
+  double* rowcnt = scratch + table;
+  hipLaunchKernelGGL(shell_rows_kernel, dim3(unsigned((n * n + 3) / 4)), dim3(256), 0, s, data, n, mode, rowbins,
+                     rowcnt);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
   const unsigned bins = mode == 0 ? unsigned(n / 2 + 1) : unsigned(n / 2);
-  hipLaunchKernelGGL(shell_kernel, dim3(bins), dim3(256), 0, s, data, n, mode, out);
+  hipLaunchKernelGGL(shell_sum_kernel, dim3(bins), dim3(256), 0, s, rowbins, rowcnt, n, mode, out);
   return hipGetLastError();
 }
 

@@ -179,15 +179,17 @@ class Ensemble:
         check(lib().mclbm_set_state(self._ctx, sample, _ptr(f)))
         f.record_stream(self.stream)
 
-    def observables(self, sample: int, work: Optional[torch.Tensor] = None):
-        """(S2[r = 1..n/2], E[kappa = 0..n/2]) of one sample's current state, float64 on the device."""
+    def observables(self, sample: int, work: Optional[torch.Tensor] = None, structure: bool = True,
+                    spectrum: bool = True):
+        """(S2[r = 1..n/2], E[kappa = 0..n/2]) of one sample's current state, float64 on the
+        device; an observable not asked for is returned as None."""
         self._check_sample(sample)
         n = self.samples[sample].n
         wb = int(lib().mclbm_observables_work_bytes(self._ctx, sample))
         if work is None or work.numel() < wb:
             work = self._dev_empty((wb,), torch.uint8)
-        s2 = self._dev_empty((n // 2,))
-        ek = self._dev_empty((n // 2 + 1,))
+        s2 = self._dev_empty((n // 2,)) if structure else None
+        ek = self._dev_empty((n // 2 + 1,)) if spectrum else None
         self._consume()
         check(lib().mclbm_observables(self._ctx, sample, _ptr(s2), _ptr(ek), _ptr(work), work.numel()))
         self._produce()
