@@ -157,6 +157,11 @@ mclbm_status mclbm_check(mclbm_ctx* ctx, int32_t* first_bad);
 mclbm_status mclbm_get_state(mclbm_ctx* ctx, int32_t sample, double* f_dev);
 mclbm_status mclbm_set_state(mclbm_ctx* ctx, int32_t sample, const double* f_dev);
 
+/* Populations f (not shifted, double) of `count` cells of one sample at its
+ * current step: cells_dev[count] (device, int64 cell indices, each checked
+ * against n^3 before anything is enqueued), f_dev[count][27] (device). */
+mclbm_status mclbm_get_cells(mclbm_ctx* ctx, int32_t sample, const int64_t* cells_dev, int32_t count, double* f_dev);
+
 /* Write NaN into population i of cell `cell` of one sample (failure-path
  * tests). */
 mclbm_status mclbm_poison(mclbm_ctx* ctx, int32_t sample, int64_t cell, int32_t i);

@@ -53,6 +53,7 @@ SIGNATURES = {
     "mclbm_check": (_i32, [_ctxp, _ip]),
     "mclbm_get_state": (_i32, [_ctxp, _i32, _vp]),
     "mclbm_set_state": (_i32, [_ctxp, _i32, _vp]),
+    "mclbm_get_cells": (_i32, [_ctxp, _i32, _vp, _i32, _vp]),
     "mclbm_poison": (_i32, [_ctxp, _i32, _i64, _i32]),
     "mclbm_checkpoint_bytes": (_sz, [_ctxp]),
     "mclbm_checkpoint": (_i32, [_ctxp, _vp, _sz]),

@@ -656,6 +656,23 @@ mclbm_status mclbm_set_state(mclbm_ctx* c, int32_t sample, const double* f_dev) 
   return MCLBM_OK;
 }
 
+mclbm_status mclbm_get_cells(mclbm_ctx* c, int32_t sample, const int64_t* cells_dev, int32_t count, double* f_dev) {
+  mclbm_status st = check_ctx(c, true);
+  if (st != MCLBM_OK) return st;
+  if (sample < 0 || sample >= c->m) return fail(MCLBM_ERR_ARG, "sample out of range");
+  if (count < 0 || (count > 0 && (!cells_dev || !f_dev))) return fail(MCLBM_ERR_ARG, "bad cell list");
+  if (count == 0) return MCLBM_OK;
+  // the cell indices live on the device; validate them on a host copy
+  std::vector<int64_t> h(count);
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  HIP_TRY(hipMemcpy(h.data(), cells_dev, sizeof(int64_t) * count, hipMemcpyDeviceToHost));
+  for (int64_t v : h)
+    if (v < 0 || v >= c->cells(sample)) return fail(MCLBM_ERR_ARG, "cell index out of range");
+  HIP_TRY(launch_gather_cells(c->precision, c->pop, c->d_samples, sample, int32_t(c->steps[sample] & 1), cells_dev,
+                              count, f_dev, c->stream));
+  return MCLBM_OK;
+}
+
 mclbm_status mclbm_poison(mclbm_ctx* c, int32_t sample, int64_t cell, int32_t i) {
   mclbm_status st = check_ctx(c, true);
   if (st != MCLBM_OK) return st;

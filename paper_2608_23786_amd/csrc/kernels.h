@@ -47,6 +47,8 @@ hipError_t launch_get_state(int precision, const void* pop, const DevSample* sam
                             int32_t parity, double* f, hipStream_t s);
 hipError_t launch_set_state(int precision, void* pop, const DevSample* samples, int32_t sample, int32_t n,
                             int32_t parity, const double* f, hipStream_t s);
+hipError_t launch_gather_cells(int precision, const void* pop, const DevSample* samples, int32_t sample, int32_t parity,
+                               const int64_t* cells, int32_t count, double* f, hipStream_t s);
 hipError_t launch_poison(int precision, void* pop, const DevSample* samples, int32_t sample, int32_t parity,
                          int64_t cell, int32_t i, hipStream_t s);
 

@@ -669,6 +669,25 @@ __global__ void __launch_bounds__(256)
   write_state(pop + sp.offset, ncell, c, parity & 1, g);
 }
 
+// Populations (unshifted, double) of selected cells of one sample: f[k][27].
+template <typename T>
+__global__ void __launch_bounds__(64)
+    gather_cells_kernel(const T* pop, const DevSample* samples, int sample, int parity, const int64_t* cells,
+                        int count, double* f) {
+  const int k = blockIdx.x * 64 + threadIdx.x;
+  if (k >= count) return;
+  const DevSample& sp = samples[sample];
+  const int l = sp.log2n;
+  const uint32_t ncell = 1u << (3 * l);
+  const Cell c = make_cell(uint32_t(cells[k]), l);
+  T g[Q];
+  load_state(pop + sp.offset, ncell, c, parity & 1, g);
+  static_for<0, Q>([&](auto ic) {
+    constexpr int i = decltype(ic)::value;
+    f[size_t(k) * Q + i] = weight(i) + double(g[i]);
+  });
+}
+
 template <typename T>
 __global__ void poison_kernel(T* pop, const DevSample* samples, int sample, int parity, uint32_t cell, int i) {
   const DevSample& sp = samples[sample];
@@ -1068,6 +1087,18 @@ hipError_t launch_set_state(int precision, void* pop, const DevSample* samples, 
   else
     hipLaunchKernelGGL(set_state_kernel<float>, dim3(blocks), dim3(256), 0, s, static_cast<float*>(pop), samples,
                        sample, parity, f);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather_cells(int precision, const void* pop, const DevSample* samples, int32_t sample, int32_t parity,
+                               const int64_t* cells, int32_t count, double* f, hipStream_t s) {
+  const unsigned blocks = unsigned((count + 63) / 64);
+  if (precision == 0)
+    hipLaunchKernelGGL(gather_cells_kernel<double>, dim3(blocks), dim3(64), 0, s, static_cast<const double*>(pop),
+                       samples, sample, parity, cells, count, f);
+  else
+    hipLaunchKernelGGL(gather_cells_kernel<float>, dim3(blocks), dim3(64), 0, s, static_cast<const float*>(pop),
+                       samples, sample, parity, cells, count, f);
   return hipGetLastError();
 }
 

@@ -202,6 +202,15 @@ class Ensemble:
         self._produce()
         return out
 
+    def get_cells(self, sample: int, cells) -> torch.Tensor:
+        """Populations f[k][27] (float64, device) of the given cell indices of one sample."""
+        idx = torch.as_tensor(cells, dtype=torch.int64).to(self.device).contiguous()
+        out = self._dev_empty((idx.numel(), 27))
+        self._consume()
+        check(lib().mclbm_get_cells(self._ctx, sample, _ptr(idx), idx.numel(), _ptr(out)))
+        self._produce()
+        return out
+
     def poison(self, sample: int, cell: int, i: int):
         check(lib().mclbm_poison(self._ctx, sample, cell, i))
 

@@ -1,0 +1,143 @@
+"""Parity at the full workload sizes, in the launch configuration the
+benchmark times, on sampled outputs the oracle computes one by one, plus
+properties that hold at any size.
+
+Sampled one-step check: for a cell x the post-stream population i after one
+step is the i-th population of the collision at x - c_i. The pre-step
+populations of the 27 neighbours are read back from the GPU state (FP32
+values widened to double), the oracle collides each neighbour in FP64, and
+the result is compared with the GPU's post-step populations at x. Both even
+and odd AA parities are covered. FP32 bound: 2e-6 of max|f - w| (float
+rounding of the collision); FP64 bound: 2e-13 (see test_gpu_parity).
+"""
+import numpy as np
+import pytest
+import torch
+
+import mc_inputs
+import oracle
+
+pytestmark = pytest.mark.gpu
+mc = pytest.importorskip("paper_2608_23786_amd")
+
+C, W = oracle.velocity_set()
+
+
+def neighbours(n, cells):
+    """cell indices of x - c_i for every cell (rows) and velocity (columns)"""
+    cells = np.asarray(cells, dtype=np.int64)
+    x, y, z = cells % n, (cells // n) % n, cells // (n * n)
+    out = np.zeros((len(cells), 27), dtype=np.int64)
+    for i in range(27):
+        xs, ys, zs = (x - C[i, 0]) % n, (y - C[i, 1]) % n, (z - C[i, 2]) % n
+        out[:, i] = (zs * n + ys) * n + xs
+    return out
+
+
+def check_one_step(ens, samples, k, rng, tol):
+    """Advance one tick and compare sampled post-step populations with the oracle."""
+    pre = {}
+    for s in samples:
+        n = ens.samples[s].n
+        cells = rng.choice(n ** 3, size=k, replace=False)
+        nb = neighbours(n, cells)
+        fpre = ens.get_cells(s, nb.ravel()).cpu().numpy().reshape(k, 27, 27)
+        pre[s] = (cells, fpre)
+    steps_before = {s: ens.steps(s) for s in samples}
+    ens.step(1)
+    worst = 0.0
+    for s in samples:
+        if ens.steps(s) == steps_before[s]:
+            continue
+        smp = ens.samples[s]
+        om = oracle.omega_shear(oracle.lattice_viscosity(smp.n, smp.u0, smp.re))
+        cells, fpre = pre[s]
+        post = ens.get_cells(s, cells).cpu().numpy()
+        expect = np.zeros_like(post)
+        for kk in range(len(cells)):
+            for i in range(27):
+                fs, *_ = oracle.collide(fpre[kk, i], om)
+                expect[kk, i] = fs[i]
+        err = np.max(np.abs(post - expect)) / np.max(np.abs(expect - W))
+        worst = max(worst, err)
+        assert err < tol, (s, err)
+    return worst
+
+
+def full_ensemble(name):
+    wl = mc_inputs.WORKLOADS[name]
+    samples = []
+    for g in wl.groups:
+        samples += [mc.Sample(g.n, g.u0, g.re, g.amp, g.project, g.stride)] * g.count
+    ens = mc.Ensemble(samples, wl.precision)
+    ens.init(wl.seed)
+    return wl, ens
+
+
+def test_rtgv64x64_full_size_sampled_steps_and_invariants():
+    """64 x 64^3 FP32 in the autotuned launch shape the benchmark uses."""
+    wl, ens = full_ensemble("rtgv64x64_f32")
+    shape = ens.autotune(reps=1)
+    print("launch", shape)
+    rng = np.random.default_rng(64)
+    rec = ens.step(20, record_every=10).cpu().numpy()
+    worst = max(check_one_step(ens, [0, 31, 63], 48, rng, 2e-6),   # even parity (20 steps taken)
+                check_one_step(ens, [5, 40], 48, rng, 2e-6))        # odd parity
+    print(f"sampled one-step error (FP32, full size): {worst:.3e}")
+    rec2 = ens.step(480, record_every=50).cpu().numpy()
+    red = ens.reduce().cpu().numpy()
+    assert ens.check() == -1
+    n3 = 64 ** 3
+    allrec = np.concatenate([rec, rec2, red[None]], axis=0)
+    # mass and momentum conserved per sample (FP32 storage: rounding only)
+    assert np.max(np.abs(allrec[:, :, 0] - n3)) < 1e-6 * n3
+    assert np.max(np.abs(allrec[:, :, 1:4])) < 1e-6 * n3 * wl.groups[0].u0
+    # kinetic energy decays; the stabiliser is finite (the closed form is not
+    # clamped, so single nodes may leave [0, 2]) and its mean stays near the
+    # BGK value for this resolved flow
+    ke = allrec[:, :, 4]
+    assert np.all(ke[-1] < ke[1])
+    assert np.all(np.isfinite(allrec[:, :, 5:8]))
+    assert np.all(allrec[1:, :, 7] > 0.5) and np.all(allrec[1:, :, 7] < 2.5)
+
+
+def test_mixed48_full_size_sampled_steps():
+    """32 x 64^3 + 12 x 128^3 + 4 x 256^3 in one launch per tick, strides 16:4:1."""
+    wl, ens = full_ensemble("mixed48_f32")
+    ens.autotune(reps=1)
+    rng = np.random.default_rng(48)
+    ens.step(16)
+    # tick 16: every sample steps; tick 17: only the 256^3 samples
+    worst = max(check_one_step(ens, [0, 33, 45], 32, rng, 2e-6),
+                check_one_step(ens, [44, 47, 1], 32, rng, 2e-6))
+    print(f"sampled one-step error (mixed, full size): {worst:.3e}")
+    assert [ens.steps(s) for s in (0, 32, 44)] == [2, 5, 18]
+    ens.step(14)   # back to a tick where every sample steps (32)
+    rec = ens.step(16, record_every=16).cpu().numpy()[0]
+    assert ens.check() == -1
+    for s in (0, 32, 44):
+        n3 = ens.samples[s].n ** 3
+        assert abs(rec[s, 0] - n3) < 1e-6 * n3
+
+
+def test_fp64_full_size_sampled_steps():
+    """The plain single-sample FP64 method at 64^3."""
+    ens = mc.Ensemble([mc.Sample(64, 0.025, 1600.0, 0.05, True)], "f64")
+    ens.init(7)
+    ens.step(10)
+    rng = np.random.default_rng(7)
+    worst = max(check_one_step(ens, [0], 64, rng, 2e-13), check_one_step(ens, [0], 64, rng, 2e-13))
+    print(f"sampled one-step error (FP64): {worst:.3e}")
+
+
+def test_512_cubed_sample_sampled_steps():
+    """One 512^3 FP32 sample (14.5 GB of populations, pointer addressing)."""
+    n = 512
+    ens = mc.Ensemble([mc.Sample(n, 0.05 * 32 / n, 12.5 * n, 0.05, True)], "f32s")
+    ens.init(2611)
+    ens.step(2)
+    rng = np.random.default_rng(512)
+    worst = max(check_one_step(ens, [0], 32, rng, 2e-6), check_one_step(ens, [0], 32, rng, 2e-6))
+    print(f"sampled one-step error (512^3): {worst:.3e}")
+    red = ens.reduce().cpu().numpy()[0]
+    assert abs(red[0] - n ** 3) < 1e-6 * n ** 3
