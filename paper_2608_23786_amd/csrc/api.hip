@@ -168,6 +168,14 @@ mclbm_status validate_desc(int32_t m, const mclbm_sample_desc* d, int32_t precis
   return MCLBM_OK;
 }
 
+// Elements from one population plane to the next: n^3 plus a pad that keeps
+// the 27 plane addresses of a node off a common power-of-two stride.
+uint64_t plane_stride(int n, size_t elem) {
+  const uint64_t n3 = uint64_t(n) * n * n;
+  if (n3 * elem < (uint64_t(1) << 16)) return n3;
+  return n3 + kPlanePadBytes / elem;
+}
+
 struct Layout {
   size_t samples, flags, ycoef, pmat, tables, table_bytes, partials, partial_blocks, pop, state_bytes, total;
 };
@@ -194,7 +202,7 @@ Layout layout_of(int32_t m, const mclbm_sample_desc* d, int32_t precision) {
   off = align_up(off + L.partial_blocks * kRecord * sizeof(double));
   L.pop = off;
   size_t st = 0;
-  for (int s = 0; s < m; ++s) st = align_up(st + size_t(Q) * d[s].n * d[s].n * d[s].n * elem);
+  for (int s = 0; s < m; ++s) st = align_up(st + size_t(Q) * plane_stride(d[s].n, elem) * elem);
   L.state_bytes = st;
   off += st;
   L.total = off;
@@ -286,7 +294,7 @@ StepLaunch make_launch(mclbm_ctx* c, const Table* t, void* pop, void* dst) {
   L.buffer_ok = c->buffer_addr;
   L.nontemporal = c->nontemporal;
   for (int s = 0; s < c->m; ++s)
-    if (uint64_t(Q) * uint64_t(c->cells(s)) * c->elem >= (uint64_t(1) << 31)) L.buffer_ok = 0;
+    if (uint64_t(Q) * c->h_samples[s].pstride * c->elem >= (uint64_t(1) << 31)) L.buffer_ok = 0;
   return L;
 }
 
@@ -489,11 +497,12 @@ mclbm_status mclbm_create(mclbm_ctx** out, int32_t m, const mclbm_sample_desc* d
     h.offset = off / c->elem;
     h.n = desc[s].n;
     h.log2n = ilog2(desc[s].n);
+    h.pstride = uint32_t(plane_stride(desc[s].n, c->elem));
     h.u0 = desc[s].u0;
     h.amp = desc[s].amp;
     h.project = desc[s].project;
     fill_sample(c, s, lattice_nu(desc[s]));
-    off = align_up(off + size_t(Q) * c->cells(s) * c->elem);
+    off = align_up(off + size_t(Q) * h.pstride * c->elem);
     c->max_stride = std::max(c->max_stride, desc[s].stride);
   }
   hipError_t e = hipMemcpy(c->d_samples, c->h_samples.data(), sizeof(DevSample) * m, hipMemcpyHostToDevice);
@@ -807,6 +816,7 @@ mclbm_status mclbm_backward(mclbm_ctx* c, int64_t ticks, int32_t ckpt_every, con
   st = get_table(c, 0, true, c->block, true, &push);
   if (st != MCLBM_OK) return st;
 
+  const int32_t buffer_ok = make_launch(c, nat, c->pop, nullptr).buffer_ok;
   int cur = 0;
   const int64_t nseg = (ticks + ckpt_every - 1) / ckpt_every;
   for (int64_t k = nseg - 1; k >= 0; --k) {
@@ -822,7 +832,7 @@ mclbm_status mclbm_backward(mclbm_ctx* c, int64_t ticks, int32_t ckpt_every, con
     }
     for (int64_t n = n1 - 1; n >= n0; --n) {
       HIP_TRY(launch_adjoint_step(c->precision, state_at(n), lam[cur], lam[1 - cur], c->d_samples, table_ptr(c, nat),
-                                  nat->nseg, nat->total_blocks, c->stream));
+                                  nat->nseg, nat->total_blocks, buffer_ok, c->stream));
       cur = 1 - cur;
     }
   }

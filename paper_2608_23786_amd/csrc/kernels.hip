@@ -324,9 +324,9 @@ struct BufPlanes {
   static constexpr int aux = NT ? kAuxNontemporal : 0;
   __amdgpu_buffer_rsrc_t rsrc;
   uint32_t plane_bytes;
-  __device__ __forceinline__ BufPlanes(T* base, uint32_t ncell)
-      : rsrc(__builtin_amdgcn_make_buffer_rsrc(base, 0, int(uint32_t(Q) * ncell * uint32_t(sizeof(T))), kBufferFlags)),
-        plane_bytes(ncell * uint32_t(sizeof(T))) {}
+  __device__ __forceinline__ BufPlanes(T* base, uint32_t pstride)
+      : rsrc(__builtin_amdgcn_make_buffer_rsrc(base, 0, int(uint32_t(Q) * pstride * uint32_t(sizeof(T))), kBufferFlags)),
+        plane_bytes(pstride * uint32_t(sizeof(T))) {}
   __device__ __forceinline__ T load(int plane, uint32_t idx) const {
     if constexpr (sizeof(T) == 4)
       return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(rsrc, int(idx * 4u), int(plane * plane_bytes), aux));
@@ -348,46 +348,46 @@ struct BufPlanes {
 template <typename T, bool NT>
 struct PtrPlanes {
   T* base;
-  uint32_t ncell;
-  __device__ __forceinline__ PtrPlanes(T* b, uint32_t n) : base(b), ncell(n) {}
+  uint32_t pstride;
+  __device__ __forceinline__ PtrPlanes(T* b, uint32_t p) : base(b), pstride(p) {}
   __device__ __forceinline__ T load(int plane, uint32_t idx) const {
-    if constexpr (NT) return __builtin_nontemporal_load(base + size_t(plane) * ncell + idx);
-    else return ld(base + size_t(plane) * ncell, idx);
+    if constexpr (NT) return __builtin_nontemporal_load(base + size_t(plane) * pstride + idx);
+    else return ld(base + size_t(plane) * pstride, idx);
   }
   __device__ __forceinline__ void store(int plane, uint32_t idx, T v) const {
-    if constexpr (NT) __builtin_nontemporal_store(v, base + size_t(plane) * ncell + idx);
-    else st(base + size_t(plane) * ncell, idx, v);
+    if constexpr (NT) __builtin_nontemporal_store(v, base + size_t(plane) * pstride + idx);
+    else st(base + size_t(plane) * pstride, idx, v);
   }
 };
 
 // populations of the post-stream state at a node, for either AA parity
 template <typename T>
-__device__ __forceinline__ void load_state(const T* base, uint32_t ncell, const Cell& c, bool odd, T (&g)[Q]) {
+__device__ __forceinline__ void load_state(const T* base, uint32_t pstride, const Cell& c, bool odd, T (&g)[Q]) {
   if (!odd) {
     static_for<0, Q>([&](auto ic) {
       constexpr int i = decltype(ic)::value;
-      g[i] = ld(base + size_t(i) * ncell, c.cell);
+      g[i] = ld(base + size_t(i) * pstride, c.cell);
     });
   } else {
     static_for<0, Q>([&](auto ic) {
       constexpr int i = decltype(ic)::value;
-      g[i] = ld(base + size_t(opposite(i)) * ncell, neighbour<i, -1>(c));
+      g[i] = ld(base + size_t(opposite(i)) * pstride, neighbour<i, -1>(c));
     });
   }
 }
 
 // the inverse mapping: write a post-stream state at a node
 template <typename T>
-__device__ __forceinline__ void write_state(T* base, uint32_t ncell, const Cell& c, bool odd, const T (&g)[Q]) {
+__device__ __forceinline__ void write_state(T* base, uint32_t pstride, const Cell& c, bool odd, const T (&g)[Q]) {
   if (!odd) {
     static_for<0, Q>([&](auto ic) {
       constexpr int i = decltype(ic)::value;
-      st(base + size_t(i) * ncell, c.cell, g[i]);
+      st(base + size_t(i) * pstride, c.cell, g[i]);
     });
   } else {
     static_for<0, Q>([&](auto ic) {
       constexpr int i = decltype(ic)::value;
-      st(base + size_t(opposite(i)) * ncell, neighbour<i, -1>(c), g[i]);
+      st(base + size_t(opposite(i)) * pstride, neighbour<i, -1>(c), g[i]);
     });
   }
 }
@@ -476,10 +476,9 @@ __global__ void __launch_bounds__(BLOCK) kbc_step_kernel(StepArgs<T> a) {
   const Seg sg = a.segs[find_segment(a.segs, a.nseg, b)];
   const DevSample& sp = a.samples[sg.sample];
   const int l = sp.log2n;
-  const uint32_t ncell = 1u << (3 * l);
   const Cell c = make_cell(uint32_t(b - sg.first_block) * BLOCK + threadIdx.x, l);
   using Planes = typename std::conditional<BUF, BufPlanes<T, NT>, PtrPlanes<T, NT>>::type;
-  const Planes src(a.pop + sp.offset, ncell);
+  const Planes src(a.pop + sp.offset, sp.pstride);
   const bool odd = (KIND != kPush) && (sg.parity & 1);
 
   T g[Q];
@@ -510,7 +509,7 @@ __global__ void __launch_bounds__(BLOCK) kbc_step_kernel(StepArgs<T> a) {
       });
     }
   } else if constexpr (KIND == kPush) {
-    const Planes dst(a.dst + sp.offset, ncell);
+    const Planes dst(a.dst + sp.offset, sp.pstride);
     static_for<0, Q>([&](auto ic) {
       constexpr int i = decltype(ic)::value;
       dst.store(i, neighbour<i, +1>(c), g[i]);
@@ -596,7 +595,6 @@ __global__ void __launch_bounds__(256)
   const Seg sg = segs[find_segment(segs, nseg, b)];
   const DevSample& sp = samples[sg.sample];
   const int l = sp.log2n;
-  const uint32_t ncell = 1u << (3 * l);
   const uint32_t cell = uint32_t(b - sg.first_block) * 256u + threadIdx.x;
   double u[3];
   Basis bs;
@@ -607,7 +605,7 @@ __global__ void __launch_bounds__(256)
     constexpr int i = decltype(ic)::value;
     const double cu = double(cx(i)) * u[0] + double(cy(i)) * u[1] + double(cz(i)) * u[2];
     const double gi = weight(i) * (3.0 * cu + 4.5 * cu * cu - usq15);
-    st(base + size_t(i) * ncell, cell, T(gi));
+    st(base + size_t(i) * sp.pstride, cell, T(gi));
   });
 }
 
@@ -620,7 +618,7 @@ __global__ void __launch_bounds__(256)
   const uint32_t ncell = 1u << (3 * l);
   const Cell c = make_cell(blockIdx.x * 256u + threadIdx.x, l);
   T g[Q];
-  load_state(pop + sp.offset, ncell, c, parity & 1, g);
+  load_state(pop + sp.offset, sp.pstride, c, parity & 1, g);
   double d = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
   static_for<0, Q>([&](auto ic) {
     constexpr int i = decltype(ic)::value;
@@ -647,7 +645,7 @@ __global__ void __launch_bounds__(256)
   const uint32_t ncell = 1u << (3 * l);
   const Cell c = make_cell(blockIdx.x * 256u + threadIdx.x, l);
   T g[Q];
-  load_state(pop + sp.offset, ncell, c, parity & 1, g);
+  load_state(pop + sp.offset, sp.pstride, c, parity & 1, g);
   static_for<0, Q>([&](auto ic) {
     constexpr int i = decltype(ic)::value;
     f[size_t(i) * ncell + c.cell] = weight(i) + double(g[i]);
@@ -666,7 +664,7 @@ __global__ void __launch_bounds__(256)
     constexpr int i = decltype(ic)::value;
     g[i] = T(f[size_t(i) * ncell + c.cell] - weight(i));
   });
-  write_state(pop + sp.offset, ncell, c, parity & 1, g);
+  write_state(pop + sp.offset, sp.pstride, c, parity & 1, g);
 }
 
 // Populations (unshifted, double) of selected cells of one sample: f[k][27].
@@ -678,10 +676,9 @@ __global__ void __launch_bounds__(64)
   if (k >= count) return;
   const DevSample& sp = samples[sample];
   const int l = sp.log2n;
-  const uint32_t ncell = 1u << (3 * l);
   const Cell c = make_cell(uint32_t(cells[k]), l);
   T g[Q];
-  load_state(pop + sp.offset, ncell, c, parity & 1, g);
+  load_state(pop + sp.offset, sp.pstride, c, parity & 1, g);
   static_for<0, Q>([&](auto ic) {
     constexpr int i = decltype(ic)::value;
     f[size_t(k) * Q + i] = weight(i) + double(g[i]);
@@ -692,16 +689,15 @@ template <typename T>
 __global__ void poison_kernel(T* pop, const DevSample* samples, int sample, int parity, uint32_t cell, int i) {
   const DevSample& sp = samples[sample];
   const int l = sp.log2n;
-  const uint32_t ncell = 1u << (3 * l);
   const Cell c = make_cell(cell, l);
   T* base = pop + sp.offset;
   const T nan = T(__builtin_nan(""));
   // slot of population i of this node (see load_state)
   if (!(parity & 1)) {
-    base[size_t(i) * ncell + cell] = nan;
+    base[size_t(i) * sp.pstride + cell] = nan;
   } else {
     const uint32_t nb = c.oz[1 - cz(i)] + c.oy[1 - cy(i)] + c.ox[1 - cx(i)];
-    base[size_t(opposite(i)) * ncell + nb] = nan;
+    base[size_t(opposite(i)) * sp.pstride + nb] = nan;
   }
 }
 
@@ -712,11 +708,10 @@ __global__ void __launch_bounds__(256)
   const Seg sg = segs[find_segment(segs, nseg, b)];
   const DevSample& sp = samples[sg.sample];
   const int l = sp.log2n;
-  const uint32_t ncell = 1u << (3 * l);
   const Cell c = make_cell(uint32_t(b - sg.first_block) * 256u + threadIdx.x, l);
   T g[Q];
-  load_state(pop + sp.offset, ncell, c, sg.parity & 1, g);
-  write_state(dst + sp.offset, ncell, c, false, g);
+  load_state(pop + sp.offset, sp.pstride, c, sg.parity & 1, g);
+  write_state(dst + sp.offset, sp.pstride, c, false, g);
 }
 
 // ---------------------------------------------------------------- adjoint
@@ -732,7 +727,7 @@ __global__ void __launch_bounds__(256) adjoint_seed_kernel(const T* pop, T* lam,
   const uint32_t ncell = 1u << (3 * l);
   const Cell c = make_cell(uint32_t(b - sg.first_block) * 256u + threadIdx.x, l);
   T g[Q];
-  load_state(pop + sp.offset, ncell, c, sg.parity & 1, g);
+  load_state(pop + sp.offset, sp.pstride, c, sg.parity & 1, g);
   double d = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
   static_for<0, Q>([&](auto ic) {
     constexpr int i = decltype(ic)::value;
@@ -750,29 +745,32 @@ __global__ void __launch_bounds__(256) adjoint_seed_kernel(const T* pop, T* lam,
   static_for<0, Q>([&](auto ic) {
     constexpr int i = decltype(ic)::value;
     const double cu = double(cx(i)) * ux + double(cy(i)) * uy + double(cz(i)) * uz;
-    st(lb + size_t(i) * ncell, c.cell, T(coef * (cu - usq)));
+    st(lb + size_t(i) * sp.pstride, c.cell, T(coef * (cu - usq)));
   });
 }
 
 // One reverse step: lambda_n(x) = (d collide / d g_n(x))^T [lambda_{n+1, i}(x + c_i)]_i,
 // the transpose of "collide at x, then move population i to x + c_i".
-template <typename T>
+template <typename T, bool BUF>
 __global__ void __launch_bounds__(256) adjoint_step_kernel(const T* state, const T* lam_in, T* lam_out,
                                                            const DevSample* samples, const Seg* segs, int nseg) {
   const int b = blockIdx.x;
   const Seg sg = segs[find_segment(segs, nseg, b)];
   const DevSample& sp = samples[sg.sample];
   const int l = sp.log2n;
-  const uint32_t ncell = 1u << (3 * l);
   const Cell c = make_cell(uint32_t(b - sg.first_block) * 256u + threadIdx.x, l);
   const Relax<T> rp = relax_of<T>(sp);
+  // every array is streamed once per reverse step: non-temporal accesses
+  using Planes = typename std::conditional<BUF, BufPlanes<T, true>, PtrPlanes<T, true>>::type;
+  const Planes st_in(const_cast<T*>(state) + sp.offset, sp.pstride);
+  const Planes lam_src(const_cast<T*>(lam_in) + sp.offset, sp.pstride);
+  const Planes lam_dst(lam_out + sp.offset, sp.pstride);
 
   T g[Q], nu[Q];
-  load_state(state + sp.offset, ncell, c, false, g);
-  const T* lb = lam_in + sp.offset;
   static_for<0, Q>([&](auto ic) {
     constexpr int i = decltype(ic)::value;
-    nu[i] = ld(lb + size_t(i) * ncell, neighbour<i, +1>(c));
+    g[i] = st_in.load(i, c.cell);
+    nu[i] = lam_src.load(i, neighbour<i, +1>(c));
   });
 
   // forward intermediates, as in kbc_collide
@@ -889,14 +887,13 @@ __global__ void __launch_bounds__(256) adjoint_step_kernel(const T* state, const
   jyb -= T(3) * m.inv * S * m.jy;
   jzb -= T(3) * m.inv * S * m.jz;
   const T drhob = S - m.inv * m.inv * invb;
-  T* lo = lam_out + sp.offset;
   static_for<0, Q>([&](auto ic) {
     constexpr int i = decltype(ic)::value;
     T v = nu[i] + fbar[i] + drhob;
     if constexpr (cx(i) != 0) v += signed_term<cx(i)>(jxb);
     if constexpr (cy(i) != 0) v += signed_term<cy(i)>(jyb);
     if constexpr (cz(i) != 0) v += signed_term<cz(i)>(jzb);
-    st(lo + size_t(i) * ncell, c.cell, v);
+    lam_dst.store(i, c.cell, v);
   });
 }
 
@@ -909,7 +906,6 @@ __global__ void __launch_bounds__(256) init_adjoint_kernel(const T* lam, const D
   const Seg sg = segs[find_segment(segs, nseg, b)];
   const DevSample& sp = samples[sg.sample];
   const int l = sp.log2n;
-  const uint32_t ncell = 1u << (3 * l);
   const uint32_t cell = uint32_t(b - sg.first_block) * 256u + threadIdx.x;
   double u[3];
   Basis bs;
@@ -918,7 +914,7 @@ __global__ void __launch_bounds__(256) init_adjoint_kernel(const T* lam, const D
   double ub[3] = {0.0, 0.0, 0.0};
   static_for<0, Q>([&](auto ic) {
     constexpr int i = decltype(ic)::value;
-    const double li = double(ld(lb + size_t(i) * ncell, cell)) * weight(i);
+    const double li = double(ld(lb + size_t(i) * sp.pstride, cell)) * weight(i);
     const double cu = double(cx(i)) * u[0] + double(cy(i)) * u[1] + double(cz(i)) * u[2];
     ub[0] += li * (3.0 * cx(i) + 9.0 * cu * cx(i) - 3.0 * u[0]);
     ub[1] += li * (3.0 * cy(i) + 9.0 * cu * cy(i) - 3.0 * u[1]);
@@ -1135,18 +1131,28 @@ hipError_t launch_adjoint_seed(int precision, const void* pop, void* lam, const 
   return hipGetLastError();
 }
 
+template <typename T>
+hipError_t launch_adjoint_step_t(const void* state, const void* lam_in, void* lam_out, const DevSample* samples,
+                                 const Seg* segs, int32_t nseg, int32_t total_blocks, int32_t buffer_ok,
+                                 hipStream_t s) {
+  const T* a = static_cast<const T*>(state);
+  const T* b = static_cast<const T*>(lam_in);
+  T* o = static_cast<T*>(lam_out);
+  if (buffer_ok)
+    hipLaunchKernelGGL((adjoint_step_kernel<T, true>), dim3(total_blocks), dim3(256), 0, s, a, b, o, samples, segs,
+                       nseg);
+  else
+    hipLaunchKernelGGL((adjoint_step_kernel<T, false>), dim3(total_blocks), dim3(256), 0, s, a, b, o, samples, segs,
+                       nseg);
+  return hipGetLastError();
+}
+
 hipError_t launch_adjoint_step(int precision, const void* state, const void* lam_in, void* lam_out,
                                const DevSample* samples, const Seg* segs, int32_t nseg, int32_t total_blocks,
-                               hipStream_t s) {
+                               int32_t buffer_ok, hipStream_t s) {
   if (precision == 0)
-    hipLaunchKernelGGL(adjoint_step_kernel<double>, dim3(total_blocks), dim3(256), 0, s,
-                       static_cast<const double*>(state), static_cast<const double*>(lam_in),
-                       static_cast<double*>(lam_out), samples, segs, nseg);
-  else
-    hipLaunchKernelGGL(adjoint_step_kernel<float>, dim3(total_blocks), dim3(256), 0, s,
-                       static_cast<const float*>(state), static_cast<const float*>(lam_in),
-                       static_cast<float*>(lam_out), samples, segs, nseg);
-  return hipGetLastError();
+    return launch_adjoint_step_t<double>(state, lam_in, lam_out, samples, segs, nseg, total_blocks, buffer_ok, s);
+  return launch_adjoint_step_t<float>(state, lam_in, lam_out, samples, segs, nseg, total_blocks, buffer_ok, s);
 }
 
 hipError_t launch_init_adjoint(int precision, const void* lam, const DevSample* samples, const Seg* segs,

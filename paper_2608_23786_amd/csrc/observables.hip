@@ -216,7 +216,6 @@ __global__ void __launch_bounds__(64) point_values_kernel(const T* pop, const De
   const DevSample& sp = samples[sg.sample];
   const int l = sp.log2n;
   const int n = 1 << l;
-  const uint32_t ncell = 1u << (3 * l);
   const int q3 = q * q * q;
   const int j = blockIdx.x * 64 + threadIdx.x;
   if (j >= q3) return;
@@ -239,7 +238,7 @@ __global__ void __launch_bounds__(64) point_values_kernel(const T* pop, const De
       idx = (size_t(zs) << (2 * l)) + (size_t(ys) << l) + xs;
       slot = opposite(i);
     }
-    const double v = double(base[size_t(slot) * ncell + idx]);
+    const double v = double(base[size_t(slot) * sp.pstride + idx]);
     d += v;
     jxs += cx(i) * v;
     jys += cy(i) * v;
