@@ -24,8 +24,11 @@ Contents and the passage each part follows:
     (SF_single_spec2); 1-point Wasserstein distance between equal-size
     empirical laws by sorted rearrangement, eq. (wassersteinPermutations).
 
+Lattices: D3Q27 (q = 27, the default) and the paper's D3Q19 (q = 19).
+
 Array conventions: fields are C-ordered [z][y][x] (x fastest); populations
-f[cell][27] with i = 9*(cx+1) + 3*(cy+1) + (cz+1); velocities u[3][z][y][x].
+f[cell][q] with, for D3Q27, i = 9*(cx+1) + 3*(cy+1) + (cz+1), and for D3Q19
+the same order without the eight corner velocities; velocities u[3][z][y][x].
 """
 import ctypes
 import math
@@ -53,41 +56,58 @@ def lib():
             from . import build as _b
             _b.build()
         L = ctypes.CDLL(path)
-        L.oracle_velocity_set.argtypes = [_ip, _dp]
-        L.oracle_moment_basis.argtypes = [_dp, _dp, _ip]
-        L.oracle_equilibrium.argtypes = [ctypes.c_double, _dp, _dp]
-        L.oracle_collide.argtypes = [_dp, ctypes.c_double, ctypes.c_int32, _dp, _dp, _dp, _dp]
-        L.oracle_collide_z.argtypes = [_dp, ctypes.c_double, _dp, _dp]
-        L.oracle_run.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_double, ctypes.c_int32, _dp, _dp,
+        _q = ctypes.c_int32
+        L.oracle_velocity_set.argtypes = [_q, _ip, _dp]
+        L.oracle_moment_basis.argtypes = [_q, _dp, _dp, _ip]
+        L.oracle_equilibrium.argtypes = [_q, ctypes.c_double, _dp, _dp]
+        L.oracle_collide.argtypes = [_q, _dp, ctypes.c_double, ctypes.c_int32, _dp, _dp, _dp, _dp]
+        L.oracle_collide_z.argtypes = [_q, _dp, ctypes.c_double, _dp, _dp]
+        L.oracle_run.argtypes = [_q, ctypes.c_int32, ctypes.c_int32, ctypes.c_double, ctypes.c_int32, _dp, _dp,
                                  ctypes.c_int32]
-        L.oracle_run_z.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_double, _dp, ctypes.c_int32]
-        L.oracle_init_field.argtypes = [ctypes.c_int64, _dp, _dp]
-        L.oracle_init_field_z.argtypes = [ctypes.c_int64, _dp, _dp]
+        L.oracle_run_z.argtypes = [_q, ctypes.c_int32, ctypes.c_int32, ctypes.c_double, _dp, ctypes.c_int32]
+        L.oracle_init_field.argtypes = [_q, ctypes.c_int64, _dp, _dp]
+        L.oracle_init_field_z.argtypes = [_q, ctypes.c_int64, _dp, _dp]
+        for name in ("oracle_velocity_set", "oracle_moment_basis", "oracle_equilibrium", "oracle_collide",
+                     "oracle_collide_z", "oracle_run", "oracle_run_z", "oracle_init_field", "oracle_init_field_z"):
+            getattr(L, name).restype = ctypes.c_int32
         L.oracle_max_threads.restype = ctypes.c_int32
         _LIB = L
     return _LIB
 
 
 # ---------------------------------------------------------------- lattice
-def velocity_set():
-    c = np.zeros((27, 3), dtype=np.int32)
-    w = np.zeros(27)
-    lib().oracle_velocity_set(_ptr(c, _ip), _ptr(w))
+LATTICES = (27, 19)
+
+
+def _lat(q):
+    if q not in LATTICES:
+        raise ValueError(f"unknown lattice: {q} velocities")
+    return q
+
+
+def _ok(rc):
+    assert rc == 1, "oracle call rejected its lattice"
+
+
+def velocity_set(q=27):
+    c = np.zeros((_lat(q), 3), dtype=np.int32)
+    w = np.zeros(q)
+    _ok(lib().oracle_velocity_set(q, _ptr(c, _ip), _ptr(w)))
     return c, w
 
 
-def moment_basis():
-    M = np.zeros((27, 27))
-    Minv = np.zeros((27, 27))
-    g = np.zeros(27, dtype=np.int32)
-    lib().oracle_moment_basis(_ptr(M), _ptr(Minv), _ptr(g, _ip))
+def moment_basis(q=27):
+    M = np.zeros((_lat(q), q))
+    Minv = np.zeros((q, q))
+    g = np.zeros(q, dtype=np.int32)
+    _ok(lib().oracle_moment_basis(q, _ptr(M), _ptr(Minv), _ptr(g, _ip)))
     return M, Minv, g
 
 
-def equilibrium(rho, u):
+def equilibrium(rho, u, q=27):
     u = np.ascontiguousarray(u, dtype=np.float64)
-    feq = np.zeros(27)
-    lib().oracle_equilibrium(float(rho), _ptr(u), _ptr(feq))
+    feq = np.zeros(_lat(q))
+    _ok(lib().oracle_equilibrium(q, float(rho), _ptr(u), _ptr(feq)))
     return feq
 
 
@@ -95,21 +115,23 @@ MODE_KBC, MODE_BGK, MODE_EXACT = 0, 1, 2
 
 
 def collide(f, omega, mode=MODE_KBC):
-    """One collision at one node. Returns (f*, gamma, ds, dh)."""
+    """One collision at one node (the lattice from len(f)). Returns (f*, gamma, ds, dh)."""
     f = np.ascontiguousarray(f, dtype=np.float64)
-    fs = np.zeros(27)
-    ds = np.zeros(27)
-    dh = np.zeros(27)
+    q = _lat(f.shape[0])
+    fs = np.zeros(q)
+    ds = np.zeros(q)
+    dh = np.zeros(q)
     g = np.zeros(1)
-    lib().oracle_collide(_ptr(f), float(omega), int(mode), _ptr(fs), _ptr(g), _ptr(ds), _ptr(dh))
+    _ok(lib().oracle_collide(q, _ptr(f), float(omega), int(mode), _ptr(fs), _ptr(g), _ptr(ds), _ptr(dh)))
     return fs, float(g[0]), ds, dh
 
 
 def collide_complex(f, omega):
     f = np.ascontiguousarray(f, dtype=np.complex128)
-    fs = np.zeros(27, dtype=np.complex128)
+    q = _lat(f.shape[0])
+    fs = np.zeros(q, dtype=np.complex128)
     g = np.zeros(1, dtype=np.complex128)
-    lib().oracle_collide_z(_ptr(f), float(omega), _ptr(fs), _ptr(g))
+    _ok(lib().oracle_collide_z(q, _ptr(f), float(omega), _ptr(fs), _ptr(g)))
     return fs, g[0]
 
 
@@ -193,37 +215,38 @@ def initial_velocity(n, u0, amp, y, project):
     return u0 * (taylor_green(n) + amp * s)
 
 
-def equilibrium_field(u):
-    """eq. (initialPopulations): f = f^eq(1, u) at every node -> f[ncell][27]."""
+def equilibrium_field(u, q=27):
+    """eq. (initialPopulations): f = f^eq(1, u) at every node -> f[ncell][q]."""
     n = u.shape[1]
     ncell = n ** 3
     if np.iscomplexobj(u):
         uu = np.ascontiguousarray(u.reshape(3, ncell), dtype=np.complex128)
-        f = np.zeros((ncell, 27), dtype=np.complex128)
-        lib().oracle_init_field_z(ncell, _ptr(uu), _ptr(f))
+        f = np.zeros((ncell, _lat(q)), dtype=np.complex128)
+        _ok(lib().oracle_init_field_z(q, ncell, _ptr(uu), _ptr(f)))
     else:
         uu = np.ascontiguousarray(u.reshape(3, ncell), dtype=np.float64)
-        f = np.zeros((ncell, 27))
-        lib().oracle_init_field(ncell, _ptr(uu), _ptr(f))
+        f = np.zeros((ncell, _lat(q)))
+        _ok(lib().oracle_init_field(q, ncell, _ptr(uu), _ptr(f)))
     return f
 
 
-def init_populations(n, u0, amp, y, project):
-    return equilibrium_field(initial_velocity(n, u0, amp, y, project))
+def init_populations(n, u0, amp, y, project, q=27):
+    return equilibrium_field(initial_velocity(n, u0, amp, y, project), q)
 
 
 # ---------------------------------------------------------------- time stepping
 def run(f, n, steps, omega, mode=MODE_KBC, threads=0, gamma_stats=False):
-    """Advance f[ncell][27] in place by `steps` steps; optionally return the
-    per-step (min, max, mean) of gamma."""
-    assert f.shape == (n ** 3, 27) and f.flags.c_contiguous
+    """Advance f[ncell][q] in place by `steps` steps (the lattice from the
+    second dimension); optionally return the per-step (min, max, mean) of gamma."""
+    q = _lat(f.shape[1])
+    assert f.shape == (n ** 3, q) and f.flags.c_contiguous
     gs = np.zeros((max(steps, 1), 3)) if gamma_stats else None
     if np.iscomplexobj(f):
         assert mode == MODE_KBC
-        lib().oracle_run_z(n, steps, float(omega), _ptr(f), int(threads))
+        _ok(lib().oracle_run_z(q, n, steps, float(omega), _ptr(f), int(threads)))
     else:
-        lib().oracle_run(n, steps, float(omega), int(mode), _ptr(f), _ptr(gs) if gs is not None else None,
-                         int(threads))
+        _ok(lib().oracle_run(q, n, steps, float(omega), int(mode), _ptr(f), _ptr(gs) if gs is not None else None,
+                             int(threads)))
     return gs[:steps] if gs is not None else None
 
 
@@ -234,7 +257,7 @@ def max_threads():
 # ---------------------------------------------------------------- moments and reductions
 def moments(f, n):
     """rho[z][y][x], u[3][z][y][x] with rho = sum f, rho u = sum c f."""
-    c, _ = velocity_set()
+    c, _ = velocity_set(f.shape[1])
     rho = f.sum(axis=1)
     j = f @ c.astype(np.float64)
     u = (j / rho[:, None]).T
@@ -249,14 +272,14 @@ def kinetic_energy(u):
 
 def reductions(f, n):
     """mass, jx, jy, jz (sums over nodes), kinetic energy."""
-    c, _ = velocity_set()
+    c, _ = velocity_set(f.shape[1])
     rho, u = moments(f, n)
     j = f @ c.astype(np.float64)
     return np.array([rho.sum(), j[:, 0].sum(), j[:, 1].sum(), j[:, 2].sum(), kinetic_energy(u)])
 
 
 # ---------------------------------------------------------------- gradient reference
-def ke_gradient_complex_step(n, u0, re, amp, y, project, steps, h=1e-30, threads=0, params=None):
+def ke_gradient_complex_step(n, u0, re, amp, y, project, steps, h=1e-30, threads=0, params=None, q=27):
     """d KE(T) / d Y_p for one sample by the complex step Im KE(Y + i h e_p) / h."""
     omega = omega_shear(lattice_viscosity(n, u0, re))
     params = range(24) if params is None else params
@@ -264,16 +287,16 @@ def ke_gradient_complex_step(n, u0, re, amp, y, project, steps, h=1e-30, threads
     for p in params:
         yc = np.asarray(y, dtype=np.complex128).copy()
         yc[p] += 1j * h
-        f = init_populations(n, u0, amp, yc, project)
+        f = init_populations(n, u0, amp, yc, project, q)
         run(f, n, steps, omega, threads=threads)
         _, u = moments(f, n)
         grad[p] = kinetic_energy(u).imag / h
     return grad
 
 
-def ke_after(n, u0, re, amp, y, project, steps, threads=0):
+def ke_after(n, u0, re, amp, y, project, steps, threads=0, q=27):
     omega = omega_shear(lattice_viscosity(n, u0, re))
-    f = init_populations(n, u0, amp, np.asarray(y, dtype=np.float64), project)
+    f = init_populations(n, u0, amp, np.asarray(y, dtype=np.float64), project, q)
     run(f, n, steps, omega, threads=threads)
     _, u = moments(f, n)
     return float(kinetic_energy(u))

@@ -8,7 +8,9 @@
 //
 // What it follows (paper section "Deterministic numerical methodology"):
 //   * the D3Q27 velocity set (tensor product of the 1-D {-1,0,1} set with
-//     weights 2/3, 1/6, 1/6), speed of sound c_s^2 = 1/3;
+//     weights 2/3, 1/6, 1/6), speed of sound c_s^2 = 1/3, or the paper's own
+//     D3Q19 set (the 19 of those velocities with at most two non-zero
+//     components, with the usual D3Q19 weights 1/3, 1/18, 1/36);
 //   * the second-order truncated equilibrium, eq. (equilibrium);
 //   * density and momentum as the zeroth and first moments;
 //   * the multi-relaxation form J = -M^{-1} S M (f - f^eq), eqs.
@@ -22,12 +24,15 @@
 //     H-function, eq. (kbc_entropy), by bisection on its derivative;
 //   * periodic streaming, eq. (lbIteration), done as a two-lattice pull.
 //
-// Reading of the paper for D3Q27 (the paper uses D3Q19 and defers the
-// moment basis to an earlier work): the 27 raw moments M_pqr, p,q,r in
-// {0,1,2}; the three diagonal second moments are replaced by the trace T and
-// the differences Nxz = M200 - M002, Nyz = M020 - M002. Kinematic group:
-// M000, M100, M010, M001. Shear group: Nxz, Nyz, M110, M101, M011. Hom group:
-// T and the 17 raw moments of order 3 to 6.
+// Moment basis (the paper defers the tensors of Table 1 to an earlier work):
+// the raw moments M_pqr, p,q,r in {0,1,2}, that do not vanish identically on
+// the velocity set (all 27 for D3Q27; for D3Q19 the 19 with at most two
+// non-zero exponents); the three diagonal second moments are replaced by the
+// trace T and the differences Nxz = M200 - M002, Nyz = M020 - M002.
+// Kinematic group: M000, M100, M010, M001. Shear group: Nxz, Nyz, M110,
+// M101, M011. Hom group: T and the remaining raw moments of order >= 3
+// (17 of order 3 to 6 for D3Q27; for D3Q19 the 6 of order 3 and the 3 of
+// order 4, the Q and A tensors of Table 1).
 //
 // When <dh|dh> <= 1e-30 the closed form is undefined; gamma = 2 (BGK) is
 // used then. The hom part is zero in that case up to rounding.
@@ -36,13 +41,15 @@
 // (every operation below is analytic in the populations; the threshold test
 // looks at the real part only).
 //
-// State layout at this interface: f[cell][i], cell = (z*n + y)*n + x,
-// i = 9*(cx+1) + 3*(cy+1) + (cz+1).
+// State layout at this interface: f[cell][i], cell = (z*n + y)*n + x. D3Q27:
+// i = 9*(cx+1) + 3*(cy+1) + (cz+1). D3Q19: the same order with the eight
+// corner velocities left out (so the opposite of i is q-1-i in both).
 
 #include <cmath>
 #include <complex>
 #include <cstdint>
 #include <cstring>
+#include <type_traits>
 #include <vector>
 
 #ifdef _OPENMP
@@ -51,29 +58,36 @@
 
 namespace {
 
-constexpr int Q = 27;
 using cplx = std::complex<double>;
 
 inline double re(double v) { return v; }
 inline double re(const cplx& v) { return v.real(); }
 
+template <int Q>
 struct VelocitySet {
   int c[Q][3];
   double w[Q];
   VelocitySet() {
     const double w1[3] = {1.0 / 6.0, 2.0 / 3.0, 1.0 / 6.0};  // 1-D weights of -1, 0, +1
-    for (int i = 0; i < Q; ++i) {
+    // D3Q19 weights by number of non-zero components (rest, axis, diagonal)
+    const double w19[3] = {1.0 / 3.0, 1.0 / 18.0, 1.0 / 36.0};
+    int k = 0;
+    for (int i = 0; i < 27; ++i) {
       int a = i / 9, b = (i / 3) % 3, d = i % 3;
-      c[i][0] = a - 1;
-      c[i][1] = b - 1;
-      c[i][2] = d - 1;
-      w[i] = w1[a] * w1[b] * w1[d];
+      int nz = (a != 1) + (b != 1) + (d != 1);
+      if (Q == 19 && nz == 3) continue;
+      c[k][0] = a - 1;
+      c[k][1] = b - 1;
+      c[k][2] = d - 1;
+      w[k] = (Q == 27) ? w1[a] * w1[b] * w1[d] : w19[nz];
+      ++k;
     }
   }
 };
 
-const VelocitySet& vs() {
-  static const VelocitySet v;
+template <int Q>
+const VelocitySet<Q>& vs() {
+  static const VelocitySet<Q> v;
   return v;
 }
 
@@ -84,21 +98,26 @@ int ipow(int base, int e) {
 }
 
 // Moment matrix in the kinematic / shear / hom basis and its inverse.
+template <int Q>
 struct MomentBasis {
   double M[Q][Q];
   double Minv[Q][Q];
   int group[Q];  // 0 kinematic, 1 shear, 2 hom
+  bool complete = false;
 
   MomentBasis() {
-    const VelocitySet& v = vs();
+    const VelocitySet<Q>& v = vs<Q>();
     // raw monomial rows, indexed by exponents (p, q, r)
     auto raw = [&](int p, int q, int r, int i) {
       return double(ipow(v.c[i][0], p) * ipow(v.c[i][1], q) * ipow(v.c[i][2], r));
     };
     int row = 0;
     auto put_raw = [&](int p, int q, int r, int g) {
-      for (int i = 0; i < Q; ++i) M[row][i] = raw(p, q, r, i);
-      group[row++] = g;
+      if (row < Q) {
+        for (int i = 0; i < Q; ++i) M[row][i] = raw(p, q, r, i);
+        group[row] = g;
+      }
+      ++row;
     };
     // kinematic
     put_raw(0, 0, 0, 0);
@@ -114,13 +133,19 @@ struct MomentBasis {
     put_raw(1, 0, 1, 1);
     put_raw(0, 1, 1, 1);
     // hom: trace of the second moment, then every raw moment of order >= 3
+    // that does not vanish on the whole velocity set
     for (int i = 0; i < Q; ++i) M[row][i] = raw(2, 0, 0, i) + raw(0, 2, 0, i) + raw(0, 0, 2, i);
     group[row++] = 2;
     for (int p = 0; p <= 2; ++p)
       for (int q = 0; q <= 2; ++q)
-        for (int r = 0; r <= 2; ++r)
-          if (p + q + r >= 3) put_raw(p, q, r, 2);
-    invert();
+        for (int r = 0; r <= 2; ++r) {
+          if (p + q + r < 3) continue;
+          bool nonzero = false;
+          for (int i = 0; i < Q; ++i) nonzero = nonzero || raw(p, q, r, i) != 0.0;
+          if (nonzero) put_raw(p, q, r, 2);
+        }
+    complete = row == Q;
+    if (complete) invert();
   }
 
   // Gauss-Jordan elimination with partial pivoting.
@@ -148,15 +173,16 @@ struct MomentBasis {
   }
 };
 
-const MomentBasis& basis() {
-  static const MomentBasis b;
+template <int Q>
+const MomentBasis<Q>& basis() {
+  static const MomentBasis<Q> b;
   return b;
 }
 
 // eq. (equilibrium) with c_s^2 = 1/3
-template <class T>
+template <int Q, class T>
 void equilibrium(const T& rho, const T u[3], T feq[Q]) {
-  const VelocitySet& v = vs();
+  const VelocitySet<Q>& v = vs<Q>();
   T usq = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
   for (int i = 0; i < Q; ++i) {
     T cu = double(v.c[i][0]) * u[0] + double(v.c[i][1]) * u[1] + double(v.c[i][2]) * u[2];
@@ -164,9 +190,9 @@ void equilibrium(const T& rho, const T u[3], T feq[Q]) {
   }
 }
 
-template <class T>
+template <int Q, class T>
 void density_velocity(const T f[Q], T& rho, T u[3]) {
-  const VelocitySet& v = vs();
+  const VelocitySet<Q>& v = vs<Q>();
   rho = 0.0;
   T j[3] = {0.0, 0.0, 0.0};
   for (int i = 0; i < Q; ++i) {
@@ -180,8 +206,9 @@ void density_velocity(const T f[Q], T& rho, T u[3]) {
 // H(f*) = sum f*_i ln(f*_i / w_i), f*(gamma') = f - omega ds - (omega gamma'/2) dh.
 // H is convex in gamma'; its derivative is -(omega/2) sum dh_i (ln(f*_i/w_i) + 1).
 // Bisection on the derivative inside the interval where every f*_i > 0.
+template <int Q>
 double exact_entropic_gamma(const double f[Q], const double ds[Q], const double dh[Q], double omega) {
-  const VelocitySet& v = vs();
+  const VelocitySet<Q>& v = vs<Q>();
   double base[Q];
   for (int i = 0; i < Q; ++i) base[i] = f[i] - omega * ds[i];
   // admissible interval of t = omega*gamma/2: base_i - t dh_i > 0 for all i
@@ -231,12 +258,12 @@ double exact_entropic_gamma(const double f[Q], const double ds[Q], const double 
 // mode 0: closed-form gamma (eq. entropyControl)
 // mode 1: gamma forced to 2 (BGK)
 // mode 2: exact entropic gamma (real scalar only)
-template <class T>
+template <int Q, class T>
 void collide(const T f[Q], double omega, int mode, T fstar[Q], T* gamma_out, T ds_out[Q], T dh_out[Q]) {
-  const MomentBasis& mb = basis();
+  const MomentBasis<Q>& mb = basis<Q>();
   T rho, u[3], feq[Q], fneq[Q];
-  density_velocity(f, rho, u);
-  equilibrium(rho, u, feq);
+  density_velocity<Q>(f, rho, u);
+  equilibrium<Q>(rho, u, feq);
   for (int i = 0; i < Q; ++i) fneq[i] = f[i] - feq[i];
   // moments of the non-equilibrium part in the grouped basis
   T m[Q];
@@ -266,7 +293,7 @@ void collide(const T f[Q], double omega, int mode, T fstar[Q], T* gamma_out, T d
     if constexpr (std::is_same<T, double>::value) {
       double hh = 0.0;
       for (int i = 0; i < Q; ++i) hh += dh[i] * dh[i];
-      if (hh > 0.0) gamma = exact_entropic_gamma(f, ds, dh, omega);
+      if (hh > 0.0) gamma = exact_entropic_gamma<Q>(f, ds, dh, omega);
     }
   }
   // relaxation rates per group: kinematic 0, shear omega, hom omega*gamma/2
@@ -292,14 +319,14 @@ void collide(const T f[Q], double omega, int mode, T fstar[Q], T* gamma_out, T d
 
 // One time step: collide every node, then pull-stream periodically.
 // gamma_cell (optional) receives the gamma used at each node.
-template <class T>
+template <int Q, class T>
 void step(int n, double omega, int mode, const T* f, T* fnew, T* post, double* gamma_cell) {
-  const VelocitySet& v = vs();
+  const VelocitySet<Q>& v = vs<Q>();
   const int64_t ncell = int64_t(n) * n * n;
 #pragma omp parallel for schedule(static)
   for (int64_t cell = 0; cell < ncell; ++cell) {
     T g;
-    collide(f + cell * Q, omega, mode, post + cell * Q, &g, (T*)nullptr, (T*)nullptr);
+    collide<Q>(f + cell * Q, omega, mode, post + cell * Q, &g, (T*)nullptr, (T*)nullptr);
     if (gamma_cell) gamma_cell[cell] = re(g);
   }
 #pragma omp parallel for schedule(static)
@@ -317,13 +344,13 @@ void step(int n, double omega, int mode, const T* f, T* fnew, T* post, double* g
       }
 }
 
-template <class T>
+template <int Q, class T>
 void run(int n, int steps, double omega, int mode, T* f, double* gamma_stats) {
   const int64_t len = int64_t(n) * n * n * Q;
   std::vector<T> tmp(len), post(len);
   std::vector<double> gcell(gamma_stats ? int64_t(n) * n * n : 0);
   for (int s = 0; s < steps; ++s) {
-    step<T>(n, omega, mode, f, tmp.data(), post.data(), gamma_stats ? gcell.data() : nullptr);
+    step<Q, T>(n, omega, mode, f, tmp.data(), post.data(), gamma_stats ? gcell.data() : nullptr);
     std::memcpy(f, tmp.data(), sizeof(T) * len);
     if (gamma_stats) {
       double gmin = 1e300, gmax = -1e300, gsum = 0.0;
@@ -339,76 +366,109 @@ void run(int n, int steps, double omega, int mode, T* f, double* gamma_stats) {
   }
 }
 
+// D3Q27 or D3Q19 by the number of velocities q (any other q: no effect, 0)
+template <class F>
+int32_t with_lattice(int32_t q, F&& f) {
+  if (q == 27) {
+    f(std::integral_constant<int, 27>{});
+    return 1;
+  }
+  if (q == 19) {
+    f(std::integral_constant<int, 19>{});
+    return 1;
+  }
+  return 0;
+}
+
 }  // namespace
 
 extern "C" {
 
-// Velocity set: c[27][3] integers and w[27].
-void oracle_velocity_set(int32_t* c, double* w) {
-  const VelocitySet& v = vs();
-  for (int i = 0; i < Q; ++i) {
-    for (int a = 0; a < 3; ++a) c[3 * i + a] = v.c[i][a];
-    w[i] = v.w[i];
-  }
-}
-
-// Moment matrix (row-major 27x27), its inverse and the group of each row.
-void oracle_moment_basis(double* M, double* Minv, int32_t* group) {
-  const MomentBasis& b = basis();
-  for (int r = 0; r < Q; ++r) {
-    group[r] = b.group[r];
-    for (int k = 0; k < Q; ++k) {
-      M[r * Q + k] = b.M[r][k];
-      Minv[r * Q + k] = b.Minv[r][k];
+// Velocity set: c[q][3] integers and w[q]. Returns 0 for an unknown q.
+int32_t oracle_velocity_set(int32_t q, int32_t* c, double* w) {
+  return with_lattice(q, [&](auto qc) {
+    constexpr int Q = decltype(qc)::value;
+    const VelocitySet<Q>& v = vs<Q>();
+    for (int i = 0; i < Q; ++i) {
+      for (int a = 0; a < 3; ++a) c[3 * i + a] = v.c[i][a];
+      w[i] = v.w[i];
     }
-  }
+  });
 }
 
-void oracle_equilibrium(double rho, const double* u, double* feq) { equilibrium<double>(rho, u, feq); }
-
-void oracle_collide(const double* f, double omega, int32_t mode, double* fstar, double* gamma, double* ds,
-                    double* dh) {
-  collide<double>(f, omega, mode, fstar, gamma, ds, dh);
+// Moment matrix (row-major q x q), its inverse and the group of each row.
+int32_t oracle_moment_basis(int32_t q, double* M, double* Minv, int32_t* group) {
+  return with_lattice(q, [&](auto qc) {
+    constexpr int Q = decltype(qc)::value;
+    const MomentBasis<Q>& b = basis<Q>();
+    for (int r = 0; r < Q; ++r) {
+      group[r] = b.group[r];
+      for (int k = 0; k < Q; ++k) {
+        M[r * Q + k] = b.M[r][k];
+        Minv[r * Q + k] = b.Minv[r][k];
+      }
+    }
+  });
 }
 
-void oracle_collide_z(const double* f_ri, double omega, double* fstar_ri, double* gamma_ri) {
-  collide<cplx>(reinterpret_cast<const cplx*>(f_ri), omega, 0, reinterpret_cast<cplx*>(fstar_ri),
-                reinterpret_cast<cplx*>(gamma_ri), nullptr, nullptr);
+int32_t oracle_equilibrium(int32_t q, double rho, const double* u, double* feq) {
+  return with_lattice(q, [&](auto qc) { equilibrium<decltype(qc)::value, double>(rho, u, feq); });
 }
 
-// Advance f[n^3][27] by `steps` steps in place. gamma_stats (optional):
+int32_t oracle_collide(int32_t q, const double* f, double omega, int32_t mode, double* fstar, double* gamma,
+                       double* ds, double* dh) {
+  return with_lattice(q, [&](auto qc) { collide<decltype(qc)::value, double>(f, omega, mode, fstar, gamma, ds, dh); });
+}
+
+int32_t oracle_collide_z(int32_t q, const double* f_ri, double omega, double* fstar_ri, double* gamma_ri) {
+  return with_lattice(q, [&](auto qc) {
+    collide<decltype(qc)::value, cplx>(reinterpret_cast<const cplx*>(f_ri), omega, 0,
+                                       reinterpret_cast<cplx*>(fstar_ri), reinterpret_cast<cplx*>(gamma_ri),
+                                       nullptr, nullptr);
+  });
+}
+
+// Advance f[n^3][q] by `steps` steps in place. gamma_stats (optional):
 // steps x (min, max, mean) of the gamma used at each step.
-void oracle_run(int32_t n, int32_t steps, double omega, int32_t mode, double* f, double* gamma_stats,
-                int32_t threads) {
+int32_t oracle_run(int32_t q, int32_t n, int32_t steps, double omega, int32_t mode, double* f, double* gamma_stats,
+                   int32_t threads) {
 #ifdef _OPENMP
   if (threads > 0) omp_set_num_threads(threads);
 #endif
-  run<double>(n, steps, omega, mode, f, gamma_stats);
+  return with_lattice(q, [&](auto qc) { run<decltype(qc)::value, double>(n, steps, omega, mode, f, gamma_stats); });
 }
 
 // Same in complex arithmetic (interleaved re/im), closed-form gamma only.
-void oracle_run_z(int32_t n, int32_t steps, double omega, double* f_ri, int32_t threads) {
+int32_t oracle_run_z(int32_t q, int32_t n, int32_t steps, double omega, double* f_ri, int32_t threads) {
 #ifdef _OPENMP
   if (threads > 0) omp_set_num_threads(threads);
 #endif
-  run<cplx>(n, steps, omega, 0, reinterpret_cast<cplx*>(f_ri), nullptr);
+  return with_lattice(q, [&](auto qc) {
+    run<decltype(qc)::value, cplx>(n, steps, omega, 0, reinterpret_cast<cplx*>(f_ri), nullptr);
+  });
 }
 
 // Equilibrium populations f = f^eq(1, u) for every node; u is [3][ncell].
-void oracle_init_field(int64_t ncell, const double* u, double* f) {
-  for (int64_t cell = 0; cell < ncell; ++cell) {
-    double uc[3] = {u[cell], u[ncell + cell], u[2 * ncell + cell]};
-    equilibrium<double>(1.0, uc, f + cell * Q);
-  }
+int32_t oracle_init_field(int32_t q, int64_t ncell, const double* u, double* f) {
+  return with_lattice(q, [&](auto qc) {
+    constexpr int Q = decltype(qc)::value;
+    for (int64_t cell = 0; cell < ncell; ++cell) {
+      double uc[3] = {u[cell], u[ncell + cell], u[2 * ncell + cell]};
+      equilibrium<Q, double>(1.0, uc, f + cell * Q);
+    }
+  });
 }
 
-void oracle_init_field_z(int64_t ncell, const double* u_ri, double* f_ri) {
+int32_t oracle_init_field_z(int32_t q, int64_t ncell, const double* u_ri, double* f_ri) {
   const cplx* u = reinterpret_cast<const cplx*>(u_ri);
   cplx* f = reinterpret_cast<cplx*>(f_ri);
-  for (int64_t cell = 0; cell < ncell; ++cell) {
-    cplx uc[3] = {u[cell], u[ncell + cell], u[2 * ncell + cell]};
-    equilibrium<cplx>(cplx(1.0), uc, f + cell * Q);
-  }
+  return with_lattice(q, [&](auto qc) {
+    constexpr int Q = decltype(qc)::value;
+    for (int64_t cell = 0; cell < ncell; ++cell) {
+      cplx uc[3] = {u[cell], u[ncell + cell], u[2 * ncell + cell]};
+      equilibrium<Q, cplx>(cplx(1.0), uc, f + cell * Q);
+    }
+  });
 }
 
 int32_t oracle_max_threads(void) {

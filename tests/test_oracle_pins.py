@@ -18,14 +18,16 @@ import oracle
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
 
-def random_state(seed, n, amp_u=0.05, amp_noise=1e-3, rho_noise=1e-3):
+LATTICES = pytest.mark.parametrize("q", [27, 19])
+
+
+def random_state(seed, n, amp_u=0.05, amp_noise=1e-3, rho_noise=1e-3, q=27):
     """Non-equilibrium populations: equilibrium of a random (rho, u) field plus noise."""
     rng = np.random.default_rng(seed)
     ncell = n ** 3
-    f = np.zeros((ncell, 27))
     rho = 1.0 + rng.uniform(-rho_noise, rho_noise, ncell)
     u = rng.uniform(-amp_u, amp_u, (ncell, 3))
-    c, w = oracle.velocity_set()
+    c, w = oracle.velocity_set(q)
     cu = u @ c.T
     usq = np.sum(u * u, axis=1)[:, None]
     f = rho[:, None] * w[None, :] * (1 + 3 * cu + 4.5 * cu ** 2 - 1.5 * usq)
@@ -33,15 +35,25 @@ def random_state(seed, n, amp_u=0.05, amp_noise=1e-3, rho_noise=1e-3):
     return np.ascontiguousarray(f)
 
 
-def textbook_feq(rho, u):
+WCLASS = {27: {0: 8 / 27, 1: 2 / 27, 2: 1 / 54, 3: 1 / 216},   # D3Q27
+          19: {0: 1 / 3, 1: 1 / 18, 2: 1 / 36}}                # D3Q19 (no corners)
+
+
+def lattice_velocities(q):
+    """The velocities in index order: {-1,0,1}^3 with cx slowest; D3Q19 leaves
+    out the eight corners."""
+    return [v for v in itertools.product((-1, 0, 1), repeat=3) if q == 27 or np.count_nonzero(v) < 3]
+
+
+def textbook_feq(rho, u, q=27):
     """Second-order Maxwellian truncation written from the textbook form with
-    c_s^2 = 1/3 and the D3Q27 weights (8/27, 2/27, 1/54, 1/216 by number of
-    non-zero velocity components)."""
-    wclass = {0: 8 / 27, 1: 2 / 27, 2: 1 / 54, 3: 1 / 216}
-    out = np.zeros(27)
-    for i, (cx, cy, cz) in enumerate(itertools.product((-1, 0, 1), repeat=3)):
-        cvec = np.array([cx, cy, cz], float)
-        w = wclass[int(np.count_nonzero(cvec))]
+    c_s^2 = 1/3 and the textbook weights by number of non-zero velocity
+    components."""
+    vel = lattice_velocities(q)
+    out = np.zeros(q)
+    for i, v in enumerate(vel):
+        cvec = np.array(v, float)
+        w = WCLASS[q][int(np.count_nonzero(cvec))]
         cu = cvec @ u
         out[i] = rho * w * (1 + cu / (1 / 3) + (cu ** 2 - np.dot(u, u) / 3) / (2 / 9))
     return out
@@ -71,22 +83,51 @@ def test_velocity_set_index_convention_and_weights():
         assert abs(np.sum(w * cf[:, a] * cf[:, b] * cf[:, g])) < 1e-15
 
 
-def test_moment_basis_invertible_and_grouped():
-    M, Minv, g = oracle.moment_basis()
-    assert np.max(np.abs(M @ Minv - np.eye(27))) < 1e-13
-    assert list(np.bincount(g)) == [4, 5, 18]
+def test_d3q19_velocity_set_and_weights():
+    """D3Q19: the D3Q27 order without corners, opposite q-1-i, and weights
+    fixed by sum w = 1, sum w cx^2 = 1/3, sum w cx^2 cy^2 = 1/9 (three
+    classes, three conditions); isotropic through fourth order."""
+    c, w = oracle.velocity_set(19)
+    vel = lattice_velocities(19)
+    assert len(vel) == 19
+    for i in range(19):
+        assert tuple(c[i]) == vel[i]
+        assert tuple(c[18 - i]) == tuple(-np.array(vel[i]))
+    cf = c.astype(float)
+    nz = np.count_nonzero(c, axis=1)
+    A = np.array([[1, 6, 12], [0, 2, 8], [0, 0, 4]], float)   # the three conditions per class
+    wc = np.linalg.solve(A, [1, 1 / 3, 1 / 9])
+    assert np.max(np.abs(w - wc[nz])) < 1e-15
+    for a, b in itertools.product(range(3), repeat=2):
+        assert abs(np.sum(w * cf[:, a] * cf[:, b]) - (a == b) / 3) < 1e-15
+    for a, b, g, d in itertools.product(range(3), repeat=4):
+        iso = ((a == b) * (g == d) + (a == g) * (b == d) + (a == d) * (b == g)) / 9
+        assert abs(np.sum(w * cf[:, a] * cf[:, b] * cf[:, g] * cf[:, d]) - iso) < 1e-15
+    for a, b, g in itertools.product(range(3), repeat=3):
+        assert abs(np.sum(w * cf[:, a] * cf[:, b] * cf[:, g])) < 1e-15
 
 
-def test_equilibrium_moments():
+@pytest.mark.parametrize("q,groups", [(27, [4, 5, 18]), (19, [4, 5, 10])])
+def test_moment_basis_invertible_and_grouped(q, groups):
+    """Table 1's groups: kinematic (4), shear (5), hom (T, and Q and A: the
+    raw moments of order >= 3 that the lattice supports)."""
+    M, Minv, g = oracle.moment_basis(q)
+    assert np.max(np.abs(M @ Minv - np.eye(q))) < 1e-13
+    assert list(np.bincount(g)) == groups
+    assert np.linalg.matrix_rank(M) == q
+
+
+@LATTICES
+def test_equilibrium_moments(q):
     """The truncated Maxwellian reproduces rho, rho u and rho/3 I + rho u u."""
-    c, _ = oracle.velocity_set()
+    c, _ = oracle.velocity_set(q)
     cf = c.astype(float)
     rng = np.random.default_rng(1)
     for _ in range(10):
         rho = 1 + rng.uniform(-0.1, 0.1)
         u = rng.uniform(-0.1, 0.1, 3)
-        feq = oracle.equilibrium(rho, u)
-        assert np.max(np.abs(feq - textbook_feq(rho, u))) < 1e-16
+        feq = oracle.equilibrium(rho, u, q)
+        assert np.max(np.abs(feq - textbook_feq(rho, u, q))) < 1e-16
         assert abs(feq.sum() - rho) < 1e-15
         assert np.max(np.abs(cf.T @ feq - rho * u)) < 1e-16
         P = (cf.T * feq) @ cf
@@ -94,29 +135,32 @@ def test_equilibrium_moments():
 
 
 # ---------------------------------------------------------------- collision pins
-def test_equilibrium_is_fixed_point():
+@LATTICES
+def test_equilibrium_is_fixed_point(q):
     rng = np.random.default_rng(2)
     for omega in (0.7, 1.3, 1.99):
         for _ in range(5):
-            feq = oracle.equilibrium(1 + rng.uniform(-0.05, 0.05), rng.uniform(-0.08, 0.08, 3))
+            feq = oracle.equilibrium(1 + rng.uniform(-0.05, 0.05), rng.uniform(-0.08, 0.08, 3), q)
             fs, gamma, ds, dh = oracle.collide(feq, omega)
             assert np.max(np.abs(fs - feq)) < 5e-16
             assert np.max(np.abs(ds)) < 5e-16 and np.max(np.abs(dh)) < 5e-16
 
 
-def test_uniform_state_stays_bitwise_uniform():
+@LATTICES
+def test_uniform_state_stays_bitwise_uniform(q):
     n = 6
-    feq = oracle.equilibrium(1.01, np.array([0.03, -0.02, 0.01]))
+    feq = oracle.equilibrium(1.01, np.array([0.03, -0.02, 0.01]), q)
     f = np.ascontiguousarray(np.tile(feq, (n ** 3, 1)))
     oracle.run(f, n, 3, 1.9)
     assert np.all(f == f[0:1, :])
     assert np.max(np.abs(f[0] - feq)) < 5e-16
 
 
-def test_collision_conserves_mass_and_momentum():
-    c, _ = oracle.velocity_set()
+@LATTICES
+def test_collision_conserves_mass_and_momentum(q):
+    c, _ = oracle.velocity_set(q)
     cf = c.astype(float)
-    f = random_state(3, 3, amp_noise=5e-2)
+    f = random_state(3, 3, amp_noise=5e-2, q=q)
     for omega in (0.5, 1.0, 1.5, 1.999):
         for cell in range(f.shape[0]):
             fs, *_ = oracle.collide(f[cell], omega)
@@ -124,10 +168,11 @@ def test_collision_conserves_mass_and_momentum():
             assert np.max(np.abs(cf.T @ (fs - f[cell]))) < 1e-15
 
 
-def test_step_conserves_totals():
+@LATTICES
+def test_step_conserves_totals(q):
     n = 8
-    c, _ = oracle.velocity_set()
-    f = random_state(4, n, amp_noise=1e-2)
+    c, _ = oracle.velocity_set(q)
+    f = random_state(4, n, amp_noise=1e-2, q=q)
     mass0 = f.sum()
     j0 = (f @ c.astype(float)).sum(axis=0)
     oracle.run(f, n, 5, 1.95)
@@ -135,15 +180,16 @@ def test_step_conserves_totals():
     assert np.max(np.abs((f @ c.astype(float)).sum(axis=0) - j0)) < 1e-14 * mass0
 
 
-def test_bgk_special_cases():
+@LATTICES
+def test_bgk_special_cases(q):
     """gamma = 2 gives the textbook BGK collision; at omega = 1 the closed-form
     gamma is exactly 2, so KBC collapses to BGK with f* = f^eq."""
-    f = random_state(5, 2, amp_noise=2e-2)
-    c, _ = oracle.velocity_set()
+    f = random_state(5, 2, amp_noise=2e-2, q=q)
+    c, _ = oracle.velocity_set(q)
     for cell in range(f.shape[0]):
         rho = f[cell].sum()
         u = (c.astype(float).T @ f[cell]) / rho
-        feq = textbook_feq(rho, u)
+        feq = textbook_feq(rho, u, q)
         for omega in (0.8, 1.6, 1.97):
             fs, gamma, *_ = oracle.collide(f[cell], omega, oracle.MODE_BGK)
             assert gamma == 2.0
@@ -153,37 +199,39 @@ def test_bgk_special_cases():
         assert np.max(np.abs(fs - feq)) < 1e-15
 
 
-def test_shear_hom_split():
+@LATTICES
+def test_shear_hom_split(q):
     """ds carries exactly the traceless and off-diagonal second moments of
-    f^neq and no other raw moment; ds + dh = f^neq; closed form of ds."""
-    c, w = oracle.velocity_set()
+    f^neq and no other raw moment; ds + dh = f^neq; closed form of ds (the
+    same class-wise formulas on both lattices: corners carry no shear part)."""
+    c, w = oracle.velocity_set(q)
     cf = c.astype(float)
-    f = random_state(6, 2, amp_noise=3e-2)
+    f = random_state(6, 2, amp_noise=3e-2, q=q)
     for cell in range(f.shape[0]):
         fc = f[cell]
         rho = fc.sum()
         u = (cf.T @ fc) / rho
-        fneq = fc - textbook_feq(rho, u)
+        fneq = fc - textbook_feq(rho, u, q)
         _, _, ds, dh = oracle.collide(fc, 1.7)
         assert np.max(np.abs(ds + dh - fneq)) < 1e-15
 
-        def mom(v, p, q, r):
-            return np.sum(v * cf[:, 0] ** p * cf[:, 1] ** q * cf[:, 2] ** r)
+        def mom(v, a, b, e):
+            return np.sum(v * cf[:, 0] ** a * cf[:, 1] ** b * cf[:, 2] ** e)
 
         nxz = mom(fneq, 2, 0, 0) - mom(fneq, 0, 0, 2)
         nyz = mom(fneq, 0, 2, 0) - mom(fneq, 0, 0, 2)
         assert abs(mom(ds, 2, 0, 0) - mom(ds, 0, 0, 2) - nxz) < 1e-16
         assert abs(mom(ds, 0, 2, 0) - mom(ds, 0, 0, 2) - nyz) < 1e-16
-        for (p, q, r) in ((1, 1, 0), (1, 0, 1), (0, 1, 1)):
-            assert abs(mom(ds, p, q, r) - mom(fneq, p, q, r)) < 1e-16
+        for (a, b, e) in ((1, 1, 0), (1, 0, 1), (0, 1, 1)):
+            assert abs(mom(ds, a, b, e) - mom(fneq, a, b, e)) < 1e-16
         assert abs(mom(ds, 2, 0, 0) + mom(ds, 0, 2, 0) + mom(ds, 0, 0, 2)) < 1e-16
-        for p, q, r in itertools.product(range(3), repeat=3):
-            if p + q + r <= 1 or p + q + r >= 3:
-                assert abs(mom(ds, p, q, r)) < 1e-16
+        for a, b, e in itertools.product(range(3), repeat=3):
+            if a + b + e <= 1 or a + b + e >= 3:
+                assert abs(mom(ds, a, b, e)) < 1e-16
         # closed form per velocity class
-        exp = np.zeros(27)
+        exp = np.zeros(q)
         pxy, pxz, pyz = mom(fneq, 1, 1, 0), mom(fneq, 1, 0, 1), mom(fneq, 0, 1, 1)
-        for i in range(27):
+        for i in range(q):
             cx, cy, cz = c[i]
             nz = np.count_nonzero(c[i])
             if nz == 1:
@@ -193,16 +241,17 @@ def test_shear_hom_split():
         assert np.max(np.abs(exp - ds)) < 1e-16
 
 
-def test_closed_form_gamma_minimises_quadratic_entropy():
+@LATTICES
+def test_closed_form_gamma_minimises_quadratic_entropy(q):
     """The closed form makes the quadratic expansion of H around f^eq,
     sum (f* - f^eq)^2 / f^eq, stationary in gamma."""
-    c, _ = oracle.velocity_set()
-    f = random_state(7, 2, amp_noise=2e-2)
+    c, _ = oracle.velocity_set(q)
+    f = random_state(7, 2, amp_noise=2e-2, q=q)
     for cell in range(f.shape[0]):
         fc = f[cell]
         rho = fc.sum()
         u = (c.astype(float).T @ fc) / rho
-        feq = textbook_feq(rho, u)
+        feq = textbook_feq(rho, u, q)
         omega = 1.93
         _, gamma, ds, dh = oracle.collide(fc, omega)
 
@@ -217,19 +266,20 @@ def test_closed_form_gamma_minimises_quadratic_entropy():
         assert abs(slope) < 1e-6 * curv * d + 1e-30
 
 
-def test_exact_entropic_gamma_limit():
+@LATTICES
+def test_exact_entropic_gamma_limit(q):
     """Near equilibrium and at rest the closed form approaches the exact
     minimiser of the discrete H-function, and the exact minimiser never
     increases H."""
     rng = np.random.default_rng(8)
-    c, w = oracle.velocity_set()
+    c, w = oracle.velocity_set(q)
     omega = 1.98
     diffs = []
     for amp in (1e-2, 1e-3, 1e-4):
         dd = []
         for _ in range(10):
-            feq = oracle.equilibrium(1.0, np.zeros(3))
-            f = feq * (1 + amp * rng.uniform(-1, 1, 27))
+            feq = oracle.equilibrium(1.0, np.zeros(3), q)
+            f = feq * (1 + amp * rng.uniform(-1, 1, q))
             # restore the mass and momentum of the rest state so that u = 0
             f = f - w * (f.sum() - 1.0)
             jx = c.astype(float).T @ f
@@ -276,25 +326,27 @@ def _cube_symmetries():
 
 
 def _apply_symmetry(f, n, R):
-    c, _ = oracle.velocity_set()
-    sigma = np.zeros(27, int)
-    for i in range(27):
+    q = f.shape[1]
+    c, _ = oracle.velocity_set(q)
+    sigma = np.zeros(q, int)
+    for i in range(q):
         rc = R @ c[i]
-        sigma[i] = [k for k in range(27) if tuple(c[k]) == tuple(rc)][0]
-    fz = f.reshape(n, n, n, 27)
+        sigma[i] = [k for k in range(q) if tuple(c[k]) == tuple(rc)][0]
+    fz = f.reshape(n, n, n, q)
     out = np.zeros_like(fz)
     idx = np.arange(n)
     Z, Yg, X = np.meshgrid(idx, idx, idx, indexing="ij")
     P = np.stack([X, Yg, Z], axis=-1)
     Pn = np.einsum("ab,zyxb->zyxa", R, P) % n
-    for i in range(27):
+    for i in range(q):
         out[Pn[..., 2], Pn[..., 1], Pn[..., 0], sigma[i]] = fz[..., i]
-    return np.ascontiguousarray(out.reshape(n ** 3, 27))
+    return np.ascontiguousarray(out.reshape(n ** 3, q))
 
 
-def test_cube_symmetry_equivariance():
+@LATTICES
+def test_cube_symmetry_equivariance(q):
     n = 6
-    f0 = random_state(9, n, amp_noise=5e-3)
+    f0 = random_state(9, n, amp_noise=5e-3, q=q)
     rng = np.random.default_rng(10)
     syms = _cube_symmetries()
     assert len(syms) == 48
@@ -308,18 +360,19 @@ def test_cube_symmetry_equivariance():
 
 
 # ---------------------------------------------------------------- streaming
-def test_streaming_is_a_permutation_and_keeps_relative_entropy():
+@LATTICES
+def test_streaming_is_a_permutation_and_keeps_relative_entropy(q):
     n = 6
-    c, w = oracle.velocity_set()
-    f = random_state(11, n, amp_noise=1e-2)
+    c, w = oracle.velocity_set(q)
+    f = random_state(11, n, amp_noise=1e-2, q=q)
     g = f.copy()
     oracle.run(g, n, 1, 0.0, mode=oracle.MODE_BGK)   # zero frequency: streaming only
-    for i in range(27):
+    for i in range(q):
         assert np.array_equal(np.sort(f[:, i]), np.sort(g[:, i]))
     # single-velocity shift check
-    fz = f.reshape(n, n, n, 27)
-    gz = g.reshape(n, n, n, 27)
-    for i in range(27):
+    fz = f.reshape(n, n, n, q)
+    gz = g.reshape(n, n, n, q)
+    for i in range(q):
         cx, cy, cz = c[i]
         assert np.array_equal(gz[..., i], np.roll(fz[..., i], shift=(cz, cy, cx), axis=(0, 1, 2)))
     hrel = lambda v: np.sum(v * np.log(v / w) - v + w)
@@ -341,13 +394,14 @@ def test_initial_relative_entropy_scales_with_dx_squared():
 
 
 # ---------------------------------------------------------------- initial data
-def test_initial_kinetic_energy_closed_form():
+@LATTICES
+def test_initial_kinetic_energy_closed_form(q):
     """Discrete orthogonality: KE(0) = U0^2 (1/8 + amp^2 sum Y^2 / 1024)
     without projection."""
     for n, seed in ((8, 1), (12, 2), (16, 3)):
         y = mc_inputs.draw_y(seed, 1)[0]
         u0, amp = 0.05, 0.3
-        f = oracle.init_populations(n, u0, amp, y, False)
+        f = oracle.init_populations(n, u0, amp, y, False, q)
         rho, u = oracle.moments(f, n)
         ke = oracle.kinetic_energy(u)
         assert abs(ke - u0 ** 2 * (1 / 8 + amp ** 2 * np.sum(y ** 2) / 1024)) < 1e-15
@@ -401,7 +455,8 @@ def test_leray_projection_properties():
 
 # ---------------------------------------------------------------- analytic decay
 @pytest.mark.slow
-def test_two_dimensional_taylor_green_decay_rate():
+@LATTICES
+def test_two_dimensional_taylor_green_decay_rate(q):
     """A z-independent 2-D Taylor-Green mode decays like exp(-2 nu k^2 t), so
     its kinetic energy like exp(-4 nu k^2 t), k = 2 pi / n per lattice unit."""
     n = 24
@@ -410,7 +465,7 @@ def test_two_dimensional_taylor_green_decay_rate():
     omega = oracle.omega_shear(nu)
     X, Y, Z = oracle.grid(n)
     u = u0 * np.stack([np.sin(X) * np.cos(Y), -np.cos(X) * np.sin(Y), np.zeros_like(X)])
-    f = oracle.equilibrium_field(u)
+    f = oracle.equilibrium_field(u, q)
     steps = 120
     oracle.run(f, n, 20, omega)      # let the initial pressure transient pass
     _, ua = oracle.moments(f, n)
@@ -438,17 +493,18 @@ def test_unit_conversion_reproduces_paper_tables():
 
 
 # ---------------------------------------------------------------- complex step
-def test_complex_step_matches_central_differences():
+@LATTICES
+def test_complex_step_matches_central_differences(q):
     n, steps = 8, 6
     y = mc_inputs.draw_y(3, 1)[0]
-    g = oracle.ke_gradient_complex_step(n, 0.05, 100.0, 0.5, y, True, steps, params=[0, 5, 13, 23])
+    g = oracle.ke_gradient_complex_step(n, 0.05, 100.0, 0.5, y, True, steps, params=[0, 5, 13, 23], q=q)
     h = 1e-4
     for p in (0, 5, 13, 23):
         yp, ym = y.copy(), y.copy()
         yp[p] += h
         ym[p] -= h
-        fd = (oracle.ke_after(n, 0.05, 100.0, 0.5, yp, True, steps) -
-              oracle.ke_after(n, 0.05, 100.0, 0.5, ym, True, steps)) / (2 * h)
+        fd = (oracle.ke_after(n, 0.05, 100.0, 0.5, yp, True, steps, q=q) -
+              oracle.ke_after(n, 0.05, 100.0, 0.5, ym, True, steps, q=q)) / (2 * h)
         assert abs(fd - g[p]) <= 1e-6 * abs(g).max() + 1e-14
 
 
