@@ -21,19 +21,30 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0     # MI355X HBM3E
-BYTES_PER_LUP = {"f32s": 216, "f64": 432}   # 27 loads + 27 stores per node update
+# q loads + q stores per node update
+BYTES_PER_LUP = {("f32s", 27): 216, ("f64", 27): 432, ("f32s", 19): 152, ("f64", 19): 304}
+
+# sources the collide-and-stream kernel is compiled from (the counter summary
+# is valid only for the exact sources it was taken with)
+STEP_SOURCES = ["lattice.h", "lbm_device.h", "step_kernel.h", "step_d3q27.hip", "step_d3q19.hip"]
+
+
+def step_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for name in STEP_SOURCES:
+        h.update(open(os.path.join(ROOT, "paper_2608_23786_amd", "csrc", name), "rb").read())
+    return h.hexdigest()
 
 
 def counter_traffic(workload):
     """HBM bytes per collide-and-stream launch from the committed counter
     summary, or None when the kernel source changed since it was taken."""
-    import hashlib
     path = os.path.join(ROOT, "profiles", f"kbc_step_{workload}.traffic.txt")
     if not os.path.exists(path):
         return None
     vals = dict(line.strip().split("=", 1) for line in open(path) if "=" in line and not line.startswith("#"))
-    src = os.path.join(ROOT, "paper_2608_23786_amd", "csrc", "kernels.hip")
-    if hashlib.sha256(open(src, "rb").read()).hexdigest() != vals.get("kernel_source_sha256"):
+    if step_source_hash() != vals.get("kernel_source_sha256"):
         return None
     return int(vals["traffic_bytes_per_launch"])
 
@@ -42,7 +53,7 @@ def build_ensemble(wl, mc, torch):
     samples = []
     for g in wl.groups:
         samples += [mc.Sample(g.n, g.u0, g.re, g.amp, g.project, g.stride)] * g.count
-    ens = mc.Ensemble(samples, wl.precision)
+    ens = mc.Ensemble(samples, wl.precision, lattice=wl.lattice)
     ens.init(wl.seed)
     return ens
 
@@ -96,7 +107,7 @@ def kernel_roofline(ens, wl, torch, ticks):
     avg_ms, launches = ens.launch_time()
     ens.time_launches(False)
     ens.use_graphs(True)
-    bytes_per_launch = BYTES_PER_LUP[wl.precision] * lups / launches
+    bytes_per_launch = BYTES_PER_LUP[wl.precision, wl.lattice] * lups / launches
     achieved = bytes_per_launch / (avg_ms / 1e3) / 1e9
     return avg_ms, launches, bytes_per_launch, achieved
 
@@ -215,6 +226,68 @@ def bench_adjoint(mc, torch):
     return out
 
 
+def bench_lattice(mc, torch, name, ticks=500):
+    """Another lattice on the 64-sample ensemble: autotuned launch, timed
+    ticks with the reductions fused every 50, kernel roofline."""
+    import mc_inputs
+    wl = mc_inputs.WORKLOADS[name]
+    ens = build_ensemble(wl, mc, torch)
+    tuned = ens.autotune(reps=3)
+    ens.step(20)
+    sec, lups = timed_ticks(ens, torch, ticks, wl.save_every)
+    avg_ms, launches, bpl, achieved = kernel_roofline(ens, wl, torch, 40)
+    if ens.check() >= 0:
+        raise SystemExit(f"{name} became unstable")
+    out = {"workload": wl.name, "lattice": f"D3Q{wl.lattice}", "ticks": ticks, "MLUPS": round(lups / sec / 1e6, 1),
+           "launch": dict(zip(("block", "xcd_remap", "buffer_addressing", "nontemporal"), tuned)),
+           "kernel_avg_ms": round(avg_ms, 5), "bytes_per_lup": BYTES_PER_LUP[wl.precision, wl.lattice],
+           "kernel_GBps_algorithmic": round(achieved, 1), "kernel_frac_of_peak": round(achieved / HBM_PEAK_GBS, 4)}
+    del ens
+    torch.cuda.empty_cache()
+    return out
+
+
+def bench_sequence(mc, torch):
+    """Capacity run of the vanishing-viscosity sequence: 8 samples at each of
+    128^3, 256^3 and 512^3 in one ensemble (132 GB of FP32 populations), the
+    same Y at every resolution, strides 16:4:1, FP64 records every 16 ticks.
+    After the timed ticks, the velocities at the 8^3 nodes common to all
+    resolutions give the 1-point Wasserstein distances 128<->256 and
+    256<->512 (mean over nodes and components, physical units u / U0)."""
+    import mc_inputs
+    import numpy as np
+    wl = mc_inputs.WORKLOADS["sequence512x8_f32"]
+    samples = []
+    for g in wl.groups:
+        samples += [mc.Sample(g.n, g.u0, g.re, g.amp, g.project, g.stride)] * g.count
+    ens = mc.Ensemble(samples, wl.precision, lattice=wl.lattice)
+    per = wl.groups[0].count
+    y = np.tile(mc_inputs.draw_y(wl.seed, per), (len(wl.groups), 1))
+    ens.init(0, torch.from_numpy(y))
+    tuned = ens.autotune(reps=1)
+    ticks, every = wl.ticks, wl.save_every
+    sec, lups = timed_ticks(ens, torch, ticks, every)
+    if ens.check() >= 0:
+        raise SystemExit("sequence workload became unstable")
+    pv = ens.point_values(8)                       # [m][3][8^3], lattice units
+    scale = torch.tensor([1.0 / s.u0 for s in samples], dtype=torch.float64, device=pv.device)
+    pv = (pv * scale[:, None, None]).contiguous()
+    w1 = {}
+    for a, b in ((0, 1), (1, 2)):
+        pa, pb = pv[a * per:(a + 1) * per].contiguous(), pv[b * per:(b + 1) * per].contiguous()
+        terms = mc.w1_1pt(pa, pb, 8)               # on the current stream, like pv
+        w1[f"{wl.groups[a].n}<->{wl.groups[b].n}"] = [round(float(v), 8) for v in terms.cpu()]
+    gb = sum(s.n ** 3 for s in samples) * BYTES_PER_LUP[wl.precision, wl.lattice] / 2 / 1e9
+    out = {"workload": wl.name, "ticks": ticks, "steps": [ticks // g.stride for g in wl.groups],
+           "population_GB": round(gb, 1), "lattice_updates": lups, "seconds": round(sec, 4),
+           "MLUPS": round(lups / sec / 1e6, 1),
+           "launch": dict(zip(("block", "xcd_remap", "buffer_addressing", "nontemporal"), tuned)),
+           "W1_1pt_u_over_U0": w1}
+    del ens, pv
+    torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(seconds_target=15.0):
     """The oracle on one 64^3 RTGV sample of the workload, on all host cores."""
     import mc_inputs
@@ -250,6 +323,7 @@ def main():
     ap.add_argument("--copy-gib", type=float, default=4.0, help="size of the copy-kernel bandwidth probe")
     ap.add_argument("--sweep", action="store_true", help="time every launch shape and report the table")
     ap.add_argument("--no-extra", action="store_true", help="skip the mixed-resolution and adjoint workloads")
+    ap.add_argument("--no-capacity", action="store_true", help="skip the 132 GB vanishing-viscosity sequence")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (this build has no multi-GPU path); got --gpus {args.gpus}",
@@ -294,6 +368,12 @@ def main():
         print(f"[bench] mixed48: {extra['mixed48']}", file=sys.stderr, flush=True)
         extra["adjoint128x8"] = bench_adjoint(mc, torch)
         print(f"[bench] adjoint128x8: {extra['adjoint128x8']}", file=sys.stderr, flush=True)
+        if wl.lattice == 27:
+            extra["d3q19"] = bench_lattice(mc, torch, "rtgv64x64_f32_d3q19")
+            print(f"[bench] d3q19: {extra['d3q19']}", file=sys.stderr, flush=True)
+        if not args.no_capacity:
+            extra["sequence512x8"] = bench_sequence(mc, torch)
+            print(f"[bench] sequence512x8: {extra['sequence512x8']}", file=sys.stderr, flush=True)
     out = {
         "metric": "aggregate MLUPS & % HBM roofline, batched FP32 vs plain FP64, at stated rel. error",
         "value": round(mlups, 1),
@@ -307,7 +387,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f32" if wl.precision == "f32s" else "f64",
         "data": "synthetic",
-        "config": {"workload": wl.name, "samples": wl.m,
+        "config": {"workload": wl.name, "samples": wl.m, "lattice": f"D3Q{wl.lattice}",
                    "lattices": [f"{g.count}x{g.n}^3 stride {g.stride}" for g in wl.groups],
                    "precision": "FP32 shifted populations (f - w), FP64 reductions" if wl.precision == "f32s"
                    else "FP64", "reduce_every": rec_every, "launch": dict(zip(("block", "xcd_remap", "buffer_addressing", "nontemporal"),
@@ -316,7 +396,7 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": counter_traffic(wl.name),
                      "traffic_unit": "bytes per launch", "algorithmic_bytes_per_launch": int(round(bpl)),
-                     "kernel": "kbc_step_kernel", "bytes_per_lup": BYTES_PER_LUP[wl.precision],
+                     "kernel": "kbc_step_kernel", "bytes_per_lup": BYTES_PER_LUP[wl.precision, wl.lattice],
                      "avg_launch_ms": round(avg_ms, 5), "launches_timed": launches,
                      "measured_copy_GBps": round(b_meas, 1), "frac_of_measured_copy": round(achieved / b_meas, 4)},
         "fp64_single_sample": f64,

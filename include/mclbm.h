@@ -1,8 +1,8 @@
 /* mclbm.h - C ABI of the MI355X Monte Carlo KBC lattice Boltzmann library.
  *
  * The library evolves an ensemble of M independent samples of the randomized
- * Taylor-Green vortex (RTGV) with a D3Q27 lattice Boltzmann scheme whose
- * collision is the entropic multi-relaxation (KBC) operator: the
+ * Taylor-Green vortex (RTGV) with a D3Q27 or D3Q19 lattice Boltzmann scheme
+ * whose collision is the entropic multi-relaxation (KBC) operator: the
  * non-equilibrium part of the populations is split into a shear part and a
  * higher-order part, the shear part relaxes with omega (fixed by the
  * viscosity), the higher-order part with omega*gamma/2, and gamma is chosen
@@ -23,8 +23,12 @@
  *                                 unit volume of u)
  *
  * Conventions shared by every call
- *   - Velocities: index i = 9*(cx+1) + 3*(cy+1) + (cz+1), c in {-1,0,1}^3;
- *     the opposite velocity of i is 26 - i.
+ *   - Velocities: D3Q27 numbers its 27 velocities c in {-1,0,1}^3 by
+ *     i = 9*(cx+1) + 3*(cy+1) + (cz+1); D3Q19 (the paper's lattice, section
+ *     on the deterministic scheme) keeps the same order without the eight
+ *     corner velocities (|cx| = |cy| = |cz| = 1). With q velocities the
+ *     opposite of population k is q - 1 - k. Weights: D3Q27 8/27, 2/27,
+ *     1/54, 1/216; D3Q19 1/3, 1/18, 1/36 (rest, axis, diagonal, corner).
  *   - Nodes: x_n = 2*pi*n/N, n = 0..N-1 per axis (periodic box [0, 2pi)^3).
  *     Fields are C-ordered [z][y][x] (x fastest); cell = (z*N + y)*N + x.
  *   - Random parameters: Y[m][24] in [-1, 1]; Y[m][p] multiplies the product
@@ -84,6 +88,11 @@ typedef enum {
   MCLBM_FP32_SHIFTED = 1     /* g = f - w stored and computed in float */
 } mclbm_precision;
 
+typedef enum {
+  MCLBM_D3Q27 = 27,          /* 27 velocities; hom group: T and 17 moments of order 3-6 */
+  MCLBM_D3Q19 = 19           /* 19 velocities; hom group: T, Q (order 3), A (order 4) of Table 1 */
+} mclbm_lattice;
+
 /* One sample of the ensemble. */
 typedef struct {
   int32_t n;        /* lattice points per axis: a power of two, 8 <= n <= 1024 */
@@ -100,15 +109,17 @@ typedef struct {
 double mclbm_omega(int32_t n, double u0, double re);
 
 /* Bytes of device workspace mclbm_create needs for this ensemble (0 if the
- * descriptors are invalid). Population storage is one in-place buffer of
- * 27 * n^3 values per sample, plus small tables. */
-size_t mclbm_workspace_bytes(int32_t m, const mclbm_sample_desc* desc, int32_t precision);
+ * descriptors, the precision or the lattice are invalid). Population storage
+ * is one in-place buffer of q * n^3 values per sample (q = lattice), plus
+ * small tables. */
+size_t mclbm_workspace_bytes(int32_t m, const mclbm_sample_desc* desc, int32_t precision, int32_t lattice);
 
-/* Create a context for m samples (1 <= m <= 256). `workspace` is device memory
- * of at least mclbm_workspace_bytes() bytes, 256-byte aligned; `hip_stream` is
- * a hipStream_t (NULL for the null stream). The descriptors are copied. */
+/* Create a context for m samples (1 <= m <= 256) on one lattice
+ * (MCLBM_D3Q27 or MCLBM_D3Q19). `workspace` is device memory of at least
+ * mclbm_workspace_bytes() bytes, 256-byte aligned; `hip_stream` is a
+ * hipStream_t (NULL for the null stream). The descriptors are copied. */
 mclbm_status mclbm_create(mclbm_ctx** out, int32_t m, const mclbm_sample_desc* desc, int32_t precision,
-                          void* workspace, size_t workspace_bytes, void* hip_stream);
+                          int32_t lattice, void* workspace, size_t workspace_bytes, void* hip_stream);
 
 mclbm_status mclbm_destroy(mclbm_ctx* ctx);
 
@@ -152,18 +163,18 @@ mclbm_status mclbm_reduce(mclbm_ctx* ctx, double* red_dev);
 mclbm_status mclbm_check(mclbm_ctx* ctx, int32_t* first_bad);
 
 /* Populations f (not shifted) of one sample at its current step, in double,
- * layout [27][n^3] (device). get copies out; set replaces the state (the
- * sample's step count is kept). */
+ * layout [q][n^3] (device, q = the lattice's velocities). get copies out; set
+ * replaces the state (the sample's step count is kept). */
 mclbm_status mclbm_get_state(mclbm_ctx* ctx, int32_t sample, double* f_dev);
 mclbm_status mclbm_set_state(mclbm_ctx* ctx, int32_t sample, const double* f_dev);
 
 /* Populations f (not shifted, double) of `count` cells of one sample at its
  * current step: cells_dev[count] (device, int64 cell indices, each checked
- * against n^3 before anything is enqueued), f_dev[count][27] (device). */
+ * against n^3 before anything is enqueued), f_dev[count][q] (device). */
 mclbm_status mclbm_get_cells(mclbm_ctx* ctx, int32_t sample, const int64_t* cells_dev, int32_t count, double* f_dev);
 
-/* Write NaN into population i of cell `cell` of one sample (failure-path
- * tests). */
+/* Write NaN into population i (0 <= i < q) of cell `cell` of one sample
+ * (failure-path tests). */
 mclbm_status mclbm_poison(mclbm_ctx* ctx, int32_t sample, int64_t cell, int32_t i);
 
 /* Checkpoint: a device copy of the whole ensemble state and its step

@@ -73,6 +73,7 @@ class Workload:
     seed: int
     save_every: int = 0
     notes: str = ""
+    lattice: int = 27     # velocities: 27 (D3Q27) or 19 (D3Q19, the paper's set)
 
     @property
     def m(self) -> int:
@@ -98,6 +99,21 @@ WORKLOADS = {
          SampleGroup(128, 12, diffusive_u0(128), 3200.0, 0.05, True, 4),
          SampleGroup(256, 4, diffusive_u0(256), 6400.0, 0.05, True, 1)],
         "f32s", 1000, 2609, 16),
+    # the 64-sample ensemble on the paper's D3Q19 lattice (same flow, seed and steps)
+    "rtgv64x64_f32_d3q19": Workload(
+        "rtgv64x64_f32_d3q19", [SampleGroup(64, 64, diffusive_u0(64), 1600.0, 0.05, True)], "f32s", 500, 2608, 50,
+        lattice=19),
+    # vanishing-viscosity sequence: 8 samples at each of 128^3, 256^3, 512^3
+    # (Re = 12.5 N, diffusive U0, the same Y at every resolution), strides
+    # 16:4:1; the run to t = 9 takes 234,684 ticks, the benchmark times a
+    # bounded number of them and compares the resolutions at equal physical
+    # time through 1-point Wasserstein distances on the 8^3 common nodes
+    "sequence512x8_f32": Workload(
+        "sequence512x8_f32",
+        [SampleGroup(128, 8, diffusive_u0(128), 1600.0, 0.05, True, 16),
+         SampleGroup(256, 8, diffusive_u0(256), 3200.0, 0.05, True, 4),
+         SampleGroup(512, 8, diffusive_u0(512), 6400.0, 0.05, True, 1)],
+        "f32s", 256, 2611, 16),
     # adjoint workload: 8 x 128^3, FP32 forward, 1000 steps, checkpoints every 50
     "adjoint128x8_f32": Workload(
         "adjoint128x8_f32", [SampleGroup(128, 8, diffusive_u0(128), 1600.0, 0.05, True)], "f32s", 1000, 2610, 50),

@@ -14,6 +14,7 @@ OK, ERR_ARG, ERR_OOM, ERR_HIP, ERR_STATE, ERR_UNSTABLE, ERR_UNSUPPORTED = range(
 STATUS_NAMES = {0: "OK", 1: "ERR_ARG", 2: "ERR_OOM", 3: "ERR_HIP", 4: "ERR_STATE", 5: "ERR_UNSTABLE",
                 6: "ERR_UNSUPPORTED"}
 FP64, FP32_SHIFTED = 0, 1
+D3Q27, D3Q19 = 27, 19
 
 
 class SampleDesc(ctypes.Structure):
@@ -41,8 +42,8 @@ _ctxp = _c.c_void_p
 # name: (restype, argtypes)
 SIGNATURES = {
     "mclbm_omega": (_c.c_double, [_i32, _c.c_double, _c.c_double]),
-    "mclbm_workspace_bytes": (_sz, [_i32, _descp, _i32]),
-    "mclbm_create": (_i32, [_c.POINTER(_ctxp), _i32, _descp, _i32, _vp, _sz, _vp]),
+    "mclbm_workspace_bytes": (_sz, [_i32, _descp, _i32, _i32]),
+    "mclbm_create": (_i32, [_c.POINTER(_ctxp), _i32, _descp, _i32, _i32, _vp, _sz, _vp]),
     "mclbm_destroy": (_i32, [_ctxp]),
     "mclbm_init": (_i32, [_ctxp, _u64, _dp]),
     "mclbm_get_y": (_i32, [_ctxp, _dp]),

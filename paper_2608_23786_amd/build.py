@@ -8,7 +8,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmclbm.so")
 
-SOURCES = ["kernels.hip", "observables.hip", "api.hip"]
+SOURCES = ["step_d3q27.hip", "step_d3q19.hip", "kernels.hip", "observables.hip", "api.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

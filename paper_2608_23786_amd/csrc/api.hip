@@ -90,6 +90,7 @@ struct Table {
 struct mclbm_ctx {
   int m = 0;
   int precision = 0;
+  int q = 27;                // velocities of the lattice (27 or 19)
   size_t elem = 8;
   std::vector<mclbm_sample_desc> desc;
   hipStream_t stream = nullptr;
@@ -148,10 +149,11 @@ void drop_graphs(mclbm_ctx* c) {
   c->graphs.clear();
 }
 
-mclbm_status validate_desc(int32_t m, const mclbm_sample_desc* d, int32_t precision) {
+mclbm_status validate_desc(int32_t m, const mclbm_sample_desc* d, int32_t precision, int32_t lattice) {
   if (m < 1 || m > kMaxSamples) return fail(MCLBM_ERR_ARG, "m must be in [1, 256]");
   if (!d) return fail(MCLBM_ERR_ARG, "descriptor array is NULL");
   if (precision != MCLBM_FP64 && precision != MCLBM_FP32_SHIFTED) return fail(MCLBM_ERR_ARG, "unknown precision");
+  if (lattice != MCLBM_D3Q27 && lattice != MCLBM_D3Q19) return fail(MCLBM_ERR_ARG, "lattice must be 27 or 19");
   for (int s = 0; s < m; ++s) {
     const mclbm_sample_desc& e = d[s];
     const int nmax = precision == MCLBM_FP64 ? 512 : 1024;
@@ -169,7 +171,7 @@ mclbm_status validate_desc(int32_t m, const mclbm_sample_desc* d, int32_t precis
 }
 
 // Elements from one population plane to the next: n^3 plus a pad that keeps
-// the 27 plane addresses of a node off a common power-of-two stride.
+// the plane addresses of a node off a common power-of-two stride.
 uint64_t plane_stride(int n, size_t elem) {
   const uint64_t n3 = uint64_t(n) * n * n;
   if (n3 * elem < (uint64_t(1) << 16)) return n3;
@@ -180,7 +182,7 @@ struct Layout {
   size_t samples, flags, ycoef, pmat, tables, table_bytes, partials, partial_blocks, pop, state_bytes, total;
 };
 
-Layout layout_of(int32_t m, const mclbm_sample_desc* d, int32_t precision) {
+Layout layout_of(int32_t m, const mclbm_sample_desc* d, int32_t precision, int32_t lattice) {
   Layout L{};
   const size_t elem = precision == MCLBM_FP64 ? 8 : 4;
   size_t off = 0;
@@ -202,7 +204,7 @@ Layout layout_of(int32_t m, const mclbm_sample_desc* d, int32_t precision) {
   off = align_up(off + L.partial_blocks * kRecord * sizeof(double));
   L.pop = off;
   size_t st = 0;
-  for (int s = 0; s < m; ++s) st = align_up(st + size_t(Q) * plane_stride(d[s].n, elem) * elem);
+  for (int s = 0; s < m; ++s) st = align_up(st + size_t(lattice) * plane_stride(d[s].n, elem) * elem);
   L.state_bytes = st;
   off += st;
   L.total = off;
@@ -294,7 +296,7 @@ StepLaunch make_launch(mclbm_ctx* c, const Table* t, void* pop, void* dst) {
   L.buffer_ok = c->buffer_addr;
   L.nontemporal = c->nontemporal;
   for (int s = 0; s < c->m; ++s)
-    if (uint64_t(Q) * c->h_samples[s].pstride * c->elem >= (uint64_t(1) << 31)) L.buffer_ok = 0;
+    if (uint64_t(c->q) * c->h_samples[s].pstride * c->elem >= (uint64_t(1) << 31)) L.buffer_ok = 0;
   return L;
 }
 
@@ -321,7 +323,7 @@ mclbm_status run_tick(mclbm_ctx* c, double* record_out) {
       if (!e0 || !e1) return fail(MCLBM_ERR_HIP, "hipEventCreate failed");
       HIP_TRY(hipEventRecord(e0, c->stream));
     }
-    HIP_TRY(launch_step(c->precision, record_out ? kStepRecord : kStep, L, c->stream));
+    HIP_TRY(launch_step(c->q, c->precision, record_out ? kStepRecord : kStep, L, c->stream));
     if (c->timing) HIP_TRY(hipEventRecord(e1, c->stream));
     if (record_out)
       HIP_TRY(launch_record_finalize(c->d_partials, L.segs, t->nseg, c->d_samples, record_out, c->stream));
@@ -451,18 +453,18 @@ double mclbm_omega(int32_t n, double u0, double re) {
   return omega_of(lattice_nu(n, u0, re));
 }
 
-size_t mclbm_workspace_bytes(int32_t m, const mclbm_sample_desc* desc, int32_t precision) {
-  if (validate_desc(m, desc, precision) != MCLBM_OK) return 0;
-  return layout_of(m, desc, precision).total;
+size_t mclbm_workspace_bytes(int32_t m, const mclbm_sample_desc* desc, int32_t precision, int32_t lattice) {
+  if (validate_desc(m, desc, precision, lattice) != MCLBM_OK) return 0;
+  return layout_of(m, desc, precision, lattice).total;
 }
 
 mclbm_status mclbm_create(mclbm_ctx** out, int32_t m, const mclbm_sample_desc* desc, int32_t precision,
-                          void* workspace, size_t workspace_bytes, void* hip_stream) {
+                          int32_t lattice, void* workspace, size_t workspace_bytes, void* hip_stream) {
   if (!out) return fail(MCLBM_ERR_ARG, "out is NULL");
   *out = nullptr;
-  mclbm_status st = validate_desc(m, desc, precision);
+  mclbm_status st = validate_desc(m, desc, precision, lattice);
   if (st != MCLBM_OK) return st;
-  const Layout L = layout_of(m, desc, precision);
+  const Layout L = layout_of(m, desc, precision, lattice);
   if (!workspace) return fail(MCLBM_ERR_ARG, "workspace is NULL");
   if (reinterpret_cast<uintptr_t>(workspace) % kAlign) return fail(MCLBM_ERR_ARG, "workspace must be 256-byte aligned");
   if (workspace_bytes < L.total)
@@ -471,6 +473,7 @@ mclbm_status mclbm_create(mclbm_ctx** out, int32_t m, const mclbm_sample_desc* d
   mclbm_ctx* c = new mclbm_ctx();
   c->m = m;
   c->precision = precision;
+  c->q = lattice;
   c->elem = precision == MCLBM_FP64 ? 8 : 4;
   c->desc.assign(desc, desc + m);
   c->stream = static_cast<hipStream_t>(hip_stream);
@@ -502,7 +505,7 @@ mclbm_status mclbm_create(mclbm_ctx** out, int32_t m, const mclbm_sample_desc* d
     h.amp = desc[s].amp;
     h.project = desc[s].project;
     fill_sample(c, s, lattice_nu(desc[s]));
-    off = align_up(off + size_t(Q) * h.pstride * c->elem);
+    off = align_up(off + size_t(c->q) * h.pstride * c->elem);
     c->max_stride = std::max(c->max_stride, desc[s].stride);
   }
   hipError_t e = hipMemcpy(c->d_samples, c->h_samples.data(), sizeof(DevSample) * m, hipMemcpyHostToDevice);
@@ -560,7 +563,7 @@ mclbm_status mclbm_init(mclbm_ctx* c, uint64_t seed, const double* y_host) {
   const Table* t = nullptr;
   st = get_table(c, 0, true, kAuxBlock, true, &t);
   if (st != MCLBM_OK) return st;
-  HIP_TRY(launch_init(c->precision, c->pop, c->d_samples, table_ptr(c, t), t->nseg, t->total_blocks, c->d_ycoef,
+  HIP_TRY(launch_init(c->q, c->precision, c->pop, c->d_samples, table_ptr(c, t), t->nseg, t->total_blocks, c->d_ycoef,
                       c->stream));
   c->initialized = true;
   return MCLBM_OK;
@@ -623,7 +626,7 @@ mclbm_status mclbm_moments(mclbm_ctx* c, int32_t sample, double* rho_dev, double
   mclbm_status st = check_ctx(c, true);
   if (st != MCLBM_OK) return st;
   if (sample < 0 || sample >= c->m) return fail(MCLBM_ERR_ARG, "sample out of range");
-  HIP_TRY(launch_moments(c->precision, c->pop, c->d_samples, sample, c->desc[sample].n, int32_t(c->steps[sample] & 1),
+  HIP_TRY(launch_moments(c->q, c->precision, c->pop, c->d_samples, sample, c->desc[sample].n, int32_t(c->steps[sample] & 1),
                          rho_dev, u_dev, c->stream));
   return check_flags(c, nullptr);
 }
@@ -636,7 +639,7 @@ mclbm_status mclbm_reduce(mclbm_ctx* c, double* red_dev) {
   st = get_table(c, c->tick, true, c->block, false, &t);
   if (st != MCLBM_OK) return st;
   StepLaunch L = make_launch(c, t, c->pop, nullptr);
-  HIP_TRY(launch_step(c->precision, kReduceOnly, L, c->stream));
+  HIP_TRY(launch_step(c->q, c->precision, kReduceOnly, L, c->stream));
   HIP_TRY(launch_record_finalize(c->d_partials, L.segs, t->nseg, c->d_samples, red_dev, c->stream));
   return check_flags(c, nullptr);
 }
@@ -651,7 +654,7 @@ mclbm_status mclbm_get_state(mclbm_ctx* c, int32_t sample, double* f_dev) {
   mclbm_status st = check_ctx(c, true);
   if (st != MCLBM_OK) return st;
   if (sample < 0 || sample >= c->m || !f_dev) return fail(MCLBM_ERR_ARG, "bad sample or NULL buffer");
-  HIP_TRY(launch_get_state(c->precision, c->pop, c->d_samples, sample, c->desc[sample].n,
+  HIP_TRY(launch_get_state(c->q, c->precision, c->pop, c->d_samples, sample, c->desc[sample].n,
                            int32_t(c->steps[sample] & 1), f_dev, c->stream));
   return MCLBM_OK;
 }
@@ -660,7 +663,7 @@ mclbm_status mclbm_set_state(mclbm_ctx* c, int32_t sample, const double* f_dev) 
   mclbm_status st = check_ctx(c, true);
   if (st != MCLBM_OK) return st;
   if (sample < 0 || sample >= c->m || !f_dev) return fail(MCLBM_ERR_ARG, "bad sample or NULL buffer");
-  HIP_TRY(launch_set_state(c->precision, c->pop, c->d_samples, sample, c->desc[sample].n,
+  HIP_TRY(launch_set_state(c->q, c->precision, c->pop, c->d_samples, sample, c->desc[sample].n,
                            int32_t(c->steps[sample] & 1), f_dev, c->stream));
   return MCLBM_OK;
 }
@@ -677,7 +680,7 @@ mclbm_status mclbm_get_cells(mclbm_ctx* c, int32_t sample, const int64_t* cells_
   HIP_TRY(hipMemcpy(h.data(), cells_dev, sizeof(int64_t) * count, hipMemcpyDeviceToHost));
   for (int64_t v : h)
     if (v < 0 || v >= c->cells(sample)) return fail(MCLBM_ERR_ARG, "cell index out of range");
-  HIP_TRY(launch_gather_cells(c->precision, c->pop, c->d_samples, sample, int32_t(c->steps[sample] & 1), cells_dev,
+  HIP_TRY(launch_gather_cells(c->q, c->precision, c->pop, c->d_samples, sample, int32_t(c->steps[sample] & 1), cells_dev,
                               count, f_dev, c->stream));
   return MCLBM_OK;
 }
@@ -686,8 +689,9 @@ mclbm_status mclbm_poison(mclbm_ctx* c, int32_t sample, int64_t cell, int32_t i)
   mclbm_status st = check_ctx(c, true);
   if (st != MCLBM_OK) return st;
   if (sample < 0 || sample >= c->m) return fail(MCLBM_ERR_ARG, "sample out of range");
-  if (cell < 0 || cell >= c->cells(sample) || i < 0 || i >= Q) return fail(MCLBM_ERR_ARG, "cell or velocity out of range");
-  HIP_TRY(launch_poison(c->precision, c->pop, c->d_samples, sample, int32_t(c->steps[sample] & 1), cell, i, c->stream));
+  if (cell < 0 || cell >= c->cells(sample) || i < 0 || i >= c->q)
+    return fail(MCLBM_ERR_ARG, "cell or velocity out of range");
+  HIP_TRY(launch_poison(c->q, c->precision, c->pop, c->d_samples, sample, int32_t(c->steps[sample] & 1), cell, i, c->stream));
   return MCLBM_OK;
 }
 
@@ -698,14 +702,15 @@ mclbm_status mclbm_checkpoint(mclbm_ctx* c, void* dst_dev, size_t bytes) {
   if (st != MCLBM_OK) return st;
   if (!dst_dev) return fail(MCLBM_ERR_ARG, "dst_dev is NULL");
   if (bytes < mclbm_checkpoint_bytes(c)) return fail(MCLBM_ERR_OOM, "checkpoint buffer too small");
-  // header: magic, m, precision, tick, steps[m]
+  // header: magic, m, precision, lattice, tick, steps[m]
   HIP_TRY(hipStreamSynchronize(c->stream));
-  std::vector<int64_t> h(4 + c->m);
+  std::vector<int64_t> h(5 + c->m);
   h[0] = int64_t(kCkptMagic);
   h[1] = c->m;
   h[2] = c->precision;
-  h[3] = c->tick;
-  for (int s = 0; s < c->m; ++s) h[4 + s] = c->steps[s];
+  h[3] = c->q;
+  h[4] = c->tick;
+  for (int s = 0; s < c->m; ++s) h[5 + s] = c->steps[s];
   HIP_TRY(hipMemcpy(dst_dev, h.data(), sizeof(int64_t) * h.size(), hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpyAsync(static_cast<char*>(dst_dev) + kHeaderBytes, c->pop, c->state_bytes, hipMemcpyDeviceToDevice,
                          c->stream));
@@ -718,14 +723,14 @@ mclbm_status mclbm_restore(mclbm_ctx* c, const void* src_dev, size_t bytes) {
   if (!src_dev) return fail(MCLBM_ERR_ARG, "src_dev is NULL");
   if (bytes < mclbm_checkpoint_bytes(c)) return fail(MCLBM_ERR_OOM, "checkpoint buffer too small");
   HIP_TRY(hipStreamSynchronize(c->stream));
-  std::vector<int64_t> h(4 + c->m);
+  std::vector<int64_t> h(5 + c->m);
   HIP_TRY(hipMemcpy(h.data(), src_dev, sizeof(int64_t) * h.size(), hipMemcpyDeviceToHost));
-  if (h[0] != int64_t(kCkptMagic) || h[1] != c->m || h[2] != c->precision)
+  if (h[0] != int64_t(kCkptMagic) || h[1] != c->m || h[2] != c->precision || h[3] != c->q)
     return fail(MCLBM_ERR_ARG, "checkpoint does not belong to this ensemble");
   HIP_TRY(hipMemcpyAsync(c->pop, static_cast<const char*>(src_dev) + kHeaderBytes, c->state_bytes,
                          hipMemcpyDeviceToDevice, c->stream));
-  c->tick = h[3];
-  for (int s = 0; s < c->m; ++s) c->steps[s] = h[4 + s];
+  c->tick = h[4];
+  for (int s = 0; s < c->m; ++s) c->steps[s] = h[5 + s];
   HIP_TRY(hipMemsetAsync(c->d_flags, 0, sizeof(int32_t) * kMaxSamples, c->stream));
   return MCLBM_OK;
 }
@@ -765,7 +770,7 @@ mclbm_status mclbm_forward_ckpt(mclbm_ctx* c, int64_t ticks, int32_t ckpt_every,
     const Table* t = nullptr;
     st = get_table(c, c->tick, true, kAuxBlock, false, &t);
     if (st != MCLBM_OK) return st;
-    HIP_TRY(launch_canonical_copy(c->precision, c->pop, static_cast<char*>(ckpt_dev) + size_t(k) * c->state_bytes,
+    HIP_TRY(launch_canonical_copy(c->q, c->precision, c->pop, static_cast<char*>(ckpt_dev) + size_t(k) * c->state_bytes,
                                   c->d_samples, table_ptr(c, t), t->nseg, t->total_blocks, c->stream));
     st = run_plain_ticks(c, std::min<int64_t>(ckpt_every, ticks - k * ckpt_every));
     if (st != MCLBM_OK) return st;
@@ -799,7 +804,7 @@ mclbm_status mclbm_backward(mclbm_ctx* c, int64_t ticks, int32_t ckpt_every, con
     st = get_table(c, c->tick, true, c->block, false, &t);
     if (st != MCLBM_OK) return st;
     StepLaunch L = make_launch(c, t, c->pop, nullptr);
-    HIP_TRY(launch_step(c->precision, kReduceOnly, L, c->stream));
+    HIP_TRY(launch_step(c->q, c->precision, kReduceOnly, L, c->stream));
     HIP_TRY(launch_record_finalize(c->d_partials, L.segs, t->nseg, c->d_samples, records, c->stream));
     HIP_TRY(launch_extract(records, c->m, 4, ke_dev, c->stream));
   }
@@ -807,7 +812,7 @@ mclbm_status mclbm_backward(mclbm_ctx* c, int64_t ticks, int32_t ckpt_every, con
   const Table* aux = nullptr;      // every sample, live parities (seed)
   st = get_table(c, c->tick, true, kAuxBlock, false, &aux);
   if (st != MCLBM_OK) return st;
-  HIP_TRY(launch_adjoint_seed(c->precision, c->pop, lam[0], c->d_samples, table_ptr(c, aux), aux->nseg,
+  HIP_TRY(launch_adjoint_seed(c->q, c->precision, c->pop, lam[0], c->d_samples, table_ptr(c, aux), aux->nseg,
                               aux->total_blocks, 1.0 / c->m, c->stream));
   const Table* nat = nullptr;      // every sample, natural layout
   st = get_table(c, 0, true, kAuxBlock, true, &nat);
@@ -828,15 +833,15 @@ mclbm_status mclbm_backward(mclbm_ctx* c, int64_t ticks, int32_t ckpt_every, con
     };
     for (int64_t n = n0 + 1; n < n1; ++n) {
       StepLaunch L = make_launch(c, push, const_cast<char*>(state_at(n - 1)), const_cast<char*>(state_at(n)));
-      HIP_TRY(launch_step(c->precision, kPush, L, c->stream));
+      HIP_TRY(launch_step(c->q, c->precision, kPush, L, c->stream));
     }
     for (int64_t n = n1 - 1; n >= n0; --n) {
-      HIP_TRY(launch_adjoint_step(c->precision, state_at(n), lam[cur], lam[1 - cur], c->d_samples, table_ptr(c, nat),
+      HIP_TRY(launch_adjoint_step(c->q, c->precision, state_at(n), lam[cur], lam[1 - cur], c->d_samples, table_ptr(c, nat),
                                   nat->nseg, nat->total_blocks, buffer_ok, c->stream));
       cur = 1 - cur;
     }
   }
-  HIP_TRY(launch_init_adjoint(c->precision, lam[cur], c->d_samples, table_ptr(c, nat), nat->nseg, nat->total_blocks,
+  HIP_TRY(launch_init_adjoint(c->q, c->precision, lam[cur], c->d_samples, table_ptr(c, nat), nat->nseg, nat->total_blocks,
                               c->d_ycoef, partials, c->stream));
   HIP_TRY(launch_init_adjoint_finalize(partials, table_ptr(c, nat), nat->nseg, c->d_samples, c->d_pmat, dJdY_dev,
                                        c->stream));
@@ -863,7 +868,7 @@ mclbm_status mclbm_observables(mclbm_ctx* c, int32_t sample, double* s2_dev, dou
   double* u = static_cast<double*>(work_dev);
   double2* x = reinterpret_cast<double2*>(static_cast<char*>(work_dev) + align_up(3 * n3 * sizeof(double)));
   double* scratch = reinterpret_cast<double*>(reinterpret_cast<char*>(x) + align_up(3 * n3 * 2 * sizeof(double)));
-  HIP_TRY(launch_moments(c->precision, c->pop, c->d_samples, sample, n, int32_t(c->steps[sample] & 1), nullptr, u,
+  HIP_TRY(launch_moments(c->q, c->precision, c->pop, c->d_samples, sample, n, int32_t(c->steps[sample] & 1), nullptr, u,
                          c->stream));
   HIP_TRY(launch_fft3(n, x, u, 3, -1, c->stream));
   HIP_TRY(launch_psd(x, n3, x, c->stream));
@@ -885,7 +890,7 @@ mclbm_status mclbm_point_values(mclbm_ctx* c, int32_t q, double* out_dev) {
   const Table* t = nullptr;
   st = get_table(c, c->tick, true, kAuxBlock, false, &t);
   if (st != MCLBM_OK) return st;
-  HIP_TRY(launch_point_values(c->precision, c->pop, c->d_samples, table_ptr(c, t), t->nseg, q, out_dev, c->stream));
+  HIP_TRY(launch_point_values(c->q, c->precision, c->pop, c->d_samples, table_ptr(c, t), t->nseg, q, out_dev, c->stream));
   return MCLBM_OK;
 }
 

@@ -28,42 +28,50 @@ struct StepLaunch {
 
 enum StepKind { kStep = 0, kStepRecord = 1, kReduceOnly = 2, kPush = 3 };
 
-hipError_t launch_step(int precision, StepKind kind, const StepLaunch& L, hipStream_t s);
+// Lattice-dependent launches take the lattice q (27: D3Q27, 19: D3Q19) and the
+// precision (0: double, 1: float shifted populations).
+hipError_t launch_step(int q, int precision, StepKind kind, const StepLaunch& L, hipStream_t s);
+// per lattice and precision (step_d3q27.hip, step_d3q19.hip)
+hipError_t launch_step_d3q27_f32(StepKind kind, const StepLaunch& L, hipStream_t s);
+hipError_t launch_step_d3q27_f64(StepKind kind, const StepLaunch& L, hipStream_t s);
+hipError_t launch_step_d3q19_f32(StepKind kind, const StepLaunch& L, hipStream_t s);
+hipError_t launch_step_d3q19_f64(StepKind kind, const StepLaunch& L, hipStream_t s);
 
 // Records from block partials: one block per segment, writes out[sample*kRecord + k].
 hipError_t launch_record_finalize(const double* partials, const Seg* segs, int32_t nseg, const DevSample* samples,
                                   double* out, hipStream_t s);
 
 // Initial equilibrium populations of every sample in `segs` (blocks of 256 cells).
-hipError_t launch_init(int precision, void* pop, const DevSample* samples, const Seg* segs, int32_t nseg,
+hipError_t launch_init(int q, int precision, void* pop, const DevSample* samples, const Seg* segs, int32_t nseg,
                        int32_t total_blocks, const double* ycoef, hipStream_t s);
 
 // Density and velocity (double) of one sample; parity selects the AA layout.
-hipError_t launch_moments(int precision, const void* pop, const DevSample* samples, int32_t sample, int32_t n,
-                          int32_t parity, double* rho, double* u, hipStream_t s);
+hipError_t launch_moments(int q, int precision, const void* pop, const DevSample* samples, int32_t sample,
+                          int32_t n, int32_t parity, double* rho, double* u, hipStream_t s);
 
-// Unshifted populations f[27][n^3] in double, out of or into the state.
-hipError_t launch_get_state(int precision, const void* pop, const DevSample* samples, int32_t sample, int32_t n,
-                            int32_t parity, double* f, hipStream_t s);
-hipError_t launch_set_state(int precision, void* pop, const DevSample* samples, int32_t sample, int32_t n,
+// Unshifted populations f[q][n^3] in double, out of or into the state.
+hipError_t launch_get_state(int q, int precision, const void* pop, const DevSample* samples, int32_t sample,
+                            int32_t n, int32_t parity, double* f, hipStream_t s);
+hipError_t launch_set_state(int q, int precision, void* pop, const DevSample* samples, int32_t sample, int32_t n,
                             int32_t parity, const double* f, hipStream_t s);
-hipError_t launch_gather_cells(int precision, const void* pop, const DevSample* samples, int32_t sample, int32_t parity,
-                               const int64_t* cells, int32_t count, double* f, hipStream_t s);
-hipError_t launch_poison(int precision, void* pop, const DevSample* samples, int32_t sample, int32_t parity,
-                         int64_t cell, int32_t i, hipStream_t s);
+hipError_t launch_gather_cells(int q, int precision, const void* pop, const DevSample* samples, int32_t sample,
+                               int32_t parity, const int64_t* cells, int32_t count, double* f, hipStream_t s);
+// k: storage plane (population index in the lattice's own numbering)
+hipError_t launch_poison(int q, int precision, void* pop, const DevSample* samples, int32_t sample, int32_t parity,
+                         int64_t cell, int32_t k, hipStream_t s);
 
 // Copy the state of every sample in `segs` into natural layout at dst (same offsets).
-hipError_t launch_canonical_copy(int precision, const void* pop, void* dst, const DevSample* samples, const Seg* segs,
-                                 int32_t nseg, int32_t total_blocks, hipStream_t s);
+hipError_t launch_canonical_copy(int q, int precision, const void* pop, void* dst, const DevSample* samples,
+                                 const Seg* segs, int32_t nseg, int32_t total_blocks, hipStream_t s);
 
 // Adjoint: seed lambda_T from the state (parity-aware), one reverse step, and the
 // initial-data adjoint with its per-sample projection onto the 24 parameters.
-hipError_t launch_adjoint_seed(int precision, const void* pop, void* lam, const DevSample* samples, const Seg* segs,
-                               int32_t nseg, int32_t total_blocks, double inv_m, hipStream_t s);
-hipError_t launch_adjoint_step(int precision, const void* state, const void* lam_in, void* lam_out,
+hipError_t launch_adjoint_seed(int q, int precision, const void* pop, void* lam, const DevSample* samples,
+                               const Seg* segs, int32_t nseg, int32_t total_blocks, double inv_m, hipStream_t s);
+hipError_t launch_adjoint_step(int q, int precision, const void* state, const void* lam_in, void* lam_out,
                                const DevSample* samples, const Seg* segs, int32_t nseg, int32_t total_blocks,
                                int32_t buffer_ok, hipStream_t s);
-hipError_t launch_init_adjoint(int precision, const void* lam, const DevSample* samples, const Seg* segs,
+hipError_t launch_init_adjoint(int q, int precision, const void* lam, const DevSample* samples, const Seg* segs,
                                int32_t nseg, int32_t total_blocks, const double* ycoef, double* partials,
                                hipStream_t s);
 hipError_t launch_init_adjoint_finalize(const double* partials, const Seg* segs, int32_t nseg,
@@ -82,8 +90,9 @@ hipError_t launch_psd(const double2* x, size_t n3, double2* out, hipStream_t s);
 // scratch: shell_scratch_doubles(n) doubles.
 size_t shell_scratch_doubles(int n);
 hipError_t launch_shells(const double2* data, int n, int mode, double* scratch, double* out, hipStream_t s);
-hipError_t launch_point_values(int precision, const void* pop, const DevSample* samples, const Seg* segs,
-                               int32_t nseg, int q, double* out, hipStream_t s);
+// lattice: 27 or 19; q: common nodes per axis
+hipError_t launch_point_values(int lattice, int precision, const void* pop, const DevSample* samples,
+                               const Seg* segs, int32_t nseg, int q, double* out, hipStream_t s);
 hipError_t launch_w1(const double* a, const double* b, int m, int q, double* col, double* out, hipStream_t s);
 
 }  // namespace mclbm

@@ -209,7 +209,7 @@ __global__ void __launch_bounds__(256) shell_sum_kernel(const double* rowbins, c
 }
 
 // Velocity of every sample at the q^3 nodes x = (n/q) * j: out[s][3][q^3].
-template <typename T>
+template <int QN, typename T>
 __global__ void __launch_bounds__(64) point_values_kernel(const T* pop, const DevSample* samples, const Seg* segs,
                                                           int q, double* out) {
   const Seg sg = segs[blockIdx.y];
@@ -227,16 +227,17 @@ __global__ void __launch_bounds__(64) point_values_kernel(const T* pop, const De
   const bool odd = sg.parity & 1;
   double d = 0.0, jxs = 0.0, jys = 0.0, jzs = 0.0;
   for (int i = 0; i < Q; ++i) {
+    if (!in_lattice<QN>(i)) continue;
     size_t idx;
     int slot;
     if (!odd) {
       idx = (size_t(z) << (2 * l)) + (size_t(y) << l) + x;
-      slot = i;
+      slot = plane_of<QN>(i);
     } else {
       const uint32_t xs = (x - uint32_t(cx(i))) & msk, ys = (y - uint32_t(cy(i))) & msk,
                      zs = (z - uint32_t(cz(i))) & msk;
       idx = (size_t(zs) << (2 * l)) + (size_t(ys) << l) + xs;
-      slot = opposite(i);
+      slot = plane_of<QN>(opposite(i));
     }
     const double v = double(base[size_t(slot) * sp.pstride + idx]);
     d += v;
@@ -359,15 +360,23 @@ hipError_t launch_shells(const double2* data, int n, int mode, double* scratch, 
   return hipGetLastError();
 }
 
-hipError_t launch_point_values(int precision, const void* pop, const DevSample* samples, const Seg* segs,
-                               int32_t nseg, int q, double* out, hipStream_t s) {
-  const unsigned bx = unsigned((q * q * q + 63) / 64);
-  if (precision == 0)
-    hipLaunchKernelGGL(point_values_kernel<double>, dim3(bx, nseg), dim3(64), 0, s, static_cast<const double*>(pop),
+hipError_t launch_point_values(int lattice, int precision, const void* pop, const DevSample* samples,
+                               const Seg* segs, int32_t nseg, int q, double* out, hipStream_t s) {
+  const dim3 grid(unsigned((q * q * q + 63) / 64), unsigned(nseg));
+  if (lattice == 27 && precision == 0)
+    hipLaunchKernelGGL((point_values_kernel<27, double>), grid, dim3(64), 0, s, static_cast<const double*>(pop),
+                       samples, segs, q, out);
+  else if (lattice == 27)
+    hipLaunchKernelGGL((point_values_kernel<27, float>), grid, dim3(64), 0, s, static_cast<const float*>(pop),
+                       samples, segs, q, out);
+  else if (lattice == 19 && precision == 0)
+    hipLaunchKernelGGL((point_values_kernel<19, double>), grid, dim3(64), 0, s, static_cast<const double*>(pop),
+                       samples, segs, q, out);
+  else if (lattice == 19)
+    hipLaunchKernelGGL((point_values_kernel<19, float>), grid, dim3(64), 0, s, static_cast<const float*>(pop),
                        samples, segs, q, out);
   else
-    hipLaunchKernelGGL(point_values_kernel<float>, dim3(bx, nseg), dim3(64), 0, s, static_cast<const float*>(pop),
-                       samples, segs, q, out);
+    return hipErrorInvalidValue;
   return hipGetLastError();
 }
 

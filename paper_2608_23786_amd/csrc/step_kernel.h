@@ -1,0 +1,148 @@
+// The fused collide-and-stream kernel and its launch shapes. Each
+// (lattice, precision) pair is instantiated in a translation unit of its
+// own (step_d3q27.hip, step_d3q19.hip), which keeps the compile of the
+// library parallel.
+#pragma once
+
+#include "lbm_device.h"
+
+namespace mclbm {
+namespace {
+
+// ---------------------------------------------------------------- collide and stream
+template <typename T>
+struct StepArgs {
+  T* pop;
+  T* dst;
+  const DevSample* samples;
+  const Seg* segs;
+  int32_t nseg;
+  int32_t total_blocks;
+  int32_t xcd_remap;
+  int32_t* flags;
+  double* partials;
+};
+
+template <int QN, typename T, int BLOCK, StepKind KIND, bool BUF, bool NT>
+__global__ void __launch_bounds__(BLOCK) kbc_step_kernel(StepArgs<T> a) {
+  const int b = remap_block(blockIdx.x, a.total_blocks, a.xcd_remap);
+  const Seg sg = a.segs[find_segment(a.segs, a.nseg, b)];
+  const DevSample& sp = a.samples[sg.sample];
+  const int l = sp.log2n;
+  const Cell c = make_cell(uint32_t(b - sg.first_block) * BLOCK + threadIdx.x, l);
+  using Planes = typename std::conditional<BUF, BufPlanes<T, NT, QN>, PtrPlanes<T, NT, QN>>::type;
+  const Planes src(a.pop + sp.offset, sp.pstride);
+  const bool odd = (KIND != kPush) && (sg.parity & 1);
+
+  // rows longer than a wave, held whole by the block: x-shifts by lane exchange
+  const uint32_t n = 1u << l;
+  const bool rows = n > 64u && n <= uint32_t(BLOCK);
+  __shared__ EdgeLds<T, BLOCK> edge_in, edge_out;
+
+  T g[Q];
+  if (!odd) {
+    for_vel<QN>([&](auto ic) {
+      constexpr int i = decltype(ic)::value;
+      g[i] = src.load(i, c.cell);
+    });
+  } else if (rows) {
+    for_vel<QN>([&](auto ic) {
+      constexpr int i = decltype(ic)::value;
+      g[i] = src.load(opposite(i), neighbour_yz<i, -1>(c));
+    });
+    row_shift<QN, +1, BLOCK>(g, edge_in, n);
+  } else {
+    for_vel<QN>([&](auto ic) {
+      constexpr int i = decltype(ic)::value;
+      g[i] = src.load(opposite(i), neighbour<i, -1>(c));
+    });
+  }
+  const CellResult<T> res = kbc_collide<QN>(g, relax_of<T>(sp));
+  if (res.bad) a.flags[sg.sample] = 1;
+
+  if constexpr (KIND == kStep || KIND == kStepRecord || KIND == kPush) {
+    const bool pushes = KIND == kPush || odd;
+    T* const out = KIND == kPush ? a.dst : a.pop;
+    const Planes dst(out + sp.offset, sp.pstride);
+    if (!pushes) {
+      for_vel<QN>([&](auto ic) {
+        constexpr int i = decltype(ic)::value;
+        dst.store(opposite(i), c.cell, g[i]);
+      });
+    } else if (rows) {
+      row_shift<QN, +1, BLOCK>(g, edge_out, n);
+      for_vel<QN>([&](auto ic) {
+        constexpr int i = decltype(ic)::value;
+        dst.store(i, neighbour_yz<i, +1>(c), g[i]);
+      });
+    } else {
+      for_vel<QN>([&](auto ic) {
+        constexpr int i = decltype(ic)::value;
+        dst.store(i, neighbour<i, +1>(c), g[i]);
+      });
+    }
+  }
+
+  if constexpr (KIND == kStepRecord || KIND == kReduceOnly) {
+    const Macro<T>& m = res.m;
+    const double drho = double(m.drho);
+    const double jx = double(m.jx), jy = double(m.jy), jz = double(m.jz);
+    const double rho = 1.0 + drho;
+    const double ux = jx / rho, uy = jy / rho, uz = jz / rho;
+    double v[kRecord] = {drho, jx, jy, jz, 0.5 * (ux * ux + uy * uy + uz * uz), double(res.gamma),
+                         double(res.gamma), double(res.gamma)};
+    block_record<BLOCK>(v, a.partials + size_t(b) * kRecord);
+  }
+}
+
+template <int QN, typename T, int BLOCK, StepKind KIND>
+hipError_t launch_step_t(const StepLaunch& L, hipStream_t s) {
+  const bool buf = L.buffer_ok;
+  StepArgs<T> a;
+  a.pop = static_cast<T*>(L.pop);
+  a.dst = static_cast<T*>(L.dst);
+  a.samples = L.samples;
+  a.segs = L.segs;
+  a.nseg = L.nseg;
+  a.total_blocks = L.total_blocks;
+  a.xcd_remap = L.xcd_remap;
+  a.flags = L.flags;
+  a.partials = L.partials;
+  const dim3 grid(L.total_blocks), blk(BLOCK);
+  if (buf && L.nontemporal)
+    hipLaunchKernelGGL((kbc_step_kernel<QN, T, BLOCK, KIND, true, true>), grid, blk, 0, s, a);
+  else if (buf)
+    hipLaunchKernelGGL((kbc_step_kernel<QN, T, BLOCK, KIND, true, false>), grid, blk, 0, s, a);
+  else if (L.nontemporal)
+    hipLaunchKernelGGL((kbc_step_kernel<QN, T, BLOCK, KIND, false, true>), grid, blk, 0, s, a);
+  else
+    hipLaunchKernelGGL((kbc_step_kernel<QN, T, BLOCK, KIND, false, false>), grid, blk, 0, s, a);
+  return hipGetLastError();
+}
+
+template <int QN, typename T, StepKind KIND>
+hipError_t launch_step_b(const StepLaunch& L, hipStream_t s) {
+  switch (L.block) {
+    case 128: return launch_step_t<QN, T, 128, KIND>(L, s);
+    case 256: return launch_step_t<QN, T, 256, KIND>(L, s);
+    case 512: return launch_step_t<QN, T, 512, KIND>(L, s);
+    case 1024:
+      if constexpr (std::is_same<T, float>::value) return launch_step_t<QN, T, 1024, KIND>(L, s);
+      else return hipErrorInvalidValue;
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <int QN, typename T>
+hipError_t launch_step_k(StepKind kind, const StepLaunch& L, hipStream_t s) {
+  switch (kind) {
+    case kStep: return launch_step_b<QN, T, kStep>(L, s);
+    case kStepRecord: return launch_step_b<QN, T, kStepRecord>(L, s);
+    case kReduceOnly: return launch_step_b<QN, T, kReduceOnly>(L, s);
+    case kPush: return launch_step_b<QN, T, kPush>(L, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+}  // namespace
+}  // namespace mclbm

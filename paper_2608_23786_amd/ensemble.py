@@ -53,16 +53,17 @@ class Ensemble:
     """An ensemble of RTGV samples evolved in one in-place population buffer."""
 
     def __init__(self, samples: Sequence[Sample], precision: str = "f32s", device="cuda:0",
-                 stream: Optional[torch.cuda.Stream] = None):
+                 stream: Optional[torch.cuda.Stream] = None, lattice: int = 27):
         if precision not in PRECISIONS:
             raise ValueError(f"precision must be one of {list(PRECISIONS)}")
         self.samples: List[Sample] = list(samples)
         self.m = len(self.samples)
         self.precision = precision
+        self.q = int(lattice)   # 27 (D3Q27) or 19 (D3Q19); the library validates it
         self.device = torch.device(device)
         L = lib()
         self._desc = (SampleDesc * self.m)(*[s.desc() for s in self.samples])
-        nbytes = L.mclbm_workspace_bytes(self.m, self._desc, PRECISIONS[precision])
+        nbytes = L.mclbm_workspace_bytes(self.m, self._desc, PRECISIONS[precision], self.q)
         if nbytes == 0:
             # the library reports the reason of invalid descriptors on create
             nbytes = 256
@@ -71,7 +72,7 @@ class Ensemble:
         base = self.workspace.data_ptr()
         self._ws_ptr = (base + 255) // 256 * 256
         self._ctx = ctypes.c_void_p()
-        check(L.mclbm_create(ctypes.byref(self._ctx), self.m, self._desc, PRECISIONS[precision],
+        check(L.mclbm_create(ctypes.byref(self._ctx), self.m, self._desc, PRECISIONS[precision], self.q,
                              ctypes.c_void_p(self._ws_ptr), nbytes, ctypes.c_void_p(self.stream.cuda_stream)))
 
     def __del__(self):
@@ -166,7 +167,7 @@ class Ensemble:
     def get_state(self, sample: int) -> torch.Tensor:
         self._check_sample(sample)
         n = self.samples[sample].n
-        f = self._dev_empty((27, n, n, n))
+        f = self._dev_empty((self.q, n, n, n))
         check(lib().mclbm_get_state(self._ctx, sample, _ptr(f)))
         self._produce()
         return f
@@ -174,7 +175,7 @@ class Ensemble:
     def set_state(self, sample: int, f: torch.Tensor):
         self._check_sample(sample)
         n = self.samples[sample].n
-        _require_cuda(f, torch.float64, 27 * n ** 3, "f")
+        _require_cuda(f, torch.float64, self.q * n ** 3, "f")
         self._consume()
         check(lib().mclbm_set_state(self._ctx, sample, _ptr(f)))
         f.record_stream(self.stream)
@@ -203,9 +204,9 @@ class Ensemble:
         return out
 
     def get_cells(self, sample: int, cells) -> torch.Tensor:
-        """Populations f[k][27] (float64, device) of the given cell indices of one sample."""
+        """Populations f[k][q] (float64, device) of the given cell indices of one sample."""
         idx = torch.as_tensor(cells, dtype=torch.int64).to(self.device).contiguous()
-        out = self._dev_empty((idx.numel(), 27))
+        out = self._dev_empty((idx.numel(), self.q))
         self._consume()
         check(lib().mclbm_get_cells(self._ctx, sample, _ptr(idx), idx.numel(), _ptr(out)))
         self._produce()

@@ -57,22 +57,29 @@ def test_workspace_sizing_and_validation():
     import paper_2608_23786_amd as mc
     from paper_2608_23786_amd import _lib
     L = mc.lib()
+    Q27, Q19 = _lib.D3Q27, _lib.D3Q19
     good = (mc.SampleDesc * 2)(mc.Sample(32, 0.05, 100.0).desc(), mc.Sample(64, 0.025, 1600.0, 0.05, True, 2).desc())
-    nb32 = L.mclbm_workspace_bytes(2, good, _lib.FP32_SHIFTED)
-    nb64 = L.mclbm_workspace_bytes(2, good, _lib.FP64)
+    nb32 = L.mclbm_workspace_bytes(2, good, _lib.FP32_SHIFTED, Q27)
+    nb64 = L.mclbm_workspace_bytes(2, good, _lib.FP64, Q27)
     assert nb32 >= 27 * (32 ** 3 + 64 ** 3) * 4
     assert nb64 >= 27 * (32 ** 3 + 64 ** 3) * 8
     assert nb64 > nb32
+    # D3Q19 stores 19 planes per sample: 8 planes fewer than D3Q27
+    nb19 = L.mclbm_workspace_bytes(2, good, _lib.FP32_SHIFTED, Q19)
+    assert nb19 >= 19 * (32 ** 3 + 64 ** 3) * 4
+    assert nb32 - nb19 >= 8 * (32 ** 3 + 64 ** 3) * 4
     for bad in (mc.Sample(48, 0.05, 100.0), mc.Sample(4, 0.05, 100.0), mc.Sample(32, 0.0, 100.0),
                 mc.Sample(32, 0.05, -1.0), mc.Sample(32, 0.05, 100.0, stride=3),
                 mc.Sample(32, 0.05, 100.0, amp=float("nan"))):
         arr = (mc.SampleDesc * 1)(bad.desc())
-        assert L.mclbm_workspace_bytes(1, arr, _lib.FP32_SHIFTED) == 0
+        assert L.mclbm_workspace_bytes(1, arr, _lib.FP32_SHIFTED, Q27) == 0
     arr = (mc.SampleDesc * 1)(mc.Sample(1024, 0.05, 100.0).desc())
-    assert L.mclbm_workspace_bytes(1, arr, _lib.FP64) == 0          # FP64 limited to n <= 512
-    assert L.mclbm_workspace_bytes(1, arr, _lib.FP32_SHIFTED) > 0
-    assert L.mclbm_workspace_bytes(0, arr, _lib.FP32_SHIFTED) == 0
-    assert L.mclbm_workspace_bytes(1, arr, 7) == 0
+    assert L.mclbm_workspace_bytes(1, arr, _lib.FP64, Q27) == 0          # FP64 limited to n <= 512
+    assert L.mclbm_workspace_bytes(1, arr, _lib.FP32_SHIFTED, Q27) > 0
+    assert L.mclbm_workspace_bytes(0, arr, _lib.FP32_SHIFTED, Q27) == 0
+    assert L.mclbm_workspace_bytes(1, arr, 7, Q27) == 0
+    for lattice in (0, 15, 26, 28):
+        assert L.mclbm_workspace_bytes(1, arr, _lib.FP32_SHIFTED, lattice) == 0
 
 
 def test_create_rejects_bad_arguments_before_touching_the_device():
@@ -81,11 +88,14 @@ def test_create_rejects_bad_arguments_before_touching_the_device():
     L = mc.lib()
     arr = (mc.SampleDesc * 1)(mc.Sample(16, 0.05, 100.0).desc())
     ctx = ctypes.c_void_p()
-    assert L.mclbm_create(ctypes.byref(ctx), 1, arr, _lib.FP64, None, 1 << 20, None) == _lib.ERR_ARG
+    q27 = _lib.D3Q27
+    assert L.mclbm_create(ctypes.byref(ctx), 1, arr, _lib.FP64, q27, None, 1 << 20, None) == _lib.ERR_ARG
     assert "workspace" in L.mclbm_last_error().decode()
-    assert L.mclbm_create(ctypes.byref(ctx), 1, arr, _lib.FP64, ctypes.c_void_p(256), 16, None) == _lib.ERR_OOM
-    assert L.mclbm_create(ctypes.byref(ctx), 1, arr, _lib.FP64, ctypes.c_void_p(100), 1 << 30, None) == _lib.ERR_ARG
-    assert L.mclbm_create(None, 1, arr, _lib.FP64, ctypes.c_void_p(256), 1 << 30, None) == _lib.ERR_ARG
+    assert L.mclbm_create(ctypes.byref(ctx), 1, arr, _lib.FP64, q27, ctypes.c_void_p(256), 16, None) == _lib.ERR_OOM
+    assert L.mclbm_create(ctypes.byref(ctx), 1, arr, _lib.FP64, q27, ctypes.c_void_p(100), 1 << 30, None) == _lib.ERR_ARG
+    assert L.mclbm_create(None, 1, arr, _lib.FP64, q27, ctypes.c_void_p(256), 1 << 30, None) == _lib.ERR_ARG
+    assert L.mclbm_create(ctypes.byref(ctx), 1, arr, _lib.FP64, 21, ctypes.c_void_p(256), 1 << 30, None) == _lib.ERR_ARG
+    assert "lattice" in L.mclbm_last_error().decode()
     assert L.mclbm_stream_copy(None, None, 16, None) == _lib.ERR_ARG
     assert L.mclbm_ticks(None) == -1
 

@@ -93,6 +93,30 @@ def test_central_differences_of_gpu_forward():
         assert abs(fd - dj[s, p]) <= 1e-6 * np.max(np.abs(dj)), (s, p, fd, dj[s, p])
 
 
+def test_central_differences_at_128_cubed():
+    """Rows of two waves: the adjoint pulls lambda and the recompute pushes
+    populations by lane exchange. Central differences of the GPU FP64
+    forward over both AA parities and two checkpoint segments."""
+    samples = [mc.Sample(128, 0.0125, 1600.0, 0.3, True)]
+    steps, every, h = 6, 3, 1e-3
+    y = mc_inputs.draw_y(29, 1)
+    dj, _, _ = gpu_gradient(samples, "f64", y, steps, every)
+
+    def J(yy):
+        ens = mc.Ensemble(samples, "f64")
+        ens.init(0, torch.from_numpy(yy))
+        ens.step(steps)
+        return float(ens.reduce()[:, 4].mean())
+
+    for p in (0, 11, 17):
+        yp, ym = y.copy(), y.copy()
+        yp[0, p] += h
+        ym[0, p] -= h
+        fd = (J(yp) - J(ym)) / (2 * h)
+        print(f"p={p}: fd {fd:.6e} adjoint {dj[0, p]:.6e}")
+        assert abs(fd - dj[0, p]) <= 1e-6 * np.max(np.abs(dj)), (p, fd, dj[0, p])
+
+
 def test_projected_gradient_lies_in_the_range_of_the_projection():
     """With the Leray projection on, J depends on Y only through P Y, so dJ/dY
     is annihilated by I - P (P symmetric idempotent on the coefficients)."""

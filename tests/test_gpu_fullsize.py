@@ -130,11 +130,15 @@ def test_fp64_full_size_sampled_steps():
     print(f"sampled one-step error (FP64): {worst:.3e}")
 
 
-def test_512_cubed_sample_sampled_steps():
-    """One 512^3 FP32 sample (14.5 GB of populations, pointer addressing)."""
+@pytest.mark.parametrize("block", [256, 1024])
+def test_512_cubed_sample_sampled_steps(block):
+    """One 512^3 FP32 sample (14.5 GB of populations, pointer addressing);
+    block 256 addresses x-shifts directly, block 1024 (two rows of 8 waves)
+    by lane exchange."""
     n = 512
     ens = mc.Ensemble([mc.Sample(n, 0.05 * 32 / n, 12.5 * n, 0.05, True)], "f32s")
     ens.init(2611)
+    ens.set_launch(block, 0, 0, 1)
     ens.step(2)
     rng = np.random.default_rng(512)
     worst = max(check_one_step(ens, [0], 32, rng, 2e-6), check_one_step(ens, [0], 32, rng, 2e-6))

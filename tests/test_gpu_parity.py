@@ -232,6 +232,36 @@ def test_results_do_not_depend_on_launch_shape_or_graphs(precision):
             assert np.array_equal(a, b), (block, xcd, graphs, buf, nt)
 
 
+def run_rows_state(precision, block, ticks=9):
+    """1 x 128^3 (stride 4) + 1 x 256^3: rows of 2 and 4 waves."""
+    y = mc_inputs.draw_y(31, 2)
+    ens = mc.Ensemble([mc.Sample(128, 0.0125, 1600.0, 0.3, True, 4), mc.Sample(256, 0.00625, 3200.0, 0.3, True, 1)],
+                      precision)
+    ens.init(0, torch.from_numpy(y))
+    ens.set_launch(block, 0, 1, 1)
+    ens.use_graphs(False)
+    rec = ens.step(ticks - 1, record_every=4).cpu().numpy()
+    ens.step(1)
+    return [ens.get_state(s).cpu().numpy() for s in range(2)], rec
+
+
+@pytest.mark.parametrize("precision,blocks", [("f32s", (128, 512, 1024)), ("f64", (128, 256, 512))])
+def test_row_exchange_is_bitwise_equal_to_direct_addressing(precision, blocks):
+    """Rows longer than a wave held whole by a block move their x-shifted
+    populations by lane exchange instead of direct addresses. The arithmetic
+    is the same, so the state after several ticks of both AA parities (and
+    the fused records) must be bitwise equal: 256^3 with block 128 is
+    addressed directly, with larger blocks by exchange (4 waves per row);
+    128^3 uses the exchange in every shape."""
+    ref, rec_ref = run_rows_state(precision, blocks[0])
+    for block in blocks[1:]:
+        out, rec = run_rows_state(precision, block)
+        for s, (a, b) in enumerate(zip(ref, out)):
+            assert np.array_equal(a, b), (block, s)
+        # block partials are summed in another order: the records agree to rounding
+        assert np.allclose(rec, rec_ref, rtol=1e-12, atol=1e-12), block
+
+
 def test_checkpoint_restore_is_exact():
     y = mc_inputs.draw_y(4, 2)
     ens = mc.Ensemble([mc.Sample(16, 0.05, 100.0, 0.2, True), mc.Sample(8, 0.05, 100.0, 0.2, True, 2)], "f32s")
