@@ -260,11 +260,21 @@ def bench_sequence(mc, torch):
     samples = []
     for g in wl.groups:
         samples += [mc.Sample(g.n, g.u0, g.re, g.amp, g.project, g.stride)] * g.count
+    # launch shape: autotuned on one sample of the finest resolution, which
+    # steps on every tick and carries 95 % of the updates (tuning the whole
+    # ensemble would time 64 ticks of 1.1e9 updates per candidate)
+    finest = wl.groups[-1]
+    proxy = mc.Ensemble([mc.Sample(finest.n, finest.u0, finest.re, finest.amp, finest.project)], wl.precision,
+                        lattice=wl.lattice)
+    proxy.init(wl.seed)
+    tuned = proxy.autotune(reps=2)
+    del proxy
+    torch.cuda.empty_cache()
     ens = mc.Ensemble(samples, wl.precision, lattice=wl.lattice)
     per = wl.groups[0].count
     y = np.tile(mc_inputs.draw_y(wl.seed, per), (len(wl.groups), 1))
     ens.init(0, torch.from_numpy(y))
-    tuned = ens.autotune(reps=1)
+    ens.set_launch(*tuned)
     ticks, every = wl.ticks, wl.save_every
     sec, lups = timed_ticks(ens, torch, ticks, every)
     if ens.check() >= 0:
@@ -286,6 +296,26 @@ def bench_sequence(mc, torch):
     del ens, pv
     torch.cuda.empty_cache()
     return out
+
+
+# ensembles for the counter runs of the collide-and-stream kernel beyond the
+# default workload: (lattice, samples, n, block, buffer addressing)
+TRAFFIC_PROBES = ((27, 8, 128, 512, 1), (27, 4, 256, 512, 1), (27, 1, 512, 512, 0), (19, 64, 64, 256, 1))
+
+
+def traffic_probe(mc, torch, ticks=4):
+    """A few plain ticks of each TRAFFIC_PROBES ensemble (FP32, graphs off), for
+    hardware-counter passes; prints one line per ensemble."""
+    for q, m, n, block, buf in TRAFFIC_PROBES:
+        ens = mc.Ensemble([mc.Sample(n, 0.05 * 32 / n, 25.0 * n, 0.05, True)] * m, "f32s", lattice=q)
+        ens.init(3)
+        ens.set_launch(block, 0, buf, 1)
+        ens.use_graphs(False)
+        ens.step(ticks)
+        ens.synchronize()
+        print(f"[traffic-probe] D3Q{q} {m} x {n}^3 block {block} buffer {buf}: {ticks} ticks", flush=True)
+        del ens
+        torch.cuda.empty_cache()
 
 
 def cpu_baseline(seconds_target=15.0):
@@ -324,6 +354,8 @@ def main():
     ap.add_argument("--sweep", action="store_true", help="time every launch shape and report the table")
     ap.add_argument("--no-extra", action="store_true", help="skip the mixed-resolution and adjoint workloads")
     ap.add_argument("--no-capacity", action="store_true", help="skip the 132 GB vanishing-viscosity sequence")
+    ap.add_argument("--traffic-probe", action="store_true",
+                    help="only run a few ticks of the larger-lattice and D3Q19 ensembles (for counter passes)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (this build has no multi-GPU path); got --gpus {args.gpus}",
@@ -334,6 +366,9 @@ def main():
     import mc_inputs
     import paper_2608_23786_amd as mc
 
+    if args.traffic_probe:
+        traffic_probe(mc, torch)
+        return
     wl = mc_inputs.WORKLOADS[args.workload]
     print(f"[bench] workload {wl.name}: {wl.m} samples, precision {wl.precision}", file=sys.stderr, flush=True)
     b_meas = stream_bandwidth(mc, torch, nbytes=int(args.copy_gib * (1 << 30)) // 16 * 16)

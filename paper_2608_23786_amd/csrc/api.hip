@@ -956,12 +956,18 @@ mclbm_status mclbm_autotune(mclbm_ctx* c, int32_t reps, void* scratch_dev, size_
   HIP_TRY(hipEventCreate(&e0));
   HIP_TRY(hipEventCreate(&e1));
   const int64_t per = 2 * int64_t(c->max_stride) * reps;
+  // buffer addressing needs every sample's populations below 2 GiB; without
+  // it both settings run the same pointer kernels, so only one is timed
+  bool buffer_possible = true;
+  for (int s = 0; s < c->m; ++s)
+    buffer_possible = buffer_possible && uint64_t(c->q) * c->h_samples[s].pstride * c->elem < (uint64_t(1) << 31);
   for (int b : blocks) {
     bool fits = !(b == 1024 && c->precision == MCLBM_FP64);
     for (int s = 0; s < c->m; ++s) fits = fits && c->cells(s) >= b;
     if (!fits) continue;
     for (int v = 0; v < 8; ++v) {
       const int x = v & 1, f = (v >> 1) & 1, nt = v >> 2;
+      if (f && !buffer_possible) continue;
       c->block = b;
       c->xcd_remap = x;
       c->buffer_addr = f;
