@@ -34,8 +34,9 @@
 // (17 of order 3 to 6 for D3Q27; for D3Q19 the 6 of order 3 and the 3 of
 // order 4, the Q and A tensors of Table 1).
 //
-// When <dh|dh> <= 1e-30 the closed form is undefined; gamma = 2 (BGK) is
-// used then. The hom part is zero in that case up to rounding.
+// When <dh|dh> <= 1e-30 the closed form is undefined and the exact
+// minimiser is set by rounding noise alone; gamma = 2 (BGK) is used then by
+// both. The hom part is zero in that case up to rounding.
 //
 // Scalar type: double, or std::complex<double> for complex-step derivatives
 // (every operation below is analytic in the populations; the threshold test
@@ -290,10 +291,12 @@ void collide(const T f[Q], double omega, int mode, T fstar[Q], T* gamma_out, T d
     }
     if (re(hh) > 1e-30) gamma = 2.0 / omega - (2.0 - 2.0 / omega) * sh / hh;
   } else if (mode == 2) {
+    // the same threshold as the closed form: with <dh|dh> <= 1e-30 the
+    // H-function does not depend on gamma beyond rounding, and gamma = 2
     if constexpr (std::is_same<T, double>::value) {
       double hh = 0.0;
-      for (int i = 0; i < Q; ++i) hh += dh[i] * dh[i];
-      if (hh > 0.0) gamma = exact_entropic_gamma<Q>(f, ds, dh, omega);
+      for (int i = 0; i < Q; ++i) hh += dh[i] * dh[i] / feq[i];
+      if (hh > 1e-30) gamma = exact_entropic_gamma<Q>(f, ds, dh, omega);
     }
   }
   // relaxation rates per group: kinematic 0, shear omega, hom omega*gamma/2
