@@ -26,7 +26,8 @@ BYTES_PER_LUP = {("f32s", 27): 216, ("f64", 27): 432, ("f32s", 19): 152, ("f64",
 
 # sources the collide-and-stream kernel is compiled from (the counter summary
 # is valid only for the exact sources it was taken with)
-STEP_SOURCES = ["lattice.h", "lbm_device.h", "step_kernel.h", "step_d3q27.hip", "step_d3q19.hip"]
+STEP_SOURCES = ["lattice.h", "lbm_device.h", "step_kernel.h", "step_d3q27_f32.hip", "step_d3q27_f64.hip",
+                "step_d3q19_f32.hip", "step_d3q19_f64.hip"]
 
 
 def step_source_hash():

@@ -89,6 +89,11 @@ typedef enum {
 } mclbm_precision;
 
 typedef enum {
+  MCLBM_GAMMA_CLOSED_FORM = 0, /* eq. (entropyControl): first-order closed form (default) */
+  MCLBM_GAMMA_EXACT = 1        /* eq. (kbc_entropy): minimiser of the discrete H-function */
+} mclbm_stabiliser;
+
+typedef enum {
   MCLBM_D3Q27 = 27,          /* 27 velocities; hom group: T and 17 moments of order 3-6 */
   MCLBM_D3Q19 = 19           /* 19 velocities; hom group: T, Q (order 3), A (order 4) of Table 1 */
 } mclbm_lattice;
@@ -236,6 +241,19 @@ mclbm_status mclbm_point_values(mclbm_ctx* ctx, int32_t q, double* out_dev);
 size_t mclbm_w1_work_bytes(int32_t q);
 mclbm_status mclbm_w1_1pt(const double* a_dev, const double* b_dev, int32_t m, int32_t q, double* out_dev,
                           void* work_dev, size_t work_bytes, void* hip_stream);
+
+/* Stabiliser gamma of the higher-order relaxation omega_hom = omega gamma / 2
+ * (Table 1). MCLBM_GAMMA_CLOSED_FORM (default) evaluates eq. (entropyControl).
+ * MCLBM_GAMMA_EXACT minimises the discrete H-function of the post-collision
+ * state, eq. (kbc_entropy): with t = omega gamma / 2, H(t) is convex where
+ * every f*_i > 0; four safeguarded Newton steps on H'(t) = 0 start from the
+ * closed form (a step leaving that interval is replaced by the midpoint
+ * towards its edge), so the records report the exact gamma. The exact mode
+ * runs 256-thread blocks only (mclbm_set_launch accepts no other size then,
+ * mclbm_autotune returns MCLBM_ERR_UNSUPPORTED) and has no adjoint
+ * (mclbm_forward_ckpt and mclbm_backward return MCLBM_ERR_UNSUPPORTED).
+ * Captured graphs are dropped. MCLBM_ERR_ARG for any other mode. */
+mclbm_status mclbm_set_stabiliser(mclbm_ctx* ctx, int32_t mode);
 
 /* Launch shape of the collide-and-stream kernel, one for the whole ensemble
  * launch: threads (= lattice nodes) per block, 128, 256, 512 or 1024 (1024:

@@ -15,6 +15,7 @@ STATUS_NAMES = {0: "OK", 1: "ERR_ARG", 2: "ERR_OOM", 3: "ERR_HIP", 4: "ERR_STATE
                 6: "ERR_UNSUPPORTED"}
 FP64, FP32_SHIFTED = 0, 1
 D3Q27, D3Q19 = 27, 19
+GAMMA_CLOSED_FORM, GAMMA_EXACT = 0, 1
 
 
 class SampleDesc(ctypes.Structure):
@@ -71,6 +72,7 @@ SIGNATURES = {
     "mclbm_set_launch": (_i32, [_ctxp, _i32, _i32, _i32, _i32]),
     "mclbm_get_launch": (_i32, [_ctxp, _ip, _ip, _ip, _ip]),
     "mclbm_autotune": (_i32, [_ctxp, _i32, _vp, _sz, _ip, _ip, _ip, _ip]),
+    "mclbm_set_stabiliser": (_i32, [_ctxp, _i32]),
     "mclbm_use_graphs": (_i32, [_ctxp, _i32]),
     "mclbm_ticks": (_i64, [_ctxp]),
     "mclbm_steps": (_i64, [_ctxp, _i32]),

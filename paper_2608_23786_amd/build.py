@@ -8,7 +8,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmclbm.so")
 
-SOURCES = ["step_d3q27.hip", "step_d3q19.hip", "kernels.hip", "observables.hip", "api.hip"]
+SOURCES = ["step_d3q27_f32.hip", "step_d3q27_f64.hip", "step_d3q19_f32.hip", "step_d3q19_f64.hip", "kernels.hip",
+           "observables.hip", "api.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

@@ -122,6 +122,7 @@ struct mclbm_ctx {
   int xcd_remap = 0;
   int buffer_addr = 1;       // buffer-resource addressing where every sample fits
   int nontemporal = 1;       // non-temporal population loads and stores
+  int exact_gamma = 0;       // 1: exact entropic stabiliser (256-thread blocks)
 
   // launch tables by key
   std::map<std::string, Table> tables;
@@ -295,6 +296,7 @@ StepLaunch make_launch(mclbm_ctx* c, const Table* t, void* pop, void* dst) {
   L.partials = c->d_partials;
   L.buffer_ok = c->buffer_addr;
   L.nontemporal = c->nontemporal;
+  L.exact_gamma = c->exact_gamma;
   for (int s = 0; s < c->m; ++s)
     if (uint64_t(c->q) * c->h_samples[s].pstride * c->elem >= (uint64_t(1) << 31)) L.buffer_ok = 0;
   return L;
@@ -757,6 +759,7 @@ static mclbm_status check_adjoint(mclbm_ctx* c, int64_t ticks, int32_t ckpt_ever
   if (ticks < 1 || ckpt_every < 1) return fail(MCLBM_ERR_ARG, "ticks and ckpt_every must be >= 1");
   for (int s = 0; s < c->m; ++s)
     if (c->desc[s].stride != 1) return fail(MCLBM_ERR_UNSUPPORTED, "the adjoint needs every stride to be 1");
+  if (c->exact_gamma) return fail(MCLBM_ERR_UNSUPPORTED, "the adjoint is built for the closed-form stabiliser");
   return MCLBM_OK;
 }
 
@@ -917,6 +920,8 @@ mclbm_status mclbm_set_launch(mclbm_ctx* c, int32_t block_threads, int32_t xcd_r
     return fail(MCLBM_ERR_UNSUPPORTED, "1024-thread blocks are built for the FP32 path only");
   for (int s = 0; s < c->m; ++s)
     if (c->cells(s) < block_threads) return fail(MCLBM_ERR_ARG, "block larger than a sample's lattice");
+  if (c->exact_gamma && block_threads != 256)
+    return fail(MCLBM_ERR_UNSUPPORTED, "the exact stabiliser runs 256-thread blocks only");
   if (xcd_remap != 0 && xcd_remap != 1) return fail(MCLBM_ERR_ARG, "xcd_remap must be 0 or 1");
   if (buffer_addressing != 0 && buffer_addressing != 1) return fail(MCLBM_ERR_ARG, "buffer_addressing must be 0 or 1");
   if (nontemporal != 0 && nontemporal != 1) return fail(MCLBM_ERR_ARG, "nontemporal must be 0 or 1");
@@ -944,6 +949,7 @@ mclbm_status mclbm_autotune(mclbm_ctx* c, int32_t reps, void* scratch_dev, size_
   mclbm_status st = check_ctx(c, true);
   if (st != MCLBM_OK) return st;
   if (reps < 1) return fail(MCLBM_ERR_ARG, "reps must be >= 1");
+  if (c->exact_gamma) return fail(MCLBM_ERR_UNSUPPORTED, "the exact stabiliser has one launch shape");
   st = mclbm_checkpoint(c, scratch_dev, scratch_bytes);
   if (st != MCLBM_OK) return st;
   const bool timing0 = c->timing, graphs0 = c->use_graphs;
@@ -1011,6 +1017,18 @@ mclbm_status mclbm_autotune(mclbm_ctx* c, int32_t reps, void* scratch_dev, size_
   if (best_buffer) *best_buffer = bf;
   if (best_nt) *best_nt = bn;
   return mclbm_restore(c, scratch_dev, scratch_bytes);
+}
+
+mclbm_status mclbm_set_stabiliser(mclbm_ctx* c, int32_t mode) {
+  mclbm_status st = check_ctx(c, false);
+  if (st != MCLBM_OK) return st;
+  if (mode != MCLBM_GAMMA_CLOSED_FORM && mode != MCLBM_GAMMA_EXACT)
+    return fail(MCLBM_ERR_ARG, "stabiliser mode must be 0 (closed form) or 1 (exact)");
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  c->exact_gamma = mode == MCLBM_GAMMA_EXACT;
+  if (c->exact_gamma) c->block = 256;  // every lattice has at least 512 nodes
+  drop_graphs(c);
+  return MCLBM_OK;
 }
 
 mclbm_status mclbm_use_graphs(mclbm_ctx* c, int32_t enable) {

@@ -24,6 +24,7 @@ struct StepLaunch {
   double* partials;          // record mode: kRecord doubles per block
   int32_t buffer_ok;         // buffer-resource addressing (every sample's populations span < 2 GiB)
   int32_t nontemporal;       // non-temporal loads and stores of the populations
+  int32_t exact_gamma;       // 1: exact minimiser of the H-function (block 256 only)
 };
 
 enum StepKind { kStep = 0, kStepRecord = 1, kReduceOnly = 2, kPush = 3 };
@@ -31,7 +32,7 @@ enum StepKind { kStep = 0, kStepRecord = 1, kReduceOnly = 2, kPush = 3 };
 // Lattice-dependent launches take the lattice q (27: D3Q27, 19: D3Q19) and the
 // precision (0: double, 1: float shifted populations).
 hipError_t launch_step(int q, int precision, StepKind kind, const StepLaunch& L, hipStream_t s);
-// per lattice and precision (step_d3q27.hip, step_d3q19.hip)
+// per lattice and precision (step_d3q27_f32.hip, ...)
 hipError_t launch_step_d3q27_f32(StepKind kind, const StepLaunch& L, hipStream_t s);
 hipError_t launch_step_d3q27_f64(StepKind kind, const StepLaunch& L, hipStream_t s);
 hipError_t launch_step_d3q19_f32(StepKind kind, const StepLaunch& L, hipStream_t s);

@@ -231,9 +231,63 @@ struct CellResult {
   bool bad;
 };
 
-// KBC collision of one node in place: g <- g*. Between the passes g[] holds
-// the shifted equilibrium, so every g^eq_i is evaluated once.
+// Exact entropic stabiliser (eq. (kbc_entropy)): with t = omega gamma / 2 the
+// post-collision populations are f*_i(t) = b_i - t dh_i, b_i = f_i - omega ds_i,
+// and H(t) = sum f*_i ln(f*_i / w_i) is convex in t on the interval where
+// every f*_i > 0, with
+//   -H'(t) = sum dh_i ln(f*_i / w_i)      (sum dh_i = 0),
+//    H''(t) = sum dh_i^2 / f*_i.
+// Newton's method from the closed-form t (the first-order solution of
+// H'(t) = 0) converges quadratically; a step that would leave the interval is
+// replaced by the midpoint towards its edge. ln(f*_i / w_i) is evaluated as
+// log1p((f*_i - w_i) / w_i) from the shifted values, which keeps its relative
+// accuracy for populations near their weights.
+constexpr int kExactNewtonSteps = 4;
+
 template <int QN, typename T>
+__device__ __forceinline__ T exact_entropic_t(const T (&geq)[Q], const T (&fneq)[Q], const Shear<T>& s, T omega,
+                                              T t) {
+  T lo = T(-1e30), hi = T(1e30);
+  for_vel<QN>([&](auto ic) {
+    constexpr int i = decltype(ic)::value;
+    if constexpr (nonzeros(i) == 1 || nonzeros(i) == 2) {
+      const T ds = shear_part<i>(s);
+      const T dh = fneq[i] - ds;
+      const T base = (T(weight<QN>(i)) + geq[i]) + (fneq[i] - omega * ds);
+      if (dh > T(0)) hi = vmin(hi, base / dh);
+      if (dh < T(0)) lo = lo > base / dh ? lo : base / dh;
+    } else {
+      const T dh = fneq[i];
+      const T base = T(weight<QN>(i)) + geq[i] + fneq[i];
+      if (dh > T(0)) hi = vmin(hi, base / dh);
+      if (dh < T(0)) lo = lo > base / dh ? lo : base / dh;
+    }
+  });
+  for (int it = 0; it < kExactNewtonSteps; ++it) {
+    T d1 = T(0), d2 = T(0);
+    for_vel<QN>([&](auto ic) {
+      constexpr int i = decltype(ic)::value;
+      T ds = T(0);
+      if constexpr (nonzeros(i) == 1 || nonzeros(i) == 2) ds = shear_part<i>(s);
+      const T dh = fneq[i] - ds;
+      constexpr double w = weight<QN>(i);
+      // f*_i - w_i in shifted form
+      const T gs = geq[i] + (fneq[i] - omega * ds) - t * dh;
+      d1 += dh * log1p(gs * T(1.0 / w));
+      d2 += dh * dh * recip(T(w) + gs);
+    });
+    T tn = t + d1 / d2;
+    if (!(tn < hi)) tn = T(0.5) * (t + hi);
+    if (!(tn > lo)) tn = T(0.5) * (t + lo);
+    t = tn;
+  }
+  return t;
+}
+
+// KBC collision of one node in place: g <- g*. Between the passes g[] holds
+// the shifted equilibrium, so every g^eq_i is evaluated once. EXACT selects
+// the exact minimiser of the discrete H-function instead of the closed form.
+template <int QN, bool EXACT = false, typename T>
 __device__ __forceinline__ CellResult<T> kbc_collide(T (&g)[Q], const Relax<T>& rp) {
   CellResult<T> res;
   res.m = macroscopic<QN>(g);
@@ -263,7 +317,13 @@ __device__ __forceinline__ CellResult<T> kbc_collide(T (&g)[Q], const Relax<T>& 
   });
   T gamma = T(2);
   if (B > T(1e-30)) gamma = rp.two_over_omega - rp.kappa * (A / B);
-  const T t = T(0.5) * rp.omega * gamma;
+  T t = T(0.5) * rp.omega * gamma;
+  if constexpr (EXACT) {
+    if (B > T(1e-30)) {
+      t = exact_entropic_t<QN>(g, fneq, s, rp.omega, t);
+      gamma = T(2) * t / rp.omega;
+    }
+  }
   // g* = g - omega ds - t dh = (g^eq - ds) + (2 - omega) ds + (1 - t) dh.
   // The shear relaxation enters through eps = 2 - omega, which keeps the
   // viscosity (proportional to eps for omega near 2) at full relative
@@ -280,6 +340,7 @@ __device__ __forceinline__ CellResult<T> kbc_collide(T (&g)[Q], const Relax<T>& 
   });
   res.gamma = gamma;
   res.bad = !(m.rho > T(0)) || !(m.usq15 < T(1.5)) || !(fmin > T(0));
+  if constexpr (EXACT) res.bad = res.bad || !(t == t);
   return res;
 }
 

@@ -1,6 +1,6 @@
 // The fused collide-and-stream kernel and its launch shapes. Each
 // (lattice, precision) pair is instantiated in a translation unit of its
-// own (step_d3q27.hip, step_d3q19.hip), which keeps the compile of the
+// own (step_d3q27_f32.hip, ...), which keeps the compile of the
 // library parallel.
 #pragma once
 
@@ -23,7 +23,7 @@ struct StepArgs {
   double* partials;
 };
 
-template <int QN, typename T, int BLOCK, StepKind KIND, bool BUF, bool NT>
+template <int QN, typename T, int BLOCK, StepKind KIND, bool BUF, bool NT, bool EXACT = false>
 __global__ void __launch_bounds__(BLOCK) kbc_step_kernel(StepArgs<T> a) {
   const int b = remap_block(blockIdx.x, a.total_blocks, a.xcd_remap);
   const Seg sg = a.segs[find_segment(a.segs, a.nseg, b)];
@@ -57,7 +57,7 @@ __global__ void __launch_bounds__(BLOCK) kbc_step_kernel(StepArgs<T> a) {
       g[i] = src.load(opposite(i), neighbour<i, -1>(c));
     });
   }
-  const CellResult<T> res = kbc_collide<QN>(g, relax_of<T>(sp));
+  const CellResult<T> res = kbc_collide<QN, EXACT>(g, relax_of<T>(sp));
   if (res.bad) a.flags[sg.sample] = 1;
 
   if constexpr (KIND == kStep || KIND == kStepRecord || KIND == kPush) {
@@ -133,8 +133,39 @@ hipError_t launch_step_b(const StepLaunch& L, hipStream_t s) {
   }
 }
 
+// The exact stabiliser (eq. (kbc_entropy)) is compiled for one launch shape:
+// 256 threads, non-temporal access, either addressing.
+template <int QN, typename T, StepKind KIND>
+hipError_t launch_step_exact(const StepLaunch& L, hipStream_t s) {
+  StepArgs<T> a;
+  a.pop = static_cast<T*>(L.pop);
+  a.dst = static_cast<T*>(L.dst);
+  a.samples = L.samples;
+  a.segs = L.segs;
+  a.nseg = L.nseg;
+  a.total_blocks = L.total_blocks;
+  a.xcd_remap = L.xcd_remap;
+  a.flags = L.flags;
+  a.partials = L.partials;
+  if (L.block != 256) return hipErrorInvalidValue;
+  if (L.buffer_ok)
+    hipLaunchKernelGGL((kbc_step_kernel<QN, T, 256, KIND, true, true, true>), dim3(L.total_blocks), dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL((kbc_step_kernel<QN, T, 256, KIND, false, true, true>), dim3(L.total_blocks), dim3(256), 0, s,
+                       a);
+  return hipGetLastError();
+}
+
 template <int QN, typename T>
 hipError_t launch_step_k(StepKind kind, const StepLaunch& L, hipStream_t s) {
+  if (L.exact_gamma) {
+    switch (kind) {
+      case kStep: return launch_step_exact<QN, T, kStep>(L, s);
+      case kStepRecord: return launch_step_exact<QN, T, kStepRecord>(L, s);
+      case kReduceOnly: return launch_step_exact<QN, T, kReduceOnly>(L, s);
+      default: return hipErrorInvalidValue;
+    }
+  }
   switch (kind) {
     case kStep: return launch_step_b<QN, T, kStep>(L, s);
     case kStepRecord: return launch_step_b<QN, T, kStepRecord>(L, s);

@@ -248,6 +248,14 @@ class Ensemble:
         check(lib().mclbm_autotune(self._ctx, reps, _ptr(scratch), scratch.numel(), *[ctypes.byref(x) for x in v]))
         return tuple(x.value for x in v)
 
+    def set_stabiliser(self, mode: str):
+        """'closed_form' (eq. (entropyControl), default) or 'exact' (minimiser of
+        the discrete H-function, eq. (kbc_entropy))."""
+        modes = {"closed_form": _lib.GAMMA_CLOSED_FORM, "exact": _lib.GAMMA_EXACT}
+        if mode not in modes:
+            raise ValueError(f"stabiliser must be one of {list(modes)}")
+        check(lib().mclbm_set_stabiliser(self._ctx, modes[mode]))
+
     def use_graphs(self, enable: bool):
         check(lib().mclbm_use_graphs(self._ctx, int(enable)))
 

@@ -1,0 +1,134 @@
+"""The exact entropic stabiliser (minimiser of the discrete H-function,
+eq. (kbc_entropy)) on the GPU against the oracle's exact mode, which brackets
+the root of dH/dgamma and bisects it to the last bit in FP64 (GPU tests).
+
+Tolerances: the two exact minimisers agree to far below the rounding of the
+post-collision populations, so the FP64 bounds are those of the closed form:
+2e-13 of max|f - w| for steps from non-equilibrium states, 1e-12 relative L2
+of u over a run. FP32: the two steps of the test start from states with
+0.5 % noise on every population and |u| up to 0.05; every post-collision
+population comes out of sums of about 30 float terms no larger than
+max|f - w|, so its rounding is bounded by 30 * 2^-24 ~ 2e-6 of max|f - w| per
+step, 5e-6 over two steps (FP32 Newton iterates reach the FP64 root to
+~2e-6 relative, which moves f* by far less).
+"""
+import numpy as np
+import pytest
+import torch
+
+import mc_inputs
+import oracle
+
+pytestmark = pytest.mark.gpu
+mc = pytest.importorskip("paper_2608_23786_amd")
+
+
+def to_gpu_layout(f, n, q):
+    return torch.from_numpy(np.ascontiguousarray(f.T.reshape(q, n, n, n))).cuda()
+
+
+def from_gpu_layout(fg, n, q):
+    return np.ascontiguousarray(fg.cpu().numpy().reshape(q, n ** 3).T)
+
+
+@pytest.mark.parametrize("q", [27, 19])
+@pytest.mark.parametrize("precision,tol", [("f64", 2e-13), ("f32s", 5e-6)])
+def test_single_steps_match_oracle_exact_mode(q, precision, tol):
+    n = 8
+    rng = np.random.default_rng(300 + q)
+    _, w = oracle.velocity_set(q)
+    u = rng.uniform(-0.05, 0.05, (3, n, n, n))
+    f = oracle.equilibrium_field(u, q)
+    f *= 1 + rng.uniform(-5e-3, 5e-3, f.shape)
+    f = np.ascontiguousarray(f)
+    ens = mc.Ensemble([mc.Sample(n, 0.05, 100.0)], precision, lattice=q)
+    ens.init(0, torch.zeros(1, 24, dtype=torch.float64))
+    ens.set_stabiliser("exact")
+    ens.set_state(0, to_gpu_layout(f, n, q))
+    ens.step(2)
+    fg = from_gpu_layout(ens.get_state(0), n, q)
+    om = oracle.omega_shear(oracle.lattice_viscosity(n, 0.05, 100.0))
+    fc = f.copy()
+    oracle.run(f, n, 2, om, mode=oracle.MODE_EXACT)
+    oracle.run(fc, n, 2, om, mode=oracle.MODE_KBC)
+    err = np.max(np.abs(fg - f)) / np.max(np.abs(f - w))
+    gap = np.max(np.abs(fc - f)) / np.max(np.abs(f - w))
+    print(f"D3Q{q} {precision}: exact GPU vs exact oracle {err:.3e}; closed form vs exact {gap:.3e}")
+    assert err < tol
+    # the test distinguishes the two stabilisers
+    assert gap > 20 * tol
+
+
+def test_rtgv_run_and_records_match_oracle_exact_mode():
+    n, u0, re, amp, steps = 16, 0.05, 400.0, 0.3, 24
+    y = mc_inputs.draw_y(77, 1)
+    ens = mc.Ensemble([mc.Sample(n, u0, re, amp, True)], "f64")
+    ens.init(0, torch.from_numpy(y))
+    ens.set_stabiliser("exact")
+    rec = ens.step(steps, record_every=8).cpu().numpy()
+    _, u_g = (t.cpu().numpy() for t in ens.moments(0))
+    om = oracle.omega_shear(oracle.lattice_viscosity(n, u0, re))
+    f = oracle.init_populations(n, u0, amp, y[0], True)
+    gs = oracle.run(f, n, steps, om, mode=oracle.MODE_EXACT, gamma_stats=True)
+    _, u_o = oracle.moments(f, n)
+    err = float(np.linalg.norm(u_g - u_o) / np.linalg.norm(u_o))
+    print(f"exact stabiliser, 16^3 x {steps} steps FP64: rel L2(u) = {err:.3e}")
+    assert err < 1e-12
+    # records of ticks 8 and 16 carry the gamma statistics of the step taken there
+    for k, t in ((1, 8), (2, 16)):
+        assert abs(rec[k, 0, 5] - gs[t, 0]) < 1e-9
+        assert abs(rec[k, 0, 6] - gs[t, 1]) < 1e-9
+        assert abs(rec[k, 0, 7] - gs[t, 2]) < 1e-10
+
+
+def test_exact_stabiliser_does_not_increase_entropy():
+    """Streaming permutes populations, so the total discrete H-function over
+    the lattice changes only by the collisions; with the exact minimiser each
+    collision satisfies H(f*) <= H(f)."""
+    n = 16
+    _, w = oracle.velocity_set()
+    y = mc_inputs.draw_y(78, 1)
+    ens = mc.Ensemble([mc.Sample(n, 0.05, 50.0, 0.5, True)], "f64")
+    ens.init(0, torch.from_numpy(y))
+    ens.set_stabiliser("exact")
+
+    def total_h():
+        f = from_gpu_layout(ens.get_state(0), n, 27)
+        return float(np.sum(f * np.log(f / w)))
+
+    h = [total_h()]
+    for _ in range(6):
+        ens.step(1)
+        h.append(total_h())
+    assert all(b <= a + 1e-13 * abs(a) for a, b in zip(h, h[1:])), h
+
+
+def test_mode_switch_and_unsupported_combinations():
+    samples = [mc.Sample(16, 0.05, 200.0, 0.3, True)]
+    y = torch.from_numpy(mc_inputs.draw_y(79, 1))
+    ref = mc.Ensemble(samples, "f32s")
+    ref.init(0, y)
+    ref.step(10)
+    ens = mc.Ensemble(samples, "f32s")
+    ens.init(0, y)
+    with pytest.raises(ValueError):
+        ens.set_stabiliser("newton")
+    ens.set_stabiliser("exact")
+    ens.step(4)
+    assert ens.get_launch()[0] == 256
+    with pytest.raises(mc.MclbmError, match="ERR_UNSUPPORTED"):
+        ens.set_launch(512, 0, 1, 1)
+    with pytest.raises(mc.MclbmError, match="ERR_UNSUPPORTED"):
+        ens.autotune(reps=1)
+    ens2 = mc.Ensemble(samples, "f32s")
+    ens2.init(0, y)
+    ens2.set_stabiliser("exact")
+    with pytest.raises(mc.MclbmError, match="ERR_UNSUPPORTED"):
+        ens2.forward_ckpt(4, 2)
+    # back to the closed form: the same kernels as a closed-form ensemble
+    ens3 = mc.Ensemble(samples, "f32s")
+    ens3.init(0, y)
+    ens3.set_stabiliser("exact")
+    ens3.set_stabiliser("closed_form")
+    ens3.step(10)
+    assert torch.equal(ens3.get_state(0), ref.get_state(0))
