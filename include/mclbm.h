@@ -242,6 +242,23 @@ size_t mclbm_w1_work_bytes(int32_t q);
 mclbm_status mclbm_w1_1pt(const double* a_dev, const double* b_dev, int32_t m, int32_t q, double* out_dev,
                           void* work_dev, size_t work_bytes, void* hip_stream);
 
+/* Dissipation rate per unit volume and Kolmogorov length from a series of
+ * records of mclbm_step (the definition of the sample dissipation rate
+ * before eq. (kolmogorov_microscale), and that equation): d_m(t) =
+ * -(d/dt) KE_m(t), with KE_m the kinetic energy per unit volume in units of
+ * u0^2 (field 4 of the records divided by u0^2) and t the physical time of
+ * the record, t = steps * (2 pi / n) * u0 (unit reference velocity, box of
+ * side 2 pi); the derivative is a centred difference inside the series and
+ * one-sided at its ends. eta(t) = (eps^3 / mean_m d_m(t))^(1/4) with
+ * eps = 1 / Re.
+ * records_dev: [nrec][m][8] (device) as written by mclbm_step, the first
+ * taken at tick first_tick, the others every record_every ticks (both
+ * multiples of every stride; nrec >= 2). diss_dev: [nrec][m] (device).
+ * eta_dev: [nrec] (device) or NULL; it needs one Re for all samples
+ * (MCLBM_ERR_ARG otherwise); a non-positive mean dissipation gives NaN. */
+mclbm_status mclbm_dissipation(mclbm_ctx* ctx, const double* records_dev, int32_t nrec, int64_t first_tick,
+                               int32_t record_every, double* diss_dev, double* eta_dev);
+
 /* Stabiliser gamma of the higher-order relaxation omega_hom = omega gamma / 2
  * (Table 1). MCLBM_GAMMA_CLOSED_FORM (default) evaluates eq. (entropyControl).
  * MCLBM_GAMMA_EXACT minimises the discrete H-function of the post-collision

@@ -72,6 +72,7 @@ SIGNATURES = {
     "mclbm_set_launch": (_i32, [_ctxp, _i32, _i32, _i32, _i32]),
     "mclbm_get_launch": (_i32, [_ctxp, _ip, _ip, _ip, _ip]),
     "mclbm_autotune": (_i32, [_ctxp, _i32, _vp, _sz, _ip, _ip, _ip, _ip]),
+    "mclbm_dissipation": (_i32, [_ctxp, _vp, _i32, _i64, _i32, _vp, _vp]),
     "mclbm_set_stabiliser": (_i32, [_ctxp, _i32]),
     "mclbm_use_graphs": (_i32, [_ctxp, _i32]),
     "mclbm_ticks": (_i64, [_ctxp]),

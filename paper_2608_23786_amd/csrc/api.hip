@@ -102,6 +102,7 @@ struct mclbm_ctx {
   int32_t* d_flags = nullptr;
   double* d_ycoef = nullptr;
   double* d_pmat = nullptr;
+  DissSample* d_diss = nullptr;
   Seg* d_tables = nullptr;
   size_t table_pool_bytes = 0;
   double* d_partials = nullptr;
@@ -180,7 +181,7 @@ uint64_t plane_stride(int n, size_t elem) {
 }
 
 struct Layout {
-  size_t samples, flags, ycoef, pmat, tables, table_bytes, partials, partial_blocks, pop, state_bytes, total;
+  size_t samples, flags, ycoef, pmat, diss, tables, table_bytes, partials, partial_blocks, pop, state_bytes, total;
 };
 
 Layout layout_of(int32_t m, const mclbm_sample_desc* d, int32_t precision, int32_t lattice) {
@@ -195,6 +196,8 @@ Layout layout_of(int32_t m, const mclbm_sample_desc* d, int32_t precision, int32
   off = align_up(off + sizeof(double) * 24 * kMaxSamples);
   L.pmat = off;
   off = align_up(off + sizeof(double) * 24 * 24);
+  L.diss = off;
+  off = align_up(off + sizeof(DissSample) * kMaxSamples);
   L.tables = off;
   L.table_bytes = size_t(kMaxTables) * align_up(sizeof(Seg) * m);
   off = align_up(off + L.table_bytes);
@@ -485,6 +488,7 @@ mclbm_status mclbm_create(mclbm_ctx** out, int32_t m, const mclbm_sample_desc* d
   c->d_flags = reinterpret_cast<int32_t*>(c->ws + L.flags);
   c->d_ycoef = reinterpret_cast<double*>(c->ws + L.ycoef);
   c->d_pmat = reinterpret_cast<double*>(c->ws + L.pmat);
+  c->d_diss = reinterpret_cast<DissSample*>(c->ws + L.diss);
   c->d_tables = reinterpret_cast<Seg*>(c->ws + L.tables);
   c->table_pool_bytes = L.table_bytes;
   c->d_partials = reinterpret_cast<double*>(c->ws + L.partials);
@@ -513,6 +517,15 @@ mclbm_status mclbm_create(mclbm_ctx** out, int32_t m, const mclbm_sample_desc* d
   hipError_t e = hipMemcpy(c->d_samples, c->h_samples.data(), sizeof(DevSample) * m, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(c->d_pmat, c->pmat.data(), sizeof(double) * 24 * 24, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemset(c->d_flags, 0, sizeof(int32_t) * kMaxSamples);
+  if (e == hipSuccess) {
+    std::vector<DissSample> ds(m);
+    for (int s = 0; s < m; ++s) {
+      ds[s].inv_u0sq = 1.0 / (desc[s].u0 * desc[s].u0);
+      ds[s].dt = 2.0 * M_PI / desc[s].n * desc[s].u0;  // dx * u0 / U_c with U_c = 1
+      ds[s].stride = desc[s].stride;
+    }
+    e = hipMemcpy(c->d_diss, ds.data(), sizeof(DissSample) * m, hipMemcpyHostToDevice);
+  }
   if (e != hipSuccess) {
     delete c;
     return fail(MCLBM_ERR_HIP, std::string("context upload: ") + hipGetErrorString(e));
@@ -1017,6 +1030,25 @@ mclbm_status mclbm_autotune(mclbm_ctx* c, int32_t reps, void* scratch_dev, size_
   if (best_buffer) *best_buffer = bf;
   if (best_nt) *best_nt = bn;
   return mclbm_restore(c, scratch_dev, scratch_bytes);
+}
+
+mclbm_status mclbm_dissipation(mclbm_ctx* c, const double* records_dev, int32_t nrec, int64_t first_tick,
+                               int32_t record_every, double* diss_dev, double* eta_dev) {
+  mclbm_status st = check_ctx(c, false);
+  if (st != MCLBM_OK) return st;
+  if (!records_dev || !diss_dev) return fail(MCLBM_ERR_ARG, "records_dev and diss_dev must be given");
+  if (nrec < 2) return fail(MCLBM_ERR_ARG, "at least two records are needed");
+  if (first_tick < 0 || record_every < 1) return fail(MCLBM_ERR_ARG, "first_tick >= 0 and record_every >= 1");
+  for (int s = 0; s < c->m; ++s)
+    if (first_tick % c->desc[s].stride || record_every % c->desc[s].stride)
+      return fail(MCLBM_ERR_ARG, "records must fall on ticks where every sample steps");
+  if (eta_dev)
+    for (int s = 1; s < c->m; ++s)
+      if (c->desc[s].re != c->desc[0].re)
+        return fail(MCLBM_ERR_ARG, "the Kolmogorov length needs one viscosity for the whole ensemble");
+  HIP_TRY(launch_dissipation(records_dev, c->d_diss, c->m, nrec, first_tick, record_every, 1.0 / c->desc[0].re,
+                             diss_dev, eta_dev, c->stream));
+  return MCLBM_OK;
 }
 
 mclbm_status mclbm_set_stabiliser(mclbm_ctx* c, int32_t mode) {

@@ -80,6 +80,16 @@ hipError_t launch_init_adjoint_finalize(const double* partials, const Seg* segs,
                                         hipStream_t s);
 hipError_t launch_extract(const double* records, int32_t m, int32_t field, double* out, hipStream_t s);
 
+// Per-sample constants of the dissipation rate (a small device table).
+struct DissSample {
+  double inv_u0sq;  // 1 / u0^2: KE in units of u0^2
+  double dt;        // physical time of one step, (2 pi / n) * u0
+  int64_t stride;   // ticks per step
+};
+hipError_t launch_dissipation(const double* records, const DissSample* smp, int32_t m, int32_t nrec,
+                              int64_t first_tick, int32_t record_every, double eps, double* diss, double* eta,
+                              hipStream_t s);
+
 hipError_t launch_stream_copy(void* dst, const void* src, size_t bytes, hipStream_t s);
 
 // Observables (observables.hip).

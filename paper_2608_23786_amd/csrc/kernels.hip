@@ -464,6 +464,29 @@ __global__ void extract_kernel(const double* records, int m, int field, double* 
   if (s < m) out[s] = records[size_t(s) * kRecord + field];
 }
 
+// Dissipation rate per sample and record, d = -dKE/dt in physical units
+// (KE / u0^2 against t = steps * (2 pi / n) * u0): centred differences inside
+// the series, one-sided at its ends; and eta = (eps^3 / mean_s d)^(1/4).
+// One thread per record.
+__global__ void dissipation_kernel(const double* records, const DissSample* smp, int m, int nrec,
+                                   int64_t first_tick, int record_every, double eps, double* diss, double* eta) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= nrec) return;
+  const int k0 = k > 0 ? k - 1 : 0, k1 = k + 1 < nrec ? k + 1 : nrec - 1;
+  double mean = 0.0;
+  for (int s = 0; s < m; ++s) {
+    const DissSample& d = smp[s];
+    const double ke0 = records[(size_t(k0) * m + s) * kRecord + 4] * d.inv_u0sq;
+    const double ke1 = records[(size_t(k1) * m + s) * kRecord + 4] * d.inv_u0sq;
+    const double t0 = double((first_tick + int64_t(k0) * record_every) / d.stride) * d.dt;
+    const double t1 = double((first_tick + int64_t(k1) * record_every) / d.stride) * d.dt;
+    const double v = -(ke1 - ke0) / (t1 - t0);
+    diss[size_t(k) * m + s] = v;
+    mean += v;
+  }
+  if (eta) eta[k] = sqrt(sqrt(eps * eps * eps / (mean / m)));
+}
+
 // One 16-byte element per thread (the fastest plain copy measured on gfx950).
 __global__ void __launch_bounds__(256) stream_copy_kernel(const float4* __restrict__ src, float4* __restrict__ dst,
                                                           size_t n4) {
@@ -618,6 +641,14 @@ hipError_t launch_init_adjoint_finalize(const double* partials, const Seg* segs,
 
 hipError_t launch_extract(const double* records, int32_t m, int32_t field, double* out, hipStream_t s) {
   hipLaunchKernelGGL(extract_kernel, dim3((m + 255) / 256), dim3(256), 0, s, records, m, field, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_dissipation(const double* records, const DissSample* smp, int32_t m, int32_t nrec,
+                              int64_t first_tick, int32_t record_every, double eps, double* diss, double* eta,
+                              hipStream_t s) {
+  hipLaunchKernelGGL(dissipation_kernel, dim3((nrec + 63) / 64), dim3(64), 0, s, records, smp, m, nrec, first_tick,
+                     record_every, eps, diss, eta);
   return hipGetLastError();
 }
 

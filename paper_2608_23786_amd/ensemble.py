@@ -248,6 +248,19 @@ class Ensemble:
         check(lib().mclbm_autotune(self._ctx, reps, _ptr(scratch), scratch.numel(), *[ctypes.byref(x) for x in v]))
         return tuple(x.value for x in v)
 
+    def dissipation(self, records: torch.Tensor, first_tick: int, record_every: int, eta: bool = True):
+        """Dissipation rate d[nrec, m] (physical units) and, when eta, the
+        Kolmogorov length eta[nrec] from records [nrec, m, 8] of `step`."""
+        _require_cuda(records, torch.float64, name="records")
+        nrec = records.numel() // (self.m * 8)
+        diss = self._dev_empty((nrec, self.m))
+        et = self._dev_empty((nrec,)) if eta else None
+        self._consume()
+        check(lib().mclbm_dissipation(self._ctx, _ptr(records), nrec, first_tick, record_every, _ptr(diss),
+                                      _ptr(et) if et is not None else None))
+        self._produce()
+        return diss, et
+
     def set_stabiliser(self, mode: str):
         """'closed_form' (eq. (entropyControl), default) or 'exact' (minimiser of
         the discrete H-function, eq. (kbc_entropy))."""
