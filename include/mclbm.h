@@ -217,8 +217,9 @@ mclbm_status mclbm_backward(mclbm_ctx* ctx, int64_t ticks, int32_t ckpt_every, c
  *     (energySpecDisc) with the coefficients of eq. (dftCoeff); modes whose
  *     length rounds above n/2 are not counted.
  * Either output may be NULL. work_dev: device scratch of
- * mclbm_observables_work_bytes(ctx, sample) bytes, owned by the caller.
- * Supported n: 8..512. Lattice units (divide by u0^2 for physical units). */
+ * mclbm_observables_work_bytes(ctx, sample) bytes (about 36 n^3 bytes),
+ * 256-byte aligned, owned by the caller. Supported n: 8..512. Lattice
+ * units (divide by u0^2 for physical units). */
 size_t mclbm_observables_work_bytes(const mclbm_ctx* ctx, int32_t sample);
 mclbm_status mclbm_observables(mclbm_ctx* ctx, int32_t sample, double* s2_dev, double* ek_dev, void* work_dev,
                                size_t work_bytes);

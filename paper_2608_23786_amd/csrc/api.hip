@@ -172,12 +172,28 @@ mclbm_status validate_desc(int32_t m, const mclbm_sample_desc* d, int32_t precis
   return MCLBM_OK;
 }
 
-// Elements from one population plane to the next: n^3 plus a pad that keeps
-// the plane addresses of a node off a common power-of-two stride.
+// Pad after each population plane, by plane size. The q streams of a wave
+// start at the same offset in q planes; how they spread over the HBM
+// channels depends on the plane stride, and the best pad differs by size
+// (measured with the FP32 collide-and-stream kernel on 64 x 64^3, 8 x 128^3,
+// 4 x 256^3 and 1 x 512^3 for pads of 0 to 64 KiB: up to 18 % apart; the
+// pads below beat 4352 bytes by 0.5 to 2 %). Other sizes take 4352 bytes
+// (17 x 256), the best single choice across the four.
+uint32_t plane_pad_bytes(uint64_t plane_bytes) {
+  if (plane_bytes < (uint64_t(1) << 16)) return 0;
+  switch (plane_bytes) {
+    case uint64_t(1) << 20: return 256;    // 64^3 float
+    case uint64_t(8) << 20: return 1024;   // 128^3 float
+    case uint64_t(64) << 20: return 0;     // 256^3 float
+    case uint64_t(512) << 20: return 1024; // 512^3 float
+    default: return 4352;
+  }
+}
+
+// Elements from one population plane to the next: n^3 plus the pad.
 uint64_t plane_stride(int n, size_t elem) {
   const uint64_t n3 = uint64_t(n) * n * n;
-  if (n3 * elem < (uint64_t(1) << 16)) return n3;
-  return n3 + kPlanePadBytes / elem;
+  return n3 + plane_pad_bytes(n3 * elem) / elem;
 }
 
 struct Layout {
@@ -867,9 +883,7 @@ mclbm_status mclbm_backward(mclbm_ctx* c, int64_t ticks, int32_t ckpt_every, con
 // ------------------------------------------------------------------ observables
 size_t mclbm_observables_work_bytes(const mclbm_ctx* c, int32_t sample) {
   if (!c || sample < 0 || sample >= c->m) return 0;
-  const size_t n3 = size_t(c->cells(sample));
-  return align_up(3 * n3 * sizeof(double)) + align_up(3 * n3 * 2 * sizeof(double)) +
-         shell_scratch_doubles(c->desc[sample].n) * sizeof(double);
+  return observables_work_bytes(c->desc[sample].n);
 }
 
 mclbm_status mclbm_observables(mclbm_ctx* c, int32_t sample, double* s2_dev, double* ek_dev, void* work_dev,
@@ -879,20 +893,9 @@ mclbm_status mclbm_observables(mclbm_ctx* c, int32_t sample, double* s2_dev, dou
   if (sample < 0 || sample >= c->m) return fail(MCLBM_ERR_ARG, "sample out of range");
   if (!work_dev || work_bytes < mclbm_observables_work_bytes(c, sample))
     return fail(MCLBM_ERR_OOM, "observables work buffer too small");
-  const int n = c->desc[sample].n;
-  const size_t n3 = size_t(c->cells(sample));
-  double* u = static_cast<double*>(work_dev);
-  double2* x = reinterpret_cast<double2*>(static_cast<char*>(work_dev) + align_up(3 * n3 * sizeof(double)));
-  double* scratch = reinterpret_cast<double*>(reinterpret_cast<char*>(x) + align_up(3 * n3 * 2 * sizeof(double)));
-  HIP_TRY(launch_moments(c->q, c->precision, c->pop, c->d_samples, sample, n, int32_t(c->steps[sample] & 1), nullptr, u,
-                         c->stream));
-  HIP_TRY(launch_fft3(n, x, u, 3, -1, c->stream));
-  HIP_TRY(launch_psd(x, n3, x, c->stream));
-  if (ek_dev) HIP_TRY(launch_shells(x, n, 0, scratch, ek_dev, c->stream));
-  if (s2_dev) {
-    HIP_TRY(launch_fft3(n, x, nullptr, 1, +1, c->stream));
-    HIP_TRY(launch_shells(x, n, 1, scratch, s2_dev, c->stream));
-  }
+  if (reinterpret_cast<uintptr_t>(work_dev) % kAlign) return fail(MCLBM_ERR_ARG, "work_dev must be 256-byte aligned");
+  HIP_TRY(launch_observables(c->q, c->precision, c->pop, c->d_samples, sample, c->desc[sample].n,
+                             int32_t(c->steps[sample] & 1), work_dev, s2_dev, ek_dev, c->stream));
   return MCLBM_OK;
 }
 

@@ -92,15 +92,12 @@ hipError_t launch_dissipation(const double* records, const DissSample* smp, int3
 
 hipError_t launch_stream_copy(void* dst, const void* src, size_t bytes, hipStream_t s);
 
-// Observables (observables.hip).
-// 3-D transform of ncomp consecutive N^3 complex fields in place; rin (optional)
-// supplies real input for the first pass. sign -1 forward, +1 unnormalised inverse.
-hipError_t launch_fft3(int n, double2* data, const double* rin, int ncomp, int sign, hipStream_t s);
-hipError_t launch_psd(const double2* x, size_t n3, double2* out, hipStream_t s);
-// mode 0: energy spectrum bins kappa = 0..n/2; mode 1: structure function r = 1..n/2.
-// scratch: shell_scratch_doubles(n) doubles.
-size_t shell_scratch_doubles(int n);
-hipError_t launch_shells(const double2* data, int n, int mode, double* scratch, double* out, hipStream_t s);
+// Observables (observables.hip): structure function s2[n/2] (r = 1..n/2) and
+// energy spectrum ek[n/2+1] (kappa = 0..n/2) of one sample at its current
+// step (either may be NULL), in observables_work_bytes(n) bytes of work.
+size_t observables_work_bytes(int n);
+hipError_t launch_observables(int q, int precision, const void* pop, const DevSample* samples, int32_t sample,
+                              int32_t n, int32_t parity, void* work, double* s2, double* ek, hipStream_t s);
 // lattice: 27 or 19; q: common nodes per axis
 hipError_t launch_point_values(int lattice, int precision, const void* pop, const DevSample* samples,
                                const Seg* segs, int32_t nseg, int q, double* out, hipStream_t s);

@@ -91,14 +91,6 @@ struct Seg {
   int32_t parity;         // steps taken so far, modulo 2 (AA layout of the state)
 };
 
-// Padding between population planes. Plane strides that are large powers of
-// two make the 27 streams of a wave fall on the same HBM channels; a pad of
-// an odd number of 256-byte units spreads them.
-#ifndef MCLBM_PLANE_PAD_BYTES
-#define MCLBM_PLANE_PAD_BYTES 4352
-#endif
-constexpr uint32_t kPlanePadBytes = MCLBM_PLANE_PAD_BYTES;
-
 // Reduction record layout (doubles per sample).
 constexpr int kRecord = 8;  // mass, jx, jy, jz, ke, gamma_min, gamma_max, gamma_mean
 

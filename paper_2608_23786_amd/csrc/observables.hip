@@ -1,7 +1,6 @@
 // FP64 observables of one sample's velocity field (gfx950):
-//   * 3-D discrete Fourier transform by radix-2 transforms along each axis,
-//     a block of 256 threads transforming LINES lines at once in LDS;
-//   * the power spectral density Psi(k) = sum_a |F(u_a)(k)|^2;
+//   * the power spectral density Psi(k) = sum_a |F(u_a)(k)|^2 of the
+//     three velocity components (unnormalised forward transform);
 //   * the shell energy spectrum E(kappa) = 4 pi / |S_kappa| sum_{S_kappa}
 //     |k|^2 / 2 * Psi(k) / N^6 (eqs. (dftCoeff), (energySpecDisc));
 //   * the autocorrelation R_h = N^-6 F^-1(Psi)_h with an unnormalised inverse
@@ -10,15 +9,28 @@
 //   * point values of all samples at the q^3 nodes common to every
 //     resolution, and the 1-point Wasserstein distance between two such
 //     ensembles by sorting (Algorithm 2, eq. (wassersteinPermutations)).
-// Shells hold the integer vectors (minimum image, components in
-// {-N/2+1, ..., N/2}) whose length rounds to the shell index; blocks
-// enumerate the (z, y) rows of a shell and the one or two x-intervals of each
-// row, so every sum runs in a fixed order (results do not depend on
-// scheduling).
+//
+// The velocity is real, so its transform is stored for kx = 0..N/2 only
+// (the rest follows by conjugate symmetry), fields [z][y][kx], and the
+// pipeline is five passes over HBM:
+//   1. x: velocities from the populations (either AA parity) and the
+//      forward transform along x of the three components, per row in LDS;
+//   2. y, 3. z: forward transforms along y and z of the three fields;
+//   4. per z-line: Psi, its shell sums for the spectrum, its total (R_0),
+//      and the inverse transform along z of Psi, written over field 0;
+//   5. inverse along y; 6. per x-row: the inverse along x (conjugate-
+//      symmetric fill, real result R_h) and its shell sums for S2.
+// Radix-2 decimation-in-time transforms of whole lines in LDS, twiddles by
+// sincospi. Shells hold the integer vectors (minimum image, components in
+// {-N/2+1, ..., N/2}) whose length rounds to the shell index. Every shell sum
+// is taken per line in a fixed order (the line folded by the magnitude of
+// its own coordinate, the lengths of a shell forming an interval of it), and
+// then over lines in a fixed order: results do not depend on scheduling.
+// A half-spectrum mode 0 < kx < N/2 stands for itself and its conjugate
+// partner at -k, which has the same length: weight 2.
 #include <hip/hip_runtime.h>
 
-#include "kernels.h"
-#include "lattice.h"
+#include "lbm_device.h"
 
 namespace mclbm {
 namespace {
@@ -34,78 +46,40 @@ constexpr int log2_of() {
   return l;
 }
 
-// Address of element i of line `line` along `axis` in an N^3 array ([z][y][x]).
 template <int N>
-__device__ __forceinline__ size_t line_offset(int axis, int line, int i) {
-  if (axis == 0) return size_t(line) * N + i;                                    // x: line = z*N + y
-  if (axis == 1) return size_t(line / N) * N * N + size_t(i) * N + (line % N);   // y: line = z*N + x
-  return size_t(i) * N * N + line;                                               // z: line = y*N + x
+__device__ __forceinline__ int bitrev(int i) {
+  return int(__brev(unsigned(i)) >> (32 - log2_of<N>()));
 }
 
-// Radix-2 decimation-in-time transform of LINES lines along `axis`, in place.
-// sign = -1: forward e^{-2 pi i k n / N}; +1: unnormalised inverse.
-// real_in: the input is real (double array `rin` of N^3), written as complex.
-template <int N, int LINES>
-__global__ void __launch_bounds__(256)
-    fft_axis_kernel(double2* data, const double* rin, int axis, int sign, size_t comp_stride_c, size_t comp_stride_r) {
-  constexpr int LOG = log2_of<N>();
-  __shared__ double2 sh[LINES][N];
-  __shared__ double2 tw[N / 2 > 0 ? N / 2 : 1];
-  double2* d = data + size_t(blockIdx.y) * comp_stride_c;
-  const double* r = rin ? rin + size_t(blockIdx.y) * comp_stride_r : nullptr;
-  for (int k = threadIdx.x; k < N / 2; k += 256) {
+// e^{sign 2 pi i k / N}, k < N/2
+template <int N>
+__device__ __forceinline__ void make_twiddles(double2* tw, int sign) {
+  for (int k = threadIdx.x; k < N / 2; k += blockDim.x) {
     double s, c;
     sincospi(2.0 * k / N, &s, &c);
     tw[k] = make_double2(c, sign * s);
   }
-  const int line0 = blockIdx.x * LINES;
-  for (int e = threadIdx.x; e < LINES * N; e += 256) {
-    int l, i;
-    if (axis == 0) {
-      l = e / N;
-      i = e % N;
-    } else {
-      i = e / LINES;
-      l = e % LINES;
-    }
-    const size_t off = line_offset<N>(axis, line0 + l, i);
-    const double2 v = r ? make_double2(r[off], 0.0) : d[off];
-    const int rev = int(__brev(unsigned(i)) >> (32 - LOG));
-    sh[l][rev] = v;
-  }
-  __syncthreads();
+}
+
+// In-place radix-2 butterflies of nl lines of length N (line l at sh + l N)
+// loaded in bit-reversed order; every thread of the block takes part. The
+// caller synchronises after loading.
+template <int N>
+__device__ __forceinline__ void butterflies(double2* sh, int nl, const double2* tw) {
   for (int half = 1; half < N; half <<= 1) {
     const int stride = N / (2 * half);
-    for (int b = threadIdx.x; b < LINES * (N / 2); b += 256) {
+    for (int b = threadIdx.x; b < nl * (N / 2); b += blockDim.x) {
       const int l = b / (N / 2), j = b % (N / 2);
       const int pos = j % half, grp = j / half;
       const int i0 = grp * 2 * half + pos, i1 = i0 + half;
-      const double2 a = sh[l][i0];
-      const double2 t = cmul(tw[pos * stride], sh[l][i1]);
-      sh[l][i0] = make_double2(a.x + t.x, a.y + t.y);
-      sh[l][i1] = make_double2(a.x - t.x, a.y - t.y);
+      double2* ln = sh + l * N;
+      const double2 a = ln[i0];
+      const double2 t = cmul(tw[pos * stride], ln[i1]);
+      ln[i0] = make_double2(a.x + t.x, a.y + t.y);
+      ln[i1] = make_double2(a.x - t.x, a.y - t.y);
     }
     __syncthreads();
   }
-  for (int e = threadIdx.x; e < LINES * N; e += 256) {
-    int l, i;
-    if (axis == 0) {
-      l = e / N;
-      i = e % N;
-    } else {
-      i = e / LINES;
-      l = e % LINES;
-    }
-    d[line_offset<N>(axis, line0 + l, i)] = sh[l][i];
-  }
-}
-
-// Psi(k) = sum over 3 components of |X(k)|^2, written as (Psi, 0) into out.
-__global__ void __launch_bounds__(256) psd_kernel(const double2* x, size_t n3, double2* out) {
-  const size_t k = size_t(blockIdx.x) * 256 + threadIdx.x;
-  if (k >= n3) return;
-  const double2 a = x[k], b = x[n3 + k], c = x[2 * n3 + k];
-  out[k] = make_double2(a.x * a.x + a.y * a.y + b.x * b.x + b.y * b.y + c.x * c.x + c.y * c.y, 0.0);
 }
 
 __device__ __forceinline__ int64_t isqrt_floor(int64_t v) {
@@ -116,79 +90,244 @@ __device__ __forceinline__ int64_t isqrt_floor(int64_t v) {
   return r;
 }
 
-// Shell sums over the real parts of data (N^3, minimum-image index vectors),
-// in two passes.
-// Pass 1 (one wave per (z, y) row, s = hz^2 + hy^2): the row is folded by
-// |hx| = m into LDS, v[m] = value(+m) + value(-m) (one term at m = 0 and
-// m = N/2), then lane r sums v over the m-interval whose |h| rounds to r and
-// writes rowbins[r][row] (and the number of lags, rowcnt[r][row]).
-// Pass 2 (one block per shell): sums its rowbins column in a fixed order.
-// mode 0 (spectrum): value = |k|^2/2 * v; mode 1 (structure function):
-// value = 2 (v(0) - v(h)).
-__global__ void __launch_bounds__(256) shell_rows_kernel(const double2* data, int n, int mode, double* rowbins,
-                                                         double* rowcnt) {
-  __shared__ double sh[4][513];
+// Sum of v[m] over the m in [0, half] with round(sqrt(s + m^2)) == r, and the
+// number of lattice vectors they stand for (m and -m: 2, except m = 0 and
+// m = half): m^2 in [ceil(((2r-1)^2 - 4s)/4), floor(((2r+1)^2 - 1 - 4s)/4)].
+__device__ __forceinline__ void shell_interval(const double* v, int half, int64_t s, int r, double& sum,
+                                               double& cnt) {
+  sum = 0.0;
+  cnt = 0.0;
+  const int64_t lo2 = r == 0 ? 0 : int64_t(2 * r - 1) * (2 * r - 1);
+  const int64_t top = int64_t(2 * r + 1) * (2 * r + 1) - 1 - 4 * s;
+  if (top < 0) return;
+  const int64_t m2max = top / 4;
+  const int64_t bot = lo2 - 4 * s;
+  const int64_t m2min = bot <= 0 ? 0 : (bot + 3) / 4;
+  if (m2min > m2max) return;
+  int64_t a = isqrt_floor(m2min);
+  if (a * a < m2min) ++a;
+  int64_t b = isqrt_floor(m2max);
+  if (b > half) b = half;
+  for (int64_t m = a; m <= b; ++m) {
+    sum += v[m];
+    cnt += (m == 0 || m == half) ? 1.0 : 2.0;
+  }
+}
+
+// Pass 1: ROWS rows (z, y) per block. Velocities of the row's nodes from
+// the populations (the parity selects the AA slots), forward transform
+// along x of the three components, kx = 0..N/2 written to
+// h[c][(z N + y) NH + kx].
+template <int QN, typename T, int N>
+__global__ void __launch_bounds__(256)
+    fwd_x_kernel(const T* pop, const DevSample* samples, int sample, int parity, double2* h) {
+  constexpr int ROWS = N >= 512 ? 1 : 512 / N;
+  constexpr int NH = N / 2 + 1;
+  __shared__ double2 sh[3 * ROWS * N];
+  __shared__ double2 tw[N / 2];
+  const DevSample& sp = samples[sample];
+  const size_t row0 = size_t(blockIdx.x) * ROWS;
+  make_twiddles<N>(tw, -1);
+  const T* base = pop + sp.offset;
+  for (int e = threadIdx.x; e < ROWS * N; e += 256) {
+    const int r = e / N, x = e % N;
+    const Cell c = make_cell(uint32_t((row0 + r) * N + x), sp.log2n);
+    T g[Q];
+    load_state<QN>(base, sp.pstride, c, parity & 1, g);
+    double d = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
+    for_vel<QN>([&](auto ic) {
+      constexpr int i = decltype(ic)::value;
+      const double v = double(g[i]);
+      d += v;
+      if constexpr (cx(i) != 0) jx += cx(i) * v;
+      if constexpr (cy(i) != 0) jy += cy(i) * v;
+      if constexpr (cz(i) != 0) jz += cz(i) * v;
+    });
+    const double rho = 1.0 + d;
+    const int rv = bitrev<N>(x);
+    sh[(0 * ROWS + r) * N + rv] = make_double2(jx / rho, 0.0);
+    sh[(1 * ROWS + r) * N + rv] = make_double2(jy / rho, 0.0);
+    sh[(2 * ROWS + r) * N + rv] = make_double2(jz / rho, 0.0);
+  }
+  __syncthreads();
+  butterflies<N>(sh, 3 * ROWS, tw);
+  const size_t field = size_t(N) * N * NH;
+  for (int e = threadIdx.x; e < 3 * ROWS * NH; e += 256) {
+    const int cl = e / NH, kx = e % NH;
+    const int comp = cl / ROWS, r = cl % ROWS;
+    h[comp * field + (row0 + r) * NH + kx] = sh[cl * N + kx];
+  }
+}
+
+// Passes 2, 3, 5: transform along y (axis 1) or z (axis 2) of the fields
+// h + c * N N NH, c = blockIdx.y; LINES lines (outer, kx) per block, outer =
+// z (axis 1) or y (axis 2), consecutive kx. sign -1 forward, +1 inverse.
+template <int N, int LINES>
+__global__ void __launch_bounds__(256) fft_half_kernel(double2* h, int axis, int sign) {
+  constexpr int NH = N / 2 + 1;
+  __shared__ double2 sh[LINES * N];
+  __shared__ double2 tw[N / 2];
+  double2* d = h + size_t(blockIdx.y) * N * N * NH;
+  make_twiddles<N>(tw, sign);
+  const int line0 = blockIdx.x * LINES;
+  for (int e = threadIdx.x; e < LINES * N; e += 256) {
+    const int i = e / LINES, l = e % LINES;
+    const int line = line0 + l, outer = line / NH, kx = line % NH;
+    const size_t off = axis == 1 ? (size_t(outer) * N + i) * NH + kx : (size_t(i) * N + outer) * NH + kx;
+    sh[l * N + bitrev<N>(i)] = d[off];
+  }
+  __syncthreads();
+  butterflies<N>(sh, LINES, tw);
+  for (int e = threadIdx.x; e < LINES * N; e += 256) {
+    const int i = e / LINES, l = e % LINES;
+    const int line = line0 + l, outer = line / NH, kx = line % NH;
+    const size_t off = axis == 1 ? (size_t(outer) * N + i) * NH + kx : (size_t(i) * N + outer) * NH + kx;
+    d[off] = sh[l * N + i];
+  }
+}
+
+// Pass 4: LINES z-lines (y, kx) per block. Psi at every kz; per line, the
+// shell sums of |k|^2/2 Psi (the line folded by |kz|) into
+// sbins[kappa][line] with the number of modes in scnt[kappa][line], and the
+// sum of Psi into sbins[N/2 + 1][line]; both weighted by the kx weight. Then
+// the inverse transform of Psi along z, written over field 0.
+template <int N, int LINES>
+__global__ void __launch_bounds__(256) psd_zinv_kernel(double2* h, double* sbins, double* scnt) {
+  constexpr int NH = N / 2 + 1, HALF = N / 2;
+  __shared__ double2 sh[LINES * N];
+  __shared__ double fold[LINES * (HALF + 1)];
+  __shared__ double2 tw[N / 2];
+  const size_t field = size_t(N) * N * NH;
+  const int nlines = N * NH;
+  make_twiddles<N>(tw, +1);
+  const int line0 = blockIdx.x * LINES;
+  for (int e = threadIdx.x; e < LINES * N; e += 256) {
+    const int i = e / LINES, l = e % LINES;
+    const int line = line0 + l, y = line / NH, kx = line % NH;
+    const size_t off = (size_t(i) * N + y) * NH + kx;
+    const double2 a = h[off], b = h[field + off], c = h[2 * field + off];
+    const double psd = a.x * a.x + a.y * a.y + b.x * b.x + b.y * b.y + c.x * c.x + c.y * c.y;
+    sh[l * N + bitrev<N>(i)] = make_double2(psd, 0.0);
+  }
+  __syncthreads();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int rows = n * n;
-  const int row = blockIdx.x * 4 + wave;
-  const int half = n / 2;
-  if (row < rows) {
-    const int iz = row / n, iy = row % n;
-    const int hz = iz <= half ? iz : iz - n, hy = iy <= half ? iy : iy - n;
-    const int64_t s = int64_t(hz) * hz + int64_t(hy) * hy;
-    const size_t base = size_t(row) * n;
-    const double v0 = data[0].x;
-    for (int m = lane; m <= half; m += 64) {
-      const double k2 = double(s) + double(m) * m;
-      const double a = data[base + m].x;
-      double v = mode == 0 ? 0.5 * k2 * a : 2.0 * (v0 - a);
-      if (m >= 1 && m <= half - 1) {
-        const double b = data[base + (n - m)].x;
-        v += mode == 0 ? 0.5 * k2 * b : 2.0 * (v0 - b);
-      }
-      sh[wave][m] = v;
+  for (int l = wave; l < LINES; l += 4) {
+    const int line = line0 + l, y = line / NH, kx = line % NH;
+    const int ky = y <= HALF ? y : y - N;
+    const int64_t s = int64_t(kx) * kx + int64_t(ky) * ky;
+    const double2* ln = sh + l * N;
+    double total = 0.0;
+    for (int m = lane; m <= HALF; m += 64) {
+      double v = ln[bitrev<N>(m)].x;
+      if (m >= 1 && m <= HALF - 1) v += ln[bitrev<N>(N - m)].x;
+      total += v;
+      fold[l * (HALF + 1) + m] = 0.5 * (double(s) + double(m) * m) * v;
+    }
+    total = wave_sum(total);
+    if (lane == 0) {
+      const double wkx = (kx == 0 || kx == HALF) ? 1.0 : 2.0;
+      sbins[size_t(HALF + 1) * nlines + line] = wkx * total;
     }
   }
   __syncthreads();
-  if (row < rows) {
-    const int iz = row / n, iy = row % n;
-    const int hz = iz <= half ? iz : iz - n, hy = iy <= half ? iy : iy - n;
+  for (int l = wave; l < LINES; l += 4) {
+    const int line = line0 + l, y = line / NH, kx = line % NH;
+    const int ky = y <= HALF ? y : y - N;
+    const int64_t s = int64_t(kx) * kx + int64_t(ky) * ky;
+    const double wkx = (kx == 0 || kx == HALF) ? 1.0 : 2.0;
+    for (int r = lane; r <= HALF; r += 64) {
+      double sum, cnt;
+      shell_interval(fold + l * (HALF + 1), HALF, s, r, sum, cnt);
+      sbins[size_t(r) * nlines + line] = wkx * sum;
+      scnt[size_t(r) * nlines + line] = wkx * cnt;
+    }
+  }
+  butterflies<N>(sh, LINES, tw);
+  for (int e = threadIdx.x; e < LINES * N; e += 256) {
+    const int i = e / LINES, l = e % LINES;
+    const int line = line0 + l, y = line / NH, kx = line % NH;
+    h[(size_t(i) * N + y) * NH + kx] = sh[l * N + i];
+  }
+}
+
+// Pass 6: ROWS x-rows (z, y) per block of field 0 (Psi transformed back along
+// z and y): the conjugate-symmetric fill of kx = N/2+1..N-1, the inverse
+// transform along x (R_h times N^6, real), and per row the shell sums of
+// 2 (R_0 - R_h) folded by |hx| into rbins[r][row], with the number of lags in
+// rcnt[r][row]. r0: R_0 times N^6 (the sum of Psi).
+template <int N>
+__global__ void __launch_bounds__(256)
+    inv_x_rows_kernel(const double2* h, const double* r0, double* rbins, double* rcnt) {
+  constexpr int NH = N / 2 + 1, HALF = N / 2;
+  constexpr int ROWS = (N * N < 1024 / N) ? N * N : 1024 / N;
+  __shared__ double2 sh[ROWS * N];
+  __shared__ double fold[ROWS * (HALF + 1)];
+  __shared__ double2 tw[N / 2];
+  make_twiddles<N>(tw, +1);
+  const int rows = N * N;
+  const int row0 = blockIdx.x * ROWS;
+  for (int e = threadIdx.x; e < ROWS * N; e += 256) {
+    const int r = e / N, k = e % N;
+    const size_t rowoff = size_t(row0 + r) * NH;
+    double2 v;
+    if (k <= HALF) {
+      v = h[rowoff + k];
+    } else {
+      const double2 c = h[rowoff + (N - k)];
+      v = make_double2(c.x, -c.y);
+    }
+    sh[r * N + bitrev<N>(k)] = v;
+  }
+  __syncthreads();
+  butterflies<N>(sh, ROWS, tw);
+  const double R0 = *r0;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int r = wave; r < ROWS; r += 4) {
+    for (int m = lane; m <= HALF; m += 64) {
+      double v = 2.0 * (R0 - sh[r * N + m].x);
+      if (m >= 1 && m <= HALF - 1) v += 2.0 * (R0 - sh[r * N + (N - m)].x);
+      fold[r * (HALF + 1) + m] = v;
+    }
+  }
+  __syncthreads();
+  for (int r = wave; r < ROWS; r += 4) {
+    const int row = row0 + r, iz = row / N, iy = row % N;
+    const int hz = iz <= HALF ? iz : iz - N, hy = iy <= HALF ? iy : iy - N;
     const int64_t s = int64_t(hz) * hz + int64_t(hy) * hy;
-    for (int r = lane; r <= half; r += 64) {
-      // m^2 in [ceil(((2r-1)^2 - 4s)/4), floor(((2r+1)^2 - 1 - 4s)/4)], m in [0, N/2]
-      double sum = 0.0, cnt = 0.0;
-      const int64_t lo2 = r == 0 ? 0 : int64_t(2 * r - 1) * (2 * r - 1);
-      const int64_t top = int64_t(2 * r + 1) * (2 * r + 1) - 1 - 4 * s;
-      if (top >= 0) {
-        const int64_t m2max = top / 4;
-        const int64_t bot = lo2 - 4 * s;
-        const int64_t m2min = bot <= 0 ? 0 : (bot + 3) / 4;
-        if (m2min <= m2max) {
-          int64_t a = isqrt_floor(m2min);
-          if (a * a < m2min) ++a;
-          int64_t b = isqrt_floor(m2max);
-          if (b > half) b = half;
-          for (int64_t m = a; m <= b; ++m) {
-            sum += sh[wave][m];
-            cnt += (m == 0 || m == half) ? 1.0 : 2.0;
-          }
-        }
-      }
-      rowbins[size_t(r) * rows + row] = sum;
-      rowcnt[size_t(r) * rows + row] = cnt;
+    for (int sh_r = lane; sh_r <= HALF; sh_r += 64) {
+      double sum, cnt;
+      shell_interval(fold + r * (HALF + 1), HALF, s, sh_r, sum, cnt);
+      rbins[size_t(sh_r) * rows + row] = sum;
+      rcnt[size_t(sh_r) * rows + row] = cnt;
     }
   }
 }
 
-__global__ void __launch_bounds__(256) shell_sum_kernel(const double* rowbins, const double* rowcnt, int n, int mode,
-                                                        double* out) {
-  const int rows = n * n;
+// Sum of a bins row over its `lines` entries in a fixed order (one block).
+__global__ void __launch_bounds__(256) line_total_kernel(const double* v, int lines, double* out) {
+  __shared__ double red[256];
+  double acc = 0.0;
+  for (int k = threadIdx.x; k < lines; k += 256) acc += v[k];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if (threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = red[0];
+}
+
+// One block per shell: the bins of its row summed in a fixed order.
+// mode 0 (spectrum, shells 0..N/2): 4 pi / count * sum / N^6;
+// mode 1 (structure function, shells 1..N/2): sum / count / N^6.
+__global__ void __launch_bounds__(256) shell_sum_kernel(const double* bins, const double* cnts, int lines, int n,
+                                                        int mode, double* out) {
   const int r = mode == 0 ? int(blockIdx.x) : int(blockIdx.x) + 1;
   __shared__ double sa[256], sc[256];
   double acc = 0.0, cnt = 0.0;
-  for (int k = threadIdx.x; k < rows; k += 256) {
-    acc += rowbins[size_t(r) * rows + k];
-    cnt += rowcnt[size_t(r) * rows + k];
+  for (int k = threadIdx.x; k < lines; k += 256) {
+    acc += bins[size_t(r) * lines + k];
+    cnt += cnts[size_t(r) * lines + k];
   }
   sa[threadIdx.x] = acc;
   sc[threadIdx.x] = cnt;
@@ -311,53 +450,102 @@ __global__ void __launch_bounds__(256) w1_reduce_kernel(const double* col, int q
   if (threadIdx.x == 0) out[blockIdx.x] = red[0] / q3;
 }
 
+// LINES for the transforms along y and z (LDS: LINES * N complex doubles);
+// it divides N, so it divides the N (N/2 + 1) lines of a field
 template <int N>
-hipError_t fft3_t(double2* data, const double* rin, int ncomp, int sign, hipStream_t s) {
-  constexpr int LINES = N >= 512 ? 4 : (N >= 256 ? 8 : 16);
-  const unsigned blocks = unsigned((N * N) / LINES);
-  const size_t n3 = size_t(N) * N * N;
-  for (int axis = 0; axis < 3; ++axis) {
-    hipLaunchKernelGGL((fft_axis_kernel<N, LINES>), dim3(blocks, ncomp), dim3(256), 0, s, data,
-                       axis == 0 ? rin : nullptr, axis, sign, n3, n3);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-  }
-  return hipSuccess;
+constexpr int half_lines() {
+  return N >= 512 ? 4 : (N >= 256 ? 8 : (N >= 16 ? 16 : 8));
 }
 
-}  // namespace
+struct ObsWork {
+  double2* h;       // 3 fields of N * N * NH complex
+  double* sbins;    // (N/2 + 2) x N NH
+  double* scnt;     // (N/2 + 1) x N NH
+  double* rbins;    // (N/2 + 1) x N N
+  double* rcnt;     // (N/2 + 1) x N N
+  double* r0;       // 1
+};
 
-hipError_t launch_fft3(int n, double2* data, const double* rin, int ncomp, int sign, hipStream_t s) {
+size_t align256(size_t b) { return (b + 255) / 256 * 256; }
+
+ObsWork carve(void* work, int n) {
+  const size_t nh = size_t(n / 2 + 1), lines = size_t(n) * nh, rows = size_t(n) * n, half = size_t(n / 2);
+  char* p = static_cast<char*>(work);
+  ObsWork w;
+  w.h = reinterpret_cast<double2*>(p);
+  p += align256(3 * rows * nh * sizeof(double2));
+  w.sbins = reinterpret_cast<double*>(p);
+  p += align256((half + 2) * lines * sizeof(double));
+  w.scnt = reinterpret_cast<double*>(p);
+  p += align256((half + 1) * lines * sizeof(double));
+  w.rbins = reinterpret_cast<double*>(p);
+  p += align256((half + 1) * rows * sizeof(double));
+  w.rcnt = reinterpret_cast<double*>(p);
+  p += align256((half + 1) * rows * sizeof(double));
+  w.r0 = reinterpret_cast<double*>(p);
+  return w;
+}
+
+template <int QN, typename T, int N>
+hipError_t observables_t(const T* pop, const DevSample* samples, int sample, int parity, void* work, double* s2,
+                         double* ek, hipStream_t s) {
+  constexpr int NH = N / 2 + 1, L = half_lines<N>();
+  constexpr int ROWS_X = N >= 512 ? 1 : 512 / N;
+  constexpr int ROWS_R = (N * N < 1024 / N) ? N * N : 1024 / N;
+  static_assert(N % L == 0 && (N * N) % ROWS_X == 0 && (N * N) % ROWS_R == 0, "launch shapes must tile the field");
+  const ObsWork w = carve(work, N);
+  const int lines = N * NH;
+  hipLaunchKernelGGL((fwd_x_kernel<QN, T, N>), dim3(N * N / ROWS_X), dim3(256), 0, s, pop, samples, sample, parity,
+                     w.h);
+  hipLaunchKernelGGL((fft_half_kernel<N, L>), dim3(lines / L, 3), dim3(256), 0, s, w.h, 1, -1);
+  hipLaunchKernelGGL((fft_half_kernel<N, L>), dim3(lines / L, 3), dim3(256), 0, s, w.h, 2, -1);
+  hipLaunchKernelGGL((psd_zinv_kernel<N, L>), dim3(lines / L), dim3(256), 0, s, w.h, w.sbins, w.scnt);
+  if (ek) hipLaunchKernelGGL(shell_sum_kernel, dim3(N / 2 + 1), dim3(256), 0, s, w.sbins, w.scnt, lines, N, 0, ek);
+  if (s2) {
+    hipLaunchKernelGGL(line_total_kernel, dim3(1), dim3(256), 0, s, w.sbins + size_t(N / 2 + 1) * lines, lines, w.r0);
+    hipLaunchKernelGGL((fft_half_kernel<N, L>), dim3(lines / L, 1), dim3(256), 0, s, w.h, 1, +1);
+    hipLaunchKernelGGL((inv_x_rows_kernel<N>), dim3(N * N / ROWS_R), dim3(256), 0, s, w.h, w.r0, w.rbins, w.rcnt);
+    hipLaunchKernelGGL(shell_sum_kernel, dim3(N / 2), dim3(256), 0, s, w.rbins, w.rcnt, N * N, N, 1, s2);
+  }
+  return hipGetLastError();
+}
+
+template <int QN, typename T>
+hipError_t observables_n(int n, const void* pop, const DevSample* samples, int sample, int parity, void* work,
+                         double* s2, double* ek, hipStream_t s) {
+  const T* p = static_cast<const T*>(pop);
   switch (n) {
-    case 8: return fft3_t<8>(data, rin, ncomp, sign, s);
-    case 16: return fft3_t<16>(data, rin, ncomp, sign, s);
-    case 32: return fft3_t<32>(data, rin, ncomp, sign, s);
-    case 64: return fft3_t<64>(data, rin, ncomp, sign, s);
-    case 128: return fft3_t<128>(data, rin, ncomp, sign, s);
-    case 256: return fft3_t<256>(data, rin, ncomp, sign, s);
-    case 512: return fft3_t<512>(data, rin, ncomp, sign, s);
+    case 8: return observables_t<QN, T, 8>(p, samples, sample, parity, work, s2, ek, s);
+    case 16: return observables_t<QN, T, 16>(p, samples, sample, parity, work, s2, ek, s);
+    case 32: return observables_t<QN, T, 32>(p, samples, sample, parity, work, s2, ek, s);
+    case 64: return observables_t<QN, T, 64>(p, samples, sample, parity, work, s2, ek, s);
+    case 128: return observables_t<QN, T, 128>(p, samples, sample, parity, work, s2, ek, s);
+    case 256: return observables_t<QN, T, 256>(p, samples, sample, parity, work, s2, ek, s);
+    case 512: return observables_t<QN, T, 512>(p, samples, sample, parity, work, s2, ek, s);
     default: return hipErrorInvalidValue;
   }
 }
 
-hipError_t launch_psd(const double2* x, size_t n3, double2* out, hipStream_t s) {
-  hipLaunchKernelGGL(psd_kernel, dim3(unsigned((n3 + 255) / 256)), dim3(256), 0, s, x, n3, out);
-  return hipGetLastError();
+}  // namespace
+
+size_t observables_work_bytes(int n) {
+  const size_t nh = size_t(n / 2 + 1), lines = size_t(n) * nh, rows = size_t(n) * n, half = size_t(n / 2);
+  return align256(3 * rows * nh * sizeof(double2)) + align256((half + 2) * lines * sizeof(double)) +
+         align256((half + 1) * lines * sizeof(double)) + 2 * align256((half + 1) * rows * sizeof(double)) +
+         align256(sizeof(double));
 }
 
-size_t shell_scratch_doubles(int n) { return size_t(2) * (n / 2 + 1) * size_t(n) * n; }
-
-hipError_t launch_shells(const double2* data, int n, int mode, double* scratch, double* out, hipStream_t s) {
-  const size_t table = size_t(n / 2 + 1) * size_t(n) * n;
-  double* rowbins = scratch;
-  double* rowcnt = scratch + table;
-  hipLaunchKernelGGL(shell_rows_kernel, dim3(unsigned((n * n + 3) / 4)), dim3(256), 0, s, data, n, mode, rowbins,
-                     rowcnt);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  const unsigned bins = mode == 0 ? unsigned(n / 2 + 1) : unsigned(n / 2);
-  hipLaunchKernelGGL(shell_sum_kernel, dim3(bins), dim3(256), 0, s, rowbins, rowcnt, n, mode, out);
-  return hipGetLastError();
+hipError_t launch_observables(int q, int precision, const void* pop, const DevSample* samples, int32_t sample,
+                              int32_t n, int32_t parity, void* work, double* s2, double* ek, hipStream_t s) {
+  if (q == 27) {
+    return precision == 0 ? observables_n<27, double>(n, pop, samples, sample, parity, work, s2, ek, s)
+                          : observables_n<27, float>(n, pop, samples, sample, parity, work, s2, ek, s);
+  }
+  if (q == 19) {
+    return precision == 0 ? observables_n<19, double>(n, pop, samples, sample, parity, work, s2, ek, s)
+                          : observables_n<19, float>(n, pop, samples, sample, parity, work, s2, ek, s);
+  }
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_point_values(int lattice, int precision, const void* pop, const DevSample* samples,

@@ -17,12 +17,18 @@ pytestmark = pytest.mark.gpu
 mc = pytest.importorskip("paper_2608_23786_amd")
 
 
-@pytest.mark.parametrize("n", [8, 16, 32, 64])
-def test_structure_function_and_spectrum_match_oracle_on_the_same_field(n):
+@pytest.mark.parametrize("n,steps,precision,lattice", [(8, 4, "f64", 27), (16, 8, "f64", 27), (32, 16, "f64", 27),
+                                                        (64, 32, "f64", 27), (128, 7, "f64", 27),
+                                                        (32, 5, "f32s", 27), (32, 3, "f32s", 19),
+                                                        (16, 6, "f64", 19)])
+def test_structure_function_and_spectrum_match_oracle_on_the_same_field(n, steps, precision, lattice):
+    """Both AA parities (the first pass reads the populations), both lattices
+    and precisions: the transforms and shell sums run in FP64 on the
+    velocities the library's own read-out gives."""
     y = mc_inputs.draw_y(31, 2)
-    ens = mc.Ensemble([mc.Sample(n, 0.05 * 32 / n, 25.0 * n, 0.3, True)] * 2, "f64")
+    ens = mc.Ensemble([mc.Sample(n, 0.05 * 32 / n, 25.0 * n, 0.3, True)] * 2, precision, lattice=lattice)
     ens.init(0, torch.from_numpy(y))
-    ens.step(max(4, n // 2))
+    ens.step(steps)
     for s in range(2):
         s2, ek = ens.observables(s)
         _, u = ens.moments(s)
