@@ -149,14 +149,19 @@ def bench_mixed(mc, torch, with_sf=True):
     """Uneven batch 32 x 64^3 + 12 x 128^3 + 4 x 256^3 (strides 16:4:1), 1000
     ticks, FP64 reductions fused every 16 ticks (all samples at equal physical
     time) and, when with_sf, the FP64 structure function of every sample per
-    saved tick. Returns a dict of throughput figures."""
+    saved tick (one batch of launches per resolution). Returns a dict of
+    throughput figures."""
     import mc_inputs
     wl = mc_inputs.WORKLOADS["mixed48_f32"]
     ens = build_ensemble(wl, mc, torch)
     tuned = ens.autotune(reps=1)
     ens.step(32)
     ticks, every = wl.ticks, wl.save_every
-    work = ens._dev_empty((max(int(mc.lib().mclbm_observables_work_bytes(ens._ctx, s)) for s in range(ens.m)),),
+    groups, first = [], 0
+    for g in wl.groups:
+        groups.append((first, g.count))
+        first += g.count
+    work = ens._dev_empty((max(int(mc.lib().mclbm_observables_range_work_bytes(ens._ctx, a, c)) for a, c in groups),),
                           torch.uint8)
     t0 = ens.ticks
     lups = sum(cells_per_tick(ens, t0 + k) for k in range(ticks))
@@ -169,8 +174,8 @@ def bench_mixed(mc, torch, with_sf=True):
         ens.step(min(every, ticks - k), record_every=every)
         saves += 1
         if with_sf:
-            for s in range(ens.m):
-                ens.observables(s, work, structure=True, spectrum=False)
+            for a, c in groups:
+                ens.observables_range(a, c, work, structure=True, spectrum=False)
     e1.record(ens.stream)
     ens.synchronize()
     sec = e0.elapsed_time(e1) / 1e3

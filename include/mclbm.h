@@ -224,6 +224,16 @@ size_t mclbm_observables_work_bytes(const mclbm_ctx* ctx, int32_t sample);
 mclbm_status mclbm_observables(mclbm_ctx* ctx, int32_t sample, double* s2_dev, double* ek_dev, void* work_dev,
                                size_t work_bytes);
 
+/* The same for `count` consecutive samples first..first+count-1 that share
+ * one n, in one set of launches per run of equal AA parity (the ensemble's
+ * resolution groups): s2_dev[count][n/2], ek_dev[count][n/2+1] (device,
+ * either may be NULL); work_dev: mclbm_observables_range_work_bytes bytes,
+ * 256-byte aligned (0 bytes means an invalid range). MCLBM_ERR_ARG when the
+ * range leaves the ensemble or mixes resolutions. */
+size_t mclbm_observables_range_work_bytes(const mclbm_ctx* ctx, int32_t first, int32_t count);
+mclbm_status mclbm_observables_range(mclbm_ctx* ctx, int32_t first, int32_t count, double* s2_dev, double* ek_dev,
+                                     void* work_dev, size_t work_bytes);
+
 /* Velocity of every sample at the q^3 nodes common to all resolutions
  * (node j = (jx, jy, jz) at lattice index (n/q) j, i.e. x = 2 pi j / q):
  * out_dev[m][3][q^3], double, component-major per sample (appendix on the

@@ -881,22 +881,47 @@ mclbm_status mclbm_backward(mclbm_ctx* c, int64_t ticks, int32_t ckpt_every, con
 }
 
 // ------------------------------------------------------------------ observables
+size_t mclbm_observables_range_work_bytes(const mclbm_ctx* c, int32_t first, int32_t count) {
+  if (!c || first < 0 || count < 1 || first + count > c->m) return 0;
+  for (int s = first + 1; s < first + count; ++s)
+    if (c->desc[s].n != c->desc[first].n) return 0;
+  return observables_work_bytes(c->desc[first].n, count);
+}
+
 size_t mclbm_observables_work_bytes(const mclbm_ctx* c, int32_t sample) {
-  if (!c || sample < 0 || sample >= c->m) return 0;
-  return observables_work_bytes(c->desc[sample].n);
+  return mclbm_observables_range_work_bytes(c, sample, 1);
+}
+
+mclbm_status mclbm_observables_range(mclbm_ctx* c, int32_t first, int32_t count, double* s2_dev, double* ek_dev,
+                                     void* work_dev, size_t work_bytes) {
+  mclbm_status st = check_ctx(c, true);
+  if (st != MCLBM_OK) return st;
+  if (first < 0 || count < 1 || first + count > c->m) return fail(MCLBM_ERR_ARG, "sample range out of bounds");
+  const int n = c->desc[first].n;
+  for (int s = first + 1; s < first + count; ++s)
+    if (c->desc[s].n != n) return fail(MCLBM_ERR_ARG, "the samples of a range must share one n");
+  if (!work_dev || work_bytes < observables_work_bytes(n, count))
+    return fail(MCLBM_ERR_OOM, "observables work buffer too small");
+  if (reinterpret_cast<uintptr_t>(work_dev) % kAlign) return fail(MCLBM_ERR_ARG, "work_dev must be 256-byte aligned");
+  // one set of launches per run of samples with the same AA parity
+  const size_t per = observables_work_bytes(n, 1);
+  for (int a = first; a < first + count;) {
+    const int parity = int(c->steps[a] & 1);
+    int b = a + 1;
+    while (b < first + count && int(c->steps[b] & 1) == parity) ++b;
+    const int k = a - first;
+    HIP_TRY(launch_observables(c->q, c->precision, c->pop, c->d_samples, a, b - a, n, parity,
+                               static_cast<char*>(work_dev) + size_t(k) * per,
+                               s2_dev ? s2_dev + size_t(k) * (n / 2) : nullptr,
+                               ek_dev ? ek_dev + size_t(k) * (n / 2 + 1) : nullptr, c->stream));
+    a = b;
+  }
+  return MCLBM_OK;
 }
 
 mclbm_status mclbm_observables(mclbm_ctx* c, int32_t sample, double* s2_dev, double* ek_dev, void* work_dev,
                                size_t work_bytes) {
-  mclbm_status st = check_ctx(c, true);
-  if (st != MCLBM_OK) return st;
-  if (sample < 0 || sample >= c->m) return fail(MCLBM_ERR_ARG, "sample out of range");
-  if (!work_dev || work_bytes < mclbm_observables_work_bytes(c, sample))
-    return fail(MCLBM_ERR_OOM, "observables work buffer too small");
-  if (reinterpret_cast<uintptr_t>(work_dev) % kAlign) return fail(MCLBM_ERR_ARG, "work_dev must be 256-byte aligned");
-  HIP_TRY(launch_observables(c->q, c->precision, c->pop, c->d_samples, sample, c->desc[sample].n,
-                             int32_t(c->steps[sample] & 1), work_dev, s2_dev, ek_dev, c->stream));
-  return MCLBM_OK;
+  return mclbm_observables_range(c, sample, 1, s2_dev, ek_dev, work_dev, work_bytes);
 }
 
 mclbm_status mclbm_point_values(mclbm_ctx* c, int32_t q, double* out_dev) {

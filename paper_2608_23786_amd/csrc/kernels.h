@@ -92,12 +92,15 @@ hipError_t launch_dissipation(const double* records, const DissSample* smp, int3
 
 hipError_t launch_stream_copy(void* dst, const void* src, size_t bytes, hipStream_t s);
 
-// Observables (observables.hip): structure function s2[n/2] (r = 1..n/2) and
-// energy spectrum ek[n/2+1] (kappa = 0..n/2) of one sample at its current
-// step (either may be NULL), in observables_work_bytes(n) bytes of work.
-size_t observables_work_bytes(int n);
-hipError_t launch_observables(int q, int precision, const void* pop, const DevSample* samples, int32_t sample,
-                              int32_t n, int32_t parity, void* work, double* s2, double* ek, hipStream_t s);
+// Observables (observables.hip) of `count` consecutive samples sample0.. that
+// share n and AA parity, in one set of launches: structure functions
+// s2[count][n/2] (r = 1..n/2) and energy spectra ek[count][n/2+1]
+// (kappa = 0..n/2), either may be NULL; work: observables_work_bytes(n,
+// count) bytes, 256-byte aligned.
+size_t observables_work_bytes(int n, int count);
+hipError_t launch_observables(int q, int precision, const void* pop, const DevSample* samples, int32_t sample0,
+                              int32_t count, int32_t n, int32_t parity, void* work, double* s2, double* ek,
+                              hipStream_t s);
 // lattice: 27 or 19; q: common nodes per axis
 hipError_t launch_point_values(int lattice, int precision, const void* pop, const DevSample* samples,
                                const Seg* segs, int32_t nseg, int q, double* out, hipStream_t s);

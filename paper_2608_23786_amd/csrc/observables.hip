@@ -82,6 +82,14 @@ __device__ __forceinline__ void butterflies(double2* sh, int nl, const double2* 
   }
 }
 
+// A batch of samples shares one launch: blockIdx.z is the sample's place in
+// the batch, and its work area starts wstride bytes after the previous one.
+template <typename P>
+__device__ __forceinline__ P* in_batch(P* p, size_t wstride) {
+  using B = typename std::conditional<std::is_const<P>::value, const char, char>::type;
+  return reinterpret_cast<P*>(reinterpret_cast<B*>(p) + size_t(blockIdx.z) * wstride);
+}
+
 __device__ __forceinline__ int64_t isqrt_floor(int64_t v) {
   if (v <= 0) return 0;
   int64_t r = int64_t(sqrt(double(v)));
@@ -120,12 +128,13 @@ __device__ __forceinline__ void shell_interval(const double* v, int half, int64_
 // h[c][(z N + y) NH + kx].
 template <int QN, typename T, int N>
 __global__ void __launch_bounds__(256)
-    fwd_x_kernel(const T* pop, const DevSample* samples, int sample, int parity, double2* h) {
+    fwd_x_kernel(const T* pop, const DevSample* samples, int sample0, int parity, double2* h0, size_t wstride) {
   constexpr int ROWS = N >= 512 ? 1 : 512 / N;
   constexpr int NH = N / 2 + 1;
   __shared__ double2 sh[3 * ROWS * N];
   __shared__ double2 tw[N / 2];
-  const DevSample& sp = samples[sample];
+  const DevSample& sp = samples[sample0 + blockIdx.z];
+  double2* h = in_batch(h0, wstride);
   const size_t row0 = size_t(blockIdx.x) * ROWS;
   make_twiddles<N>(tw, -1);
   const T* base = pop + sp.offset;
@@ -163,11 +172,11 @@ __global__ void __launch_bounds__(256)
 // h + c * N N NH, c = blockIdx.y; LINES lines (outer, kx) per block, outer =
 // z (axis 1) or y (axis 2), consecutive kx. sign -1 forward, +1 inverse.
 template <int N, int LINES>
-__global__ void __launch_bounds__(256) fft_half_kernel(double2* h, int axis, int sign) {
+__global__ void __launch_bounds__(256) fft_half_kernel(double2* h0, int axis, int sign, size_t wstride) {
   constexpr int NH = N / 2 + 1;
   __shared__ double2 sh[LINES * N];
   __shared__ double2 tw[N / 2];
-  double2* d = h + size_t(blockIdx.y) * N * N * NH;
+  double2* d = in_batch(h0, wstride) + size_t(blockIdx.y) * N * N * NH;
   make_twiddles<N>(tw, sign);
   const int line0 = blockIdx.x * LINES;
   for (int e = threadIdx.x; e < LINES * N; e += 256) {
@@ -188,17 +197,20 @@ __global__ void __launch_bounds__(256) fft_half_kernel(double2* h, int axis, int
 
 // Pass 4: LINES z-lines (y, kx) per block. Psi at every kz; per line, the
 // shell sums of |k|^2/2 Psi (the line folded by |kz|) into
-// sbins[kappa][line] with the number of modes in scnt[kappa][line], and the
-// sum of Psi into sbins[N/2 + 1][line]; both weighted by the kx weight. Then
-// the inverse transform of Psi along z, written over field 0.
+// sbins[line][kappa] with the number of modes in scnt[line][kappa], and the
+// sum of Psi into sbins[line][N/2 + 1], all weighted by the kx weight (rows
+// of N/2 + 2 values). Then the inverse transform of Psi along z, written
+// over field 0.
 template <int N, int LINES>
-__global__ void __launch_bounds__(256) psd_zinv_kernel(double2* h, double* sbins, double* scnt) {
+__global__ void __launch_bounds__(256) psd_zinv_kernel(double2* h0, double* sbins0, double* scnt0, size_t wstride) {
   constexpr int NH = N / 2 + 1, HALF = N / 2;
   __shared__ double2 sh[LINES * N];
   __shared__ double fold[LINES * (HALF + 1)];
   __shared__ double2 tw[N / 2];
   const size_t field = size_t(N) * N * NH;
-  const int nlines = N * NH;
+  double2* h = in_batch(h0, wstride);
+  double* sbins = in_batch(sbins0, wstride);
+  double* scnt = in_batch(scnt0, wstride);
   make_twiddles<N>(tw, +1);
   const int line0 = blockIdx.x * LINES;
   for (int e = threadIdx.x; e < LINES * N; e += 256) {
@@ -226,7 +238,8 @@ __global__ void __launch_bounds__(256) psd_zinv_kernel(double2* h, double* sbins
     total = wave_sum(total);
     if (lane == 0) {
       const double wkx = (kx == 0 || kx == HALF) ? 1.0 : 2.0;
-      sbins[size_t(HALF + 1) * nlines + line] = wkx * total;
+      sbins[size_t(line) * (HALF + 2) + HALF + 1] = wkx * total;
+      scnt[size_t(line) * (HALF + 2) + HALF + 1] = 0.0;
     }
   }
   __syncthreads();
@@ -238,8 +251,8 @@ __global__ void __launch_bounds__(256) psd_zinv_kernel(double2* h, double* sbins
     for (int r = lane; r <= HALF; r += 64) {
       double sum, cnt;
       shell_interval(fold + l * (HALF + 1), HALF, s, r, sum, cnt);
-      sbins[size_t(r) * nlines + line] = wkx * sum;
-      scnt[size_t(r) * nlines + line] = wkx * cnt;
+      sbins[size_t(line) * (HALF + 2) + r] = wkx * sum;
+      scnt[size_t(line) * (HALF + 2) + r] = wkx * cnt;
     }
   }
   butterflies<N>(sh, LINES, tw);
@@ -253,18 +266,21 @@ __global__ void __launch_bounds__(256) psd_zinv_kernel(double2* h, double* sbins
 // Pass 6: ROWS x-rows (z, y) per block of field 0 (Psi transformed back along
 // z and y): the conjugate-symmetric fill of kx = N/2+1..N-1, the inverse
 // transform along x (R_h times N^6, real), and per row the shell sums of
-// 2 (R_0 - R_h) folded by |hx| into rbins[r][row], with the number of lags in
-// rcnt[r][row]. r0: R_0 times N^6 (the sum of Psi).
+// 2 (R_0 - R_h) folded by |hx| into rbins[row][r], with the number of lags in
+// rcnt[row][r] (rows of N/2 + 2 values). r0: R_0 times N^6 (the sum of Psi).
 template <int N>
 __global__ void __launch_bounds__(256)
-    inv_x_rows_kernel(const double2* h, const double* r0, double* rbins, double* rcnt) {
+    inv_x_rows_kernel(const double2* h0, const double* r00, double* rbins0, double* rcnt0, size_t wstride) {
   constexpr int NH = N / 2 + 1, HALF = N / 2;
   constexpr int ROWS = (N * N < 1024 / N) ? N * N : 1024 / N;
   __shared__ double2 sh[ROWS * N];
   __shared__ double fold[ROWS * (HALF + 1)];
   __shared__ double2 tw[N / 2];
+  const double2* h = in_batch(h0, wstride);
+  const double* r0 = in_batch(r00, wstride);
+  double* rbins = in_batch(rbins0, wstride);
+  double* rcnt = in_batch(rcnt0, wstride);
   make_twiddles<N>(tw, +1);
-  const int rows = N * N;
   const int row0 = blockIdx.x * ROWS;
   for (int e = threadIdx.x; e < ROWS * N; e += 256) {
     const int r = e / N, k = e % N;
@@ -297,40 +313,58 @@ __global__ void __launch_bounds__(256)
     for (int sh_r = lane; sh_r <= HALF; sh_r += 64) {
       double sum, cnt;
       shell_interval(fold + r * (HALF + 1), HALF, s, sh_r, sum, cnt);
-      rbins[size_t(sh_r) * rows + row] = sum;
-      rcnt[size_t(sh_r) * rows + row] = cnt;
+      rbins[size_t(row) * (HALF + 2) + sh_r] = sum;
+      rcnt[size_t(row) * (HALF + 2) + sh_r] = cnt;
     }
   }
 }
 
-// Sum of a bins row over its `lines` entries in a fixed order (one block).
-__global__ void __launch_bounds__(256) line_total_kernel(const double* v, int lines, double* out) {
-  __shared__ double red[256];
-  double acc = 0.0;
-  for (int k = threadIdx.x; k < lines; k += 256) acc += v[k];
-  red[threadIdx.x] = acc;
-  __syncthreads();
-  for (int st = 128; st > 0; st >>= 1) {
-    if (threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
-    __syncthreads();
+// Shell reduction, stage 1: block b sums rows [b CHUNK, (b+1) CHUNK) of the
+// row-major tables bins / cnts (width values per row) column by column, in
+// row order, into psum[b][col] / pcnt[b][col].
+constexpr int kShellChunk = 32;
+
+__global__ void __launch_bounds__(256) shell_partial_kernel(const double* bins0, const double* cnts0, int rows,
+                                                            int width, double* psum0, double* pcnt0, size_t wstride) {
+  const double* bins = in_batch(bins0, wstride);
+  const double* cnts = in_batch(cnts0, wstride);
+  double* psum = in_batch(psum0, wstride);
+  double* pcnt = in_batch(pcnt0, wstride);
+  const int r0 = blockIdx.x * kShellChunk;
+  const int r1 = r0 + kShellChunk < rows ? r0 + kShellChunk : rows;
+  for (int col = threadIdx.x; col < width; col += 256) {
+    double a = 0.0, c = 0.0;
+#pragma unroll 8
+    for (int r = r0; r < r1; ++r) {
+      a += bins[size_t(r) * width + col];
+      c += cnts[size_t(r) * width + col];
+    }
+    psum[size_t(blockIdx.x) * width + col] = a;
+    pcnt[size_t(blockIdx.x) * width + col] = c;
   }
-  if (threadIdx.x == 0) *out = red[0];
 }
 
-// One block per shell: the bins of its row summed in a fixed order.
-// mode 0 (spectrum, shells 0..N/2): 4 pi / count * sum / N^6;
-// mode 1 (structure function, shells 1..N/2): sum / count / N^6.
-__global__ void __launch_bounds__(256) shell_sum_kernel(const double* bins, const double* cnts, int lines, int n,
-                                                        int mode, double* out) {
-  const int r = mode == 0 ? int(blockIdx.x) : int(blockIdx.x) + 1;
+// Stage 2, one block per column: the partials summed over the chunks (thread
+// t takes chunks t, t + 256, ..., then a fixed tree). mode 0 (spectrum):
+// out[kappa] = 4 pi / count * sum / N^6 for kappa = 0..N/2 (out may be NULL),
+// and column N/2 + 1 (the sum of Psi, R_0 times N^6) into *r0. mode 1
+// (structure function): out[r - 1] = sum / count / N^6 for r = 1..N/2.
+__global__ void __launch_bounds__(256) shell_final_kernel(const double* psum0, const double* pcnt0, int chunks,
+                                                          int width, int n, int mode, double* out0, double* r00,
+                                                          size_t wstride) {
   __shared__ double sa[256], sc[256];
-  double acc = 0.0, cnt = 0.0;
-  for (int k = threadIdx.x; k < lines; k += 256) {
-    acc += bins[size_t(r) * lines + k];
-    cnt += cnts[size_t(r) * lines + k];
+  const double* psum = in_batch(psum0, wstride);
+  const double* pcnt = in_batch(pcnt0, wstride);
+  double* out = out0 ? out0 + size_t(blockIdx.z) * (mode == 0 ? n / 2 + 1 : n / 2) : nullptr;
+  double* r0 = r00 ? in_batch(r00, wstride) : nullptr;
+  const int col = blockIdx.x;
+  double a = 0.0, c = 0.0;
+  for (int b = threadIdx.x; b < chunks; b += 256) {
+    a += psum[size_t(b) * width + col];
+    c += pcnt[size_t(b) * width + col];
   }
-  sa[threadIdx.x] = acc;
-  sc[threadIdx.x] = cnt;
+  sa[threadIdx.x] = a;
+  sc[threadIdx.x] = c;
   __syncthreads();
   for (int st = 128; st > 0; st >>= 1) {
     if (threadIdx.x < st) {
@@ -341,9 +375,14 @@ __global__ void __launch_bounds__(256) shell_sum_kernel(const double* bins, cons
   }
   if (threadIdx.x == 0) {
     const double norm = 1.0 / (double(n) * n * n) / (double(n) * n * n);
-    const double sum = sa[0] * norm, c = sc[0];
-    if (mode == 0) out[blockIdx.x] = c > 0 ? 4.0 * M_PI / c * sum : 0.0;
-    else out[blockIdx.x] = c > 0 ? sum / c : 0.0;
+    const int half = n / 2;
+    const double sum = sa[0], cnt = sc[0];
+    if (mode == 0) {
+      if (col <= half && out) out[col] = cnt > 0 ? 4.0 * M_PI / cnt * sum * norm : 0.0;
+      if (col == half + 1 && r0) *r0 = sum;
+    } else if (col >= 1 && col <= half) {
+      out[col - 1] = cnt > 0 ? sum * norm / cnt : 0.0;
+    }
   }
 }
 
@@ -459,91 +498,113 @@ constexpr int half_lines() {
 
 struct ObsWork {
   double2* h;       // 3 fields of N * N * NH complex
-  double* sbins;    // (N/2 + 2) x N NH
-  double* scnt;     // (N/2 + 1) x N NH
-  double* rbins;    // (N/2 + 1) x N N
-  double* rcnt;     // (N/2 + 1) x N N
+  double* sbins;    // N NH rows of N/2 + 2
+  double* scnt;     // N NH rows of N/2 + 2
+  double* rbins;    // N N rows of N/2 + 2
+  double* rcnt;     // N N rows of N/2 + 2
+  double* psum;     // one row of N/2 + 2 per chunk of N N rows
+  double* pcnt;
   double* r0;       // 1
 };
 
 size_t align256(size_t b) { return (b + 255) / 256 * 256; }
 
+size_t chunks_of(size_t rows) { return (rows + kShellChunk - 1) / kShellChunk; }
+
+// bytes of one sample's work area (a multiple of 256)
+size_t sample_work_bytes(int n) {
+  const size_t nh = size_t(n / 2 + 1), lines = size_t(n) * nh, rows = size_t(n) * n, width = size_t(n / 2 + 2);
+  return align256(3 * rows * nh * sizeof(double2)) + 2 * align256(lines * width * sizeof(double)) +
+         2 * align256(rows * width * sizeof(double)) + 2 * align256(chunks_of(rows) * width * sizeof(double)) +
+         align256(sizeof(double));
+}
+
 ObsWork carve(void* work, int n) {
-  const size_t nh = size_t(n / 2 + 1), lines = size_t(n) * nh, rows = size_t(n) * n, half = size_t(n / 2);
+  const size_t nh = size_t(n / 2 + 1), lines = size_t(n) * nh, rows = size_t(n) * n, width = size_t(n / 2 + 2);
   char* p = static_cast<char*>(work);
   ObsWork w;
   w.h = reinterpret_cast<double2*>(p);
   p += align256(3 * rows * nh * sizeof(double2));
   w.sbins = reinterpret_cast<double*>(p);
-  p += align256((half + 2) * lines * sizeof(double));
+  p += align256(lines * width * sizeof(double));
   w.scnt = reinterpret_cast<double*>(p);
-  p += align256((half + 1) * lines * sizeof(double));
+  p += align256(lines * width * sizeof(double));
   w.rbins = reinterpret_cast<double*>(p);
-  p += align256((half + 1) * rows * sizeof(double));
+  p += align256(rows * width * sizeof(double));
   w.rcnt = reinterpret_cast<double*>(p);
-  p += align256((half + 1) * rows * sizeof(double));
+  p += align256(rows * width * sizeof(double));
+  w.psum = reinterpret_cast<double*>(p);
+  p += align256(chunks_of(rows) * width * sizeof(double));
+  w.pcnt = reinterpret_cast<double*>(p);
+  p += align256(chunks_of(rows) * width * sizeof(double));
   w.r0 = reinterpret_cast<double*>(p);
   return w;
 }
 
 template <int QN, typename T, int N>
-hipError_t observables_t(const T* pop, const DevSample* samples, int sample, int parity, void* work, double* s2,
-                         double* ek, hipStream_t s) {
+hipError_t observables_t(const T* pop, const DevSample* samples, int sample0, int count, int parity, void* work,
+                         double* s2, double* ek, hipStream_t s) {
   constexpr int NH = N / 2 + 1, L = half_lines<N>();
   constexpr int ROWS_X = N >= 512 ? 1 : 512 / N;
   constexpr int ROWS_R = (N * N < 1024 / N) ? N * N : 1024 / N;
+  constexpr int W = N / 2 + 2;
   static_assert(N % L == 0 && (N * N) % ROWS_X == 0 && (N * N) % ROWS_R == 0, "launch shapes must tile the field");
   const ObsWork w = carve(work, N);
-  const int lines = N * NH;
-  hipLaunchKernelGGL((fwd_x_kernel<QN, T, N>), dim3(N * N / ROWS_X), dim3(256), 0, s, pop, samples, sample, parity,
-                     w.h);
-  hipLaunchKernelGGL((fft_half_kernel<N, L>), dim3(lines / L, 3), dim3(256), 0, s, w.h, 1, -1);
-  hipLaunchKernelGGL((fft_half_kernel<N, L>), dim3(lines / L, 3), dim3(256), 0, s, w.h, 2, -1);
-  hipLaunchKernelGGL((psd_zinv_kernel<N, L>), dim3(lines / L), dim3(256), 0, s, w.h, w.sbins, w.scnt);
-  if (ek) hipLaunchKernelGGL(shell_sum_kernel, dim3(N / 2 + 1), dim3(256), 0, s, w.sbins, w.scnt, lines, N, 0, ek);
+  const size_t ws = sample_work_bytes(N);
+  const unsigned z = unsigned(count);
+  const int lines = N * NH, rows = N * N;
+  const int lchunks = int(chunks_of(lines)), rchunks = int(chunks_of(rows));
+  hipLaunchKernelGGL((fwd_x_kernel<QN, T, N>), dim3(N * N / ROWS_X, 1, z), dim3(256), 0, s, pop, samples, sample0,
+                     parity, w.h, ws);
+  hipLaunchKernelGGL((fft_half_kernel<N, L>), dim3(lines / L, 3, z), dim3(256), 0, s, w.h, 1, -1, ws);
+  hipLaunchKernelGGL((fft_half_kernel<N, L>), dim3(lines / L, 3, z), dim3(256), 0, s, w.h, 2, -1, ws);
+  hipLaunchKernelGGL((psd_zinv_kernel<N, L>), dim3(lines / L, 1, z), dim3(256), 0, s, w.h, w.sbins, w.scnt, ws);
+  hipLaunchKernelGGL(shell_partial_kernel, dim3(lchunks, 1, z), dim3(256), 0, s, w.sbins, w.scnt, lines, W, w.psum,
+                     w.pcnt, ws);
+  hipLaunchKernelGGL(shell_final_kernel, dim3(W, 1, z), dim3(256), 0, s, w.psum, w.pcnt, lchunks, W, N, 0, ek, w.r0,
+                     ws);
   if (s2) {
-    hipLaunchKernelGGL(line_total_kernel, dim3(1), dim3(256), 0, s, w.sbins + size_t(N / 2 + 1) * lines, lines, w.r0);
-    hipLaunchKernelGGL((fft_half_kernel<N, L>), dim3(lines / L, 1), dim3(256), 0, s, w.h, 1, +1);
-    hipLaunchKernelGGL((inv_x_rows_kernel<N>), dim3(N * N / ROWS_R), dim3(256), 0, s, w.h, w.r0, w.rbins, w.rcnt);
-    hipLaunchKernelGGL(shell_sum_kernel, dim3(N / 2), dim3(256), 0, s, w.rbins, w.rcnt, N * N, N, 1, s2);
+    hipLaunchKernelGGL((fft_half_kernel<N, L>), dim3(lines / L, 1, z), dim3(256), 0, s, w.h, 1, +1, ws);
+    hipLaunchKernelGGL((inv_x_rows_kernel<N>), dim3(N * N / ROWS_R, 1, z), dim3(256), 0, s, w.h, w.r0, w.rbins,
+                       w.rcnt, ws);
+    hipLaunchKernelGGL(shell_partial_kernel, dim3(rchunks, 1, z), dim3(256), 0, s, w.rbins, w.rcnt, rows, W, w.psum,
+                       w.pcnt, ws);
+    hipLaunchKernelGGL(shell_final_kernel, dim3(W, 1, z), dim3(256), 0, s, w.psum, w.pcnt, rchunks, W, N, 1, s2,
+                       nullptr, ws);
   }
   return hipGetLastError();
 }
 
 template <int QN, typename T>
-hipError_t observables_n(int n, const void* pop, const DevSample* samples, int sample, int parity, void* work,
-                         double* s2, double* ek, hipStream_t s) {
+hipError_t observables_n(int n, const void* pop, const DevSample* samples, int sample0, int count, int parity,
+                         void* work, double* s2, double* ek, hipStream_t s) {
   const T* p = static_cast<const T*>(pop);
   switch (n) {
-    case 8: return observables_t<QN, T, 8>(p, samples, sample, parity, work, s2, ek, s);
-    case 16: return observables_t<QN, T, 16>(p, samples, sample, parity, work, s2, ek, s);
-    case 32: return observables_t<QN, T, 32>(p, samples, sample, parity, work, s2, ek, s);
-    case 64: return observables_t<QN, T, 64>(p, samples, sample, parity, work, s2, ek, s);
-    case 128: return observables_t<QN, T, 128>(p, samples, sample, parity, work, s2, ek, s);
-    case 256: return observables_t<QN, T, 256>(p, samples, sample, parity, work, s2, ek, s);
-    case 512: return observables_t<QN, T, 512>(p, samples, sample, parity, work, s2, ek, s);
+    case 8: return observables_t<QN, T, 8>(p, samples, sample0, count, parity, work, s2, ek, s);
+    case 16: return observables_t<QN, T, 16>(p, samples, sample0, count, parity, work, s2, ek, s);
+    case 32: return observables_t<QN, T, 32>(p, samples, sample0, count, parity, work, s2, ek, s);
+    case 64: return observables_t<QN, T, 64>(p, samples, sample0, count, parity, work, s2, ek, s);
+    case 128: return observables_t<QN, T, 128>(p, samples, sample0, count, parity, work, s2, ek, s);
+    case 256: return observables_t<QN, T, 256>(p, samples, sample0, count, parity, work, s2, ek, s);
+    case 512: return observables_t<QN, T, 512>(p, samples, sample0, count, parity, work, s2, ek, s);
     default: return hipErrorInvalidValue;
   }
 }
 
 }  // namespace
 
-size_t observables_work_bytes(int n) {
-  const size_t nh = size_t(n / 2 + 1), lines = size_t(n) * nh, rows = size_t(n) * n, half = size_t(n / 2);
-  return align256(3 * rows * nh * sizeof(double2)) + align256((half + 2) * lines * sizeof(double)) +
-         align256((half + 1) * lines * sizeof(double)) + 2 * align256((half + 1) * rows * sizeof(double)) +
-         align256(sizeof(double));
-}
+size_t observables_work_bytes(int n, int count) { return sample_work_bytes(n) * size_t(count); }
 
-hipError_t launch_observables(int q, int precision, const void* pop, const DevSample* samples, int32_t sample,
-                              int32_t n, int32_t parity, void* work, double* s2, double* ek, hipStream_t s) {
+hipError_t launch_observables(int q, int precision, const void* pop, const DevSample* samples, int32_t sample0,
+                              int32_t count, int32_t n, int32_t parity, void* work, double* s2, double* ek,
+                              hipStream_t s) {
   if (q == 27) {
-    return precision == 0 ? observables_n<27, double>(n, pop, samples, sample, parity, work, s2, ek, s)
-                          : observables_n<27, float>(n, pop, samples, sample, parity, work, s2, ek, s);
+    return precision == 0 ? observables_n<27, double>(n, pop, samples, sample0, count, parity, work, s2, ek, s)
+                          : observables_n<27, float>(n, pop, samples, sample0, count, parity, work, s2, ek, s);
   }
   if (q == 19) {
-    return precision == 0 ? observables_n<19, double>(n, pop, samples, sample, parity, work, s2, ek, s)
-                          : observables_n<19, float>(n, pop, samples, sample, parity, work, s2, ek, s);
+    return precision == 0 ? observables_n<19, double>(n, pop, samples, sample0, count, parity, work, s2, ek, s)
+                          : observables_n<19, float>(n, pop, samples, sample0, count, parity, work, s2, ek, s);
   }
   return hipErrorInvalidValue;
 }

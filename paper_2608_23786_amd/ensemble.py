@@ -196,6 +196,22 @@ class Ensemble:
         self._produce()
         return s2, ek
 
+    def observables_range(self, first: int, count: int, work: Optional[torch.Tensor] = None, structure: bool = True,
+                          spectrum: bool = True):
+        """(S2[count, n/2], E[count, n/2+1]) of samples first..first+count-1 (one n) in one set of launches."""
+        wb = int(lib().mclbm_observables_range_work_bytes(self._ctx, first, count))
+        if wb == 0:
+            raise MclbmError(_lib.ERR_ARG, "invalid sample range (out of bounds or mixed resolutions)")
+        n = self.samples[first].n
+        if work is None or work.numel() < wb:
+            work = self._dev_empty((wb,), torch.uint8)
+        s2 = self._dev_empty((count, n // 2)) if structure else None
+        ek = self._dev_empty((count, n // 2 + 1)) if spectrum else None
+        self._consume()
+        check(lib().mclbm_observables_range(self._ctx, first, count, _ptr(s2), _ptr(ek), _ptr(work), work.numel()))
+        self._produce()
+        return s2, ek
+
     def point_values(self, q: int = 8) -> torch.Tensor:
         """Velocity at the q^3 nodes common to all resolutions: [m, 3, q^3] float64."""
         out = self._dev_empty((self.m, 3, q ** 3))

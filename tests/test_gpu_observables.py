@@ -143,3 +143,26 @@ def test_dissipation_argument_checks():
         ens.dissipation(rec, 0, 4)
     with pytest.raises(mc.MclbmError, match="ERR_ARG"):
         ens.dissipation(rec[:1].contiguous(), 0, 4, eta=False)
+
+
+def test_observables_range_equals_single_samples():
+    """A resolution group in one set of launches gives bitwise the per-sample
+    results, also when the group's samples sit at different AA parities
+    (strides 1 and 2 after an odd number of ticks)."""
+    y = mc_inputs.draw_y(33, 5)
+    samples = [mc.Sample(16, 0.05, 200.0, 0.3, True, 1), mc.Sample(16, 0.05, 200.0, 0.3, True, 2),
+               mc.Sample(16, 0.05, 200.0, 0.3, True, 1), mc.Sample(32, 0.05, 200.0, 0.3, True, 1),
+               mc.Sample(32, 0.05, 200.0, 0.3, True, 1)]
+    ens = mc.Ensemble(samples, "f32s")
+    ens.init(0, torch.from_numpy(y))
+    ens.step(6)
+    ens.step(1)   # samples 0, 2: 7 steps (odd); sample 1: 4 steps (even)
+    for first, count in ((0, 3), (3, 2)):
+        s2r, ekr = ens.observables_range(first, count)
+        for k in range(count):
+            s2, ek = ens.observables(first + k)
+            assert torch.equal(s2r[k], s2) and torch.equal(ekr[k], ek), (first, k)
+    with pytest.raises(mc.MclbmError, match="ERR_ARG"):
+        ens.observables_range(2, 2)      # 16^3 and 32^3
+    with pytest.raises(mc.MclbmError, match="ERR_ARG"):
+        ens.observables_range(4, 2)      # past the ensemble
