@@ -266,11 +266,11 @@ def bench_sequence(mc, torch):
     samples = []
     for g in wl.groups:
         samples += [mc.Sample(g.n, g.u0, g.re, g.amp, g.project, g.stride)] * g.count
-    # launch shape: autotuned on one sample of the finest resolution, which
-    # steps on every tick and carries 95 % of the updates (tuning the whole
+    # launch shape: autotuned on two samples of the finest resolution, which
+    # step on every tick and carry 95 % of the updates (tuning the whole
     # ensemble would time 64 ticks of 1.1e9 updates per candidate)
     finest = wl.groups[-1]
-    proxy = mc.Ensemble([mc.Sample(finest.n, finest.u0, finest.re, finest.amp, finest.project)], wl.precision,
+    proxy = mc.Ensemble([mc.Sample(finest.n, finest.u0, finest.re, finest.amp, finest.project)] * 2, wl.precision,
                         lattice=wl.lattice)
     proxy.init(wl.seed)
     tuned = proxy.autotune(reps=2)

@@ -198,7 +198,8 @@ mclbm_status mclbm_restore(mclbm_ctx* ctx, const void* src_dev, size_t bytes);
  *     ke_dev[m] = KE_m(T) (device, may be NULL), recomputing each segment
  *     of ckpt_every steps from its checkpoint into work_dev.
  * Sizes come from mclbm_ckpt_bytes / mclbm_backward_work_bytes. The state
- * after backward is the forward state at T. */
+ * after backward is the forward state at T. Not available with the exact
+ * stabiliser (MCLBM_ERR_UNSUPPORTED). */
 size_t mclbm_ckpt_bytes(const mclbm_ctx* ctx, int64_t ticks, int32_t ckpt_every);
 size_t mclbm_backward_work_bytes(const mclbm_ctx* ctx, int32_t ckpt_every);
 mclbm_status mclbm_forward_ckpt(mclbm_ctx* ctx, int64_t ticks, int32_t ckpt_every, void* ckpt_dev,
