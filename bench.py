@@ -337,7 +337,7 @@ def cpu_baseline(seconds_target=15.0):
     t = time.perf_counter()
     oracle.run(f, g.n, 2, om, threads=threads)
     probe = time.perf_counter() - t
-    steps = max(2, min(200, int(seconds_target / max(probe / 2, 1e-6))))
+    steps = max(2, min(2000, int(seconds_target / max(probe / 2, 1e-6))))
     t = time.perf_counter()
     oracle.run(f, g.n, steps, om, threads=threads)
     sec = time.perf_counter() - t
