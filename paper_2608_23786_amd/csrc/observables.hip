@@ -61,22 +61,47 @@ __device__ __forceinline__ void make_twiddles(double2* tw, int sign) {
   }
 }
 
-// In-place radix-2 butterflies of nl lines of length N (line l at sh + l N)
-// loaded in bit-reversed order; every thread of the block takes part. The
-// caller synchronises after loading.
+// In-place butterflies of nl lines of length N (line l at sh + l N) loaded in
+// bit-reversed order (decimation in time); every thread of the block takes
+// part and the caller synchronises after loading. Two consecutive radix-2
+// stages (spans h and 2h) run as one radix-4 step in registers: a thread
+// takes the four values i0 + {0, 1, 2, 3} h, applies the span-h pairs (one
+// twiddle) and then the span-2h pairs (two twiddles), so LDS is read and
+// written once per two stages. An odd number of stages starts with one
+// radix-2 stage.
 template <int N>
 __device__ __forceinline__ void butterflies(double2* sh, int nl, const double2* tw) {
-  for (int half = 1; half < N; half <<= 1) {
-    const int stride = N / (2 * half);
+  constexpr int LOG = log2_of<N>();
+  int half = 1;
+  if (LOG & 1) {
     for (int b = threadIdx.x; b < nl * (N / 2); b += blockDim.x) {
       const int l = b / (N / 2), j = b % (N / 2);
+      double2* ln = sh + l * N + 2 * j;
+      const double2 a = ln[0], c = ln[1];
+      ln[0] = make_double2(a.x + c.x, a.y + c.y);
+      ln[1] = make_double2(a.x - c.x, a.y - c.y);
+    }
+    __syncthreads();
+    half = 2;
+  }
+  for (; half < N; half <<= 2) {
+    const int sa = N / (2 * half), sb = N / (4 * half);  // twiddle strides of the two stages
+    for (int b = threadIdx.x; b < nl * (N / 4); b += blockDim.x) {
+      const int l = b / (N / 4), j = b % (N / 4);
       const int pos = j % half, grp = j / half;
-      const int i0 = grp * 2 * half + pos, i1 = i0 + half;
-      double2* ln = sh + l * N;
-      const double2 a = ln[i0];
-      const double2 t = cmul(tw[pos * stride], ln[i1]);
-      ln[i0] = make_double2(a.x + t.x, a.y + t.y);
-      ln[i1] = make_double2(a.x - t.x, a.y - t.y);
+      double2* ln = sh + l * N + grp * 4 * half + pos;
+      const double2 x0 = ln[0], x1 = ln[half], x2 = ln[2 * half], x3 = ln[3 * half];
+      // span h: (x0, x1) and (x2, x3), twiddle tw[pos * sa]
+      const double2 wa = tw[pos * sa];
+      const double2 t1 = cmul(wa, x1), t3 = cmul(wa, x3);
+      const double2 y0 = make_double2(x0.x + t1.x, x0.y + t1.y), y1 = make_double2(x0.x - t1.x, x0.y - t1.y);
+      const double2 y2 = make_double2(x2.x + t3.x, x2.y + t3.y), y3 = make_double2(x2.x - t3.x, x2.y - t3.y);
+      // span 2h: (y0, y2) with tw[pos * sb], (y1, y3) with tw[(pos + h) * sb]
+      const double2 u2 = cmul(tw[pos * sb], y2), u3 = cmul(tw[(pos + half) * sb], y3);
+      ln[0] = make_double2(y0.x + u2.x, y0.y + u2.y);
+      ln[2 * half] = make_double2(y0.x - u2.x, y0.y - u2.y);
+      ln[half] = make_double2(y1.x + u3.x, y1.y + u3.y);
+      ln[3 * half] = make_double2(y1.x - u3.x, y1.y - u3.y);
     }
     __syncthreads();
   }
