@@ -108,3 +108,22 @@ def test_inputs_generator_is_splitmix64():
     assert out == [0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4]
     y = mc_inputs.draw_y(2608, 3)
     assert y.shape == (3, 24) and y.min() >= -1 and y.max() < 1
+
+
+def test_header_is_c99_and_host_calls_work_from_c(tmp_path):
+    """Compile a C99 program against include/mclbm.h (gcc, -Wall -Werror),
+    link libmclbm.so and run its host-only checks."""
+    import shutil
+    import subprocess
+    import paper_2608_23786_amd as mc
+    from paper_2608_23786_amd import _lib
+    if shutil.which("gcc") is None:
+        pytest.skip("no C compiler")
+    mc.lib()   # the library exists
+    libdir = os.path.dirname(_lib.LIB_PATH)
+    exe = str(tmp_path / "abi_host_check")
+    src = os.path.join(ROOT, "tests", "c", "abi_host_check.c")
+    subprocess.run(["gcc", "-std=c99", "-Wall", "-Wextra", "-Werror", "-I", os.path.join(ROOT, "include"), src,
+                    "-L", libdir, "-lmclbm", "-Wl,-rpath," + libdir, "-o", exe], check=True)
+    out = subprocess.run([exe], capture_output=True, text=True, timeout=120)
+    assert out.returncode == 0 and out.stdout.strip() == "ok", out.stdout + out.stderr
