@@ -20,28 +20,28 @@ import oracle
 pytestmark = pytest.mark.gpu
 mc = pytest.importorskip("paper_2608_23786_amd")
 
-C, W = oracle.velocity_set()
-
-
-def neighbours(n, cells):
+def neighbours(n, cells, q=27):
     """cell indices of x - c_i for every cell (rows) and velocity (columns)"""
+    c, _ = oracle.velocity_set(q)
     cells = np.asarray(cells, dtype=np.int64)
     x, y, z = cells % n, (cells // n) % n, cells // (n * n)
-    out = np.zeros((len(cells), 27), dtype=np.int64)
-    for i in range(27):
-        xs, ys, zs = (x - C[i, 0]) % n, (y - C[i, 1]) % n, (z - C[i, 2]) % n
+    out = np.zeros((len(cells), q), dtype=np.int64)
+    for i in range(q):
+        xs, ys, zs = (x - c[i, 0]) % n, (y - c[i, 1]) % n, (z - c[i, 2]) % n
         out[:, i] = (zs * n + ys) * n + xs
     return out
 
 
 def check_one_step(ens, samples, k, rng, tol):
     """Advance one tick and compare sampled post-step populations with the oracle."""
+    q = ens.q
+    _, w = oracle.velocity_set(q)
     pre = {}
     for s in samples:
         n = ens.samples[s].n
         cells = rng.choice(n ** 3, size=k, replace=False)
-        nb = neighbours(n, cells)
-        fpre = ens.get_cells(s, nb.ravel()).cpu().numpy().reshape(k, 27, 27)
+        nb = neighbours(n, cells, q)
+        fpre = ens.get_cells(s, nb.ravel()).cpu().numpy().reshape(k, q, q)
         pre[s] = (cells, fpre)
     steps_before = {s: ens.steps(s) for s in samples}
     ens.step(1)
@@ -55,10 +55,10 @@ def check_one_step(ens, samples, k, rng, tol):
         post = ens.get_cells(s, cells).cpu().numpy()
         expect = np.zeros_like(post)
         for kk in range(len(cells)):
-            for i in range(27):
+            for i in range(q):
                 fs, *_ = oracle.collide(fpre[kk, i], om)
                 expect[kk, i] = fs[i]
-        err = np.max(np.abs(post - expect)) / np.max(np.abs(expect - W))
+        err = np.max(np.abs(post - expect)) / np.max(np.abs(expect - w))
         worst = max(worst, err)
         assert err < tol, (s, err)
     return worst
@@ -69,7 +69,7 @@ def full_ensemble(name):
     samples = []
     for g in wl.groups:
         samples += [mc.Sample(g.n, g.u0, g.re, g.amp, g.project, g.stride)] * g.count
-    ens = mc.Ensemble(samples, wl.precision)
+    ens = mc.Ensemble(samples, wl.precision, lattice=wl.lattice)
     ens.init(wl.seed)
     return wl, ens
 
@@ -145,3 +145,74 @@ def test_512_cubed_sample_sampled_steps(block):
     print(f"sampled one-step error (512^3): {worst:.3e}")
     red = ens.reduce().cpu().numpy()[0]
     assert abs(red[0] - n ** 3) < 1e-6 * n ** 3
+
+
+def test_d3q19_64x64_full_size_sampled_steps():
+    """The 64 x 64^3 ensemble on D3Q19 in its autotuned launch shape."""
+    wl, ens = full_ensemble("rtgv64x64_f32_d3q19")
+    ens.autotune(reps=1)
+    rng = np.random.default_rng(19)
+    ens.step(20)
+    worst = max(check_one_step(ens, [0, 63], 48, rng, 2e-6), check_one_step(ens, [17], 48, rng, 2e-6))
+    print(f"sampled one-step error (D3Q19, full size): {worst:.3e}")
+
+
+def test_sequence512x8_full_size_sampled_steps():
+    """The vanishing-viscosity sequence at capacity (8 x 128^3 + 8 x 256^3 +
+    8 x 512^3, 132 GB of populations, the same Y at every resolution) in the
+    launch shape the benchmark tunes on two 512^3 samples: sampled cells of
+    every resolution at a tick where all step, then of the 512^3 samples."""
+    torch.cuda.empty_cache()
+    wl = mc_inputs.WORKLOADS["sequence512x8_f32"]
+    finest = wl.groups[-1]
+    proxy = mc.Ensemble([mc.Sample(finest.n, finest.u0, finest.re, finest.amp, finest.project)] * 2, wl.precision)
+    proxy.init(wl.seed)
+    shape = proxy.autotune(reps=1)
+    del proxy
+    torch.cuda.empty_cache()
+    samples = []
+    for g in wl.groups:
+        samples += [mc.Sample(g.n, g.u0, g.re, g.amp, g.project, g.stride)] * g.count
+    ens = mc.Ensemble(samples, wl.precision)
+    y = np.tile(mc_inputs.draw_y(wl.seed, wl.groups[0].count), (len(wl.groups), 1))
+    ens.init(0, torch.from_numpy(y))
+    ens.set_launch(*shape)
+    print("launch", shape)
+    ens.step(16)
+    rng = np.random.default_rng(512)
+    worst = max(check_one_step(ens, [0, 9, 17], 16, rng, 2e-6),     # tick 16: every sample steps
+                check_one_step(ens, [16, 23], 16, rng, 2e-6))       # tick 17: the 512^3 samples
+    print(f"sampled one-step error (sequence, full size): {worst:.3e}")
+    assert [ens.steps(s) for s in (0, 8, 16)] == [2, 5, 18]
+    red = ens.reduce().cpu().numpy()
+    for s in (0, 8, 16):
+        n3 = ens.samples[s].n ** 3
+        assert abs(red[s, 0] - n3) < 1e-6 * n3
+    del ens
+    torch.cuda.empty_cache()
+
+
+def test_adjoint128x8_full_size_fp32_against_fp64():
+    """The adjoint workload's shape (8 x 128^3, FP32) over 40 steps with
+    checkpoints every 10: its per-sample gradients against the FP64 adjoint
+    of two of the samples (the FP64 adjoint is pinned to the complex step at
+    smaller sizes). J is the ensemble mean, so gradients scale with 1/M."""
+    wl = mc_inputs.WORKLOADS["adjoint128x8_f32"]
+    g = wl.groups[0]
+    y = mc_inputs.draw_y(wl.seed, g.count)
+    smp = mc.Sample(g.n, g.u0, g.re, g.amp, g.project)
+    steps, every = 40, 10
+    e32 = mc.Ensemble([smp] * g.count, "f32s")
+    e32.init(0, torch.from_numpy(y))
+    ck = e32.forward_ckpt(steps, every)
+    d32, _ = e32.backward(steps, every, ck)
+    d32 = d32.cpu().numpy() * g.count
+    del e32, ck
+    e64 = mc.Ensemble([smp] * 2, "f64")
+    e64.init(0, torch.from_numpy(y[:2].copy()))
+    ck = e64.forward_ckpt(steps, every)
+    d64, _ = e64.backward(steps, every, ck)
+    d64 = d64.cpu().numpy() * 2
+    err = np.max(np.abs(d32[:2] - d64)) / np.max(np.abs(d64))
+    print(f"adjoint 8 x 128^3 FP32 vs FP64 (40 steps): {err:.3e}")
+    assert err < 1e-4
