@@ -266,14 +266,15 @@ def bench_sequence(mc, torch):
     samples = []
     for g in wl.groups:
         samples += [mc.Sample(g.n, g.u0, g.re, g.amp, g.project, g.stride)] * g.count
-    # launch shape: autotuned on two samples of the finest resolution, which
-    # step on every tick and carry 95 % of the updates (tuning the whole
-    # ensemble would time 64 ticks of 1.1e9 updates per candidate)
+    # launch shape: autotuned on the group of the finest resolution alone,
+    # which steps on every tick and carries 95 % of the updates (tuning the
+    # whole ensemble would time 64 ticks per candidate: its largest stride is
+    # 16); the group and the tuner's copy of it take 232 GB
     finest = wl.groups[-1]
-    proxy = mc.Ensemble([mc.Sample(finest.n, finest.u0, finest.re, finest.amp, finest.project)] * 2, wl.precision,
-                        lattice=wl.lattice)
+    proxy = mc.Ensemble([mc.Sample(finest.n, finest.u0, finest.re, finest.amp, finest.project)] * finest.count,
+                        wl.precision, lattice=wl.lattice)
     proxy.init(wl.seed)
-    tuned = proxy.autotune(reps=2)
+    tuned = proxy.autotune(reps=1)
     del proxy
     torch.cuda.empty_cache()
     ens = mc.Ensemble(samples, wl.precision, lattice=wl.lattice)
@@ -285,9 +286,7 @@ def bench_sequence(mc, torch):
     sec, lups = timed_ticks(ens, torch, ticks, every)
     if ens.check() >= 0:
         raise SystemExit("sequence workload became unstable")
-    pv = ens.point_values(8)                       # [m][3][8^3], lattice units
-    scale = torch.tensor([1.0 / s.u0 for s in samples], dtype=torch.float64, device=pv.device)
-    pv = (pv * scale[:, None, None]).contiguous()
+    pv = ens.point_values(8, physical=True)       # [m][3][8^3], u / U0
     w1 = {}
     for a, b in ((0, 1), (1, 2)):
         pa, pb = pv[a * per:(a + 1) * per].contiguous(), pv[b * per:(b + 1) * per].contiguous()

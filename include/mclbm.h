@@ -239,8 +239,9 @@ mclbm_status mclbm_observables_range(mclbm_ctx* ctx, int32_t first, int32_t coun
  * (node j = (jx, jy, jz) at lattice index (n/q) j, i.e. x = 2 pi j / q):
  * out_dev[m][3][q^3], double, component-major per sample (appendix on the
  * Wasserstein distances: exact restriction to the common downsampled grid).
- * q must divide every sample's n. */
-mclbm_status mclbm_point_values(mclbm_ctx* ctx, int32_t q, double* out_dev);
+ * physical = 1 gives u / u0 (velocities of different resolutions in the
+ * same units), 0 lattice units. q must divide every sample's n. */
+mclbm_status mclbm_point_values(mclbm_ctx* ctx, int32_t q, int32_t physical, double* out_dev);
 
 /* 1-point Wasserstein distance W_{1,1} between two ensembles (Algorithm 2 with
  * eq. (wassersteinPermutations)): for each node and component, W1 of the two

@@ -924,7 +924,7 @@ mclbm_status mclbm_observables(mclbm_ctx* c, int32_t sample, double* s2_dev, dou
   return mclbm_observables_range(c, sample, 1, s2_dev, ek_dev, work_dev, work_bytes);
 }
 
-mclbm_status mclbm_point_values(mclbm_ctx* c, int32_t q, double* out_dev) {
+mclbm_status mclbm_point_values(mclbm_ctx* c, int32_t q, int32_t physical, double* out_dev) {
   mclbm_status st = check_ctx(c, true);
   if (st != MCLBM_OK) return st;
   if (!out_dev) return fail(MCLBM_ERR_ARG, "out_dev is NULL");
@@ -934,7 +934,9 @@ mclbm_status mclbm_point_values(mclbm_ctx* c, int32_t q, double* out_dev) {
   const Table* t = nullptr;
   st = get_table(c, c->tick, true, kAuxBlock, false, &t);
   if (st != MCLBM_OK) return st;
-  HIP_TRY(launch_point_values(c->q, c->precision, c->pop, c->d_samples, table_ptr(c, t), t->nseg, q, out_dev, c->stream));
+  if (physical != 0 && physical != 1) return fail(MCLBM_ERR_ARG, "physical must be 0 or 1");
+  HIP_TRY(launch_point_values(c->q, c->precision, c->pop, c->d_samples, table_ptr(c, t), t->nseg, q, physical, out_dev,
+                              c->stream));
   return MCLBM_OK;
 }
 

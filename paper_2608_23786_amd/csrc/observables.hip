@@ -414,7 +414,7 @@ __global__ void __launch_bounds__(256) shell_final_kernel(const double* psum0, c
 // Velocity of every sample at the q^3 nodes x = (n/q) * j: out[s][3][q^3].
 template <int QN, typename T>
 __global__ void __launch_bounds__(64) point_values_kernel(const T* pop, const DevSample* samples, const Seg* segs,
-                                                          int q, double* out) {
+                                                          int q, int physical, double* out) {
   const Seg sg = segs[blockIdx.y];
   const DevSample& sp = samples[sg.sample];
   const int l = sp.log2n;
@@ -448,7 +448,7 @@ __global__ void __launch_bounds__(64) point_values_kernel(const T* pop, const De
     jys += cy(i) * v;
     jzs += cz(i) * v;
   }
-  const double rho = 1.0 + d;
+  const double rho = physical ? (1.0 + d) * sp.u0 : 1.0 + d;   // u / u0 or u
   double* o = out + size_t(sg.sample) * 3 * q3;
   o[j] = jxs / rho;
   o[q3 + j] = jys / rho;
@@ -635,20 +635,20 @@ hipError_t launch_observables(int q, int precision, const void* pop, const DevSa
 }
 
 hipError_t launch_point_values(int lattice, int precision, const void* pop, const DevSample* samples,
-                               const Seg* segs, int32_t nseg, int q, double* out, hipStream_t s) {
+                               const Seg* segs, int32_t nseg, int q, int physical, double* out, hipStream_t s) {
   const dim3 grid(unsigned((q * q * q + 63) / 64), unsigned(nseg));
   if (lattice == 27 && precision == 0)
     hipLaunchKernelGGL((point_values_kernel<27, double>), grid, dim3(64), 0, s, static_cast<const double*>(pop),
-                       samples, segs, q, out);
+                       samples, segs, q, physical, out);
   else if (lattice == 27)
     hipLaunchKernelGGL((point_values_kernel<27, float>), grid, dim3(64), 0, s, static_cast<const float*>(pop),
-                       samples, segs, q, out);
+                       samples, segs, q, physical, out);
   else if (lattice == 19 && precision == 0)
     hipLaunchKernelGGL((point_values_kernel<19, double>), grid, dim3(64), 0, s, static_cast<const double*>(pop),
-                       samples, segs, q, out);
+                       samples, segs, q, physical, out);
   else if (lattice == 19)
     hipLaunchKernelGGL((point_values_kernel<19, float>), grid, dim3(64), 0, s, static_cast<const float*>(pop),
-                       samples, segs, q, out);
+                       samples, segs, q, physical, out);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();

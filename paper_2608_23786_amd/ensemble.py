@@ -212,10 +212,11 @@ class Ensemble:
         self._produce()
         return s2, ek
 
-    def point_values(self, q: int = 8) -> torch.Tensor:
-        """Velocity at the q^3 nodes common to all resolutions: [m, 3, q^3] float64."""
+    def point_values(self, q: int = 8, physical: bool = False) -> torch.Tensor:
+        """Velocity at the q^3 nodes common to all resolutions: [m, 3, q^3] float64,
+        in lattice units or, with physical, as u / u0."""
         out = self._dev_empty((self.m, 3, q ** 3))
-        check(lib().mclbm_point_values(self._ctx, q, _ptr(out)))
+        check(lib().mclbm_point_values(self._ctx, q, int(physical), _ptr(out)))
         self._produce()
         return out
 

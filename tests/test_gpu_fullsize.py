@@ -160,12 +160,13 @@ def test_d3q19_64x64_full_size_sampled_steps():
 def test_sequence512x8_full_size_sampled_steps():
     """The vanishing-viscosity sequence at capacity (8 x 128^3 + 8 x 256^3 +
     8 x 512^3, 132 GB of populations, the same Y at every resolution) in the
-    launch shape the benchmark tunes on two 512^3 samples: sampled cells of
+    launch shape the benchmark tunes on its 512^3 group: sampled cells of
     every resolution at a tick where all step, then of the 512^3 samples."""
     torch.cuda.empty_cache()
     wl = mc_inputs.WORKLOADS["sequence512x8_f32"]
     finest = wl.groups[-1]
-    proxy = mc.Ensemble([mc.Sample(finest.n, finest.u0, finest.re, finest.amp, finest.project)] * 2, wl.precision)
+    proxy = mc.Ensemble([mc.Sample(finest.n, finest.u0, finest.re, finest.amp, finest.project)] * finest.count,
+                        wl.precision)
     proxy.init(wl.seed)
     shape = proxy.autotune(reps=1)
     del proxy

@@ -77,11 +77,13 @@ def test_mixed_resolutions_point_values_and_w1():
     ens.init(0, torch.from_numpy(y))
     ens.step(16)
     pv = ens.point_values(8).cpu().numpy()
+    pvp = ens.point_values(8, physical=True).cpu().numpy()
     for s, (n, _) in enumerate(specs):
         _, u = ens.moments(s)
         u = u.cpu().numpy()
         st = n // 8
         assert np.array_equal(pv[s], u[:, ::st, ::st, ::st].reshape(3, 512))
+        assert np.allclose(pvp[s], pv[s] / samples[s].u0, rtol=1e-14, atol=0)
     # W1 between the two 16^3 samples and the two 32^3 samples (an ensemble of 2 each)
     a = torch.from_numpy(pv[[0, 2]]).cuda().contiguous()
     b = torch.from_numpy(pv[[1, 3]]).cuda().contiguous()
