@@ -257,9 +257,10 @@ def bench_sequence(mc, torch):
     """Capacity run of the vanishing-viscosity sequence: 8 samples at each of
     128^3, 256^3 and 512^3 in one ensemble (132 GB of FP32 populations), the
     same Y at every resolution, strides 16:4:1, FP64 records every 16 ticks.
-    After the timed ticks, the velocities at the 8^3 nodes common to all
-    resolutions give the 1-point Wasserstein distances 128<->256 and
-    256<->512 (mean over nodes and components, physical units u / U0)."""
+    After the timed ticks: the FP64 energy spectrum and structure function
+    of every sample, and the 1-point Wasserstein distances 128<->256 and
+    256<->512 of the velocities at the 8^3 nodes common to all resolutions
+    (mean over nodes and components, physical units u / U0)."""
     import mc_inputs
     import numpy as np
     wl = mc_inputs.WORKLOADS["sequence512x8_f32"]
@@ -286,6 +287,24 @@ def bench_sequence(mc, torch):
     sec, lups = timed_ticks(ens, torch, ticks, every)
     if ens.check() >= 0:
         raise SystemExit("sequence workload became unstable")
+    # FP64 energy spectrum and structure function of every sample (one batch
+    # of launches per resolution), ensemble means in units of U0^2
+    obs = {}
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ens.synchronize()
+    e0.record(ens.stream)
+    first = 0
+    for g in wl.groups:
+        s2, ek = ens.observables_range(first, g.count)
+        obs[g.n] = (s2, ek, g.u0)
+        first += g.count
+    e1.record(ens.stream)
+    ens.synchronize()
+    obs_sec = e0.elapsed_time(e1) / 1e3
+    spectra = {f"{n}^3": {"S2_r1_r2_r4": [round(float(s2[:, r - 1].mean()) / u0 ** 2, 10) for r in (1, 2, 4)],
+                          "E_peak_kappa": int(ek.mean(dim=0).argmax())}
+               for n, (s2, ek, u0) in obs.items()}
+    del obs
     pv = ens.point_values(8, physical=True)       # [m][3][8^3], u / U0
     w1 = {}
     for a, b in ((0, 1), (1, 2)):
@@ -297,6 +316,7 @@ def bench_sequence(mc, torch):
            "population_GB": round(gb, 1), "lattice_updates": lups, "seconds": round(sec, 4),
            "MLUPS": round(lups / sec / 1e6, 1),
            "launch": dict(zip(("block", "xcd_remap", "buffer_addressing", "nontemporal"), tuned)),
+           "observables_seconds": round(obs_sec, 4), "ensemble_mean_observables": spectra,
            "W1_1pt_u_over_U0": w1}
     del ens, pv
     torch.cuda.empty_cache()
