@@ -22,7 +22,9 @@ Contents and the passage each part follows:
   * observables: energy spectrum, eqs. (dftCoeff), (energySpecDisc);
     structure function, Lemma (structureFunctionSpectral) / eq.
     (SF_single_spec2); 1-point Wasserstein distance between equal-size
-    empirical laws by sorted rearrangement, eq. (wassersteinPermutations).
+    empirical laws by sorted rearrangement, eq. (wassersteinPermutations);
+    the ensemble-mean relative L1 sample error, eq. (sample_error), and the
+    least-squares convergence order of Algorithm (ComputeSlopes).
 
 Lattices: D3Q27 (q = 27, the default) and the paper's D3Q19 (q = 19).
 
@@ -353,3 +355,36 @@ def wasserstein1_equal_weights(a, b):
     b = np.sort(np.asarray(b, dtype=np.float64))
     assert a.shape == b.shape
     return float(np.mean(np.abs(a - b)))
+
+
+def sample_error_l1(a, b):
+    """eq. (sample_error): the mean over the M samples of the relative L1
+    distance between sample m at resolution N (a) and sample m of the
+    reference resolution (b, drawn from the same Y_m), over the common nodes.
+    a, b: point values [M][3][G]. Returns four values: one per velocity
+    component (|.| the absolute value of that component) and one for the
+    velocity vector (|.| its Euclidean length). A sample whose reference
+    values are all zero gives 0/0 (NaN) there: the definition has no value."""
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    assert a.shape == b.shape and a.ndim == 3 and a.shape[1] == 3
+    m, _, g = a.shape
+    out = np.zeros(4)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        for s in range(m):
+            for c in range(3):
+                num = sum(abs(a[s, c, k] - b[s, c, k]) for k in range(g))
+                den = sum(abs(b[s, c, k]) for k in range(g))
+                out[c] += np.float64(num) / np.float64(den)
+            num = sum(math.sqrt(sum((a[s, c, k] - b[s, c, k]) ** 2 for c in range(3))) for k in range(g))
+            den = sum(math.sqrt(sum(b[s, c, k] ** 2 for c in range(3))) for k in range(g))
+            out[3] += np.float64(num) / np.float64(den)
+    return out / m
+
+
+def eoc_slope(ns, ds):
+    """Algorithm (ComputeSlopes): the experimental order of convergence at one
+    time is the slope of the least-squares line through the points
+    (log N, log D_N) of the distances D_N to the reference resolution."""
+    return float(np.polyfit(np.log(np.asarray(ns, dtype=np.float64)),
+                            np.log(np.asarray(ds, dtype=np.float64)), 1)[0])

@@ -550,6 +550,44 @@ def test_wasserstein_sorted_matches_permutation_brute_force():
         assert abs(oracle.wasserstein1_equal_weights(a, b) - brute) < 1e-15
 
 
+def test_sample_error_closed_forms():
+    """eq. (sample_error): zero for identical ensembles; |delta_m| averaged
+    over samples (not pooled over them) when a = (1 + delta_m) b; the
+    reference in the denominator; the absolute value; the Euclidean length
+    for the vector (a 3-4-5 reference); 0/0 where a reference component
+    vanishes."""
+    rng = np.random.default_rng(21)
+    b = rng.normal(size=(2, 3, 8))
+    assert np.array_equal(oracle.sample_error_l1(b, b), np.zeros(4))
+    b[1] *= 1e3
+    a = b * np.array([1.1, 1.3])[:, None, None]
+    assert np.max(np.abs(oracle.sample_error_l1(a, b) - 0.2)) < 1e-15
+    assert np.max(np.abs(oracle.sample_error_l1(-b, b) - 2.0)) < 1e-15
+    one = np.ones((1, 3, 8))
+    assert np.max(np.abs(oracle.sample_error_l1(one, 0.5 * one) - 1.0)) < 1e-15
+    assert np.max(np.abs(oracle.sample_error_l1(0.5 * one, one) - 0.5)) < 1e-15
+    ref = np.zeros((1, 3, 8))
+    ref[0, 0], ref[0, 1] = 3.0, 4.0
+    got = oracle.sample_error_l1(ref + np.array([0.01, 0.0, 0.0])[None, :, None], ref)
+    assert abs(got[0] - 0.01 / 3) < 1e-15 and got[1] == 0.0 and np.isnan(got[2])
+    assert abs(got[3] - 0.01 / 5) < 1e-15
+
+
+def test_eoc_slope_power_laws():
+    """Algorithm (ComputeSlopes): the slope of an exact power law C N^alpha is
+    alpha; two points give log(D1/D0) / log(N1/N0); scaling N or D leaves it
+    unchanged; for three points equally spaced in log N the least-squares
+    slope is the end-to-end slope whatever the middle value."""
+    ns = [32, 64, 128, 256]
+    assert abs(oracle.eoc_slope(ns, [0.7 * n ** -0.45 for n in ns]) + 0.45) < 1e-13
+    assert abs(oracle.eoc_slope([128, 512], [0.02, 0.005]) - math.log(0.25) / math.log(4)) < 1e-14
+    ds = [0.3, 0.11, 0.07, 0.02]
+    base = oracle.eoc_slope(ns, ds)
+    assert abs(oracle.eoc_slope([3 * n for n in ns], [5 * d for d in ds]) - base) < 1e-13
+    for mid in (0.01, 0.05, 0.2):
+        assert abs(oracle.eoc_slope([64, 128, 256], [0.1, mid, 0.02]) - math.log(0.2) / math.log(4)) < 1e-14
+
+
 def test_taylor_green_field():
     """eq. (tgv_init_velo): divergence-free, and its values at sample nodes."""
     n = 8
