@@ -258,9 +258,10 @@ def bench_sequence(mc, torch):
     128^3, 256^3 and 512^3 in one ensemble (132 GB of FP32 populations), the
     same Y at every resolution, strides 16:4:1, FP64 records every 16 ticks.
     After the timed ticks: the FP64 energy spectrum and structure function
-    of every sample, and the 1-point Wasserstein distances 128<->256 and
-    256<->512 of the velocities at the 8^3 nodes common to all resolutions
-    (mean over nodes and components, physical units u / U0)."""
+    of every sample; the 1-point Wasserstein distance and the relative L1
+    sample error of the 128^3 and 256^3 ensembles against the 512^3 one, on
+    the velocities at the 8^3 nodes common to all resolutions (physical
+    units u / U0), and their orders of convergence in N."""
     import mc_inputs
     import numpy as np
     wl = mc_inputs.WORKLOADS["sequence512x8_f32"]
@@ -305,19 +306,29 @@ def bench_sequence(mc, torch):
                           "E_peak_kappa": int(ek.mean(dim=0).argmax())}
                for n, (s2, ek, u0) in obs.items()}
     del obs
+    # distances of the coarser ensembles to the finest one (the reference)
+    # and the least-squares orders of convergence over log N: Wasserstein
+    # (EOWC, from W_{1,1}) and sample-wise (EOSC, from the vector L1 error)
     pv = ens.point_values(8, physical=True)       # [m][3][8^3], u / U0
-    w1 = {}
-    for a, b in ((0, 1), (1, 2)):
-        pa, pb = pv[a * per:(a + 1) * per].contiguous(), pv[b * per:(b + 1) * per].contiguous()
-        terms = mc.w1_1pt(pa, pb, 8)               # on the current stream, like pv
-        w1[f"{wl.groups[a].n}<->{wl.groups[b].n}"] = [round(float(v), 8) for v in terms.cpu()]
+    nref, ref = wl.groups[-1].n, pv[(len(wl.groups) - 1) * per:].contiguous()
+    ns, w1, err = [], [], []
+    for k, g in enumerate(wl.groups[:-1]):
+        cur = pv[k * per:(k + 1) * per].contiguous()
+        w1.append(float(mc.w1_1pt(cur, ref, 8).sum()))          # on the current stream, like pv
+        err.append(mc.sample_error(cur, ref, 8).cpu().tolist())
+        ns.append(g.n)
+    conv = {"reference_n": nref,
+            "W1_1pt_u_over_U0": {f"{n}^3": round(v, 8) for n, v in zip(ns, w1)},
+            "sample_error_L1_xyz_vec": {f"{n}^3": [round(v, 6) for v in e] for n, e in zip(ns, err)},
+            "EOWC_W1_1pt": round(mc.eoc_slope(ns, w1), 4),
+            "EOSC_vec": round(mc.eoc_slope(ns, [e[3] for e in err]), 4)}
     gb = sum(s.n ** 3 for s in samples) * BYTES_PER_LUP[wl.precision, wl.lattice] / 2 / 1e9
     out = {"workload": wl.name, "ticks": ticks, "steps": [ticks // g.stride for g in wl.groups],
            "population_GB": round(gb, 1), "lattice_updates": lups, "seconds": round(sec, 4),
            "MLUPS": round(lups / sec / 1e6, 1),
            "launch": dict(zip(("block", "xcd_remap", "buffer_addressing", "nontemporal"), tuned)),
            "observables_seconds": round(obs_sec, 4), "ensemble_mean_observables": spectra,
-           "W1_1pt_u_over_U0": w1}
+           "convergence": conv}
     del ens, pv
     torch.cuda.empty_cache()
     return out

@@ -255,6 +255,29 @@ size_t mclbm_w1_work_bytes(int32_t q);
 mclbm_status mclbm_w1_1pt(const double* a_dev, const double* b_dev, int32_t m, int32_t q, double* out_dev,
                           void* work_dev, size_t work_bytes, void* hip_stream);
 
+/* Ensemble-mean relative L1 distance between the samples of two ensembles at
+ * the common nodes (eq. (sample_error)): out_dev[k] = (1/m) sum_m
+ * sum_nodes |a_m - b_m| / sum_nodes |b_m|, with b the reference ensemble and
+ * sample m of both drawn from the same Y_m; k = 0, 1, 2 take |.| of one
+ * velocity component, k = 3 the Euclidean length of the velocity vector.
+ * a_dev, b_dev: point values [m][3][q^3] (device, double, as written by
+ * mclbm_point_values); out_dev[4] (device). A sample whose reference values
+ * of a quantity are all zero, where the definition has no value, makes that
+ * quantity +inf (NaN if its own values are all zero too). 1 <= m <= 2^20,
+ * 1 <= q <= 64. work_dev: mclbm_sample_error_work_bytes(m) bytes of device
+ * scratch. Runs on hip_stream; the result does not depend on the launch
+ * (fixed summation order). */
+size_t mclbm_sample_error_work_bytes(int32_t m);
+mclbm_status mclbm_sample_error(const double* a_dev, const double* b_dev, int32_t m, int32_t q, double* out_dev,
+                                void* work_dev, size_t work_bytes, void* hip_stream);
+
+/* Experimental order of convergence (Algorithm (ComputeSlopes)): the slope
+ * of the least-squares line through (log n[i], log d[i]), i < k, where d[i]
+ * is a distance of resolution n[i] to the reference resolution (host
+ * arrays; k >= 2; all values positive and finite; not all n equal, else
+ * MCLBM_ERR_ARG). *slope (host) receives it. Host only: no device call. */
+mclbm_status mclbm_eoc_slope(const double* n, const double* d, int32_t k, double* slope);
+
 /* Dissipation rate per unit volume and Kolmogorov length from a series of
  * records of mclbm_step (the definition of the sample dissipation rate
  * before eq. (kolmogorov_microscale), and that equation): d_m(t) =

@@ -364,7 +364,8 @@ def sample_error_l1(a, b):
     a, b: point values [M][3][G]. Returns four values: one per velocity
     component (|.| the absolute value of that component) and one for the
     velocity vector (|.| its Euclidean length). A sample whose reference
-    values are all zero gives 0/0 (NaN) there: the definition has no value."""
+    values of a quantity are all zero, where the definition has no value,
+    makes it +inf (NaN if its own values are all zero too)."""
     a = np.asarray(a, dtype=np.float64)
     b = np.asarray(b, dtype=np.float64)
     assert a.shape == b.shape and a.ndim == 3 and a.shape[1] == 3

@@ -952,6 +952,42 @@ mclbm_status mclbm_w1_1pt(const double* a_dev, const double* b_dev, int32_t m, i
   return MCLBM_OK;
 }
 
+size_t mclbm_sample_error_work_bytes(int32_t m) { return m > 0 ? size_t(4) * m * sizeof(double) : 0; }
+
+mclbm_status mclbm_sample_error(const double* a_dev, const double* b_dev, int32_t m, int32_t q, double* out_dev,
+                                void* work_dev, size_t work_bytes, void* hip_stream) {
+  if (!a_dev || !b_dev || !out_dev || !work_dev) return fail(MCLBM_ERR_ARG, "NULL buffer");
+  if (m < 1 || m > (1 << 20)) return fail(MCLBM_ERR_ARG, "m must be in [1, 2^20]");
+  if (q < 1 || q > 64) return fail(MCLBM_ERR_ARG, "q must be in [1, 64]");
+  if (work_bytes < mclbm_sample_error_work_bytes(m)) return fail(MCLBM_ERR_OOM, "sample error work buffer too small");
+  HIP_TRY(launch_sample_error(a_dev, b_dev, m, q, static_cast<double*>(work_dev), out_dev,
+                              static_cast<hipStream_t>(hip_stream)));
+  return MCLBM_OK;
+}
+
+mclbm_status mclbm_eoc_slope(const double* n, const double* d, int32_t k, double* slope) {
+  if (!n || !d || !slope) return fail(MCLBM_ERR_ARG, "NULL argument");
+  if (k < 2) return fail(MCLBM_ERR_ARG, "at least two resolutions are needed");
+  double mx = 0.0, my = 0.0;
+  for (int32_t i = 0; i < k; ++i) {
+    if (!(n[i] > 0.0) || !(d[i] > 0.0) || !std::isfinite(n[i]) || !std::isfinite(d[i]))
+      return fail(MCLBM_ERR_ARG, "resolutions and distances must be positive and finite");
+    mx += std::log(n[i]);
+    my += std::log(d[i]);
+  }
+  mx /= k;
+  my /= k;
+  double sxy = 0.0, sxx = 0.0;
+  for (int32_t i = 0; i < k; ++i) {
+    const double x = std::log(n[i]) - mx;
+    sxy += x * (std::log(d[i]) - my);
+    sxx += x * x;
+  }
+  if (!(sxx > 0.0)) return fail(MCLBM_ERR_ARG, "the resolutions must not all be equal");
+  *slope = sxy / sxx;
+  return MCLBM_OK;
+}
+
 // ------------------------------------------------------------------ launch shape
 mclbm_status mclbm_set_launch(mclbm_ctx* c, int32_t block_threads, int32_t xcd_remap, int32_t buffer_addressing,
                               int32_t nontemporal) {

@@ -105,5 +105,7 @@ hipError_t launch_observables(int q, int precision, const void* pop, const DevSa
 hipError_t launch_point_values(int lattice, int precision, const void* pop, const DevSample* samples,
                                const Seg* segs, int32_t nseg, int q, int physical, double* out, hipStream_t s);
 hipError_t launch_w1(const double* a, const double* b, int m, int q, double* col, double* out, hipStream_t s);
+hipError_t launch_sample_error(const double* a, const double* b, int m, int q, double* ratio, double* out,
+                               hipStream_t s);
 
 }  // namespace mclbm

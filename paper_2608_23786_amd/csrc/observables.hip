@@ -514,6 +514,49 @@ __global__ void __launch_bounds__(256) w1_reduce_kernel(const double* col, int q
   if (threadIdx.x == 0) out[blockIdx.x] = red[0] / q3;
 }
 
+// One block per sample: the eight sums of the relative L1 sample error
+// (numerator and denominator for the three components and for the Euclidean
+// length of the vector) over the q^3 nodes, then their four ratios.
+__global__ void __launch_bounds__(256) sample_error_kernel(const double* a, const double* b, int q3, double* ratio) {
+  const size_t base = size_t(blockIdx.x) * 3 * q3;
+  double acc[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int j = threadIdx.x; j < q3; j += 256) {
+    double d2 = 0.0, r2 = 0.0;
+    for (int c = 0; c < 3; ++c) {
+      const double x = a[base + size_t(c) * q3 + j], r = b[base + size_t(c) * q3 + j];
+      acc[2 * c] += fabs(x - r);
+      acc[2 * c + 1] += fabs(r);
+      d2 += (x - r) * (x - r);
+      r2 += r * r;
+    }
+    acc[6] += sqrt(d2);
+    acc[7] += sqrt(r2);
+  }
+  __shared__ double red[8][256];
+  for (int k = 0; k < 8; ++k) red[k][threadIdx.x] = acc[k];
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if (threadIdx.x < st)
+      for (int k = 0; k < 8; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x < 4) ratio[size_t(blockIdx.x) * 4 + threadIdx.x] = red[2 * threadIdx.x][0] / red[2 * threadIdx.x + 1][0];
+}
+
+// out[k] = mean over the m samples of ratio[m][k], one block per k.
+__global__ void __launch_bounds__(256) sample_mean_kernel(const double* ratio, int m, double* out) {
+  __shared__ double red[256];
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < m; i += 256) acc += ratio[size_t(i) * 4 + blockIdx.x];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if (threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[blockIdx.x] = red[0] / m;
+}
+
 // LINES for the transforms along y and z (LDS: LINES * N complex doubles);
 // it divides N, so it divides the N (N/2 + 1) lines of a field
 template <int N>
@@ -662,6 +705,15 @@ hipError_t launch_w1(const double* a, const double* b, int m, int q, double* col
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(w1_reduce_kernel, dim3(3), dim3(256), 0, s, col, q3, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_sample_error(const double* a, const double* b, int m, int q, double* ratio, double* out,
+                               hipStream_t s) {
+  hipLaunchKernelGGL(sample_error_kernel, dim3(unsigned(m)), dim3(256), 0, s, a, b, q * q * q, ratio);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(sample_mean_kernel, dim3(4), dim3(256), 0, s, ratio, m, out);
   return hipGetLastError();
 }
 

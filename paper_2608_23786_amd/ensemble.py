@@ -334,6 +334,35 @@ def w1_1pt(a: torch.Tensor, b: torch.Tensor, q: int = 8, stream: Optional[torch.
     return out
 
 
+def sample_error(a: torch.Tensor, b: torch.Tensor, q: int = 8, stream: Optional[torch.cuda.Stream] = None):
+    """Ensemble-mean relative L1 error of the samples of a against those of
+    the reference b (point values [m, 3, q^3] float64 each, sample m of both
+    from the same Y_m): components x, y, z and the velocity vector."""
+    _require_cuda(a, torch.float64, name="a")
+    _require_cuda(b, torch.float64, name="b")
+    if a.shape != b.shape or a.dim() != 3 or a.shape[1] != 3 or a.shape[2] != q ** 3:
+        raise ValueError("a and b must both have shape [m, 3, q^3]")
+    s = stream if stream is not None else torch.cuda.current_stream()
+    wb = int(lib().mclbm_sample_error_work_bytes(a.shape[0]))
+    work = torch.empty(wb, dtype=torch.uint8, device=a.device)
+    out = torch.empty(4, dtype=torch.float64, device=a.device)
+    check(lib().mclbm_sample_error(_ptr(a), _ptr(b), a.shape[0], q, _ptr(out), _ptr(work), wb,
+                                   ctypes.c_void_p(s.cuda_stream)))
+    return out
+
+
+def eoc_slope(ns, ds) -> float:
+    """Least-squares slope of log d over log n (host only)."""
+    if len(ns) != len(ds):
+        raise ValueError("ns and ds must have the same length")
+    n = (ctypes.c_double * len(ns))(*[float(v) for v in ns])
+    d = (ctypes.c_double * len(ds))(*[float(v) for v in ds])
+    out = ctypes.c_double()
+    check(lib().mclbm_eoc_slope(ctypes.cast(n, ctypes.c_void_p), ctypes.cast(d, ctypes.c_void_p), len(ns),
+                                ctypes.byref(out)))
+    return out.value
+
+
 def stream_copy(dst: torch.Tensor, src: torch.Tensor, stream: Optional[torch.cuda.Stream] = None):
     nbytes = min(dst.numel() * dst.element_size(), src.numel() * src.element_size()) // 16 * 16
     s = stream if stream is not None else torch.cuda.current_stream()

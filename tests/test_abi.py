@@ -100,6 +100,23 @@ def test_create_rejects_bad_arguments_before_touching_the_device():
     assert L.mclbm_ticks(None) == -1
 
 
+def test_eoc_slope_matches_oracle_and_validates():
+    """The host-only convergence-order fit against the oracle's least squares,
+    and its argument checks."""
+    import numpy as np
+    import oracle
+    import paper_2608_23786_amd as mc
+    rng = np.random.default_rng(5)
+    for k in (2, 3, 5):
+        ns = [32 * 2 ** i for i in range(k)]
+        ds = list(rng.uniform(0.01, 1.0, k))
+        assert abs(mc.eoc_slope(ns, ds) - oracle.eoc_slope(ns, ds)) < 1e-13
+    for ns, ds in (([128], [0.1]), ([128, 128], [0.1, 0.2]), ([128, 256], [0.1, 0.0]),
+                   ([128, 256], [0.1, float("nan")]), ([0, 256], [0.1, 0.2])):
+        with pytest.raises(mc.MclbmError, match="ERR_ARG"):
+            mc.eoc_slope(ns, ds)
+
+
 def test_inputs_generator_is_splitmix64():
     """Published SplitMix64 output for seed 0 (first draws of the reference
     implementation by Vigna: 0xe220a8397b1dcdaf, 0x6e789e6aa1b965f4)."""

@@ -1,6 +1,6 @@
 """GPU observables against the oracle: structure function and energy spectrum
-(FP64 FFT on the device), point values at the common nodes, and the 1-point
-Wasserstein distance.
+(FP64 FFT on the device), point values at the common nodes, the 1-point
+Wasserstein distance and the relative L1 sample error.
 
 The observables are compared on the same velocity field (the GPU's own FP64
 moments fed to the oracle) at 1e-12 relative, which isolates the transform
@@ -168,3 +168,54 @@ def test_observables_range_equals_single_samples():
         ens.observables_range(2, 2)      # 16^3 and 32^3
     with pytest.raises(mc.MclbmError, match="ERR_ARG"):
         ens.observables_range(4, 2)      # past the ensemble
+
+
+@pytest.mark.parametrize("m,q", [(1, 1), (7, 4), (300, 8), (1000, 2)])
+def test_sample_error_matches_oracle(m, q):
+    """eq. (sample_error) on random point values at different scales per
+    sample; one component of the reference set to zero in one sample gives
+    inf on both sides, and NaN where that sample's own values are zero too."""
+    rng = np.random.default_rng(100 + m)
+    b = rng.normal(size=(m, 3, q ** 3)) * rng.uniform(0.1, 10.0, (m, 1, 1))
+    a = b + 0.1 * rng.normal(size=b.shape)
+    got = mc.sample_error(torch.from_numpy(a).cuda(), torch.from_numpy(b).cuda(), q).cpu().numpy()
+    ref = oracle.sample_error_l1(a, b)
+    assert np.max(np.abs(got - ref)) <= 1e-14 * np.max(np.abs(ref))
+    if m >= 7:
+        b[3, 2] = 0.0
+        for special in (np.isposinf, np.isnan):
+            got = mc.sample_error(torch.from_numpy(a).cuda(), torch.from_numpy(b).cuda(), q).cpu().numpy()
+            ref = oracle.sample_error_l1(a, b)
+            assert special(got[2]) and special(ref[2])
+            assert np.max(np.abs(got[[0, 1, 3]] - ref[[0, 1, 3]])) <= 1e-14 * np.max(np.abs(ref[[0, 1, 3]]))
+            a[3, 2] = 0.0
+
+
+def test_sample_error_and_eoc_across_resolutions():
+    """The same Y at 16^3, 32^3 and 64^3 (strides 16:4:1, equal physical
+    time): the sample errors and W1 of the coarse ensembles against the 64^3
+    reference, from the library's point values, against the oracle on the
+    same values; the slopes against the oracle's fit; and the errors fall
+    as the resolution rises (a smooth early-time field)."""
+    per = 3
+    y = np.tile(mc_inputs.draw_y(34, per), (3, 1))
+    samples = []
+    for n, st in ((16, 16), (32, 4), (64, 1)):
+        samples += [mc.Sample(n, 0.05 * 16 / n, 25.0 * n, 0.3, True, st)] * per
+    ens = mc.Ensemble(samples, "f64")
+    ens.init(0, torch.from_numpy(y))
+    ens.step(64)
+    pv = ens.point_values(8, physical=True)
+    ref = pv[2 * per:].contiguous()
+    pvh = pv.cpu().numpy()
+    errs, w1s = [], []
+    for g in range(2):
+        cur = pv[g * per:(g + 1) * per].contiguous()
+        e = mc.sample_error(cur, ref, 8).cpu().numpy()
+        eo = oracle.sample_error_l1(pvh[g * per:(g + 1) * per], pvh[2 * per:])
+        assert np.max(np.abs(e - eo)) <= 1e-14 * np.max(np.abs(eo))
+        errs.append(e[3])
+        w1s.append(float(mc.w1_1pt(cur, ref, 8).sum()))
+    assert errs[1] < errs[0] and w1s[1] < w1s[0], (errs, w1s)
+    for d in (errs, w1s):
+        assert abs(mc.eoc_slope([16, 32], d) - oracle.eoc_slope([16, 32], d)) < 1e-13
