@@ -145,6 +145,27 @@ def fp64_single(mc, torch, n, u0, re, ticks=200):
     return lups / sec / 1e6
 
 
+def fp64_batched(mc, torch, ticks=100):
+    """The 64 x 64^3 RTGV ensemble of the default workload in FP64 populations
+    (same physics and seed): aggregate MLUPS and the kernel's algorithmic
+    bandwidth at 432 B per node update, for comparison with the FP32 path."""
+    import dataclasses
+    import mc_inputs
+    wl = dataclasses.replace(mc_inputs.WORKLOADS["rtgv64x64_f32"], precision="f64")
+    ens = build_ensemble(wl, mc, torch)
+    tuned = ens.autotune(reps=1)
+    ens.step(20)
+    sec, lups = timed_ticks(ens, torch, ticks, 0)
+    avg_ms, _, _, gbs = kernel_roofline(ens, wl, torch, 20)
+    out = {"samples": wl.m, "n": wl.groups[0].n, "ticks": ticks, "MLUPS": round(lups / sec / 1e6, 1),
+           "launch": dict(zip(("block", "xcd_remap", "buffer_addressing", "nontemporal"), tuned)),
+           "kernel_avg_ms": round(avg_ms, 5), "bytes_per_lup": BYTES_PER_LUP[wl.precision, wl.lattice],
+           "kernel_GBps_algorithmic": round(gbs, 1), "kernel_frac_of_peak": round(gbs / HBM_PEAK_GBS, 4)}
+    del ens
+    torch.cuda.empty_cache()
+    return out
+
+
 def bench_mixed(mc, torch, with_sf=True):
     """Uneven batch 32 x 64^3 + 12 x 128^3 + 4 x 256^3 (strides 16:4:1), 1000
     ticks, FP64 reductions fused every 16 ticks (all samples at equal physical
@@ -371,9 +392,19 @@ def cpu_baseline(seconds_target=15.0):
     t = time.perf_counter()
     oracle.run(f, g.n, steps, om, threads=threads)
     sec = time.perf_counter() - t
+    t = time.perf_counter()
+    oracle.run(f, g.n, 2, om, threads=1)
+    one = time.perf_counter() - t
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            model = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")), model)
+    except OSError:
+        pass
     return {"value": g.n ** 3 * steps / sec / 1e6, "unit": "MLUPS", "cores": threads, "kind": "oracle",
             "sample": f"1 RTGV sample at {g.n}^3 of the 64x64^3 workload, {steps} steps, FP64 moment-space "
-                      f"KBC collision, two-lattice pull streaming ({sec:.1f} s)"}
+                      f"KBC collision, two-lattice pull streaming ({sec:.1f} s)",
+            "single_core_MLUPS": round(g.n ** 3 * 2 / one / 1e6, 3), "cpu_model": model}
 
 
 def main():
@@ -427,10 +458,13 @@ def main():
     avg_ms, launches, bpl, achieved = kernel_roofline(ens, wl, torch, args.roofline_ticks)
     print(f"[bench] collide-stream: {launches} launches, {avg_ms:.4f} ms avg, {achieved:.0f} GB/s algorithmic",
           file=sys.stderr, flush=True)
-    f64 = None
+    f64 = f64_batch = None
     if not args.skip_fp64:
         f64 = {"32^3 TGV Re 100 MLUPS": round(fp64_single(mc, torch, 32, 0.05, 100.0), 1),
                "64^3 Re 1600 MLUPS": round(fp64_single(mc, torch, 64, 0.025, 1600.0), 1)}
+        if wl.name == "rtgv64x64_f32":
+            f64_batch = fp64_batched(mc, torch)
+            print(f"[bench] fp64 batched: {f64_batch}", file=sys.stderr, flush=True)
     extra = {}
     if not args.no_extra:
         del ens
@@ -471,6 +505,7 @@ def main():
                      "avg_launch_ms": round(avg_ms, 5), "launches_timed": launches,
                      "measured_copy_GBps": round(b_meas, 1), "frac_of_measured_copy": round(achieved / b_meas, 4)},
         "fp64_single_sample": f64,
+        **({"fp64_batched_64x64": f64_batch} if f64_batch else {}),
         **({"launch_sweep": sweep} if sweep else {}),
         **extra,
     }

@@ -346,7 +346,8 @@ mclbm_status mclbm_time_launches(mclbm_ctx* ctx, int32_t enable);
 mclbm_status mclbm_launch_time(mclbm_ctx* ctx, double* avg_ms, int64_t* launches);
 
 /* Device-to-device copy of `bytes` (a multiple of 16) with a plain vector
- * copy kernel on `hip_stream`: the measured HBM bandwidth reference. */
+ * copy kernel (one 16-byte non-temporal load and store per thread) on
+ * `hip_stream`: the measured HBM bandwidth reference. */
 mclbm_status mclbm_stream_copy(void* dst_dev, const void* src_dev, size_t bytes, void* hip_stream);
 
 /* Message of the last failing call on this thread ("" if none). */
