@@ -325,7 +325,9 @@ mclbm_status mclbm_get_launch(const mclbm_ctx* ctx, int32_t* block_threads, int3
 /* Time every launch shape on the current state (`reps` periods of
  * 2 * max stride ticks each, after one warm-up period), keep the fastest,
  * and restore the state from a checkpoint written to scratch_dev
- * (mclbm_checkpoint_bytes). best_* (may be NULL) receive the choice. */
+ * (mclbm_checkpoint_bytes). best_* (may be NULL) receive the choice. On an
+ * error the launch shape and the state are put back as they were and the
+ * error of the failing trial is returned. */
 mclbm_status mclbm_autotune(mclbm_ctx* ctx, int32_t reps, void* scratch_dev, size_t scratch_bytes,
                             int32_t* best_block, int32_t* best_xcd, int32_t* best_buffer, int32_t* best_nt);
 
@@ -341,7 +343,9 @@ int64_t mclbm_steps(const mclbm_ctx* ctx, int32_t sample);
 /* Average duration in milliseconds, measured with HIP events on the
  * context's stream, of the collide-and-stream launches enqueued since the
  * last call (timing must be switched on with mclbm_time_launches(ctx, 1);
- * it brackets every tick launch with events). *launches gets the count. */
+ * it brackets every tick launch with events and switches graphs off while
+ * on). *launches gets the count. The context keeps two events per timed
+ * launch until mclbm_launch_time reads them, and reuses them afterwards. */
 mclbm_status mclbm_time_launches(mclbm_ctx* ctx, int32_t enable);
 mclbm_status mclbm_launch_time(mclbm_ctx* ctx, double* avg_ms, int64_t* launches);
 

@@ -251,8 +251,24 @@ double lattice_nu(int32_t n, double u0, double re) { return u0 * (double(n) / (2
 double lattice_nu(const mclbm_sample_desc& d) { return lattice_nu(d.n, d.u0, d.re); }
 double omega_of(double nu) { return 1.0 / (3.0 * nu + 0.5); }  // Table 1: 2 c_s^2 / (2 nu + c_s^2), c_s^2 = 1/3
 
+// Recycle the table pool unless `count` more tables fit: tables fetched after
+// this call stay valid together (a full pool is cleared, after the stream has
+// drained, only inside get_table or here).
+mclbm_status reserve_tables(mclbm_ctx* c, int count) {
+  const size_t slot = align_up(sizeof(Seg) * c->m);
+  if (c->table_next + size_t(count) * slot > c->table_pool_bytes) {
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    drop_graphs(c);
+    c->tables.clear();
+    c->table_next = 0;
+  }
+  return MCLBM_OK;
+}
+
 // Launch table for the samples active at `tick` (stride divides tick), with
 // their AA parities; `all` forces every sample (init, reductions, adjoint).
+// The pointer stays valid until the pool is recycled: a caller that holds
+// several tables at once reserves room for them first (reserve_tables).
 mclbm_status get_table(mclbm_ctx* c, int64_t tick, bool all, int block, bool parity_zero, const Table** out) {
   std::string key = std::to_string(block) + (all ? "A" : "T") + (parity_zero ? "0" : "P") + ":";
   std::vector<Seg> segs;
@@ -274,14 +290,10 @@ mclbm_status get_table(mclbm_ctx* c, int64_t tick, bool all, int block, bool par
     *out = &it->second;
     return MCLBM_OK;
   }
+  // pool full: wait until no launch reads a table, then start over
+  mclbm_status st = reserve_tables(c, 1);
+  if (st != MCLBM_OK) return st;
   const size_t slot = align_up(sizeof(Seg) * c->m);
-  if (c->table_next + slot > c->table_pool_bytes) {
-    // pool full: wait until no launch reads a table, then start over
-    HIP_TRY(hipStreamSynchronize(c->stream));
-    drop_graphs(c);
-    c->tables.clear();
-    c->table_next = 0;
-  }
   Table t;
   t.offset = c->table_next;
   t.nseg = int(segs.size());
@@ -372,14 +384,9 @@ mclbm_status run_graph(mclbm_ctx* c) {
   if (it == c->graphs.end()) {
     // leave room for every table of the period so that none is evicted
     // between building the tables and capturing the launches that read them
-    const size_t slot = align_up(sizeof(Seg) * c->m);
-    if (c->table_next + size_t(kMaxTables / 4 + 8) * slot > c->table_pool_bytes) {
-      HIP_TRY(hipStreamSynchronize(c->stream));
-      drop_graphs(c);
-      c->tables.clear();
-      c->table_next = 0;
-      it = c->graphs.end();
-    }
+    mclbm_status rs = reserve_tables(c, kMaxTables / 4 + 8);
+    if (rs != MCLBM_OK) return rs;
+    it = c->graphs.end();
     // make sure every table of the period exists before capturing
     const int64_t tick0 = c->tick;
     std::vector<int64_t> steps0 = c->steps;
@@ -564,10 +571,9 @@ mclbm_status mclbm_init(mclbm_ctx* c, uint64_t seed, const double* y_host) {
   mclbm_status st = check_ctx(c, false);
   if (st != MCLBM_OK) return st;
   if (y_host) {
-    for (size_t k = 0; k < size_t(c->m) * 24; ++k) {
+    for (size_t k = 0; k < size_t(c->m) * 24; ++k)
       if (!std::isfinite(y_host[k])) return fail(MCLBM_ERR_ARG, "Y contains a non-finite value");
-      c->y[k] = y_host[k];
-    }
+    std::copy(y_host, y_host + size_t(c->m) * 24, c->y.begin());
   } else {
     uint64_t state = seed;
     for (size_t k = 0; k < size_t(c->m) * 24; ++k)
@@ -841,6 +847,8 @@ mclbm_status mclbm_backward(mclbm_ctx* c, int64_t ticks, int32_t ckpt_every, con
     HIP_TRY(launch_extract(records, c->m, 4, ke_dev, c->stream));
   }
 
+  st = reserve_tables(c, 3);       // the three tables below are held together
+  if (st != MCLBM_OK) return st;
   const Table* aux = nullptr;      // every sample, live parities (seed)
   st = get_table(c, c->tick, true, kAuxBlock, false, &aux);
   if (st != MCLBM_OK) return st;
@@ -1031,16 +1039,31 @@ mclbm_status mclbm_autotune(mclbm_ctx* c, int32_t reps, void* scratch_dev, size_
   if (c->exact_gamma) return fail(MCLBM_ERR_UNSUPPORTED, "the exact stabiliser has one launch shape");
   st = mclbm_checkpoint(c, scratch_dev, scratch_bytes);
   if (st != MCLBM_OK) return st;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    if (e0) (void)hipEventDestroy(e0);
+    return fail(MCLBM_ERR_HIP, "hipEventCreate failed");
+  }
   const bool timing0 = c->timing, graphs0 = c->use_graphs;
+  const int b0 = c->block, x0 = c->xcd_remap, f0 = c->buffer_addr, n0 = c->nontemporal;
   c->use_graphs = false;
   c->timing = false;
+  const int64_t per = 2 * int64_t(c->max_stride) * reps;
+  // one trial: warm-up, timed ticks, then the state as it was
+  auto trial = [&](float* ms) -> mclbm_status {
+    mclbm_status r = run_plain_ticks(c, 2 * int64_t(c->max_stride));
+    if (r != MCLBM_OK) return r;
+    HIP_TRY(hipEventRecord(e0, c->stream));
+    r = run_plain_ticks(c, per);
+    if (r != MCLBM_OK) return r;
+    HIP_TRY(hipEventRecord(e1, c->stream));
+    HIP_TRY(hipEventSynchronize(e1));
+    HIP_TRY(hipEventElapsedTime(ms, e0, e1));
+    return mclbm_restore(c, scratch_dev, scratch_bytes);
+  };
   const int blocks[4] = {128, 256, 512, 1024};
   float best = 1e30f;
-  int bb = c->block, bx = c->xcd_remap, bf = c->buffer_addr, bn = c->nontemporal;
-  hipEvent_t e0, e1;
-  HIP_TRY(hipEventCreate(&e0));
-  HIP_TRY(hipEventCreate(&e1));
-  const int64_t per = 2 * int64_t(c->max_stride) * reps;
+  int bb = b0, bx = x0, bf = f0, bn = n0;
   // buffer addressing needs every sample's populations below 2 GiB; without
   // it both settings run the same pointer kernels, so only one is timed
   bool buffer_possible = true;
@@ -1050,31 +1073,22 @@ mclbm_status mclbm_autotune(mclbm_ctx* c, int32_t reps, void* scratch_dev, size_
     bool fits = !(b == 1024 && c->precision == MCLBM_FP64);
     for (int s = 0; s < c->m; ++s) fits = fits && c->cells(s) >= b;
     if (!fits) continue;
-    for (int v = 0; v < 8; ++v) {
+    for (int v = 0; v < 8 && st == MCLBM_OK; ++v) {
       const int x = v & 1, f = (v >> 1) & 1, nt = v >> 2;
       if (f && !buffer_possible) continue;
       c->block = b;
       c->xcd_remap = x;
       c->buffer_addr = f;
       c->nontemporal = nt;
-      st = run_plain_ticks(c, 2 * int64_t(c->max_stride));  // warm-up
-      if (st != MCLBM_OK) break;
-      HIP_TRY(hipEventRecord(e0, c->stream));
-      st = run_plain_ticks(c, per);
-      if (st != MCLBM_OK) break;
-      HIP_TRY(hipEventRecord(e1, c->stream));
-      HIP_TRY(hipEventSynchronize(e1));
       float ms = 0.f;
-      HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
-      if (ms < best) {
+      st = trial(&ms);
+      if (st == MCLBM_OK && ms < best) {
         best = ms;
         bb = b;
         bx = x;
         bf = f;
         bn = nt;
       }
-      mclbm_status rs = mclbm_restore(c, scratch_dev, scratch_bytes);
-      if (rs != MCLBM_OK) return rs;
     }
     if (st != MCLBM_OK) break;
   }
@@ -1083,7 +1097,15 @@ mclbm_status mclbm_autotune(mclbm_ctx* c, int32_t reps, void* scratch_dev, size_
   c->use_graphs = graphs0;
   c->timing = timing0;
   if (st != MCLBM_OK) {
+    // keep the error of the failed trial; put back the shape and the state
+    const std::string err = g_last_error;
+    c->block = b0;
+    c->xcd_remap = x0;
+    c->buffer_addr = f0;
+    c->nontemporal = n0;
+    drop_graphs(c);
     (void)mclbm_restore(c, scratch_dev, scratch_bytes);
+    g_last_error = err;
     return st;
   }
   c->block = bb;
@@ -1095,7 +1117,7 @@ mclbm_status mclbm_autotune(mclbm_ctx* c, int32_t reps, void* scratch_dev, size_
   if (best_xcd) *best_xcd = bx;
   if (best_buffer) *best_buffer = bf;
   if (best_nt) *best_nt = bn;
-  return mclbm_restore(c, scratch_dev, scratch_bytes);
+  return MCLBM_OK;  // every trial ended by restoring the state
 }
 
 mclbm_status mclbm_dissipation(mclbm_ctx* c, const double* records_dev, int32_t nrec, int64_t first_tick,

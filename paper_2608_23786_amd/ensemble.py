@@ -92,13 +92,25 @@ class Ensemble:
     def synchronize(self):
         self.stream.synchronize()
 
-    def _consume(self):
-        """The library's stream waits for work the caller queued on its current stream."""
+    def _consume(self, *inputs):
+        """The library's stream waits for work the caller queued on its current
+        stream; caller tensors it reads or writes are marked as used on the
+        library's stream, so that the caching allocator does not hand their
+        memory out again before the library's work on them is done."""
         self.stream.wait_stream(torch.cuda.current_stream(self.device))
+        for t in inputs:
+            if t is not None:
+                t.record_stream(self.stream)
 
-    def _produce(self):
-        """The caller's current stream waits for the library's outputs."""
-        torch.cuda.current_stream(self.device).wait_stream(self.stream)
+    def _produce(self, *outputs):
+        """The caller's current stream waits for the library's outputs, which
+        are allocated on the library's stream and marked as used on the
+        caller's stream too (freeing them there is then safe)."""
+        cur = torch.cuda.current_stream(self.device)
+        cur.wait_stream(self.stream)
+        for t in outputs:
+            if t is not None:
+                t.record_stream(cur)
 
     # ------------------------------------------------------------ lifecycle
     def init(self, seed: int = 0, y: Optional[torch.Tensor] = None):
@@ -124,7 +136,7 @@ class Ensemble:
             nrec = (ticks + record_every - 1) // record_every
             rec = self._dev_empty((max(nrec, 1), self.m, 8))
             check(lib().mclbm_step(self._ctx, ticks, record_every, _ptr(rec), nrec))
-            self._produce()
+            self._produce(rec)
             return rec[:nrec]
         check(lib().mclbm_step(self._ctx, ticks, 0, None, 0))
         return None
@@ -148,13 +160,13 @@ class Ensemble:
         rho = self._dev_empty((n, n, n))
         u = self._dev_empty((3, n, n, n))
         check(lib().mclbm_moments(self._ctx, sample, _ptr(rho), _ptr(u)))
-        self._produce()
+        self._produce(rho, u)
         return rho, u
 
     def reduce(self) -> torch.Tensor:
         red = self._dev_empty((self.m, 8))
         check(lib().mclbm_reduce(self._ctx, _ptr(red)))
-        self._produce()
+        self._produce(red)
         return red
 
     def check(self) -> int:
@@ -169,16 +181,15 @@ class Ensemble:
         n = self.samples[sample].n
         f = self._dev_empty((self.q, n, n, n))
         check(lib().mclbm_get_state(self._ctx, sample, _ptr(f)))
-        self._produce()
+        self._produce(f)
         return f
 
     def set_state(self, sample: int, f: torch.Tensor):
         self._check_sample(sample)
         n = self.samples[sample].n
         _require_cuda(f, torch.float64, self.q * n ** 3, "f")
-        self._consume()
+        self._consume(f)
         check(lib().mclbm_set_state(self._ctx, sample, _ptr(f)))
-        f.record_stream(self.stream)
 
     def observables(self, sample: int, work: Optional[torch.Tensor] = None, structure: bool = True,
                     spectrum: bool = True):
@@ -191,9 +202,9 @@ class Ensemble:
             work = self._dev_empty((wb,), torch.uint8)
         s2 = self._dev_empty((n // 2,)) if structure else None
         ek = self._dev_empty((n // 2 + 1,)) if spectrum else None
-        self._consume()
+        self._consume(work)
         check(lib().mclbm_observables(self._ctx, sample, _ptr(s2), _ptr(ek), _ptr(work), work.numel()))
-        self._produce()
+        self._produce(s2, ek)
         return s2, ek
 
     def observables_range(self, first: int, count: int, work: Optional[torch.Tensor] = None, structure: bool = True,
@@ -207,9 +218,9 @@ class Ensemble:
             work = self._dev_empty((wb,), torch.uint8)
         s2 = self._dev_empty((count, n // 2)) if structure else None
         ek = self._dev_empty((count, n // 2 + 1)) if spectrum else None
-        self._consume()
+        self._consume(work)
         check(lib().mclbm_observables_range(self._ctx, first, count, _ptr(s2), _ptr(ek), _ptr(work), work.numel()))
-        self._produce()
+        self._produce(s2, ek)
         return s2, ek
 
     def point_values(self, q: int = 8, physical: bool = False) -> torch.Tensor:
@@ -217,16 +228,16 @@ class Ensemble:
         in lattice units or, with physical, as u / u0."""
         out = self._dev_empty((self.m, 3, q ** 3))
         check(lib().mclbm_point_values(self._ctx, q, int(physical), _ptr(out)))
-        self._produce()
+        self._produce(out)
         return out
 
     def get_cells(self, sample: int, cells) -> torch.Tensor:
         """Populations f[k][q] (float64, device) of the given cell indices of one sample."""
         idx = torch.as_tensor(cells, dtype=torch.int64).to(self.device).contiguous()
         out = self._dev_empty((idx.numel(), self.q))
-        self._consume()
+        self._consume(idx)
         check(lib().mclbm_get_cells(self._ctx, sample, _ptr(idx), idx.numel(), _ptr(out)))
-        self._produce()
+        self._produce(out)
         return out
 
     def poison(self, sample: int, cell: int, i: int):
@@ -240,13 +251,13 @@ class Ensemble:
         nb = self.checkpoint_bytes()
         if buf is None:
             buf = self._dev_empty((nb,), torch.uint8)
-        self._consume()
+        self._consume(buf)
         check(lib().mclbm_checkpoint(self._ctx, _ptr(buf), buf.numel()))
-        self._produce()
+        self._produce(buf)
         return buf
 
     def restore(self, buf: torch.Tensor):
-        self._consume()
+        self._consume(buf)
         check(lib().mclbm_restore(self._ctx, _ptr(buf), buf.numel()))
 
     # ------------------------------------------------------------ launch shape
@@ -272,10 +283,10 @@ class Ensemble:
         nrec = records.numel() // (self.m * 8)
         diss = self._dev_empty((nrec, self.m))
         et = self._dev_empty((nrec,)) if eta else None
-        self._consume()
+        self._consume(records)
         check(lib().mclbm_dissipation(self._ctx, _ptr(records), nrec, first_tick, record_every, _ptr(diss),
                                       _ptr(et) if et is not None else None))
-        self._produce()
+        self._produce(diss, et)
         return diss, et
 
     def set_stabiliser(self, mode: str):
@@ -305,6 +316,7 @@ class Ensemble:
             raise MclbmError(_lib.ERR_ARG, "invalid ticks / ckpt_every")
         ck = self._dev_empty((nb,), torch.uint8)
         check(lib().mclbm_forward_ckpt(self._ctx, ticks, ckpt_every, _ptr(ck), nb))
+        self._produce(ck)
         return ck
 
     def backward(self, ticks: int, ckpt_every: int, ckpt: torch.Tensor):
@@ -312,10 +324,24 @@ class Ensemble:
         work = self._dev_empty((wb,), torch.uint8)
         dj = self._dev_empty((self.m, 24))
         ke = self._dev_empty((self.m,))
+        self._consume(ckpt)
         check(lib().mclbm_backward(self._ctx, ticks, ckpt_every, _ptr(ckpt), ckpt.numel(), _ptr(work), wb,
                                    _ptr(dj), _ptr(ke)))
-        self._produce()
+        self._produce(dj, ke)
         return dj, ke
+
+
+def _on_stream(stream: Optional[torch.cuda.Stream], *tensors) -> torch.cuda.Stream:
+    """The stream a module-level call runs on (default: the current one). A
+    different stream first waits for the current one, and the caller's
+    tensors are marked as used on it."""
+    cur = torch.cuda.current_stream()
+    if stream is None or stream == cur:
+        return cur
+    stream.wait_stream(cur)
+    for t in tensors:
+        t.record_stream(stream)
+    return stream
 
 
 def w1_1pt(a: torch.Tensor, b: torch.Tensor, q: int = 8, stream: Optional[torch.cuda.Stream] = None):
@@ -325,10 +351,11 @@ def w1_1pt(a: torch.Tensor, b: torch.Tensor, q: int = 8, stream: Optional[torch.
     _require_cuda(b, torch.float64, name="b")
     if a.shape != b.shape or a.dim() != 3 or a.shape[1] != 3 or a.shape[2] != q ** 3:
         raise ValueError("a and b must both have shape [m, 3, q^3]")
-    s = stream if stream is not None else torch.cuda.current_stream()
+    s = _on_stream(stream, a, b)
     wb = int(lib().mclbm_w1_work_bytes(q))
-    work = torch.empty(wb, dtype=torch.uint8, device=a.device)
-    out = torch.empty(3, dtype=torch.float64, device=a.device)
+    with torch.cuda.stream(s):
+        work = torch.empty(wb, dtype=torch.uint8, device=a.device)
+        out = torch.empty(3, dtype=torch.float64, device=a.device)
     check(lib().mclbm_w1_1pt(_ptr(a), _ptr(b), a.shape[0], q, _ptr(out), _ptr(work), wb,
                              ctypes.c_void_p(s.cuda_stream)))
     return out
@@ -342,10 +369,11 @@ def sample_error(a: torch.Tensor, b: torch.Tensor, q: int = 8, stream: Optional[
     _require_cuda(b, torch.float64, name="b")
     if a.shape != b.shape or a.dim() != 3 or a.shape[1] != 3 or a.shape[2] != q ** 3:
         raise ValueError("a and b must both have shape [m, 3, q^3]")
-    s = stream if stream is not None else torch.cuda.current_stream()
+    s = _on_stream(stream, a, b)
     wb = int(lib().mclbm_sample_error_work_bytes(a.shape[0]))
-    work = torch.empty(wb, dtype=torch.uint8, device=a.device)
-    out = torch.empty(4, dtype=torch.float64, device=a.device)
+    with torch.cuda.stream(s):
+        work = torch.empty(wb, dtype=torch.uint8, device=a.device)
+        out = torch.empty(4, dtype=torch.float64, device=a.device)
     check(lib().mclbm_sample_error(_ptr(a), _ptr(b), a.shape[0], q, _ptr(out), _ptr(work), wb,
                                    ctypes.c_void_p(s.cuda_stream)))
     return out
@@ -365,7 +393,7 @@ def eoc_slope(ns, ds) -> float:
 
 def stream_copy(dst: torch.Tensor, src: torch.Tensor, stream: Optional[torch.cuda.Stream] = None):
     nbytes = min(dst.numel() * dst.element_size(), src.numel() * src.element_size()) // 16 * 16
-    s = stream if stream is not None else torch.cuda.current_stream()
+    s = _on_stream(stream, dst, src)
     check(lib().mclbm_stream_copy(_ptr(dst), _ptr(src), nbytes, ctypes.c_void_p(s.cuda_stream)))
 
 
