@@ -24,7 +24,10 @@ Contents and the passage each part follows:
     (SF_single_spec2); 1-point Wasserstein distance between equal-size
     empirical laws by sorted rearrangement, eq. (wassersteinPermutations);
     the ensemble-mean relative L1 sample error, eq. (sample_error), and the
-    least-squares convergence order of Algorithm (ComputeSlopes).
+    least-squares convergence order of Algorithm (ComputeSlopes); empirical
+    ensemble mean and standard deviation, eqs. (spectrum_mean) and
+    (spectrum_var); sample-wise compensated spectrum and structure function,
+    eqs. (compensatedE) and (compensatedSF).
 
 Lattices: D3Q27 (q = 27, the default) and the paper's D3Q19 (q = 19).
 
@@ -389,3 +392,49 @@ def eoc_slope(ns, ds):
     (log N, log D_N) of the distances D_N to the reference resolution."""
     return float(np.polyfit(np.log(np.asarray(ns, dtype=np.float64)),
                             np.log(np.asarray(ds, dtype=np.float64)), 1)[0])
+
+
+def ensemble_mean_std(x):
+    """eqs. (spectrum_mean), (spectrum_var): per column of x[M][K], the
+    empirical mean (1/M) sum_m x_m and the empirical standard deviation
+    sqrt(1/(M-1) sum_m (x_m - mean)^2) (M >= 2)."""
+    x = np.asarray(x, dtype=np.float64)
+    m, k = x.shape
+    assert m >= 2
+    mean = np.zeros(k)
+    std = np.zeros(k)
+    for c in range(k):
+        mean[c] = sum(x[i, c] for i in range(m)) / m
+        std[c] = math.sqrt(sum((x[i, c] - mean[c]) ** 2 for i in range(m)) / (m - 1))
+    return mean, std
+
+
+KOLMOGOROV_CONSTANT = 1.5   # C_Kol of eq. (compensatedE)
+
+
+def compensated_spectrum(ek, d, u0):
+    """eq. (compensatedE), sample by sample: E^c_m(kappa) = kappa^(5/3)
+    E_m(kappa) / (C_Kol d_m^(2/3)), with E_m in units of u0^2 (the library's
+    spectra are in lattice units) and d_m the sample's dissipation rate in
+    the same physical units; d^(2/3) taken as the cube root of d^2.
+    ek[M][N/2+1] for kappa = 0..N/2, d[M], u0[M]."""
+    ek = np.asarray(ek, dtype=np.float64)
+    out = np.zeros_like(ek)
+    for m in range(ek.shape[0]):
+        d23 = np.cbrt(d[m] * d[m])
+        for kap in range(ek.shape[1]):
+            out[m, kap] = kap ** (5.0 / 3.0) * (ek[m, kap] / u0[m] ** 2) / (KOLMOGOROV_CONSTANT * d23)
+    return out
+
+
+def compensated_structure_function(s2, d, u0, n):
+    """eq. (compensatedSF), sample by sample: S^{2,c}_m(r) = S2_m(r) /
+    (d_m r)^(2/3) with S2_m in units of u0^2 and r the physical lag
+    r_lattice * 2 pi / n, r_lattice = 1..N/2. s2[M][N/2], d[M], u0[M]."""
+    s2 = np.asarray(s2, dtype=np.float64)
+    out = np.zeros_like(s2)
+    for m in range(s2.shape[0]):
+        for j in range(s2.shape[1]):
+            r = (j + 1) * 2.0 * math.pi / n
+            out[m, j] = (s2[m, j] / u0[m] ** 2) / np.cbrt((d[m] * r) ** 2)
+    return out

@@ -588,6 +588,44 @@ def test_eoc_slope_power_laws():
         assert abs(oracle.eoc_slope([64, 128, 256], [0.1, mid, 0.02]) - math.log(0.2) / math.log(4)) < 1e-14
 
 
+def test_ensemble_mean_std_closed_forms():
+    """eqs. (spectrum_mean), (spectrum_var): two samples give the midpoint and
+    |a - b| / sqrt(2) (the 1/(M-1) normalisation); a constant column has
+    zero spread; an affine map scales the spread by |alpha|; the Python
+    standard library's sample statistics agree."""
+    import statistics
+    mean, std = oracle.ensemble_mean_std([[1.0, -2.0, 5.0], [3.0, 4.0, 5.0]])
+    assert np.allclose(mean, [2.0, 1.0, 5.0], rtol=0, atol=1e-15)
+    assert np.allclose(std, [2 / math.sqrt(2), 6 / math.sqrt(2), 0.0], rtol=1e-15, atol=0)
+    rng = np.random.default_rng(22)
+    x = rng.normal(size=(9, 4))
+    mean, std = oracle.ensemble_mean_std(x)
+    m2, s2 = oracle.ensemble_mean_std(-3.0 * x + 7.0)
+    assert np.allclose(m2, -3.0 * mean + 7.0, rtol=1e-14) and np.allclose(s2, 3.0 * std, rtol=1e-13)
+    for c in range(4):
+        assert abs(mean[c] - statistics.fmean(x[:, c])) < 1e-15
+        assert abs(std[c] - statistics.stdev(x[:, c])) < 1e-14
+
+
+def test_compensation_of_k41_ranges_is_flat():
+    """eqs. (compensatedE), (compensatedSF): a K41 spectrum C_Kol d^(2/3)
+    kappa^(-5/3) (in units of u0^2) compensates to exactly 1, and a K41
+    structure function C (d r)^(2/3) over physical lags r to the constant C,
+    sample by sample with each sample's own d and u0."""
+    n = 32
+    d = np.array([0.3, 2.0e-3])
+    u0 = np.array([0.05, 0.0125])
+    kap = np.arange(n // 2 + 1, dtype=np.float64)
+    ek = np.zeros((2, n // 2 + 1))
+    ek[:, 1:] = (oracle.KOLMOGOROV_CONSTANT * np.cbrt(d ** 2)[:, None] * kap[1:] ** (-5.0 / 3.0)) * u0[:, None] ** 2
+    ec = oracle.compensated_spectrum(ek, d, u0)
+    assert np.max(np.abs(ec[:, 1:] - 1.0)) < 1e-14 and np.all(ec[:, 0] == 0.0)
+    r = np.arange(1, n // 2 + 1) * 2 * math.pi / n
+    s2 = 7.7 * np.cbrt((d[:, None] * r[None, :]) ** 2) * u0[:, None] ** 2
+    sc = oracle.compensated_structure_function(s2, d, u0, n)
+    assert np.max(np.abs(sc - 7.7)) < 1e-13
+
+
 def test_taylor_green_field():
     """eq. (tgv_init_velo): divergence-free, and its values at sample nodes."""
     n = 8
