@@ -170,8 +170,9 @@ def bench_mixed(mc, torch, with_sf=True):
     """Uneven batch 32 x 64^3 + 12 x 128^3 + 4 x 256^3 (strides 16:4:1), 1000
     ticks, FP64 reductions fused every 16 ticks (all samples at equal physical
     time) and, when with_sf, the FP64 structure function of every sample per
-    saved tick (one batch of launches per resolution). Returns a dict of
-    throughput figures."""
+    saved tick (one batch of launches per resolution) with the ensemble mean
+    and standard deviation of KE and S2 per resolution. Returns a dict of
+    throughput figures and the last save's statistics."""
     import mc_inputs
     wl = mc_inputs.WORKLOADS["mixed48_f32"]
     ens = build_ensemble(wl, mc, torch)
@@ -191,18 +192,33 @@ def bench_mixed(mc, torch, with_sf=True):
     sf_sec = 0.0
     e0.record(ens.stream)
     saves = 0
+    stats = []
     for k in range(0, ticks, every):
-        ens.step(min(every, ticks - k), record_every=every)
+        rec = ens.step(min(every, ticks - k), record_every=every)
         saves += 1
         if with_sf:
+            # per resolution group: the structure functions, then the ensemble
+            # mean and standard deviation of KE and of S2
+            stats = []
             for a, c in groups:
-                ens.observables_range(a, c, work, structure=True, spectrum=False)
+                s2, _ = ens.observables_range(a, c, work, structure=True, spectrum=False)
+                stats.append((mc.ensemble_moments(rec[0, a:a + c, 4:5], stream=ens.stream),
+                               mc.ensemble_moments(s2, stream=ens.stream)))
     e1.record(ens.stream)
     ens.synchronize()
     sec = e0.elapsed_time(e1) / 1e3
+    if stats:
+        last = {}
+        for g, ((ke_m, ke_s), (s2_m, s2_s)) in zip(wl.groups, stats):
+            u2 = g.u0 ** 2
+            last[f"{g.count}x{g.n}^3"] = {"E_KE": round(float(ke_m[0]) / u2, 8), "sigma_KE": round(float(ke_s[0]) / u2, 8),
+                                          "E_S2_r1": round(float(s2_m[0]) / u2, 8),
+                                          "sigma_S2_r1": round(float(s2_s[0]) / u2, 8)}
     out = {"workload": wl.name, "ticks": ticks, "saves": saves, "lattice_updates": lups,
            "seconds": round(sec, 4), "MLUPS_including_observables": round(lups / sec / 1e6, 1),
            "launch": dict(zip(("block", "xcd_remap", "buffer_addressing", "nontemporal"), tuned))}
+    if stats:
+        out["last_save_statistics_u_over_U0"] = last
     # the same ticks without the structure functions (first realign to a tick
     # where every sample steps)
     ens.step((-ens.ticks) % every)

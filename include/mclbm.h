@@ -235,6 +235,21 @@ size_t mclbm_observables_range_work_bytes(const mclbm_ctx* ctx, int32_t first, i
 mclbm_status mclbm_observables_range(mclbm_ctx* ctx, int32_t first, int32_t count, double* s2_dev, double* ek_dev,
                                      void* work_dev, size_t work_bytes);
 
+/* Sample-wise compensation (eqs. (compensatedE), (compensatedSF)) of the
+ * observables of samples first..first+count-1, which share one n:
+ * ekc_dev[s][kappa] = kappa^(5/3) (E_s(kappa) / u0_s^2) / (C_Kol d_s^(2/3)),
+ * C_Kol = 1.5, and s2c_dev[s][r-1] = (S2_s(r) / u0_s^2) / (d_s r 2 pi / n)^(2/3)
+ * for the lag r = 1..n/2 (physical lag r 2 pi / n), with d^(2/3) taken as
+ * the cube root of d^2 and d_s the sample's dissipation rate at the time of
+ * the observables (diss_dev[count], device: a row of mclbm_dissipation's
+ * output from sample `first` on). s2_dev, s2c_dev: [count][n/2]; ek_dev,
+ * ekc_dev: [count][n/2 + 1] (device, double, as written by
+ * mclbm_observables_range); either pair may be NULL, not half of one. The
+ * inner-scaled abscissae are kappa eta and r 2 pi / (n eta) with eta from
+ * mclbm_dissipation. Runs on the context's stream. */
+mclbm_status mclbm_compensate(mclbm_ctx* ctx, int32_t first, int32_t count, const double* diss_dev,
+                              const double* s2_dev, const double* ek_dev, double* s2c_dev, double* ekc_dev);
+
 /* Velocity of every sample at the q^3 nodes common to all resolutions
  * (node j = (jx, jy, jz) at lattice index (n/q) j, i.e. x = 2 pi j / q):
  * out_dev[m][3][q^3], double, component-major per sample (appendix on the
@@ -254,6 +269,16 @@ mclbm_status mclbm_point_values(mclbm_ctx* ctx, int32_t q, int32_t physical, dou
 size_t mclbm_w1_work_bytes(int32_t q);
 mclbm_status mclbm_w1_1pt(const double* a_dev, const double* b_dev, int32_t m, int32_t q, double* out_dev,
                           void* work_dev, size_t work_bytes, void* hip_stream);
+
+/* Empirical ensemble statistics (eqs. (spectrum_mean), (spectrum_var)): for
+ * each column c < k of x_dev[m][ld] (device, double, rows of ld >= k values),
+ * mean_dev[c] = (1/m) sum_i x[i][c] and std_dev[c] = sqrt(1/(m-1) sum_i
+ * (x[i][c] - mean_dev[c])^2), in two fixed-order FP64 passes on hip_stream.
+ * std_dev may be NULL (then m >= 1; with it m >= 2, else MCLBM_ERR_ARG).
+ * Rows of samples: the spectra or structure functions of a resolution group
+ * (ld = n/2 + 1 or n/2), or KE of one record (x_dev = records + 4, ld = 8). */
+mclbm_status mclbm_ensemble_moments(const double* x_dev, int32_t m, int32_t k, int64_t ld, double* mean_dev,
+                                    double* std_dev, void* hip_stream);
 
 /* Ensemble-mean relative L1 distance between the samples of two ensembles at
  * the common nodes (eq. (sample_error)): out_dev[k] = (1/m) sum_m

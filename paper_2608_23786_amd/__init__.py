@@ -4,5 +4,5 @@ The compute path is the HIP library ``libmclbm.so`` behind the C ABI in
 ``include/mclbm.h``; this package only marshals arguments to it.
 """
 from ._lib import MclbmError, SampleDesc, lib  # noqa: F401
-from .ensemble import (RECORD_FIELDS, Ensemble, EnsembleKE, Sample, eoc_slope, omega, sample_error,  # noqa: F401
-                       stream_copy, w1_1pt)
+from .ensemble import (RECORD_FIELDS, Ensemble, EnsembleKE, Sample, ensemble_moments, eoc_slope,  # noqa: F401
+                       omega, sample_error, stream_copy, w1_1pt)

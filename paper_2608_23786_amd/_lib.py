@@ -71,6 +71,8 @@ SIGNATURES = {
     "mclbm_point_values": (_i32, [_ctxp, _i32, _i32, _vp]),
     "mclbm_w1_work_bytes": (_sz, [_i32]),
     "mclbm_w1_1pt": (_i32, [_vp, _vp, _i32, _i32, _vp, _vp, _sz, _vp]),
+    "mclbm_ensemble_moments": (_i32, [_vp, _i32, _i32, _i64, _vp, _vp, _vp]),
+    "mclbm_compensate": (_i32, [_vp, _i32, _i32, _vp, _vp, _vp, _vp, _vp]),
     "mclbm_sample_error_work_bytes": (_sz, [_i32]),
     "mclbm_sample_error": (_i32, [_vp, _vp, _i32, _i32, _vp, _vp, _sz, _vp]),
     "mclbm_eoc_slope": (_i32, [_vp, _vp, _i32, _vp]),

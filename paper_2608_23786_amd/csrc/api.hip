@@ -932,6 +932,22 @@ mclbm_status mclbm_observables(mclbm_ctx* c, int32_t sample, double* s2_dev, dou
   return mclbm_observables_range(c, sample, 1, s2_dev, ek_dev, work_dev, work_bytes);
 }
 
+mclbm_status mclbm_compensate(mclbm_ctx* c, int32_t first, int32_t count, const double* diss_dev,
+                              const double* s2_dev, const double* ek_dev, double* s2c_dev, double* ekc_dev) {
+  mclbm_status st = check_ctx(c, false);
+  if (st != MCLBM_OK) return st;
+  if (first < 0 || count < 1 || first + count > c->m) return fail(MCLBM_ERR_ARG, "sample range out of bounds");
+  const int n = c->desc[first].n;
+  for (int s = first + 1; s < first + count; ++s)
+    if (c->desc[s].n != n) return fail(MCLBM_ERR_ARG, "the samples of a range must share one n");
+  if (!diss_dev) return fail(MCLBM_ERR_ARG, "diss_dev is NULL");
+  if (!s2_dev != !s2c_dev || !ek_dev != !ekc_dev)
+    return fail(MCLBM_ERR_ARG, "an input and its compensated output must both be given or both be NULL");
+  if (!s2_dev && !ek_dev) return MCLBM_OK;
+  HIP_TRY(launch_compensate(c->d_samples, first, count, n, diss_dev, s2_dev, ek_dev, s2c_dev, ekc_dev, c->stream));
+  return MCLBM_OK;
+}
+
 mclbm_status mclbm_point_values(mclbm_ctx* c, int32_t q, int32_t physical, double* out_dev) {
   mclbm_status st = check_ctx(c, true);
   if (st != MCLBM_OK) return st;
@@ -957,6 +973,15 @@ mclbm_status mclbm_w1_1pt(const double* a_dev, const double* b_dev, int32_t m, i
   if (q < 1 || q > 64) return fail(MCLBM_ERR_ARG, "q must be in [1, 64]");
   if (work_bytes < mclbm_w1_work_bytes(q)) return fail(MCLBM_ERR_OOM, "w1 work buffer too small");
   HIP_TRY(launch_w1(a_dev, b_dev, m, q, static_cast<double*>(work_dev), out_dev, static_cast<hipStream_t>(hip_stream)));
+  return MCLBM_OK;
+}
+
+mclbm_status mclbm_ensemble_moments(const double* x_dev, int32_t m, int32_t k, int64_t ld, double* mean_dev,
+                                    double* std_dev, void* hip_stream) {
+  if (!x_dev || !mean_dev) return fail(MCLBM_ERR_ARG, "NULL buffer");
+  if (k < 1 || ld < k) return fail(MCLBM_ERR_ARG, "need k >= 1 and ld >= k");
+  if (m < (std_dev ? 2 : 1)) return fail(MCLBM_ERR_ARG, "the standard deviation needs m >= 2 (the mean m >= 1)");
+  HIP_TRY(launch_ensemble_moments(x_dev, m, k, ld, mean_dev, std_dev, static_cast<hipStream_t>(hip_stream)));
   return MCLBM_OK;
 }
 

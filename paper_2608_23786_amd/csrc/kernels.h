@@ -105,6 +105,10 @@ hipError_t launch_observables(int q, int precision, const void* pop, const DevSa
 hipError_t launch_point_values(int lattice, int precision, const void* pop, const DevSample* samples,
                                const Seg* segs, int32_t nseg, int q, int physical, double* out, hipStream_t s);
 hipError_t launch_w1(const double* a, const double* b, int m, int q, double* col, double* out, hipStream_t s);
+hipError_t launch_ensemble_moments(const double* x, int m, int k, int64_t ld, double* mean, double* sd,
+                                   hipStream_t s);
+hipError_t launch_compensate(const DevSample* samples, int sample0, int count, int n, const double* d,
+                             const double* s2, const double* ek, double* s2c, double* ekc, hipStream_t s);
 hipError_t launch_sample_error(const double* a, const double* b, int m, int q, double* ratio, double* out,
                                hipStream_t s);
 

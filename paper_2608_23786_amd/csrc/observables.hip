@@ -557,6 +557,66 @@ __global__ void __launch_bounds__(256) sample_mean_kernel(const double* ratio, i
   if (threadIdx.x == 0) out[blockIdx.x] = red[0] / m;
 }
 
+// Column statistics of x[m][ld] over its m rows, one block per column: the
+// mean by a fixed-order sum, then the spread about it (second pass) with the
+// 1/(m - 1) normalisation of the empirical variance.
+__global__ void __launch_bounds__(256) ensemble_moments_kernel(const double* x, int m, int64_t ld, double* mean,
+                                                               double* sd) {
+  __shared__ double red[256];
+  const int c = blockIdx.x;
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < m; i += 256) acc += x[size_t(i) * ld + c];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if (threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+    __syncthreads();
+  }
+  const double mu = red[0] / m;
+  if (threadIdx.x == 0) mean[c] = mu;
+  if (!sd) return;
+  __syncthreads();  // every thread has read red[0]
+  acc = 0.0;
+  for (int i = threadIdx.x; i < m; i += 256) {
+    const double v = x[size_t(i) * ld + c] - mu;
+    acc += v * v;
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if (threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) sd[c] = sqrt(red[0] / (m - 1));
+}
+
+// Sample-wise compensation of the spectra and structure functions of the
+// samples sample0.. (one n): element j of a row of width n + 1 is kappa = j
+// of the spectrum for j <= n/2, else lag r = j - n/2 of the structure
+// function. Velocities in units of the sample's u0; lags in physical units.
+__global__ void __launch_bounds__(256) compensate_kernel(const DevSample* samples, int sample0, int count, int n,
+                                                         const double* d, const double* s2, const double* ek,
+                                                         double* s2c, double* ekc) {
+  constexpr double kKolmogorov = 1.5;
+  const int half = n / 2, width = n + 1;
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  if (e >= count * width) return;
+  const int s = e / width, j = e % width;
+  const double u0 = samples[sample0 + s].u0;
+  const double ds = d[s];
+  if (j <= half) {
+    if (ek) {
+      const size_t o = size_t(s) * (half + 1) + j;
+      ekc[o] = pow(double(j), 5.0 / 3.0) * (ek[o] / (u0 * u0)) / (kKolmogorov * cbrt(ds * ds));
+    }
+  } else if (s2) {
+    const int r = j - half;
+    const size_t o = size_t(s) * half + (r - 1);
+    const double dr = ds * (r * 2.0 * M_PI / n);
+    s2c[o] = (s2[o] / (u0 * u0)) / cbrt(dr * dr);
+  }
+}
+
 // LINES for the transforms along y and z (LDS: LINES * N complex doubles);
 // it divides N, so it divides the N (N/2 + 1) lines of a field
 template <int N>
@@ -714,6 +774,20 @@ hipError_t launch_sample_error(const double* a, const double* b, int m, int q, d
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(sample_mean_kernel, dim3(4), dim3(256), 0, s, ratio, m, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_ensemble_moments(const double* x, int m, int k, int64_t ld, double* mean, double* sd,
+                                   hipStream_t s) {
+  hipLaunchKernelGGL(ensemble_moments_kernel, dim3(unsigned(k)), dim3(256), 0, s, x, m, ld, mean, sd);
+  return hipGetLastError();
+}
+
+hipError_t launch_compensate(const DevSample* samples, int sample0, int count, int n, const double* d,
+                             const double* s2, const double* ek, double* s2c, double* ekc, hipStream_t s) {
+  const int total = count * (n + 1);
+  hipLaunchKernelGGL(compensate_kernel, dim3(unsigned((total + 255) / 256)), dim3(256), 0, s, samples, sample0, count,
+                     n, d, s2, ek, s2c, ekc);
   return hipGetLastError();
 }
 

@@ -289,6 +289,25 @@ class Ensemble:
         self._produce(diss, et)
         return diss, et
 
+    def compensate(self, first: int, diss: torch.Tensor, s2: Optional[torch.Tensor] = None,
+                   ek: Optional[torch.Tensor] = None):
+        """Sample-wise compensated structure functions [count, n/2] and spectra
+        [count, n/2+1] of samples first.. (one n; count = len(diss)) from their
+        dissipation rates diss[count] at the same time; velocities in units of
+        u0. Returns (s2c, ekc), None where the input is None."""
+        _require_cuda(diss, torch.float64, name="diss")
+        count = diss.numel()
+        n = self.samples[first].n if 0 <= first < self.m else 0
+        for t, w, name in ((s2, n // 2, "s2"), (ek, n // 2 + 1, "ek")):
+            if t is not None:
+                _require_cuda(t, torch.float64, count * w, name)
+        s2c = self._dev_empty((count, n // 2)) if s2 is not None else None
+        ekc = self._dev_empty((count, n // 2 + 1)) if ek is not None else None
+        self._consume(diss, s2, ek)
+        check(lib().mclbm_compensate(self._ctx, first, count, _ptr(diss), _ptr(s2), _ptr(ek), _ptr(s2c), _ptr(ekc)))
+        self._produce(s2c, ekc)
+        return s2c, ekc
+
     def set_stabiliser(self, mode: str):
         """'closed_form' (eq. (entropyControl), default) or 'exact' (minimiser of
         the discrete H-function, eq. (kbc_entropy))."""
@@ -359,6 +378,22 @@ def w1_1pt(a: torch.Tensor, b: torch.Tensor, q: int = 8, stream: Optional[torch.
     check(lib().mclbm_w1_1pt(_ptr(a), _ptr(b), a.shape[0], q, _ptr(out), _ptr(work), wb,
                              ctypes.c_void_p(s.cuda_stream)))
     return out
+
+
+def ensemble_moments(x: torch.Tensor, std: bool = True, stream: Optional[torch.cuda.Stream] = None):
+    """Empirical mean and standard deviation (1/(m-1)) over the rows of
+    x [m, k] (float64 on the device, unit stride along k; rows may be strided,
+    e.g. records[t, :, 4:5]). Returns (mean[k], std[k] or None)."""
+    if not x.is_cuda or x.dtype != torch.float64 or x.dim() != 2 or (x.shape[1] > 1 and x.stride(1) != 1):
+        raise ValueError("x must be a 2-D float64 device tensor with unit stride along its second axis")
+    m, k = x.shape
+    ld = x.stride(0) if m > 1 else k
+    s = _on_stream(stream, x)
+    with torch.cuda.stream(s):
+        mean = torch.empty(k, dtype=torch.float64, device=x.device)
+        sd = torch.empty(k, dtype=torch.float64, device=x.device) if std else None
+    check(lib().mclbm_ensemble_moments(_ptr(x), m, k, ld, _ptr(mean), _ptr(sd), ctypes.c_void_p(s.cuda_stream)))
+    return mean, sd
 
 
 def sample_error(a: torch.Tensor, b: torch.Tensor, q: int = 8, stream: Optional[torch.cuda.Stream] = None):

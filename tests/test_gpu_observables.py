@@ -219,3 +219,60 @@ def test_sample_error_and_eoc_across_resolutions():
     assert errs[1] < errs[0] and w1s[1] < w1s[0], (errs, w1s)
     for d in (errs, w1s):
         assert abs(mc.eoc_slope([16, 32], d) - oracle.eoc_slope([16, 32], d)) < 1e-13
+
+
+@pytest.mark.parametrize("m,k", [(2, 1), (7, 65), (1000, 3)])
+def test_ensemble_moments_match_oracle(m, k):
+    """eqs. (spectrum_mean), (spectrum_var) on random rows with a large common
+    offset (the two-pass spread keeps its digits)."""
+    rng = np.random.default_rng(200 + m)
+    x = 1e3 + rng.normal(size=(m, k))
+    mean, sd = mc.ensemble_moments(torch.from_numpy(x).cuda())
+    mo, so = oracle.ensemble_mean_std(x)
+    # FP64 sums of m values near 1e3 in two orders: a few units of 1e-16 relative
+    assert np.max(np.abs(mean.cpu().numpy() - mo)) <= 1e-14 * np.max(np.abs(mo))
+    assert np.max(np.abs(sd.cpu().numpy() - so)) <= 1e-11 * np.max(so)
+
+
+def test_ensemble_moments_of_records_and_argument_checks():
+    """E[KE] and sigma[KE] read straight out of the records (a strided column),
+    and the checks: one sample has a mean but no spread."""
+    y = mc_inputs.draw_y(35, 5)
+    ens = mc.Ensemble([mc.Sample(16, 0.05, 200.0, 0.3, True)] * 5, "f64")
+    ens.init(0, torch.from_numpy(y))
+    rec = ens.step(8, record_every=4)
+    mean, sd = mc.ensemble_moments(rec[1, :, 4:5])
+    ke = rec[1, :, 4].cpu().numpy()[:, None]
+    mo, so = oracle.ensemble_mean_std(ke)
+    assert abs(float(mean[0]) - mo[0]) <= 1e-14 * mo[0] and abs(float(sd[0]) - so[0]) <= 1e-12 * so[0]
+    one = torch.ones(1, 3, dtype=torch.float64, device="cuda")
+    m1, s1 = mc.ensemble_moments(one, std=False)
+    assert s1 is None and torch.equal(m1, torch.ones(3, dtype=torch.float64, device="cuda"))
+    with pytest.raises(mc.MclbmError, match="ERR_ARG"):
+        mc.ensemble_moments(one)
+
+
+@pytest.mark.parametrize("lattice", [27, 19])
+def test_compensated_observables_match_oracle(lattice):
+    """eqs. (compensatedE), (compensatedSF) on the library's own spectra,
+    structure functions and dissipation rates of a short run (3 samples,
+    32^3), against the oracle's sample-wise compensation of the same values."""
+    n, u0, every = 32, 0.05, 4
+    y = mc_inputs.draw_y(36, 3)
+    ens = mc.Ensemble([mc.Sample(n, u0, 400.0, 0.3, True)] * 3, "f64", lattice=lattice)
+    ens.init(0, torch.from_numpy(y))
+    rec = ens.step(24, record_every=every)
+    diss, _ = ens.dissipation(rec, 0, every)
+    s2, ek = ens.observables_range(0, 3)
+    d = diss[-1].contiguous()
+    s2c, ekc = ens.compensate(0, d, s2, ek)
+    dh = d.cpu().numpy()
+    assert np.all(dh > 0)
+    eo = oracle.compensated_spectrum(ek.cpu().numpy(), dh, [u0] * 3)
+    so = oracle.compensated_structure_function(s2.cpu().numpy(), dh, [u0] * 3, n)
+    assert np.max(np.abs(ekc.cpu().numpy() - eo)) <= 1e-14 * np.max(np.abs(eo))
+    assert np.max(np.abs(s2c.cpu().numpy() - so)) <= 1e-14 * np.max(np.abs(so))
+    only, none = ens.compensate(0, d, s2=s2)
+    assert none is None and torch.equal(only, s2c)
+    with pytest.raises(mc.MclbmError, match="ERR_ARG"):
+        ens.compensate(2, d, s2=s2)       # past the ensemble
