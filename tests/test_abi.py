@@ -44,6 +44,20 @@ def test_omega_reproduces_paper_tables_with_unit_spacing_convention():
         assert round(tau, 6) == r["tau"], r
 
 
+def test_omega_reproduces_paper_tables_with_the_other_spacing_convention():
+    """Rows of Tables 2 and 3 printed with dx = 2 pi / (N - 1) have the lattice
+    viscosity U0 (N - 1) / (2 pi Re); the library reaches it through
+    Re' = Re N / (N - 1), to every printed digit of tau."""
+    import paper_2608_23786_amd as mc
+    tab = json.load(open(os.path.join(ROOT, "tests", "golden", "paper_parameter_tables.json")))
+    rows = [r for r in tab["rows"] if r["dx"] == "2pi/(N-1)"]
+    assert len(rows) == 6
+    for r in rows:
+        u0 = r["Ma"] / math.sqrt(3.0)
+        tau = 1.0 / mc.omega(r["N"], u0, r["Re"] * r["N"] / (r["N"] - 1))
+        assert round(tau, 6) == r["tau"], r
+
+
 def test_omega_of_documented_configs():
     import paper_2608_23786_amd as mc
     # 32^3, U0 = 0.05, Re = 100: nu = 0.05 * 32 / (2 pi 100)
