@@ -218,7 +218,7 @@ mclbm_status mclbm_backward(mclbm_ctx* ctx, int64_t ticks, int32_t ckpt_every, c
  *     (energySpecDisc) with the coefficients of eq. (dftCoeff); modes whose
  *     length rounds above n/2 are not counted.
  * Either output may be NULL. work_dev: device scratch of
- * mclbm_observables_work_bytes(ctx, sample) bytes (about 36 n^3 bytes),
+ * mclbm_observables_work_bytes(ctx, sample) bytes (about 25 n^3 bytes),
  * 256-byte aligned, owned by the caller. Supported n: 8..512. Lattice
  * units (divide by u0^2 for physical units). */
 size_t mclbm_observables_work_bytes(const mclbm_ctx* ctx, int32_t sample);

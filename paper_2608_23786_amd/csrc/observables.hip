@@ -15,25 +15,45 @@
 // pipeline is five passes over HBM:
 //   1. x: velocities from the populations (either AA parity) and the
 //      forward transform along x of the three components, per row in LDS;
-//   2. y, 3. z: forward transforms along y and z of the three fields;
-//   4. per z-line: Psi, its shell sums for the spectrum, its total (R_0),
-//      and the inverse transform along z of Psi, written over field 0;
-//   5. inverse along y; 6. per x-row: the inverse along x (conjugate-
+//   2. y: forward transforms along y of the three fields;
+//   3. per z-line: the forward transforms along z of the three fields,
+//      Psi, its shell sums for the spectrum, its total (R_0), and the
+//      inverse transform along z of Psi, written over field 0;
+//   4. inverse along y; 5. per x-row: the inverse along x (conjugate-
 //      symmetric fill, real result R_h) and its shell sums for S2.
-// Radix-2 decimation-in-time transforms of whole lines in LDS, twiddles by
-// sincospi. Shells hold the integer vectors (minimum image, components in
+// Radix-2/4 decimation-in-time transforms of whole lines in LDS (padded
+// against bank conflicts), twiddles by sincospi; each launch hands every XCD
+// a contiguous run of blocks, so that blocks sharing cache lines share an
+// L2. Shells hold the integer vectors (minimum image, components in
 // {-N/2+1, ..., N/2}) whose length rounds to the shell index. Every shell sum
-// is taken per line in a fixed order (the line folded by the magnitude of
-// its own coordinate, the lengths of a shell forming an interval of it), and
-// then over lines in a fixed order: results do not depend on scheduling.
-// A half-spectrum mode 0 < kx < N/2 stands for itself and its conjugate
-// partner at -k, which has the same length: weight 2.
+// is taken per line (the line folded by the magnitude of its own
+// coordinate, the lengths of a shell forming an interval of it), then over
+// the lines of a block, then over blocks, each in a fixed order: results do
+// not depend on scheduling. The number of vectors in a shell depends on N
+// only and is counted exactly in the last stage. A half-spectrum mode
+// 0 < kx < N/2 stands for itself and its conjugate partner at -k, which has
+// the same length: weight 2.
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
 
 #include "lbm_device.h"
 
 namespace mclbm {
 namespace {
+
+// Lines per block of the transforms along y and z (LDS: about LINES * N
+// complex doubles); it divides n, so it divides the n (n/2 + 1) lines of a
+// field.
+constexpr int half_lines(int n) { return n >= 512 ? 4 : (n >= 256 ? 8 : (n >= 16 ? 16 : 8)); }
+
+// x-rows per block of the inverse transform along x (at most 1024 values)
+constexpr int inv_rows(int n) { return (n * n < 1024 / n) ? n * n : 1024 / n; }
+
+// rows of the spectrum's and the structure function's shell tables: one
+// per block of the pass that writes them
+constexpr size_t spectrum_bin_rows(int n) { return size_t(n) * (n / 2 + 1) / half_lines(n); }
+constexpr size_t sf_bin_rows(int n) { return size_t(n) * n / inv_rows(n); }
 
 __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
   return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
@@ -51,17 +71,30 @@ __device__ __forceinline__ int bitrev(int i) {
   return int(__brev(unsigned(i)) >> (32 - log2_of<N>()));
 }
 
-// e^{sign 2 pi i k / N}, k < N/2
+// LDS slot of element p of a line (or of the twiddle table): one spare slot
+// after every 16 complex values (256 bytes), so that the bit-reversed and
+// strided accesses of a wave spread over the LDS banks instead of landing
+// on a few of them.
+__device__ __forceinline__ int lds_pos(int p) { return p + (p >> 4); }
+
+// LDS slots of a line of N complex values
+template <int N>
+constexpr int lds_line() {
+  return N + N / 16;
+}
+
+// e^{sign 2 pi i k / N}, k < N/2, at tw[lds_pos(k)]
 template <int N>
 __device__ __forceinline__ void make_twiddles(double2* tw, int sign) {
   for (int k = threadIdx.x; k < N / 2; k += blockDim.x) {
     double s, c;
     sincospi(2.0 * k / N, &s, &c);
-    tw[k] = make_double2(c, sign * s);
+    tw[lds_pos(k)] = make_double2(c, sign * s);
   }
 }
 
-// In-place butterflies of nl lines of length N (line l at sh + l N) loaded in
+// In-place butterflies of nl lines of length N (element p of line l at
+// sh[l lds_line<N>() + lds_pos(p)]) loaded in
 // bit-reversed order (decimation in time); every thread of the block takes
 // part and the caller synchronises after loading. Two consecutive radix-2
 // stages (spans h and 2h) run as one radix-4 step in registers: a thread
@@ -76,10 +109,11 @@ __device__ __forceinline__ void butterflies(double2* sh, int nl, const double2* 
   if (LOG & 1) {
     for (int b = threadIdx.x; b < nl * (N / 2); b += blockDim.x) {
       const int l = b / (N / 2), j = b % (N / 2);
-      double2* ln = sh + l * N + 2 * j;
-      const double2 a = ln[0], c = ln[1];
-      ln[0] = make_double2(a.x + c.x, a.y + c.y);
-      ln[1] = make_double2(a.x - c.x, a.y - c.y);
+      double2* ln = sh + l * lds_line<N>();
+      const int p0 = lds_pos(2 * j), p1 = lds_pos(2 * j + 1);
+      const double2 a = ln[p0], c = ln[p1];
+      ln[p0] = make_double2(a.x + c.x, a.y + c.y);
+      ln[p1] = make_double2(a.x - c.x, a.y - c.y);
     }
     __syncthreads();
     half = 2;
@@ -89,19 +123,21 @@ __device__ __forceinline__ void butterflies(double2* sh, int nl, const double2* 
     for (int b = threadIdx.x; b < nl * (N / 4); b += blockDim.x) {
       const int l = b / (N / 4), j = b % (N / 4);
       const int pos = j % half, grp = j / half;
-      double2* ln = sh + l * N + grp * 4 * half + pos;
-      const double2 x0 = ln[0], x1 = ln[half], x2 = ln[2 * half], x3 = ln[3 * half];
-      // span h: (x0, x1) and (x2, x3), twiddle tw[pos * sa]
-      const double2 wa = tw[pos * sa];
+      double2* ln = sh + l * lds_line<N>();
+      const int i0 = grp * 4 * half + pos;
+      const int p0 = lds_pos(i0), p1 = lds_pos(i0 + half), p2 = lds_pos(i0 + 2 * half), p3 = lds_pos(i0 + 3 * half);
+      const double2 x0 = ln[p0], x1 = ln[p1], x2 = ln[p2], x3 = ln[p3];
+      // span h: (x0, x1) and (x2, x3), twiddle e^{pos sa}
+      const double2 wa = tw[lds_pos(pos * sa)];
       const double2 t1 = cmul(wa, x1), t3 = cmul(wa, x3);
       const double2 y0 = make_double2(x0.x + t1.x, x0.y + t1.y), y1 = make_double2(x0.x - t1.x, x0.y - t1.y);
       const double2 y2 = make_double2(x2.x + t3.x, x2.y + t3.y), y3 = make_double2(x2.x - t3.x, x2.y - t3.y);
-      // span 2h: (y0, y2) with tw[pos * sb], (y1, y3) with tw[(pos + h) * sb]
-      const double2 u2 = cmul(tw[pos * sb], y2), u3 = cmul(tw[(pos + half) * sb], y3);
-      ln[0] = make_double2(y0.x + u2.x, y0.y + u2.y);
-      ln[2 * half] = make_double2(y0.x - u2.x, y0.y - u2.y);
-      ln[half] = make_double2(y1.x + u3.x, y1.y + u3.y);
-      ln[3 * half] = make_double2(y1.x - u3.x, y1.y - u3.y);
+      // span 2h: (y0, y2) with e^{pos sb}, (y1, y3) with e^{(pos + h) sb}
+      const double2 u2 = cmul(tw[lds_pos(pos * sb)], y2), u3 = cmul(tw[lds_pos((pos + half) * sb)], y3);
+      ln[p0] = make_double2(y0.x + u2.x, y0.y + u2.y);
+      ln[p2] = make_double2(y0.x - u2.x, y0.y - u2.y);
+      ln[p1] = make_double2(y1.x + u3.x, y1.y + u3.y);
+      ln[p3] = make_double2(y1.x - u3.x, y1.y - u3.y);
     }
     __syncthreads();
   }
@@ -123,13 +159,12 @@ __device__ __forceinline__ int64_t isqrt_floor(int64_t v) {
   return r;
 }
 
-// Sum of v[m] over the m in [0, half] with round(sqrt(s + m^2)) == r, and the
-// number of lattice vectors they stand for (m and -m: 2, except m = 0 and
-// m = half): m^2 in [ceil(((2r-1)^2 - 4s)/4), floor(((2r+1)^2 - 1 - 4s)/4)].
-__device__ __forceinline__ void shell_interval(const double* v, int half, int64_t s, int r, double& sum,
-                                               double& cnt) {
-  sum = 0.0;
-  cnt = 0.0;
+// The m in [0, half] with round(sqrt(s + m^2)) == r form the interval
+// [a, b] (empty when a > b): m^2 in [ceil(((2r-1)^2 - 4s)/4),
+// floor(((2r+1)^2 - 1 - 4s)/4)].
+__device__ __forceinline__ void shell_range(int half, int64_t s, int r, int& a, int& b) {
+  a = 1;
+  b = 0;
   const int64_t lo2 = r == 0 ? 0 : int64_t(2 * r - 1) * (2 * r - 1);
   const int64_t top = int64_t(2 * r + 1) * (2 * r + 1) - 1 - 4 * s;
   if (top < 0) return;
@@ -137,14 +172,29 @@ __device__ __forceinline__ void shell_interval(const double* v, int half, int64_
   const int64_t bot = lo2 - 4 * s;
   const int64_t m2min = bot <= 0 ? 0 : (bot + 3) / 4;
   if (m2min > m2max) return;
-  int64_t a = isqrt_floor(m2min);
-  if (a * a < m2min) ++a;
-  int64_t b = isqrt_floor(m2max);
-  if (b > half) b = half;
-  for (int64_t m = a; m <= b; ++m) {
-    sum += v[m];
-    cnt += (m == 0 || m == half) ? 1.0 : 2.0;
-  }
+  int64_t lo = isqrt_floor(m2min);
+  if (lo * lo < m2min) ++lo;
+  int64_t hi = isqrt_floor(m2max);
+  if (hi > half) hi = half;
+  a = int(lo);
+  b = int(hi);
+}
+
+// Lattice vectors a folded index m stands for: m and -m, except m = 0 and
+// m = half (the Nyquist value is present once).
+__device__ __forceinline__ double fold_weight(int m, int half) { return (m == 0 || m == half) ? 1.0 : 2.0; }
+
+// v[a] + ... + v[b] (0 for an empty range)
+__device__ __forceinline__ double range_sum(const double* v, int a, int b) {
+  double sum = 0.0;
+  for (int m = a; m <= b; ++m) sum += v[m];
+  return sum;
+}
+
+// Lattice vectors standing behind the folded indices a..b
+__device__ __forceinline__ double range_count(int half, int a, int b) {
+  if (a > b) return 0.0;
+  return 2.0 * (b - a + 1) - (a == 0 ? 1.0 : 0.0) - (b == half ? 1.0 : 0.0);
 }
 
 // Pass 1: ROWS rows (z, y) per block. Velocities of the row's nodes from
@@ -156,11 +206,12 @@ __global__ void __launch_bounds__(256)
     fwd_x_kernel(const T* pop, const DevSample* samples, int sample0, int parity, double2* h0, size_t wstride) {
   constexpr int ROWS = N >= 512 ? 1 : 512 / N;
   constexpr int NH = N / 2 + 1;
-  __shared__ double2 sh[3 * ROWS * N];
-  __shared__ double2 tw[N / 2];
+  constexpr int LS = lds_line<N>();
+  __shared__ double2 sh[3 * ROWS * LS];
+  __shared__ double2 tw[lds_line<N / 2>()];
   const DevSample& sp = samples[sample0 + blockIdx.z];
   double2* h = in_batch(h0, wstride);
-  const size_t row0 = size_t(blockIdx.x) * ROWS;
+  const size_t row0 = size_t(remap_block(blockIdx.x, gridDim.x, 1)) * ROWS;
   make_twiddles<N>(tw, -1);
   const T* base = pop + sp.offset;
   for (int e = threadIdx.x; e < ROWS * N; e += 256) {
@@ -178,10 +229,10 @@ __global__ void __launch_bounds__(256)
       if constexpr (cz(i) != 0) jz += cz(i) * v;
     });
     const double rho = 1.0 + d;
-    const int rv = bitrev<N>(x);
-    sh[(0 * ROWS + r) * N + rv] = make_double2(jx / rho, 0.0);
-    sh[(1 * ROWS + r) * N + rv] = make_double2(jy / rho, 0.0);
-    sh[(2 * ROWS + r) * N + rv] = make_double2(jz / rho, 0.0);
+    const int rv = lds_pos(bitrev<N>(x));
+    sh[(0 * ROWS + r) * LS + rv] = make_double2(jx / rho, 0.0);
+    sh[(1 * ROWS + r) * LS + rv] = make_double2(jy / rho, 0.0);
+    sh[(2 * ROWS + r) * LS + rv] = make_double2(jz / rho, 0.0);
   }
   __syncthreads();
   butterflies<N>(sh, 3 * ROWS, tw);
@@ -189,62 +240,89 @@ __global__ void __launch_bounds__(256)
   for (int e = threadIdx.x; e < 3 * ROWS * NH; e += 256) {
     const int cl = e / NH, kx = e % NH;
     const int comp = cl / ROWS, r = cl % ROWS;
-    h[comp * field + (row0 + r) * NH + kx] = sh[cl * N + kx];
+    h[comp * field + (row0 + r) * NH + kx] = sh[cl * LS + lds_pos(kx)];
   }
 }
 
-// Passes 2, 3, 5: transform along y (axis 1) or z (axis 2) of the fields
-// h + c * N N NH, c = blockIdx.y; LINES lines (outer, kx) per block, outer =
-// z (axis 1) or y (axis 2), consecutive kx. sign -1 forward, +1 inverse.
+// Passes 2 and 4: transform along y of the fields h + c * N N NH,
+// c = blockIdx.y; LINES lines (z, kx) per block, consecutive kx. sign -1
+// forward, +1 inverse.
 template <int N, int LINES>
-__global__ void __launch_bounds__(256) fft_half_kernel(double2* h0, int axis, int sign, size_t wstride) {
-  constexpr int NH = N / 2 + 1;
-  __shared__ double2 sh[LINES * N];
-  __shared__ double2 tw[N / 2];
+__global__ void __launch_bounds__(256) fft_y_kernel(double2* h0, int sign, size_t wstride) {
+  constexpr int NH = N / 2 + 1, LS = lds_line<N>();
+  __shared__ double2 sh[LINES * LS];
+  __shared__ double2 tw[lds_line<N / 2>()];
   double2* d = in_batch(h0, wstride) + size_t(blockIdx.y) * N * N * NH;
   make_twiddles<N>(tw, sign);
-  const int line0 = blockIdx.x * LINES;
+  const int line0 = remap_block(blockIdx.x, gridDim.x, 1) * LINES;
   for (int e = threadIdx.x; e < LINES * N; e += 256) {
     const int i = e / LINES, l = e % LINES;
-    const int line = line0 + l, outer = line / NH, kx = line % NH;
-    const size_t off = axis == 1 ? (size_t(outer) * N + i) * NH + kx : (size_t(i) * N + outer) * NH + kx;
-    sh[l * N + bitrev<N>(i)] = d[off];
+    const int line = line0 + l, z = line / NH, kx = line % NH;
+    sh[l * LS + lds_pos(bitrev<N>(i))] = d[(size_t(z) * N + i) * NH + kx];
   }
   __syncthreads();
   butterflies<N>(sh, LINES, tw);
   for (int e = threadIdx.x; e < LINES * N; e += 256) {
     const int i = e / LINES, l = e % LINES;
-    const int line = line0 + l, outer = line / NH, kx = line % NH;
-    const size_t off = axis == 1 ? (size_t(outer) * N + i) * NH + kx : (size_t(i) * N + outer) * NH + kx;
-    d[off] = sh[l * N + i];
+    const int line = line0 + l, z = line / NH, kx = line % NH;
+    d[(size_t(z) * N + i) * NH + kx] = sh[l * LS + lds_pos(i)];
   }
 }
 
-// Pass 4: LINES z-lines (y, kx) per block. Psi at every kz; per line, the
-// shell sums of |k|^2/2 Psi (the line folded by |kz|) into
-// sbins[line][kappa] with the number of modes in scnt[line][kappa], and the
-// sum of Psi into sbins[line][N/2 + 1], all weighted by the kx weight (rows
-// of N/2 + 2 values). Then the inverse transform of Psi along z, written
-// over field 0.
+// Pass 3: LINES z-lines (y, kx) per block. The forward
+// transform along z of each of the three fields (already transformed along
+// x and y), one field at a time in LDS, with Psi, the sum of |.|^2 over the
+// fields at every kz, kept in registers (the element to thread map is the
+// same for every field); then the shell sums of |k|^2/2 Psi over the block's
+// lines (each line folded by |kz| and weighted by its kx weight, the lines
+// added in order) into sbins[block][kappa], the sum of Psi into
+// sbins[block][N/2 + 1] (rows of N/2 + 2 values), and the inverse transform
+// of Psi along z, written over field 0.
 template <int N, int LINES>
-__global__ void __launch_bounds__(256) psd_zinv_kernel(double2* h0, double* sbins0, double* scnt0, size_t wstride) {
-  constexpr int NH = N / 2 + 1, HALF = N / 2;
-  __shared__ double2 sh[LINES * N];
+__global__ void __launch_bounds__(256) z_psd_kernel(double2* h0, double* sbins0, size_t wstride) {
+  constexpr int NH = N / 2 + 1, HALF = N / 2, LS = lds_line<N>();
+  constexpr int PER = (LINES * N + 255) / 256;  // elements of a field per thread
+  __shared__ double2 sh[LINES * LS];
   __shared__ double fold[LINES * (HALF + 1)];
-  __shared__ double2 tw[N / 2];
+  __shared__ double tot[LINES];
+  __shared__ double2 tw[lds_line<N / 2>()];
   const size_t field = size_t(N) * N * NH;
   double2* h = in_batch(h0, wstride);
   double* sbins = in_batch(sbins0, wstride);
-  double* scnt = in_batch(scnt0, wstride);
+  make_twiddles<N>(tw, -1);
+  const int line0 = remap_block(blockIdx.x, gridDim.x, 1) * LINES;
+  double psd[PER];
+#pragma unroll
+  for (int j = 0; j < PER; ++j) psd[j] = 0.0;
+  for (int c = 0; c < 3; ++c) {
+    const double2* d = h + c * field;
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+      const int e = threadIdx.x + 256 * j;
+      if (e < LINES * N) {
+        const int i = e / LINES, l = e % LINES;
+        const int line = line0 + l, y = line / NH, kx = line % NH;
+        sh[l * LS + lds_pos(bitrev<N>(i))] = d[(size_t(i) * N + y) * NH + kx];
+      }
+    }
+    __syncthreads();
+    butterflies<N>(sh, LINES, tw);
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+      const int e = threadIdx.x + 256 * j;
+      if (e < LINES * N) {
+        const double2 v = sh[(e % LINES) * LS + lds_pos(e / LINES)];
+        psd[j] += v.x * v.x + v.y * v.y;
+      }
+    }
+    __syncthreads();  // the next field overwrites sh
+  }
+  // the twiddles of the inverse transform, and Psi in bit-reversed order
   make_twiddles<N>(tw, +1);
-  const int line0 = blockIdx.x * LINES;
-  for (int e = threadIdx.x; e < LINES * N; e += 256) {
-    const int i = e / LINES, l = e % LINES;
-    const int line = line0 + l, y = line / NH, kx = line % NH;
-    const size_t off = (size_t(i) * N + y) * NH + kx;
-    const double2 a = h[off], b = h[field + off], c = h[2 * field + off];
-    const double psd = a.x * a.x + a.y * a.y + b.x * b.x + b.y * b.y + c.x * c.x + c.y * c.y;
-    sh[l * N + bitrev<N>(i)] = make_double2(psd, 0.0);
+#pragma unroll
+  for (int j = 0; j < PER; ++j) {
+    const int e = threadIdx.x + 256 * j;
+    if (e < LINES * N) sh[(e % LINES) * LS + lds_pos(bitrev<N>(e / LINES))] = make_double2(psd[j], 0.0);
   }
   __syncthreads();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -252,61 +330,62 @@ __global__ void __launch_bounds__(256) psd_zinv_kernel(double2* h0, double* sbin
     const int line = line0 + l, y = line / NH, kx = line % NH;
     const int ky = y <= HALF ? y : y - N;
     const int64_t s = int64_t(kx) * kx + int64_t(ky) * ky;
-    const double2* ln = sh + l * N;
+    const double2* ln = sh + l * LS;
     double total = 0.0;
     for (int m = lane; m <= HALF; m += 64) {
-      double v = ln[bitrev<N>(m)].x;
-      if (m >= 1 && m <= HALF - 1) v += ln[bitrev<N>(N - m)].x;
+      double v = ln[lds_pos(bitrev<N>(m))].x;
+      if (m >= 1 && m <= HALF - 1) v += ln[lds_pos(bitrev<N>(N - m))].x;
       total += v;
       fold[l * (HALF + 1) + m] = 0.5 * (double(s) + double(m) * m) * v;
     }
     total = wave_sum(total);
-    if (lane == 0) {
-      const double wkx = (kx == 0 || kx == HALF) ? 1.0 : 2.0;
-      sbins[size_t(line) * (HALF + 2) + HALF + 1] = wkx * total;
-      scnt[size_t(line) * (HALF + 2) + HALF + 1] = 0.0;
-    }
+    if (lane == 0) tot[l] = fold_weight(kx, HALF) * total;
   }
   __syncthreads();
-  for (int l = wave; l < LINES; l += 4) {
-    const int line = line0 + l, y = line / NH, kx = line % NH;
-    const int ky = y <= HALF ? y : y - N;
-    const int64_t s = int64_t(kx) * kx + int64_t(ky) * ky;
-    const double wkx = (kx == 0 || kx == HALF) ? 1.0 : 2.0;
-    for (int r = lane; r <= HALF; r += 64) {
-      double sum, cnt;
-      shell_interval(fold + l * (HALF + 1), HALF, s, r, sum, cnt);
-      sbins[size_t(line) * (HALF + 2) + r] = wkx * sum;
-      scnt[size_t(line) * (HALF + 2) + r] = wkx * cnt;
+  const size_t blk = size_t(line0 / LINES);
+  for (int r = threadIdx.x; r <= HALF + 1; r += 256) {
+    double sum = 0.0;
+    for (int l = 0; l < LINES; ++l) {
+      if (r == HALF + 1) {
+        sum += tot[l];
+        continue;
+      }
+      const int line = line0 + l, y = line / NH, kx = line % NH;
+      const int ky = y <= HALF ? y : y - N;
+      int a, b;
+      shell_range(HALF, int64_t(kx) * kx + int64_t(ky) * ky, r, a, b);
+      sum += fold_weight(kx, HALF) * range_sum(fold + l * (HALF + 1), a, b);
     }
+    sbins[blk * (HALF + 2) + r] = sum;
   }
   butterflies<N>(sh, LINES, tw);
   for (int e = threadIdx.x; e < LINES * N; e += 256) {
     const int i = e / LINES, l = e % LINES;
     const int line = line0 + l, y = line / NH, kx = line % NH;
-    h[(size_t(i) * N + y) * NH + kx] = sh[l * N + i];
+    h[(size_t(i) * N + y) * NH + kx] = sh[l * LS + lds_pos(i)];
   }
 }
 
-// Pass 6: ROWS x-rows (z, y) per block of field 0 (Psi transformed back along
+// Pass 5: ROWS x-rows (z, y) per block of field 0 (Psi transformed back along
 // z and y): the conjugate-symmetric fill of kx = N/2+1..N-1, the inverse
-// transform along x (R_h times N^6, real), and per row the shell sums of
-// 2 (R_0 - R_h) folded by |hx| into rbins[row][r], with the number of lags in
-// rcnt[row][r] (rows of N/2 + 2 values). r0: R_0 times N^6 (the sum of Psi).
+// transform along x (R_h times N^6, real), and the shell sums of
+// 2 (R_0 - R_h) over the block's rows (each row folded by |hx|, the rows
+// added in order) into rbins[block][r] (rows of N/2 + 2 values, the last one
+// 0). r0: R_0 times N^6 (the sum of Psi).
 template <int N>
 __global__ void __launch_bounds__(256)
-    inv_x_rows_kernel(const double2* h0, const double* r00, double* rbins0, double* rcnt0, size_t wstride) {
+    inv_x_rows_kernel(const double2* h0, const double* r00, double* rbins0, size_t wstride) {
   constexpr int NH = N / 2 + 1, HALF = N / 2;
-  constexpr int ROWS = (N * N < 1024 / N) ? N * N : 1024 / N;
-  __shared__ double2 sh[ROWS * N];
+  constexpr int ROWS = inv_rows(N);
+  constexpr int LS = lds_line<N>();
+  __shared__ double2 sh[ROWS * LS];
   __shared__ double fold[ROWS * (HALF + 1)];
-  __shared__ double2 tw[N / 2];
+  __shared__ double2 tw[lds_line<N / 2>()];
   const double2* h = in_batch(h0, wstride);
   const double* r0 = in_batch(r00, wstride);
   double* rbins = in_batch(rbins0, wstride);
-  double* rcnt = in_batch(rcnt0, wstride);
   make_twiddles<N>(tw, +1);
-  const int row0 = blockIdx.x * ROWS;
+  const int row0 = remap_block(blockIdx.x, gridDim.x, 1) * ROWS;
   for (int e = threadIdx.x; e < ROWS * N; e += 256) {
     const int r = e / N, k = e % N;
     const size_t rowoff = size_t(row0 + r) * NH;
@@ -317,7 +396,7 @@ __global__ void __launch_bounds__(256)
       const double2 c = h[rowoff + (N - k)];
       v = make_double2(c.x, -c.y);
     }
-    sh[r * N + bitrev<N>(k)] = v;
+    sh[r * LS + lds_pos(bitrev<N>(k))] = v;
   }
   __syncthreads();
   butterflies<N>(sh, ROWS, tw);
@@ -325,68 +404,70 @@ __global__ void __launch_bounds__(256)
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   for (int r = wave; r < ROWS; r += 4) {
     for (int m = lane; m <= HALF; m += 64) {
-      double v = 2.0 * (R0 - sh[r * N + m].x);
-      if (m >= 1 && m <= HALF - 1) v += 2.0 * (R0 - sh[r * N + (N - m)].x);
+      double v = 2.0 * (R0 - sh[r * LS + lds_pos(m)].x);
+      if (m >= 1 && m <= HALF - 1) v += 2.0 * (R0 - sh[r * LS + lds_pos(N - m)].x);
       fold[r * (HALF + 1) + m] = v;
     }
   }
   __syncthreads();
-  for (int r = wave; r < ROWS; r += 4) {
-    const int row = row0 + r, iz = row / N, iy = row % N;
-    const int hz = iz <= HALF ? iz : iz - N, hy = iy <= HALF ? iy : iy - N;
-    const int64_t s = int64_t(hz) * hz + int64_t(hy) * hy;
-    for (int sh_r = lane; sh_r <= HALF; sh_r += 64) {
-      double sum, cnt;
-      shell_interval(fold + r * (HALF + 1), HALF, s, sh_r, sum, cnt);
-      rbins[size_t(row) * (HALF + 2) + sh_r] = sum;
-      rcnt[size_t(row) * (HALF + 2) + sh_r] = cnt;
+  const size_t blk = size_t(row0 / ROWS);
+  for (int c = threadIdx.x; c <= HALF + 1; c += 256) {
+    double sum = 0.0;
+    for (int r = 0; r < ROWS && c <= HALF; ++r) {
+      const int row = row0 + r, iz = row / N, iy = row % N;
+      const int hz = iz <= HALF ? iz : iz - N, hy = iy <= HALF ? iy : iy - N;
+      int a, b;
+      shell_range(HALF, int64_t(hz) * hz + int64_t(hy) * hy, c, a, b);
+      sum += range_sum(fold + r * (HALF + 1), a, b);
     }
+    rbins[blk * (HALF + 2) + c] = sum;
   }
 }
 
 // Shell reduction, stage 1: block b sums rows [b CHUNK, (b+1) CHUNK) of the
-// row-major tables bins / cnts (width values per row) column by column, in
-// row order, into psum[b][col] / pcnt[b][col].
+// row-major table bins (width values per row) column by column, in row
+// order, into psum[b][col].
 constexpr int kShellChunk = 32;
 
-__global__ void __launch_bounds__(256) shell_partial_kernel(const double* bins0, const double* cnts0, int rows,
-                                                            int width, double* psum0, double* pcnt0, size_t wstride) {
+__global__ void __launch_bounds__(256) shell_partial_kernel(const double* bins0, int rows, int width, double* psum0,
+                                                            size_t wstride) {
   const double* bins = in_batch(bins0, wstride);
-  const double* cnts = in_batch(cnts0, wstride);
   double* psum = in_batch(psum0, wstride);
-  double* pcnt = in_batch(pcnt0, wstride);
   const int r0 = blockIdx.x * kShellChunk;
   const int r1 = r0 + kShellChunk < rows ? r0 + kShellChunk : rows;
   for (int col = threadIdx.x; col < width; col += 256) {
-    double a = 0.0, c = 0.0;
+    double a = 0.0;
 #pragma unroll 8
-    for (int r = r0; r < r1; ++r) {
-      a += bins[size_t(r) * width + col];
-      c += cnts[size_t(r) * width + col];
-    }
+    for (int r = r0; r < r1; ++r) a += bins[size_t(r) * width + col];
     psum[size_t(blockIdx.x) * width + col] = a;
-    pcnt[size_t(blockIdx.x) * width + col] = c;
   }
 }
 
 // Stage 2, one block per column: the partials summed over the chunks (thread
-// t takes chunks t, t + 256, ..., then a fixed tree). mode 0 (spectrum):
-// out[kappa] = 4 pi / count * sum / N^6 for kappa = 0..N/2 (out may be NULL),
-// and column N/2 + 1 (the sum of Psi, R_0 times N^6) into *r0. mode 1
-// (structure function): out[r - 1] = sum / count / N^6 for r = 1..N/2.
-__global__ void __launch_bounds__(256) shell_final_kernel(const double* psum0, const double* pcnt0, int chunks,
-                                                          int width, int n, int mode, double* out0, double* r00,
-                                                          size_t wstride) {
+// t takes chunks t, t + 256, ..., then a fixed tree), and the number of
+// lattice vectors of the shell, which depends on n only: every vector with
+// components in {-N/2+1, ..., N/2} whose length rounds to the column. mode 0
+// (spectrum): out[kappa] = 4 pi / count * sum / N^6 for kappa = 0..N/2 (out
+// may be NULL), and column N/2 + 1 (the sum of Psi, R_0 times N^6) into *r0.
+// mode 1 (structure function): out[r - 1] = sum / count / N^6 for r = 1..N/2.
+__global__ void __launch_bounds__(256) shell_final_kernel(const double* psum0, int chunks, int width, int n, int mode,
+                                                          double* out0, double* r00, size_t wstride) {
   __shared__ double sa[256], sc[256];
   const double* psum = in_batch(psum0, wstride);
-  const double* pcnt = in_batch(pcnt0, wstride);
   double* out = out0 ? out0 + size_t(blockIdx.z) * (mode == 0 ? n / 2 + 1 : n / 2) : nullptr;
   double* r0 = r00 ? in_batch(r00, wstride) : nullptr;
-  const int col = blockIdx.x;
+  const int col = blockIdx.x, half = n / 2;
   double a = 0.0, c = 0.0;
-  for (int b = threadIdx.x; b < chunks; b += 256) {
-    a += psum[size_t(b) * width + col];
-    c += pcnt[size_t(b) * width + col];
+  for (int b = threadIdx.x; b < chunks; b += 256) a += psum[size_t(b) * width + col];
+  if (col <= half) {
+    // vectors (p, q, m) with |p|, |q|, |m| <= N/2 folded to p, q, m >= 0;
+    // the counts are whole numbers, exact in any order
+    for (int e = threadIdx.x; e < (half + 1) * (half + 1); e += 256) {
+      const int p = e / (half + 1), q = e % (half + 1);
+      int lo, hi;
+      shell_range(half, int64_t(p) * p + int64_t(q) * q, col, lo, hi);
+      c += fold_weight(p, half) * fold_weight(q, half) * range_count(half, lo, hi);
+    }
   }
   sa[threadIdx.x] = a;
   sc[threadIdx.x] = c;
@@ -400,7 +481,6 @@ __global__ void __launch_bounds__(256) shell_final_kernel(const double* psum0, c
   }
   if (threadIdx.x == 0) {
     const double norm = 1.0 / (double(n) * n * n) / (double(n) * n * n);
-    const int half = n / 2;
     const double sum = sa[0], cnt = sc[0];
     if (mode == 0) {
       if (col <= half && out) out[col] = cnt > 0 ? 4.0 * M_PI / cnt * sum * norm : 0.0;
@@ -617,21 +697,12 @@ __global__ void __launch_bounds__(256) compensate_kernel(const DevSample* sample
   }
 }
 
-// LINES for the transforms along y and z (LDS: LINES * N complex doubles);
-// it divides N, so it divides the N (N/2 + 1) lines of a field
-template <int N>
-constexpr int half_lines() {
-  return N >= 512 ? 4 : (N >= 256 ? 8 : (N >= 16 ? 16 : 8));
-}
 
 struct ObsWork {
   double2* h;       // 3 fields of N * N * NH complex
-  double* sbins;    // N NH rows of N/2 + 2
-  double* scnt;     // N NH rows of N/2 + 2
-  double* rbins;    // N N rows of N/2 + 2
-  double* rcnt;     // N N rows of N/2 + 2
-  double* psum;     // one row of N/2 + 2 per chunk of N N rows
-  double* pcnt;
+  double* sbins;    // spectrum_bin_rows(N) rows of N/2 + 2
+  double* rbins;    // sf_bin_rows(N) rows of N/2 + 2
+  double* psum;     // one row of N/2 + 2 per chunk of either table
   double* r0;       // 1
 };
 
@@ -639,66 +710,65 @@ size_t align256(size_t b) { return (b + 255) / 256 * 256; }
 
 size_t chunks_of(size_t rows) { return (rows + kShellChunk - 1) / kShellChunk; }
 
-// bytes of one sample's work area (a multiple of 256)
-size_t sample_work_bytes(int n) {
-  const size_t nh = size_t(n / 2 + 1), lines = size_t(n) * nh, rows = size_t(n) * n, width = size_t(n / 2 + 2);
-  return align256(3 * rows * nh * sizeof(double2)) + 2 * align256(lines * width * sizeof(double)) +
-         2 * align256(rows * width * sizeof(double)) + 2 * align256(chunks_of(rows) * width * sizeof(double)) +
-         align256(sizeof(double));
+// Byte sizes of the parts of one sample's work area (each a multiple of 256)
+struct WorkSizes {
+  size_t h, sbins, rbins, psum, r0;
+  size_t total() const { return h + sbins + rbins + psum + r0; }
+};
+
+WorkSizes work_sizes(int n) {
+  const size_t nh = size_t(n / 2 + 1), width = size_t(n / 2 + 2);
+  const size_t srows = spectrum_bin_rows(n), rrows = sf_bin_rows(n);
+  WorkSizes z;
+  z.h = align256(3 * size_t(n) * n * nh * sizeof(double2));
+  z.sbins = align256(srows * width * sizeof(double));
+  z.rbins = align256(rrows * width * sizeof(double));
+  z.psum = align256(chunks_of(std::max(srows, rrows)) * width * sizeof(double));
+  z.r0 = align256(sizeof(double));
+  return z;
 }
 
+// bytes of one sample's work area (a multiple of 256)
+size_t sample_work_bytes(int n) { return work_sizes(n).total(); }
+
 ObsWork carve(void* work, int n) {
-  const size_t nh = size_t(n / 2 + 1), lines = size_t(n) * nh, rows = size_t(n) * n, width = size_t(n / 2 + 2);
+  const WorkSizes z = work_sizes(n);
   char* p = static_cast<char*>(work);
   ObsWork w;
   w.h = reinterpret_cast<double2*>(p);
-  p += align256(3 * rows * nh * sizeof(double2));
-  w.sbins = reinterpret_cast<double*>(p);
-  p += align256(lines * width * sizeof(double));
-  w.scnt = reinterpret_cast<double*>(p);
-  p += align256(lines * width * sizeof(double));
-  w.rbins = reinterpret_cast<double*>(p);
-  p += align256(rows * width * sizeof(double));
-  w.rcnt = reinterpret_cast<double*>(p);
-  p += align256(rows * width * sizeof(double));
-  w.psum = reinterpret_cast<double*>(p);
-  p += align256(chunks_of(rows) * width * sizeof(double));
-  w.pcnt = reinterpret_cast<double*>(p);
-  p += align256(chunks_of(rows) * width * sizeof(double));
-  w.r0 = reinterpret_cast<double*>(p);
+  w.sbins = reinterpret_cast<double*>(p += z.h);
+  w.rbins = reinterpret_cast<double*>(p += z.sbins);
+  w.psum = reinterpret_cast<double*>(p += z.rbins);
+  w.r0 = reinterpret_cast<double*>(p += z.psum);
   return w;
 }
 
 template <int QN, typename T, int N>
 hipError_t observables_t(const T* pop, const DevSample* samples, int sample0, int count, int parity, void* work,
                          double* s2, double* ek, hipStream_t s) {
-  constexpr int NH = N / 2 + 1, L = half_lines<N>();
+  constexpr int NH = N / 2 + 1, L = half_lines(N);
   constexpr int ROWS_X = N >= 512 ? 1 : 512 / N;
-  constexpr int ROWS_R = (N * N < 1024 / N) ? N * N : 1024 / N;
+  constexpr int ROWS_R = inv_rows(N);
   constexpr int W = N / 2 + 2;
   static_assert(N % L == 0 && (N * N) % ROWS_X == 0 && (N * N) % ROWS_R == 0, "launch shapes must tile the field");
   const ObsWork w = carve(work, N);
   const size_t ws = sample_work_bytes(N);
   const unsigned z = unsigned(count);
   const int lines = N * NH, rows = N * N;
-  const int lchunks = int(chunks_of(lines)), rchunks = int(chunks_of(rows));
+  const int srows = int(spectrum_bin_rows(N)), rrows = int(sf_bin_rows(N));
+  const int lchunks = int(chunks_of(srows)), rchunks = int(chunks_of(rrows));
   hipLaunchKernelGGL((fwd_x_kernel<QN, T, N>), dim3(N * N / ROWS_X, 1, z), dim3(256), 0, s, pop, samples, sample0,
                      parity, w.h, ws);
-  hipLaunchKernelGGL((fft_half_kernel<N, L>), dim3(lines / L, 3, z), dim3(256), 0, s, w.h, 1, -1, ws);
-  hipLaunchKernelGGL((fft_half_kernel<N, L>), dim3(lines / L, 3, z), dim3(256), 0, s, w.h, 2, -1, ws);
-  hipLaunchKernelGGL((psd_zinv_kernel<N, L>), dim3(lines / L, 1, z), dim3(256), 0, s, w.h, w.sbins, w.scnt, ws);
-  hipLaunchKernelGGL(shell_partial_kernel, dim3(lchunks, 1, z), dim3(256), 0, s, w.sbins, w.scnt, lines, W, w.psum,
-                     w.pcnt, ws);
-  hipLaunchKernelGGL(shell_final_kernel, dim3(W, 1, z), dim3(256), 0, s, w.psum, w.pcnt, lchunks, W, N, 0, ek, w.r0,
-                     ws);
+  hipLaunchKernelGGL((fft_y_kernel<N, L>), dim3(lines / L, 3, z), dim3(256), 0, s, w.h, -1, ws);
+  hipLaunchKernelGGL((z_psd_kernel<N, L>), dim3(lines / L, 1, z), dim3(256), 0, s, w.h, w.sbins, ws);
+  hipLaunchKernelGGL(shell_partial_kernel, dim3(lchunks, 1, z), dim3(256), 0, s, w.sbins, srows, W, w.psum, ws);
+  hipLaunchKernelGGL(shell_final_kernel, dim3(W, 1, z), dim3(256), 0, s, w.psum, lchunks, W, N, 0, ek, w.r0, ws);
   if (s2) {
-    hipLaunchKernelGGL((fft_half_kernel<N, L>), dim3(lines / L, 1, z), dim3(256), 0, s, w.h, 1, +1, ws);
-    hipLaunchKernelGGL((inv_x_rows_kernel<N>), dim3(N * N / ROWS_R, 1, z), dim3(256), 0, s, w.h, w.r0, w.rbins,
-                       w.rcnt, ws);
-    hipLaunchKernelGGL(shell_partial_kernel, dim3(rchunks, 1, z), dim3(256), 0, s, w.rbins, w.rcnt, rows, W, w.psum,
-                       w.pcnt, ws);
-    hipLaunchKernelGGL(shell_final_kernel, dim3(W, 1, z), dim3(256), 0, s, w.psum, w.pcnt, rchunks, W, N, 1, s2,
-                       nullptr, ws);
+    hipLaunchKernelGGL((fft_y_kernel<N, L>), dim3(lines / L, 1, z), dim3(256), 0, s, w.h, +1, ws);
+    hipLaunchKernelGGL((inv_x_rows_kernel<N>), dim3(rows / ROWS_R, 1, z), dim3(256), 0, s, w.h, w.r0, w.rbins, ws);
+    hipLaunchKernelGGL(shell_partial_kernel, dim3(rchunks, 1, z), dim3(256), 0, s, w.rbins, rrows, W, w.psum, ws);
+    hipLaunchKernelGGL(shell_final_kernel, dim3(W, 1, z), dim3(256), 0, s, w.psum, rchunks, W, N, 1, s2, nullptr,
+                       ws);
   }
   return hipGetLastError();
 }
