@@ -43,6 +43,26 @@ int main(void) {
   expect(mclbm_ticks(NULL) == -1, "ticks of a NULL context");
   expect(mclbm_stream_copy(NULL, NULL, 16, NULL) == MCLBM_ERR_ARG, "stream copy of NULL buffers");
 
+  /* host-only arithmetic and argument checks of the statistics entry points */
+  {
+    const double ns[3] = {64.0, 128.0, 256.0}, ds[3] = {0.4, 0.2, 0.1};
+    double slope = 0.0;
+    expect(mclbm_eoc_slope(ns, ds, 3, &slope) == MCLBM_OK && slope > -1.0000001 && slope < -0.9999999,
+           "slope of d ~ 1/n is -1");
+    expect(mclbm_eoc_slope(ns, ds, 1, &slope) == MCLBM_ERR_ARG, "one point has no slope");
+    expect(mclbm_eoc_slope(NULL, ds, 3, &slope) == MCLBM_ERR_ARG, "slope without resolutions");
+  }
+  expect(mclbm_ensemble_moments(NULL, 4, 1, 1, NULL, NULL, NULL) == MCLBM_ERR_ARG, "moments of NULL");
+  expect(mclbm_ensemble_moments((const double*)256, 1, 1, 1, (double*)256, (double*)512, NULL) == MCLBM_ERR_ARG,
+         "a spread of one sample");
+  expect(mclbm_sample_error(NULL, NULL, 1, 8, NULL, NULL, 0, NULL) == MCLBM_ERR_ARG, "sample error of NULL");
+  expect(mclbm_w1_1pt(NULL, NULL, 1, 8, NULL, NULL, 0, NULL) == MCLBM_ERR_ARG, "W1 of NULL");
+  expect(mclbm_sample_error_work_bytes(0) == 0 && mclbm_w1_work_bytes(0) == 0, "work of nothing");
+  expect(mclbm_compensate(NULL, 0, 1, NULL, NULL, NULL, NULL, NULL) == MCLBM_ERR_ARG, "compensate without a context");
+  expect(mclbm_dissipation(NULL, NULL, 2, 0, 1, NULL, NULL) == MCLBM_ERR_ARG, "dissipation without a context");
+  expect(mclbm_checkpoint_bytes(NULL) == 0 && mclbm_ckpt_bytes(NULL, 10, 5) == 0, "checkpoint sizes without a context");
+  expect(mclbm_observables_range_work_bytes(NULL, 0, 1) == 0, "observables work without a context");
+
   if (fails == 0) printf("ok\n");
   return fails == 0 ? 0 : 1;
 }
