@@ -290,6 +290,32 @@ def bench_lattice(mc, torch, name, ticks=500):
     return out
 
 
+def bench_exact(mc, torch, ticks=200):
+    """The default 64 x 64^3 ensemble with the exact entropic stabiliser (the
+    minimiser of the discrete H-function by safeguarded Newton steps in every
+    node, 256-thread blocks): MLUPS, the kernel's algorithmic bandwidth, and
+    the mean gamma of both stabilisers after the timed ticks."""
+    import mc_inputs
+    wl = mc_inputs.WORKLOADS["rtgv64x64_f32"]
+    ens = build_ensemble(wl, mc, torch)
+    ens.set_stabiliser("exact")
+    ens.step(20)
+    sec, lups = timed_ticks(ens, torch, ticks, 0)
+    avg_ms, _, _, achieved = kernel_roofline(ens, wl, torch, 20)
+    gamma_exact = float(ens.reduce()[:, 7].mean())
+    ens.set_stabiliser("closed_form")
+    gamma_closed = float(ens.reduce()[:, 7].mean())
+    if ens.check() >= 0:
+        raise SystemExit("exact-stabiliser run became unstable")
+    out = {"workload": wl.name, "stabiliser": "exact", "ticks": ticks, "MLUPS": round(lups / sec / 1e6, 1),
+           "kernel_avg_ms": round(avg_ms, 5), "kernel_GBps_algorithmic": round(achieved, 1),
+           "kernel_frac_of_peak": round(achieved / HBM_PEAK_GBS, 4),
+           "mean_gamma_exact": round(gamma_exact, 5), "mean_gamma_closed_form_same_state": round(gamma_closed, 5)}
+    del ens
+    torch.cuda.empty_cache()
+    return out
+
+
 def bench_sequence(mc, torch):
     """Capacity run of the vanishing-viscosity sequence: 8 samples at each of
     128^3, 256^3 and 512^3 in one ensemble (132 GB of FP32 populations), the
@@ -492,6 +518,9 @@ def main():
         if wl.lattice == 27:
             extra["d3q19"] = bench_lattice(mc, torch, "rtgv64x64_f32_d3q19")
             print(f"[bench] d3q19: {extra['d3q19']}", file=sys.stderr, flush=True)
+        if wl.name == "rtgv64x64_f32":
+            extra["exact_stabiliser"] = bench_exact(mc, torch)
+            print(f"[bench] exact stabiliser: {extra['exact_stabiliser']}", file=sys.stderr, flush=True)
         if not args.no_capacity:
             extra["sequence512x8"] = bench_sequence(mc, torch)
             print(f"[bench] sequence512x8: {extra['sequence512x8']}", file=sys.stderr, flush=True)

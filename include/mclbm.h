@@ -324,9 +324,11 @@ mclbm_status mclbm_dissipation(mclbm_ctx* ctx, const double* records_dev, int32_
  * (Table 1). MCLBM_GAMMA_CLOSED_FORM (default) evaluates eq. (entropyControl).
  * MCLBM_GAMMA_EXACT minimises the discrete H-function of the post-collision
  * state, eq. (kbc_entropy): with t = omega gamma / 2, H(t) is convex where
- * every f*_i > 0; four safeguarded Newton steps on H'(t) = 0 start from the
+ * every f*_i > 0; safeguarded Newton steps on H'(t) = 0 start from the
  * closed form (a step leaving that interval is replaced by the midpoint
- * towards its edge), so the records report the exact gamma. The exact mode
+ * towards its edge) and stop, per node, once a step is below 2^-12 of t in
+ * FP32 or 1e-8 in FP64 (at most four), so the records report the exact
+ * gamma. The exact mode
  * runs 256-thread blocks only (mclbm_set_launch accepts no other size then,
  * mclbm_autotune returns MCLBM_ERR_UNSUPPORTED) and has no adjoint
  * (mclbm_forward_ckpt and mclbm_backward return MCLBM_ERR_UNSUPPORTED).

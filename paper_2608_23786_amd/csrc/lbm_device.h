@@ -88,6 +88,24 @@ __device__ __forceinline__ T vmin(T a, T b) {
   return a < b ? a : b;
 }
 
+// ln(1 + x) for x > -1. float: the hardware base-2 logarithm of u = 1 + x
+// (rounded to float) times ln 2, corrected by the factor x / (u - 1) that
+// restores the part of x lost in rounding u (the log1p identity in
+// Goldberg, "What every computer scientist should know about floating-point
+// arithmetic", 1991, Theorem 4, credited to Kahan); a few units in the last
+// place, and exactly x where u rounds to 1. double: the library log1p.
+template <typename T>
+__device__ __forceinline__ T log1p_acc(T x) {
+  if constexpr (std::is_same<T, float>::value) {
+    const float u = 1.0f + x;
+    const float d = u - 1.0f;
+    if (d == 0.0f) return x;
+    return (__builtin_amdgcn_logf(u) * 0.693147180559945309f) * (x * __builtin_amdgcn_rcpf(d));
+  } else {
+    return log1p(x);
+  }
+}
+
 template <typename T>
 struct Macro {
   T drho, jx, jy, jz, rho, inv, ux, uy, uz, usq15;
@@ -239,10 +257,19 @@ struct CellResult {
 //    H''(t) = sum dh_i^2 / f*_i.
 // Newton's method from the closed-form t (the first-order solution of
 // H'(t) = 0) converges quadratically; a step that would leave the interval is
-// replaced by the midpoint towards its edge. ln(f*_i / w_i) is evaluated as
-// log1p((f*_i - w_i) / w_i) from the shifted values, which keeps its relative
-// accuracy for populations near their weights.
+// replaced by the midpoint towards its edge. A node stops once its step is
+// below kExactTolerance of t (the next step would be below the rounding of
+// T), after at most kExactNewtonSteps steps; every node decides for itself,
+// so the result does not depend on its neighbours in the wave.
+// ln(f*_i / w_i) is evaluated as log1p((f*_i - w_i) / w_i) from the shifted
+// values, which keeps its relative accuracy for populations near their
+// weights.
 constexpr int kExactNewtonSteps = 4;
+
+template <typename T>
+constexpr T exact_tolerance() {
+  return std::is_same<T, float>::value ? T(1.0 / (1 << 12)) : T(1e-8);
+}
 
 template <int QN, typename T>
 __device__ __forceinline__ T exact_entropic_t(const T (&geq)[Q], const T (&fneq)[Q], const Shear<T>& s, T omega,
@@ -263,7 +290,8 @@ __device__ __forceinline__ T exact_entropic_t(const T (&geq)[Q], const T (&fneq)
       if (dh < T(0)) lo = lo > base / dh ? lo : base / dh;
     }
   });
-  for (int it = 0; it < kExactNewtonSteps; ++it) {
+  bool done = false;
+  for (int it = 0; it < kExactNewtonSteps && !done; ++it) {
     T d1 = T(0), d2 = T(0);
     for_vel<QN>([&](auto ic) {
       constexpr int i = decltype(ic)::value;
@@ -273,12 +301,13 @@ __device__ __forceinline__ T exact_entropic_t(const T (&geq)[Q], const T (&fneq)
       constexpr double w = weight<QN>(i);
       // f*_i - w_i in shifted form
       const T gs = geq[i] + (fneq[i] - omega * ds) - t * dh;
-      d1 += dh * log1p(gs * T(1.0 / w));
+      d1 += dh * log1p_acc(gs * T(1.0 / w));
       d2 += dh * dh * recip(T(w) + gs);
     });
     T tn = t + d1 / d2;
     if (!(tn < hi)) tn = T(0.5) * (t + hi);
     if (!(tn > lo)) tn = T(0.5) * (t + lo);
+    done = fabs(tn - t) <= exact_tolerance<T>() * fabs(t);
     t = tn;
   }
   return t;
