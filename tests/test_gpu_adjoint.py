@@ -138,7 +138,7 @@ def test_autograd_function():
     J = mc.EnsembleKE.apply(y, ens, 12, 5)
     J.backward()
     g, ke = oracle_gradient(samples, y.detach().numpy(), 12)
-    assert abs(float(J) - ke.mean()) / ke.mean() < 1e-12
+    assert abs(float(J.detach()) - ke.mean()) / ke.mean() < 1e-12
     assert np.max(np.abs(y.grad.numpy() - g)) / np.max(np.abs(g)) < 1e-8
 
 
