@@ -151,9 +151,12 @@ __device__ __forceinline__ P* in_batch(P* p, size_t wstride) {
   return reinterpret_cast<P*>(reinterpret_cast<B*>(p) + size_t(blockIdx.z) * wstride);
 }
 
-__device__ __forceinline__ int64_t isqrt_floor(int64_t v) {
+// floor(sqrt(v)) for 0 <= v < 2^24, which holds for every value the shell
+// ranges meet (n <= 1024): the float square root is within a unit of it and
+// the two loops correct it.
+__device__ __forceinline__ int isqrt_floor(int v) {
   if (v <= 0) return 0;
-  int64_t r = int64_t(sqrt(double(v)));
+  int r = int(sqrtf(float(v)));
   while (r * r > v) --r;
   while ((r + 1) * (r + 1) <= v) ++r;
   return r;
@@ -162,22 +165,22 @@ __device__ __forceinline__ int64_t isqrt_floor(int64_t v) {
 // The m in [0, half] with round(sqrt(s + m^2)) == r form the interval
 // [a, b] (empty when a > b): m^2 in [ceil(((2r-1)^2 - 4s)/4),
 // floor(((2r+1)^2 - 1 - 4s)/4)].
-__device__ __forceinline__ void shell_range(int half, int64_t s, int r, int& a, int& b) {
+__device__ __forceinline__ void shell_range(int half, int s, int r, int& a, int& b) {
   a = 1;
   b = 0;
-  const int64_t lo2 = r == 0 ? 0 : int64_t(2 * r - 1) * (2 * r - 1);
-  const int64_t top = int64_t(2 * r + 1) * (2 * r + 1) - 1 - 4 * s;
+  const int lo2 = r == 0 ? 0 : (2 * r - 1) * (2 * r - 1);
+  const int top = (2 * r + 1) * (2 * r + 1) - 1 - 4 * s;
   if (top < 0) return;
-  const int64_t m2max = top / 4;
-  const int64_t bot = lo2 - 4 * s;
-  const int64_t m2min = bot <= 0 ? 0 : (bot + 3) / 4;
+  const int m2max = top / 4;
+  const int bot = lo2 - 4 * s;
+  const int m2min = bot <= 0 ? 0 : (bot + 3) / 4;
   if (m2min > m2max) return;
-  int64_t lo = isqrt_floor(m2min);
+  int lo = isqrt_floor(m2min);
   if (lo * lo < m2min) ++lo;
-  int64_t hi = isqrt_floor(m2max);
+  int hi = isqrt_floor(m2max);
   if (hi > half) hi = half;
-  a = int(lo);
-  b = int(hi);
+  a = lo;
+  b = hi;
 }
 
 // Lattice vectors a folded index m stands for: m and -m, except m = 0 and
@@ -353,7 +356,7 @@ __global__ void __launch_bounds__(256) z_psd_kernel(double2* h0, double* sbins0,
       const int line = line0 + l, y = line / NH, kx = line % NH;
       const int ky = y <= HALF ? y : y - N;
       int a, b;
-      shell_range(HALF, int64_t(kx) * kx + int64_t(ky) * ky, r, a, b);
+      shell_range(HALF, kx * kx + ky * ky, r, a, b);
       sum += fold_weight(kx, HALF) * range_sum(fold + l * (HALF + 1), a, b);
     }
     sbins[blk * (HALF + 2) + r] = sum;
@@ -417,7 +420,7 @@ __global__ void __launch_bounds__(256)
       const int row = row0 + r, iz = row / N, iy = row % N;
       const int hz = iz <= HALF ? iz : iz - N, hy = iy <= HALF ? iy : iy - N;
       int a, b;
-      shell_range(HALF, int64_t(hz) * hz + int64_t(hy) * hy, c, a, b);
+      shell_range(HALF, hz * hz + hy * hy, c, a, b);
       sum += range_sum(fold + r * (HALF + 1), a, b);
     }
     rbins[blk * (HALF + 2) + c] = sum;
@@ -443,50 +446,60 @@ __global__ void __launch_bounds__(256) shell_partial_kernel(const double* bins0,
   }
 }
 
+// Number of lattice vectors of each shell, one block per shell r = 0..N/2:
+// the vectors with components in {-N/2+1, ..., N/2} whose length rounds to
+// r, counted over (p, q, m) folded to p, q, m >= 0 (whole numbers, exact in
+// any order). They depend on n only; the spectrum and the structure
+// function of every sample of a call share them.
+__global__ void __launch_bounds__(256) shell_count_kernel(int n, double* cnt) {
+  __shared__ double sc[256];
+  const int col = blockIdx.x, half = n / 2;
+  double c = 0.0;
+  for (int e = threadIdx.x; e < (half + 1) * (half + 1); e += 256) {
+    const int p = e / (half + 1), q = e % (half + 1);
+    int lo, hi;
+    shell_range(half, p * p + q * q, col, lo, hi);
+    c += fold_weight(p, half) * fold_weight(q, half) * range_count(half, lo, hi);
+  }
+  sc[threadIdx.x] = c;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if (threadIdx.x < st) sc[threadIdx.x] += sc[threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) cnt[col] = sc[0];
+}
+
 // Stage 2, one block per column: the partials summed over the chunks (thread
-// t takes chunks t, t + 256, ..., then a fixed tree), and the number of
-// lattice vectors of the shell, which depends on n only: every vector with
-// components in {-N/2+1, ..., N/2} whose length rounds to the column. mode 0
-// (spectrum): out[kappa] = 4 pi / count * sum / N^6 for kappa = 0..N/2 (out
-// may be NULL), and column N/2 + 1 (the sum of Psi, R_0 times N^6) into *r0.
-// mode 1 (structure function): out[r - 1] = sum / count / N^6 for r = 1..N/2.
-__global__ void __launch_bounds__(256) shell_final_kernel(const double* psum0, int chunks, int width, int n, int mode,
-                                                          double* out0, double* r00, size_t wstride) {
-  __shared__ double sa[256], sc[256];
+// t takes chunks t, t + 256, ..., then a fixed tree), divided by the shell's
+// number of vectors cnt[col] (shell_count_kernel). mode 0 (spectrum):
+// out[kappa] = 4 pi / count * sum / N^6 for kappa = 0..N/2 (out may be NULL),
+// and column N/2 + 1 (the sum of Psi, R_0 times N^6) into *r0. mode 1
+// (structure function): out[r - 1] = sum / count / N^6 for r = 1..N/2.
+__global__ void __launch_bounds__(256) shell_final_kernel(const double* psum0, const double* cnt, int chunks,
+                                                          int width, int n, int mode, double* out0, double* r00,
+                                                          size_t wstride) {
+  __shared__ double sa[256];
   const double* psum = in_batch(psum0, wstride);
   double* out = out0 ? out0 + size_t(blockIdx.z) * (mode == 0 ? n / 2 + 1 : n / 2) : nullptr;
   double* r0 = r00 ? in_batch(r00, wstride) : nullptr;
   const int col = blockIdx.x, half = n / 2;
-  double a = 0.0, c = 0.0;
+  double a = 0.0;
   for (int b = threadIdx.x; b < chunks; b += 256) a += psum[size_t(b) * width + col];
-  if (col <= half) {
-    // vectors (p, q, m) with |p|, |q|, |m| <= N/2 folded to p, q, m >= 0;
-    // the counts are whole numbers, exact in any order
-    for (int e = threadIdx.x; e < (half + 1) * (half + 1); e += 256) {
-      const int p = e / (half + 1), q = e % (half + 1);
-      int lo, hi;
-      shell_range(half, int64_t(p) * p + int64_t(q) * q, col, lo, hi);
-      c += fold_weight(p, half) * fold_weight(q, half) * range_count(half, lo, hi);
-    }
-  }
   sa[threadIdx.x] = a;
-  sc[threadIdx.x] = c;
   __syncthreads();
   for (int st = 128; st > 0; st >>= 1) {
-    if (threadIdx.x < st) {
-      sa[threadIdx.x] += sa[threadIdx.x + st];
-      sc[threadIdx.x] += sc[threadIdx.x + st];
-    }
+    if (threadIdx.x < st) sa[threadIdx.x] += sa[threadIdx.x + st];
     __syncthreads();
   }
   if (threadIdx.x == 0) {
     const double norm = 1.0 / (double(n) * n * n) / (double(n) * n * n);
-    const double sum = sa[0], cnt = sc[0];
+    const double sum = sa[0], cnt_c = col <= half ? cnt[col] : 0.0;
     if (mode == 0) {
-      if (col <= half && out) out[col] = cnt > 0 ? 4.0 * M_PI / cnt * sum * norm : 0.0;
+      if (col <= half && out) out[col] = cnt_c > 0 ? 4.0 * M_PI / cnt_c * sum * norm : 0.0;
       if (col == half + 1 && r0) *r0 = sum;
     } else if (col >= 1 && col <= half) {
-      out[col - 1] = cnt > 0 ? sum * norm / cnt : 0.0;
+      out[col - 1] = cnt_c > 0 ? sum * norm / cnt_c : 0.0;
     }
   }
 }
@@ -704,6 +717,7 @@ struct ObsWork {
   double* rbins;    // sf_bin_rows(N) rows of N/2 + 2
   double* psum;     // one row of N/2 + 2 per chunk of either table
   double* r0;       // 1
+  double* cnt;      // N/2 + 1 shell sizes (used in the first sample's area)
 };
 
 size_t align256(size_t b) { return (b + 255) / 256 * 256; }
@@ -712,8 +726,8 @@ size_t chunks_of(size_t rows) { return (rows + kShellChunk - 1) / kShellChunk; }
 
 // Byte sizes of the parts of one sample's work area (each a multiple of 256)
 struct WorkSizes {
-  size_t h, sbins, rbins, psum, r0;
-  size_t total() const { return h + sbins + rbins + psum + r0; }
+  size_t h, sbins, rbins, psum, r0, cnt;
+  size_t total() const { return h + sbins + rbins + psum + r0 + cnt; }
 };
 
 WorkSizes work_sizes(int n) {
@@ -725,6 +739,7 @@ WorkSizes work_sizes(int n) {
   z.rbins = align256(rrows * width * sizeof(double));
   z.psum = align256(chunks_of(std::max(srows, rrows)) * width * sizeof(double));
   z.r0 = align256(sizeof(double));
+  z.cnt = align256(width * sizeof(double));
   return z;
 }
 
@@ -740,6 +755,7 @@ ObsWork carve(void* work, int n) {
   w.rbins = reinterpret_cast<double*>(p += z.sbins);
   w.psum = reinterpret_cast<double*>(p += z.rbins);
   w.r0 = reinterpret_cast<double*>(p += z.psum);
+  w.cnt = reinterpret_cast<double*>(p += z.r0);
   return w;
 }
 
@@ -762,13 +778,15 @@ hipError_t observables_t(const T* pop, const DevSample* samples, int sample0, in
   hipLaunchKernelGGL((fft_y_kernel<N, L>), dim3(lines / L, 3, z), dim3(256), 0, s, w.h, -1, ws);
   hipLaunchKernelGGL((z_psd_kernel<N, L>), dim3(lines / L, 1, z), dim3(256), 0, s, w.h, w.sbins, ws);
   hipLaunchKernelGGL(shell_partial_kernel, dim3(lchunks, 1, z), dim3(256), 0, s, w.sbins, srows, W, w.psum, ws);
-  hipLaunchKernelGGL(shell_final_kernel, dim3(W, 1, z), dim3(256), 0, s, w.psum, lchunks, W, N, 0, ek, w.r0, ws);
+  hipLaunchKernelGGL(shell_count_kernel, dim3(NH), dim3(256), 0, s, N, w.cnt);
+  hipLaunchKernelGGL(shell_final_kernel, dim3(W, 1, z), dim3(256), 0, s, w.psum, w.cnt, lchunks, W, N, 0, ek, w.r0,
+                     ws);
   if (s2) {
     hipLaunchKernelGGL((fft_y_kernel<N, L>), dim3(lines / L, 1, z), dim3(256), 0, s, w.h, +1, ws);
     hipLaunchKernelGGL((inv_x_rows_kernel<N>), dim3(rows / ROWS_R, 1, z), dim3(256), 0, s, w.h, w.r0, w.rbins, ws);
     hipLaunchKernelGGL(shell_partial_kernel, dim3(rchunks, 1, z), dim3(256), 0, s, w.rbins, rrows, W, w.psum, ws);
-    hipLaunchKernelGGL(shell_final_kernel, dim3(W, 1, z), dim3(256), 0, s, w.psum, rchunks, W, N, 1, s2, nullptr,
-                       ws);
+    hipLaunchKernelGGL(shell_final_kernel, dim3(W, 1, z), dim3(256), 0, s, w.psum, w.cnt, rchunks, W, N, 1, s2,
+                       nullptr, ws);
   }
   return hipGetLastError();
 }

@@ -448,8 +448,9 @@ class EnsembleKE(torch.autograd.Function):
         ctx.ckpt_every = ckpt_every
         ctx.ckpt = ck
         red = ensemble.reduce()
+        mean, _ = ensemble_moments(red[:, 4:5], std=False)
         ensemble.synchronize()
-        return red[:, 4].mean().to(y.device)
+        return mean[0].to(y.device)
 
     @staticmethod
     def backward(ctx, gJ):
