@@ -107,7 +107,8 @@ WORKLOADS = {
     # (Re = 12.5 N, diffusive U0, the same Y at every resolution), strides
     # 16:4:1; the run to t = 9 takes 234,684 ticks, the benchmark times a
     # bounded number of them and compares the resolutions at equal physical
-    # time through 1-point Wasserstein distances on the 8^3 common nodes
+    # time through 1-point Wasserstein distances and the relative L1 sample
+    # error on the 8^3 common nodes
     "sequence512x8_f32": Workload(
         "sequence512x8_f32",
         [SampleGroup(128, 8, diffusive_u0(128), 1600.0, 0.05, True, 16),
