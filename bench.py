@@ -417,6 +417,34 @@ def traffic_probe(mc, torch, ticks=4):
         torch.cuda.empty_cache()
 
 
+# resolution groups of the observables probe: (samples, n)
+OBSERVABLES_PROBES = ((32, 64), (12, 128), (4, 256), (1, 512))
+
+
+def observables_probe(mc, torch, reps=3):
+    """The FP64 spectrum and structure function of each OBSERVABLES_PROBES
+    group (FP32 D3Q27 ensembles a few ticks after initialisation, one set of
+    launches per group), `reps` times, timed with HIP events; for
+    kernel-trace and counter passes. Prints one line per group."""
+    for m, n in OBSERVABLES_PROBES:
+        ens = mc.Ensemble([mc.Sample(n, 0.05 * 32 / n, 25.0 * n, 0.05, True)] * m, "f32s")
+        ens.init(5)
+        ens.step(3)
+        ens.observables_range(0, m)
+        ens.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(ens.stream)
+        for _ in range(reps):
+            ens.observables_range(0, m)
+        e1.record(ens.stream)
+        ens.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        print(f"[observables-probe] {m} x {n}^3: {ms:.3f} ms per set of launches, "
+              f"{ms * 1e6 / (m * n ** 3):.4f} ns per node", flush=True)
+        del ens
+        torch.cuda.empty_cache()
+
+
 def cpu_baseline(seconds_target=15.0):
     """The oracle on one 64^3 RTGV sample of the workload, on all host cores."""
     import mc_inputs
@@ -465,6 +493,8 @@ def main():
     ap.add_argument("--no-capacity", action="store_true", help="skip the 132 GB vanishing-viscosity sequence")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="only run a few ticks of the larger-lattice and D3Q19 ensembles (for counter passes)")
+    ap.add_argument("--observables-probe", action="store_true",
+                    help="only time the FP64 observables of one group per resolution (for counter passes)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (the library has no multi-GPU path); got --gpus {args.gpus}",
@@ -477,6 +507,9 @@ def main():
 
     if args.traffic_probe:
         traffic_probe(mc, torch)
+        return
+    if args.observables_probe:
+        observables_probe(mc, torch)
         return
     wl = mc_inputs.WORKLOADS[args.workload]
     print(f"[bench] workload {wl.name}: {wl.m} samples, precision {wl.precision}", file=sys.stderr, flush=True)
