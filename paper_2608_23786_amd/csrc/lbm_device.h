@@ -274,21 +274,26 @@ constexpr T exact_tolerance() {
 template <int QN, typename T>
 __device__ __forceinline__ T exact_entropic_t(const T (&geq)[Q], const T (&fneq)[Q], const Shear<T>& s, T omega,
                                               T t) {
+  // the interval of t where every f*_i = base_i - t dh_i > 0; in float the
+  // quotients use the hardware reciprocal (about one unit in the last place)
+  // and are moved inwards by 2^-20 of their size, so that the interval stays
+  // inside the exact one
   T lo = T(-1e30), hi = T(1e30);
   for_vel<QN>([&](auto ic) {
     constexpr int i = decltype(ic)::value;
-    if constexpr (nonzeros(i) == 1 || nonzeros(i) == 2) {
-      const T ds = shear_part<i>(s);
-      const T dh = fneq[i] - ds;
-      const T base = (T(weight<QN>(i)) + geq[i]) + (fneq[i] - omega * ds);
-      if (dh > T(0)) hi = vmin(hi, base / dh);
-      if (dh < T(0)) lo = lo > base / dh ? lo : base / dh;
+    T ds = T(0);
+    if constexpr (nonzeros(i) == 1 || nonzeros(i) == 2) ds = shear_part<i>(s);
+    const T dh = fneq[i] - ds;
+    const T base = (T(weight<QN>(i)) + geq[i]) + (fneq[i] - omega * ds);
+    T q;
+    if constexpr (std::is_same<T, float>::value) {
+      q = base * __builtin_amdgcn_rcpf(dh);
+      q = dh > T(0) ? q - fabsf(q) * 0x1.0p-20f : q + fabsf(q) * 0x1.0p-20f;
     } else {
-      const T dh = fneq[i];
-      const T base = T(weight<QN>(i)) + geq[i] + fneq[i];
-      if (dh > T(0)) hi = vmin(hi, base / dh);
-      if (dh < T(0)) lo = lo > base / dh ? lo : base / dh;
+      q = base / dh;
     }
+    if (dh > T(0)) hi = vmin(hi, q);
+    if (dh < T(0)) lo = lo > q ? lo : q;
   });
   bool done = false;
   for (int it = 0; it < kExactNewtonSteps && !done; ++it) {
