@@ -345,27 +345,32 @@ __global__ void __launch_bounds__(256) z_psd_kernel(double2* h0, double* sbins0,
     if (lane == 0) tot[l] = fold_weight(kx, HALF) * total;
   }
   __syncthreads();
-  const size_t blk = size_t(line0 / LINES);
-  for (int r = threadIdx.x; r <= HALF + 1; r += 256) {
-    double sum = 0.0;
-    for (int l = 0; l < LINES; ++l) {
-      if (r == HALF + 1) {
-        sum += tot[l];
-        continue;
-      }
-      const int line = line0 + l, y = line / NH, kx = line % NH;
-      const int ky = y <= HALF ? y : y - N;
-      int a, b;
-      shell_range(HALF, kx * kx + ky * ky, r, a, b);
-      sum += fold_weight(kx, HALF) * range_sum(fold + l * (HALF + 1), a, b);
-    }
-    sbins[blk * (HALF + 2) + r] = sum;
-  }
   butterflies<N>(sh, LINES, tw);
   for (int e = threadIdx.x; e < LINES * N; e += 256) {
     const int i = e / LINES, l = e % LINES;
     const int line = line0 + l, y = line / NH, kx = line % NH;
     h[(size_t(i) * N + y) * NH + kx] = sh[l * LS + lds_pos(i)];
+  }
+  __syncthreads();
+  // the shell sums of every (line, shell) pair over all threads, in the LDS
+  // the transform no longer needs, then the block's lines added per shell
+  // in line order
+  static_assert(sizeof(double) * LINES * (HALF + 1) <= sizeof(sh), "the line sums fit in the transform's LDS");
+  double* part = reinterpret_cast<double*>(sh);
+  for (int e = threadIdx.x; e < LINES * (HALF + 1); e += 256) {
+    const int l = e / (HALF + 1), r = e % (HALF + 1);
+    const int line = line0 + l, y = line / NH, kx = line % NH;
+    const int ky = y <= HALF ? y : y - N;
+    int a, b;
+    shell_range(HALF, kx * kx + ky * ky, r, a, b);
+    part[e] = fold_weight(kx, HALF) * range_sum(fold + l * (HALF + 1), a, b);
+  }
+  __syncthreads();
+  const size_t blk = size_t(line0 / LINES);
+  for (int r = threadIdx.x; r <= HALF + 1; r += 256) {
+    double sum = 0.0;
+    for (int l = 0; l < LINES; ++l) sum += r == HALF + 1 ? tot[l] : part[l * (HALF + 1) + r];
+    sbins[blk * (HALF + 2) + r] = sum;
   }
 }
 
@@ -413,16 +418,24 @@ __global__ void __launch_bounds__(256)
     }
   }
   __syncthreads();
+  // the shell sums of every (row, shell) pair over all threads, in the LDS
+  // the transform no longer needs, then the block's rows added per shell in
+  // row order
+  static_assert(sizeof(double) * ROWS * (HALF + 1) <= sizeof(sh), "the row sums fit in the transform's LDS");
+  double* part = reinterpret_cast<double*>(sh);
+  for (int e = threadIdx.x; e < ROWS * (HALF + 1); e += 256) {
+    const int r = e / (HALF + 1), c = e % (HALF + 1);
+    const int row = row0 + r, iz = row / N, iy = row % N;
+    const int hz = iz <= HALF ? iz : iz - N, hy = iy <= HALF ? iy : iy - N;
+    int a, b;
+    shell_range(HALF, hz * hz + hy * hy, c, a, b);
+    part[e] = range_sum(fold + r * (HALF + 1), a, b);
+  }
+  __syncthreads();
   const size_t blk = size_t(row0 / ROWS);
   for (int c = threadIdx.x; c <= HALF + 1; c += 256) {
     double sum = 0.0;
-    for (int r = 0; r < ROWS && c <= HALF; ++r) {
-      const int row = row0 + r, iz = row / N, iy = row % N;
-      const int hz = iz <= HALF ? iz : iz - N, hy = iy <= HALF ? iy : iy - N;
-      int a, b;
-      shell_range(HALF, hz * hz + hy * hy, c, a, b);
-      sum += range_sum(fold + r * (HALF + 1), a, b);
-    }
+    for (int r = 0; r < ROWS && c <= HALF; ++r) sum += part[r * (HALF + 1) + c];
     rbins[blk * (HALF + 2) + c] = sum;
   }
 }
