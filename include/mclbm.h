@@ -219,7 +219,8 @@ mclbm_status mclbm_backward(mclbm_ctx* ctx, int64_t ticks, int32_t ckpt_every, c
  *     length rounds above n/2 are not counted.
  * Either output may be NULL. work_dev: device scratch of
  * mclbm_observables_work_bytes(ctx, sample) bytes (about 25 n^3 bytes),
- * 256-byte aligned, owned by the caller. Supported n: 8..512. Lattice
+ * 256-byte aligned, owned by the caller. Supported n: 8..512 (a sample
+ * of n = 1024 gives MCLBM_ERR_UNSUPPORTED and 0 work bytes). Lattice
  * units (divide by u0^2 for physical units). */
 size_t mclbm_observables_work_bytes(const mclbm_ctx* ctx, int32_t sample);
 mclbm_status mclbm_observables(mclbm_ctx* ctx, int32_t sample, double* s2_dev, double* ek_dev, void* work_dev,

@@ -48,6 +48,7 @@ constexpr int kAuxBlock = 256;        // block of the auxiliary kernels
 constexpr int kMaxTables = 128;       // launch tables kept in the workspace
 constexpr size_t kHeaderBytes = 4096; // checkpoint header
 constexpr uint64_t kCkptMagic = 0x4d434c424d434b50ull;
+constexpr int kMaxObservablesN = 512;  // the FFT passes are instantiated for n = 8..512
 
 // Leray projection on the 24 perturbation coefficients.
 // Every basis field a_i(2x) a_j(2y) a_k(2z) e_alpha is a Laplacian eigenfunction
@@ -890,7 +891,7 @@ mclbm_status mclbm_backward(mclbm_ctx* c, int64_t ticks, int32_t ckpt_every, con
 
 // ------------------------------------------------------------------ observables
 size_t mclbm_observables_range_work_bytes(const mclbm_ctx* c, int32_t first, int32_t count) {
-  if (!c || first < 0 || count < 1 || first + count > c->m) return 0;
+  if (!c || first < 0 || count < 1 || first + count > c->m || c->desc[first].n > kMaxObservablesN) return 0;
   for (int s = first + 1; s < first + count; ++s)
     if (c->desc[s].n != c->desc[first].n) return 0;
   return observables_work_bytes(c->desc[first].n, count);
@@ -908,6 +909,7 @@ mclbm_status mclbm_observables_range(mclbm_ctx* c, int32_t first, int32_t count,
   const int n = c->desc[first].n;
   for (int s = first + 1; s < first + count; ++s)
     if (c->desc[s].n != n) return fail(MCLBM_ERR_ARG, "the samples of a range must share one n");
+  if (n > kMaxObservablesN) return fail(MCLBM_ERR_UNSUPPORTED, "the observables are built for n <= 512");
   if (!work_dev || work_bytes < observables_work_bytes(n, count))
     return fail(MCLBM_ERR_OOM, "observables work buffer too small");
   if (reinterpret_cast<uintptr_t>(work_dev) % kAlign) return fail(MCLBM_ERR_ARG, "work_dev must be 256-byte aligned");

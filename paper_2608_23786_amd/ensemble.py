@@ -212,7 +212,7 @@ class Ensemble:
         """(S2[count, n/2], E[count, n/2+1]) of samples first..first+count-1 (one n) in one set of launches."""
         wb = int(lib().mclbm_observables_range_work_bytes(self._ctx, first, count))
         if wb == 0:
-            raise MclbmError(_lib.ERR_ARG, "invalid sample range (out of bounds or mixed resolutions)")
+            raise MclbmError(_lib.ERR_ARG, "invalid sample range (out of bounds, mixed resolutions or n above 512)")
         n = self.samples[first].n
         if work is None or work.numel() < wb:
             work = self._dev_empty((wb,), torch.uint8)
