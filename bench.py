@@ -446,7 +446,10 @@ def observables_probe(mc, torch, reps=3):
 
 
 def cpu_baseline(seconds_target=15.0):
-    """The oracle on one 64^3 RTGV sample of the workload, on all host cores."""
+    """The oracle on one 64^3 RTGV sample of the workload, on all host cores
+    (and two steps on one core); for context also the 32^3 FP64 TGV
+    configuration in full."""
+    import numpy as np
     import mc_inputs
     import oracle
     wl = mc_inputs.WORKLOADS["rtgv64x64_f32"]
@@ -465,6 +468,13 @@ def cpu_baseline(seconds_target=15.0):
     t = time.perf_counter()
     oracle.run(f, g.n, 2, om, threads=1)
     one = time.perf_counter() - t
+    # the single-sample FP64 configuration in full (32^3 TGV, Re 100, 100
+    # steps), on all cores
+    tgv = mc_inputs.WORKLOADS["tgv32_f64"].groups[0]
+    f32 = oracle.init_populations(tgv.n, tgv.u0, 0.0, np.zeros(24), False)
+    t = time.perf_counter()
+    oracle.run(f32, tgv.n, 100, oracle.omega_shear(oracle.lattice_viscosity(tgv.n, tgv.u0, tgv.re)), threads=threads)
+    sec32 = time.perf_counter() - t
     model = "unknown"
     try:
         with open("/proc/cpuinfo") as fh:
@@ -474,7 +484,8 @@ def cpu_baseline(seconds_target=15.0):
     return {"value": g.n ** 3 * steps / sec / 1e6, "unit": "MLUPS", "cores": threads, "kind": "oracle",
             "sample": f"1 RTGV sample at {g.n}^3 of the 64x64^3 workload, {steps} steps, FP64 moment-space "
                       f"KBC collision, two-lattice pull streaming ({sec:.1f} s)",
-            "single_core_MLUPS": round(g.n ** 3 * 2 / one / 1e6, 3), "cpu_model": model}
+            "single_core_MLUPS": round(g.n ** 3 * 2 / one / 1e6, 3),
+            "tgv32_f64_100_steps_MLUPS": round(tgv.n ** 3 * 100 / sec32 / 1e6, 3), "cpu_model": model}
 
 
 def main():
