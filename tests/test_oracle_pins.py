@@ -408,6 +408,52 @@ def test_initial_kinetic_energy_closed_form(q):
         assert np.max(np.abs(rho - 1)) < 1e-15
 
 
+@LATTICES
+def test_initial_populations_carry_the_prescribed_velocity(q):
+    """eq. (initialPopulations): the populations of a node are the equilibrium
+    of density 1 and the node's velocity, so their zeroth moment is 1 and their
+    first moment is that velocity, component by component (moments taken here
+    from the listed velocities, not from the oracle)."""
+    n = 6
+    rng = np.random.default_rng(21)
+    u = rng.uniform(-0.08, 0.08, (3, n, n, n))
+    u[1] *= 0.5     # distinct scales per component
+    u[2] *= 0.25
+    y = mc_inputs.draw_y(22, 1)[0]
+    cf = np.array(lattice_velocities(q), dtype=float)
+    cases = ((oracle.equilibrium_field(u, q), u),
+             (oracle.init_populations(n, 0.04, 0.3, y, True, q), oracle.initial_velocity(n, 0.04, 0.3, y, True)))
+    for f, target in cases:
+        assert f.shape == (n ** 3, q)
+        assert np.max(np.abs(f.sum(axis=1) - 1.0)) < 1e-15
+        j = f @ cf
+        for a in range(3):
+            assert np.max(np.abs(j[:, a] - target[a].ravel())) < 1e-16
+
+
+@LATTICES
+def test_moments_of_equilibrium_states_and_uniform_flow_reductions(q):
+    """Density and velocity are the zeroth moment and the first moment over
+    the zeroth: the moments of equilibrium populations f^eq(rho, u), built
+    here from the textbook form, return rho and u at every node. A uniform
+    flow of velocity U at density 1 on N^3 nodes has mass N^3, momentum
+    N^3 U and kinetic energy |U|^2 / 2."""
+    n = 3
+    rng = np.random.default_rng(23)
+    rho = 1.0 + rng.uniform(-0.05, 0.05, n ** 3)
+    u = rng.uniform(-0.08, 0.08, (n ** 3, 3))
+    f = np.stack([textbook_feq(rho[k], u[k], q) for k in range(n ** 3)])
+    r, v = oracle.moments(f, n)
+    assert np.max(np.abs(r.ravel() - rho)) < 1e-15
+    for a in range(3):
+        assert np.max(np.abs(v[a].ravel() - u[:, a])) < 1e-15
+    U = np.array([0.03, -0.02, 0.01])
+    f = np.tile(textbook_feq(1.0, U, q), (n ** 3, 1))
+    red = oracle.reductions(f, n)
+    exp = [n ** 3, n ** 3 * U[0], n ** 3 * U[1], n ** 3 * U[2], 0.5 * np.dot(U, U)]
+    assert np.max(np.abs(red - exp)) < 1e-14
+
+
 def test_leray_projection_properties():
     """The projection is idempotent, leaves a spectrally divergence-free field,
     removes a pure gradient, has rank 16 on the 24 perturbation fields, and
@@ -490,6 +536,21 @@ def test_unit_conversion_reproduces_paper_tables():
         mant, ex = row["dt"]
         # three printed digits: within one unit of the last one
         assert abs(dt / 10 ** ex - mant) < 0.01, row
+
+
+def test_lattice_viscosity_reproduces_table_rows_with_dx_2pi_over_n():
+    """Re = U l / nu with l = 1 on the periodic box of side 2 pi: with dx =
+    2 pi / N a unit length is N / (2 pi) lattice units. The rows of Table 3
+    printed with that spacing (N >= 32) give their tau back from the lattice
+    viscosity, at the lattice velocity Ma c_s."""
+    with open(os.path.join(GOLDEN, "paper_parameter_tables.json")) as fh:
+        rows = [r for r in json.load(fh)["rows"] if r["dx"] == "2pi/N"]
+    assert len(rows) == 5
+    for row in rows:
+        nu = oracle.lattice_viscosity(row["N"], row["Ma"] * math.sqrt(1.0 / 3.0), row["Re"])
+        tau = 1.0 / oracle.omega_shear(nu)
+        assert abs(tau - (3.0 * nu + 0.5)) < 1e-15
+        assert round(tau, 6) == pytest.approx(row["tau"], abs=0), row
 
 
 # ---------------------------------------------------------------- complex step
@@ -613,11 +674,12 @@ def test_compensation_of_k41_ranges_is_flat():
     structure function C (d r)^(2/3) over physical lags r to the constant C,
     sample by sample with each sample's own d and u0."""
     n = 32
+    c_kol = 1.5   # the K41 constant as the paper states it with eq. (compensatedE)
     d = np.array([0.3, 2.0e-3])
     u0 = np.array([0.05, 0.0125])
     kap = np.arange(n // 2 + 1, dtype=np.float64)
     ek = np.zeros((2, n // 2 + 1))
-    ek[:, 1:] = (oracle.KOLMOGOROV_CONSTANT * np.cbrt(d ** 2)[:, None] * kap[1:] ** (-5.0 / 3.0)) * u0[:, None] ** 2
+    ek[:, 1:] = (c_kol * np.cbrt(d ** 2)[:, None] * kap[1:] ** (-5.0 / 3.0)) * u0[:, None] ** 2
     ec = oracle.compensated_spectrum(ek, d, u0)
     assert np.max(np.abs(ec[:, 1:] - 1.0)) < 1e-14 and np.all(ec[:, 0] == 0.0)
     r = np.arange(1, n // 2 + 1) * 2 * math.pi / n
