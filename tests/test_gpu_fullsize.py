@@ -32,16 +32,18 @@ def neighbours(n, cells, q=27):
     return out
 
 
-def check_one_step(ens, samples, k, rng, tol):
-    """Advance one tick and compare sampled post-step populations with the oracle."""
+def check_one_step(ens, samples, k, rng, tol, extra=()):
+    """Advance one tick and compare sampled post-step populations with the
+    oracle (k random cells per sample, plus the cells in `extra`)."""
     q = ens.q
     _, w = oracle.velocity_set(q)
     pre = {}
     for s in samples:
         n = ens.samples[s].n
-        cells = rng.choice(n ** 3, size=k, replace=False)
+        cells = np.unique(np.concatenate([rng.choice(n ** 3, size=k, replace=False),
+                                          np.asarray(extra, dtype=np.int64)]))
         nb = neighbours(n, cells, q)
-        fpre = ens.get_cells(s, nb.ravel()).cpu().numpy().reshape(k, q, q)
+        fpre = ens.get_cells(s, nb.ravel()).cpu().numpy().reshape(len(cells), q, q)
         pre[s] = (cells, fpre)
     steps_before = {s: ens.steps(s) for s in samples}
     ens.step(1)
@@ -145,6 +147,32 @@ def test_512_cubed_sample_sampled_steps(block):
     print(f"sampled one-step error (512^3): {worst:.3e}")
     red = ens.reduce().cpu().numpy()[0]
     assert abs(red[0] - n ** 3) < 1e-6 * n ** 3
+
+
+@pytest.mark.parametrize("block", [512, 1024])
+def test_1024_cubed_sample_at_the_maximum_size(block):
+    """The largest sample the FP32 path accepts: one 1024^3 sample, 2^30
+    nodes and 116 GB of populations, planes of 4 GiB (pointer addressing).
+    Block 1024 holds whole rows (x-shifts by lane exchange), block 512 does
+    not (direct addressing). The sampled cells include the last nodes of the
+    lattice, whose 4-byte elements sit at the top of a plane (byte offset
+    2^32 - 4 within it), on both AA parities; mass is conserved."""
+    torch.cuda.empty_cache()
+    n = 1024
+    ens = mc.Ensemble([mc.Sample(n, 0.05 * 32 / n, 12.5 * n, 0.05, True)], "f32s")
+    ens.init(1024)
+    ens.set_launch(block, 0, 0, 1)
+    ens.step(2)
+    rng = np.random.default_rng(1024)
+    top = [n ** 3 - 1, n ** 3 - 2, n ** 3 - n, n ** 3 - n * n, (n - 1) * n * n + 5 * n + 7, n * n - 1]
+    worst = max(check_one_step(ens, [0], 24, rng, 2e-6, top), check_one_step(ens, [0], 24, rng, 2e-6, top))
+    print(f"sampled one-step error (1024^3, block {block}): {worst:.3e}")
+    red = ens.reduce().cpu().numpy()[0]
+    assert abs(red[0] - n ** 3) < 1e-6 * n ** 3
+    assert abs(red[4] - 0.125 * (0.05 * 32 / n) ** 2) < 0.01 * 0.125 * (0.05 * 32 / n) ** 2
+    assert ens.check() == -1
+    del ens
+    torch.cuda.empty_cache()
 
 
 def test_d3q19_64x64_full_size_sampled_steps():
