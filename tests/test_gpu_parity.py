@@ -317,6 +317,47 @@ def test_state_errors():
         ens.set_launch(1024)
 
 
+@pytest.mark.parametrize("precision", ["f32s", "f64"])
+@pytest.mark.parametrize("q", [27, 19])
+def test_degenerate_rest_and_uniform_states(precision, q):
+    """Reading C4' (the stabiliser is 2 when <dh|dh> <= 1e-30): a state at
+    rest (f = w at every node, g = 0 in the shifted storage) has no
+    non-equilibrium part, so it stays exactly at rest on both AA parities,
+    with gamma exactly 2 in every record, kinetic energy 0 and mass N^3. A
+    uniform flow stays uniform: streaming a uniform field is the identity and
+    every node does the same arithmetic, so all nodes stay bitwise equal
+    (pin P1 of the oracle, here on the GPU), within rounding of the start,
+    and min and max of gamma coincide."""
+    n = 16
+    smp = mc.Sample(n, 0.05, 100.0, 0.0, False)
+    ens = mc.Ensemble([smp, smp], precision, lattice=q)
+    ens.init(1)
+    _, w = oracle.velocity_set(q)
+    U = np.array([0.03, -0.02, 0.01])
+    feq = oracle.equilibrium(1.0, U, q)
+    for s, f in ((0, w), (1, feq)):
+        ens.set_state(s, torch.from_numpy(np.ascontiguousarray(np.repeat(f[:, None], n ** 3, axis=1))).cuda())
+    rec = ens.step(7, record_every=1).cpu().numpy()   # 7 ticks: both parities, ending odd
+    assert ens.check() == -1
+    rest = ens.get_state(0).cpu().numpy().reshape(q, n ** 3)
+    assert np.array_equal(rest, np.repeat(w[:, None], n ** 3, axis=1))
+    assert np.all(rec[:, 0, 5:8] == 2.0)
+    assert np.all(rec[:, 0, 4] == 0.0) and np.all(rec[:, 0, 1:4] == 0.0)
+    assert np.all(rec[:, 0, 0] == n ** 3)
+    uni = ens.get_state(1).cpu().numpy().reshape(q, n ** 3)
+    assert np.array_equal(uni, np.repeat(uni[:, :1], n ** 3, axis=1))
+    assert np.all(rec[:, 1, 5] == rec[:, 1, 6])
+    # rounding only: FP64, or FP32 storage of g ~ 3e-2 (2e-9 per value; the
+    # collision of a rounding-level non-equilibrium part moves it by about as
+    # much per step)
+    f64 = precision == "f64"
+    assert np.max(np.abs(uni[:, 0] - feq)) < (1e-15 if f64 else 1e-7)
+    assert np.max(np.abs(rec[:, 1, 0] - n ** 3)) < (1e-9 if f64 else 1e-3)
+    mom = rec[:, 1, 1:4] / n ** 3
+    assert np.max(np.abs(mom - U)) < (1e-14 if f64 else 1e-7)
+    assert np.max(np.abs(rec[:, 1, 4] - 0.5 * np.dot(U, U))) < (1e-15 if f64 else 1e-8)
+
+
 def test_smallest_lattice_and_set_viscosity():
     """n = 8 (smallest) and a viscosity changed between steps."""
     y = mc_inputs.draw_y(1, 1)
