@@ -445,10 +445,11 @@ def observables_probe(mc, torch, reps=3):
         torch.cuda.empty_cache()
 
 
-def cpu_baseline(seconds_target=15.0):
+def cpu_baseline(seconds_target=15.0, large=True):
     """The oracle on one 64^3 RTGV sample of the workload, on all host cores
     (and two steps on one core); for context also the 32^3 FP64 TGV
-    configuration in full."""
+    configuration in full and, with `large`, one step of one 256^3 sample of
+    the mixed-resolution workload (its initialisation untimed, ~15 s)."""
     import numpy as np
     import mc_inputs
     import oracle
@@ -475,6 +476,17 @@ def cpu_baseline(seconds_target=15.0):
     t = time.perf_counter()
     oracle.run(f32, tgv.n, 100, oracle.omega_shear(oracle.lattice_viscosity(tgv.n, tgv.u0, tgv.re)), threads=threads)
     sec32 = time.perf_counter() - t
+    mlups256 = None
+    if large:
+        mixed = mc_inputs.WORKLOADS["mixed48_f32"]
+        g256 = mixed.groups[-1]
+        y256 = mc_inputs.draw_y(mixed.seed, mixed.m)[mixed.m - 1]
+        f256 = oracle.init_populations(g256.n, g256.u0, g256.amp, y256, g256.project)
+        t = time.perf_counter()
+        oracle.run(f256, g256.n, 1, oracle.omega_shear(oracle.lattice_viscosity(g256.n, g256.u0, g256.re)),
+                   threads=threads)
+        mlups256 = round(g256.n ** 3 / (time.perf_counter() - t) / 1e6, 3)
+        del f256
     model = "unknown"
     try:
         with open("/proc/cpuinfo") as fh:
@@ -485,7 +497,8 @@ def cpu_baseline(seconds_target=15.0):
             "sample": f"1 RTGV sample at {g.n}^3 of the 64x64^3 workload, {steps} steps, FP64 moment-space "
                       f"KBC collision, two-lattice pull streaming ({sec:.1f} s)",
             "single_core_MLUPS": round(g.n ** 3 * 2 / one / 1e6, 3),
-            "tgv32_f64_100_steps_MLUPS": round(tgv.n ** 3 * 100 / sec32 / 1e6, 3), "cpu_model": model}
+            "tgv32_f64_100_steps_MLUPS": round(tgv.n ** 3 * 100 / sec32 / 1e6, 3),
+            "rtgv256_one_sample_one_step_MLUPS": mlups256, "cpu_model": model}
 
 
 def main():

@@ -20,7 +20,7 @@ def test_more_than_one_gpu_is_refused():
 def test_cpu_baseline_times_the_oracle():
     sys.path.insert(0, ROOT)
     import bench
-    out = bench.cpu_baseline(seconds_target=0.5)
+    out = bench.cpu_baseline(seconds_target=0.5, large=False)
     assert out["kind"] == "oracle" and out["unit"] == "MLUPS" and out["value"] > 0
     assert out["cores"] == len(os.sched_getaffinity(0)) and out["single_core_MLUPS"] > 0
     assert "64^3" in out["sample"] and isinstance(out["cpu_model"], str) and out["tgv32_f64_100_steps_MLUPS"] > 0
