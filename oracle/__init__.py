@@ -66,10 +66,11 @@ def lib():
         L.oracle_moment_basis.argtypes = [_q, _dp, _dp, _ip]
         L.oracle_equilibrium.argtypes = [_q, ctypes.c_double, _dp, _dp]
         L.oracle_collide.argtypes = [_q, _dp, ctypes.c_double, ctypes.c_int32, _dp, _dp, _dp, _dp]
-        L.oracle_collide_z.argtypes = [_q, _dp, ctypes.c_double, _dp, _dp]
+        L.oracle_collide_z.argtypes = [_q, _dp, ctypes.c_double, ctypes.c_int32, _dp, _dp]
         L.oracle_run.argtypes = [_q, ctypes.c_int32, ctypes.c_int32, ctypes.c_double, ctypes.c_int32, _dp, _dp,
                                  ctypes.c_int32]
-        L.oracle_run_z.argtypes = [_q, ctypes.c_int32, ctypes.c_int32, ctypes.c_double, _dp, ctypes.c_int32]
+        L.oracle_run_z.argtypes = [_q, ctypes.c_int32, ctypes.c_int32, ctypes.c_double, ctypes.c_int32, _dp,
+                                   ctypes.c_int32]
         L.oracle_init_field.argtypes = [_q, ctypes.c_int64, _dp, _dp]
         L.oracle_init_field_z.argtypes = [_q, ctypes.c_int64, _dp, _dp]
         for name in ("oracle_velocity_set", "oracle_moment_basis", "oracle_equilibrium", "oracle_collide",
@@ -131,12 +132,15 @@ def collide(f, omega, mode=MODE_KBC):
     return fs, float(g[0]), ds, dh
 
 
-def collide_complex(f, omega):
+def collide_complex(f, omega, mode=MODE_KBC):
+    """collide() in complex arithmetic (complex steps): closed-form or exact
+    stabiliser. Returns (f*, gamma)."""
+    assert mode in (MODE_KBC, MODE_EXACT)
     f = np.ascontiguousarray(f, dtype=np.complex128)
     q = _lat(f.shape[0])
     fs = np.zeros(q, dtype=np.complex128)
     g = np.zeros(1, dtype=np.complex128)
-    _ok(lib().oracle_collide_z(q, _ptr(f), float(omega), _ptr(fs), _ptr(g)))
+    _ok(lib().oracle_collide_z(q, _ptr(f), float(omega), int(mode), _ptr(fs), _ptr(g)))
     return fs, g[0]
 
 
@@ -247,8 +251,8 @@ def run(f, n, steps, omega, mode=MODE_KBC, threads=0, gamma_stats=False):
     assert f.shape == (n ** 3, q) and f.flags.c_contiguous
     gs = np.zeros((max(steps, 1), 3)) if gamma_stats else None
     if np.iscomplexobj(f):
-        assert mode == MODE_KBC
-        _ok(lib().oracle_run_z(q, n, steps, float(omega), _ptr(f), int(threads)))
+        assert mode in (MODE_KBC, MODE_EXACT) and not gamma_stats
+        _ok(lib().oracle_run_z(q, n, steps, float(omega), int(mode), _ptr(f), int(threads)))
     else:
         _ok(lib().oracle_run(q, n, steps, float(omega), int(mode), _ptr(f), _ptr(gs) if gs is not None else None,
                              int(threads)))
@@ -284,8 +288,10 @@ def reductions(f, n):
 
 
 # ---------------------------------------------------------------- gradient reference
-def ke_gradient_complex_step(n, u0, re, amp, y, project, steps, h=1e-30, threads=0, params=None, q=27):
-    """d KE(T) / d Y_p for one sample by the complex step Im KE(Y + i h e_p) / h."""
+def ke_gradient_complex_step(n, u0, re, amp, y, project, steps, h=1e-30, threads=0, params=None, q=27,
+                             mode=MODE_KBC):
+    """d KE(T) / d Y_p for one sample by the complex step Im KE(Y + i h e_p) / h
+    (closed-form or exact stabiliser)."""
     omega = omega_shear(lattice_viscosity(n, u0, re))
     params = range(24) if params is None else params
     grad = np.zeros(24)
@@ -293,16 +299,16 @@ def ke_gradient_complex_step(n, u0, re, amp, y, project, steps, h=1e-30, threads
         yc = np.asarray(y, dtype=np.complex128).copy()
         yc[p] += 1j * h
         f = init_populations(n, u0, amp, yc, project, q)
-        run(f, n, steps, omega, threads=threads)
+        run(f, n, steps, omega, mode=mode, threads=threads)
         _, u = moments(f, n)
         grad[p] = kinetic_energy(u).imag / h
     return grad
 
 
-def ke_after(n, u0, re, amp, y, project, steps, threads=0, q=27):
+def ke_after(n, u0, re, amp, y, project, steps, threads=0, q=27, mode=MODE_KBC):
     omega = omega_shear(lattice_viscosity(n, u0, re))
     f = init_populations(n, u0, amp, np.asarray(y, dtype=np.float64), project, q)
-    run(f, n, steps, omega, threads=threads)
+    run(f, n, steps, omega, mode=mode, threads=threads)
     _, u = moments(f, n)
     return float(kinetic_energy(u))
 

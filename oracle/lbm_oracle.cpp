@@ -40,7 +40,8 @@
 //
 // Scalar type: double, or std::complex<double> for complex-step derivatives
 // (every operation below is analytic in the populations; the threshold test
-// looks at the real part only).
+// looks at the real part only; the exact stabiliser's root is carried into
+// complex arithmetic by Newton steps, see collide).
 //
 // State layout at this interface: f[cell][i], cell = (z*n + y)*n + x. D3Q27:
 // i = 9*(cx+1) + 3*(cy+1) + (cz+1). D3Q19: the same order with the eight
@@ -258,7 +259,7 @@ double exact_entropic_gamma(const double f[Q], const double ds[Q], const double 
 // One KBC collision at one node.
 // mode 0: closed-form gamma (eq. entropyControl)
 // mode 1: gamma forced to 2 (BGK)
-// mode 2: exact entropic gamma (real scalar only)
+// mode 2: exact entropic gamma (complex scalars: see the complex step below)
 template <int Q, class T>
 void collide(const T f[Q], double omega, int mode, T fstar[Q], T* gamma_out, T ds_out[Q], T dh_out[Q]) {
   const MomentBasis<Q>& mb = basis<Q>();
@@ -293,10 +294,36 @@ void collide(const T f[Q], double omega, int mode, T fstar[Q], T* gamma_out, T d
   } else if (mode == 2) {
     // the same threshold as the closed form: with <dh|dh> <= 1e-30 the
     // H-function does not depend on gamma beyond rounding, and gamma = 2
-    if constexpr (std::is_same<T, double>::value) {
-      double hh = 0.0;
-      for (int i = 0; i < Q; ++i) hh += dh[i] * dh[i] / feq[i];
-      if (hh > 1e-30) gamma = exact_entropic_gamma<Q>(f, ds, dh, omega);
+    double hh = 0.0;
+    for (int i = 0; i < Q; ++i) hh += re(dh[i]) * re(dh[i]) / re(feq[i]);
+    if (hh > 1e-30) {
+      if constexpr (std::is_same<T, double>::value) {
+        gamma = exact_entropic_gamma<Q>(f, ds, dh, omega);
+      } else {
+        // Complex step: the minimiser of the real parts by the same bisection,
+        // then Newton steps on the stationarity condition dH/dt = 0 in complex
+        // arithmetic. At the real root each step leaves the real part in
+        // place and puts the first-order change of the root, -(dF/df . dv) /
+        // (dF/dt) (implicit function theorem), into the imaginary part.
+        const VelocitySet<Q>& v = vs<Q>();
+        double fr[Q], dsr[Q], dhr[Q];
+        for (int i = 0; i < Q; ++i) {
+          fr[i] = re(f[i]);
+          dsr[i] = re(ds[i]);
+          dhr[i] = re(dh[i]);
+        }
+        T t = 0.5 * omega * exact_entropic_gamma<Q>(fr, dsr, dhr, omega);
+        for (int it = 0; it < 3; ++it) {
+          T dH = 0.0, d2H = 0.0;
+          for (int i = 0; i < Q; ++i) {
+            const T fs = f[i] - omega * ds[i] - t * dh[i];
+            dH -= dh[i] * (std::log(fs / v.w[i]) + 1.0);
+            d2H += dh[i] * dh[i] / fs;
+          }
+          t = t - dH / d2H;
+        }
+        gamma = 2.0 * t / omega;
+      }
     }
   }
   // relaxation rates per group: kinematic 0, shear omega, hom omega*gamma/2
@@ -423,9 +450,10 @@ int32_t oracle_collide(int32_t q, const double* f, double omega, int32_t mode, d
   return with_lattice(q, [&](auto qc) { collide<decltype(qc)::value, double>(f, omega, mode, fstar, gamma, ds, dh); });
 }
 
-int32_t oracle_collide_z(int32_t q, const double* f_ri, double omega, double* fstar_ri, double* gamma_ri) {
+int32_t oracle_collide_z(int32_t q, const double* f_ri, double omega, int32_t mode, double* fstar_ri,
+                         double* gamma_ri) {
   return with_lattice(q, [&](auto qc) {
-    collide<decltype(qc)::value, cplx>(reinterpret_cast<const cplx*>(f_ri), omega, 0,
+    collide<decltype(qc)::value, cplx>(reinterpret_cast<const cplx*>(f_ri), omega, mode,
                                        reinterpret_cast<cplx*>(fstar_ri), reinterpret_cast<cplx*>(gamma_ri),
                                        nullptr, nullptr);
   });
@@ -441,13 +469,16 @@ int32_t oracle_run(int32_t q, int32_t n, int32_t steps, double omega, int32_t mo
   return with_lattice(q, [&](auto qc) { run<decltype(qc)::value, double>(n, steps, omega, mode, f, gamma_stats); });
 }
 
-// Same in complex arithmetic (interleaved re/im), closed-form gamma only.
-int32_t oracle_run_z(int32_t q, int32_t n, int32_t steps, double omega, double* f_ri, int32_t threads) {
+// Same in complex arithmetic (interleaved re/im) for complex-step derivatives:
+// mode 0 (closed-form gamma) or 2 (exact gamma, see collide).
+int32_t oracle_run_z(int32_t q, int32_t n, int32_t steps, double omega, int32_t mode, double* f_ri,
+                     int32_t threads) {
 #ifdef _OPENMP
   if (threads > 0) omp_set_num_threads(threads);
 #endif
+  if (mode != 0 && mode != 2) return 0;
   return with_lattice(q, [&](auto qc) {
-    run<decltype(qc)::value, cplx>(n, steps, omega, 0, reinterpret_cast<cplx*>(f_ri), nullptr);
+    run<decltype(qc)::value, cplx>(n, steps, omega, mode, reinterpret_cast<cplx*>(f_ri), nullptr);
   });
 }
 

@@ -14,10 +14,11 @@ int32_t oracle_moment_basis(int32_t q, double* M, double* Minv, int32_t* group);
 int32_t oracle_equilibrium(int32_t q, double rho, const double* u, double* feq);
 int32_t oracle_collide(int32_t q, const double* f, double omega, int32_t mode, double* fstar, double* gamma,
                        double* ds, double* dh);
-int32_t oracle_collide_z(int32_t q, const double* f_ri, double omega, double* fstar_ri, double* gamma_ri);
+int32_t oracle_collide_z(int32_t q, const double* f_ri, double omega, int32_t mode, double* fstar_ri,
+                         double* gamma_ri);
 int32_t oracle_run(int32_t q, int32_t n, int32_t steps, double omega, int32_t mode, double* f, double* gamma_stats,
                    int32_t threads);
-int32_t oracle_run_z(int32_t q, int32_t n, int32_t steps, double omega, double* f_ri, int32_t threads);
+int32_t oracle_run_z(int32_t q, int32_t n, int32_t steps, double omega, int32_t mode, double* f_ri, int32_t threads);
 int32_t oracle_init_field(int32_t q, int64_t ncell, const double* u, double* f);
 int32_t oracle_init_field_z(int32_t q, int64_t ncell, const double* u_ri, double* f_ri);
 int32_t oracle_max_threads(void);
@@ -56,7 +57,8 @@ int main() {
       fz[2 * i] = f[i];
       fz[2 * i + 1] = i == 3 ? 1e-30 : 0.0;
     }
-    expect(oracle_collide_z(q, fz.data(), omega, fsz.data(), gz.data()) != 0, "complex collide", q);
+    for (int mode : {0, 2})
+      expect(oracle_collide_z(q, fz.data(), omega, mode, fsz.data(), gz.data()) != 0, "complex collide", q);
     // a small lattice: fields, runs in every mode, complex run
     const int n = 8;
     const int64_t ncell = int64_t(n) * n * n;
@@ -71,7 +73,11 @@ int main() {
     std::vector<double> uz(2 * 3 * ncell, 0.0), fzf(2 * ncell * q);
     for (int64_t k = 0; k < 3 * ncell; ++k) uz[2 * k] = uf[k];
     expect(oracle_init_field_z(q, ncell, uz.data(), fzf.data()) != 0, "complex init field", q);
-    expect(oracle_run_z(q, n, 2, omega, fzf.data(), 2) != 0, "complex run", q);
+    for (int mode : {0, 2}) {
+      std::vector<double> gz2 = fzf;
+      expect(oracle_run_z(q, n, 2, omega, mode, gz2.data(), 2) != 0, "complex run", q);
+    }
+    expect(oracle_run_z(q, n, 1, omega, 1, fzf.data(), 2) == 0, "complex run rejects BGK mode", q);
   }
   expect(oracle_velocity_set(15, nullptr, nullptr) == 0, "unknown lattice", 15);
   expect(oracle_max_threads() >= 1, "threads", 0);

@@ -57,10 +57,16 @@ MUTANTS = [
      "bgk_special_cases"),
     ("post-collision state adds the relaxation", CPP, [("fstar[i] = f[i] - acc;", "fstar[i] = f[i] + acc;")],
      "bgk_special_cases"),
-    ("exact stabiliser: logarithm without the weight", CPP, [("std::log(fs / v.w[i])", "std::log(fs)")],
+    ("exact stabiliser: logarithm without the weight", CPP,
+     [("s += -dh[i] * (std::log(fs / v.w[i]) + 1.0);", "s += -dh[i] * (std::log(fs) + 1.0);")],
      "exact_entropic_gamma"),
     ("exact stabiliser: t returned as gamma", CPP,
      [("return 2.0 * (0.5 * (lo + hi)) / omega;", "return (0.5 * (lo + hi)) / omega;")], "exact_entropic_gamma"),
+    ("exact stabiliser, complex step: Newton curvature with one dh", CPP,
+     [("d2H += dh[i] * dh[i] / fs;", "d2H += dh[i] / fs;")], "complex_step_through"),
+    ("exact stabiliser, complex step: logarithm without the weight", CPP,
+     [("dH -= dh[i] * (std::log(fs / v.w[i]) + 1.0);", "dH -= dh[i] * (std::log(fs) + 1.0);")],
+     "complex_step_through"),
     ("time loop does not keep the new state", CPP, [("std::memcpy(f, tmp.data(), sizeof(T) * len);", "")],
      "streaming_is_a_permutation"),
     # ---- streaming and initial populations (C++)

@@ -569,6 +569,49 @@ def test_complex_step_matches_central_differences(q):
         assert abs(fd - g[p]) <= 1e-6 * abs(g).max() + 1e-14
 
 
+@LATTICES
+def test_complex_step_through_the_exact_stabiliser(q):
+    """The exact stabiliser in complex arithmetic (the real minimiser by
+    bisection, then Newton steps on dH/dt = 0 in complex numbers) gives the
+    derivative of the collision: its complex step equals the central
+    differences of the real bisection-only collision, which converge to it
+    like the square of the difference step. Then the same through a few
+    steps of a small lattice."""
+    rng = np.random.default_rng(31)
+    _, w = oracle.velocity_set(q)
+    h = 1e-30
+    for _ in range(4):
+        u = rng.uniform(-0.06, 0.06, 3)
+        f = oracle.equilibrium(1.0 + rng.uniform(-0.02, 0.02), u, q) * (1 + rng.uniform(-3e-2, 3e-2, q))
+        v = rng.normal(size=q)
+        om = rng.uniform(1.5, 1.99)
+        fz, gz = oracle.collide_complex(f + 1j * h * v, om, oracle.MODE_EXACT)
+        fr, gr, *_ = oracle.collide(f, om, oracle.MODE_EXACT)
+        assert np.max(np.abs(fz.real - fr)) < 1e-16 and abs(gz.real - gr) < 1e-13
+        errs = []
+        for eps in (1e-5, 1e-6, 1e-7):
+            fp, gp, *_ = oracle.collide(f + eps * v, om, oracle.MODE_EXACT)
+            fm, gm, *_ = oracle.collide(f - eps * v, om, oracle.MODE_EXACT)
+            errs.append(max(abs(gz.imag / h - (gp - gm) / (2 * eps)) / abs(gz.imag / h),
+                            np.max(np.abs(fz.imag / h - (fp - fm) / (2 * eps))) / np.max(np.abs(fz.imag / h))))
+        assert errs[1] < 1e-3 and errs[2] < 1e-5, errs
+        assert errs[0] > 50 * errs[1], errs      # second order in the difference step
+    n, steps = 8, 4
+    y = mc_inputs.draw_y(4, 1)[0]
+    args = (n, 0.05, 100.0, 0.5)
+    g = oracle.ke_gradient_complex_step(*args, y, True, steps, params=[2, 17], q=q, mode=oracle.MODE_EXACT)
+    gk = oracle.ke_gradient_complex_step(*args, y, True, steps, params=[2, 17], q=q)
+    dh = 1e-4
+    for p in (2, 17):
+        yp, ym = y.copy(), y.copy()
+        yp[p] += dh
+        ym[p] -= dh
+        fd = (oracle.ke_after(*args, yp, True, steps, q=q, mode=oracle.MODE_EXACT) -
+              oracle.ke_after(*args, ym, True, steps, q=q, mode=oracle.MODE_EXACT)) / (2 * dh)
+        assert abs(fd - g[p]) <= 1e-6 * abs(g).max() + 1e-14
+    assert np.max(np.abs(g - gk)) > 0.0   # the stabiliser differs from the closed form
+
+
 # ---------------------------------------------------------------- observables
 def test_spectrum_of_taylor_green_sits_in_shell_two():
     n = 16
