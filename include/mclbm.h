@@ -198,8 +198,13 @@ mclbm_status mclbm_restore(mclbm_ctx* ctx, const void* src_dev, size_t bytes);
  *     ke_dev[m] = KE_m(T) (device, may be NULL), recomputing each segment
  *     of ckpt_every steps from its checkpoint into work_dev.
  * Sizes come from mclbm_ckpt_bytes / mclbm_backward_work_bytes. The state
- * after backward is the forward state at T. Not available with the exact
- * stabiliser (MCLBM_ERR_UNSUPPORTED). */
+ * after backward is the forward state at T. Both stabilisers: with the exact
+ * one (mclbm_set_stabiliser) each reverse step recomputes the forward t and
+ * differentiates it through its stationarity condition (implicit function
+ * theorem), FP64 states only: near equilibrium the exact minimiser moves f*
+ * by an amount that does not vanish with dh (the third-order part of
+ * ln(f^eq / w) along dh), so its derivative grows like 1/|dh|, and FP32
+ * rounding of dh there makes it meaningless (MCLBM_ERR_UNSUPPORTED). */
 size_t mclbm_ckpt_bytes(const mclbm_ctx* ctx, int64_t ticks, int32_t ckpt_every);
 size_t mclbm_backward_work_bytes(const mclbm_ctx* ctx, int32_t ckpt_every);
 mclbm_status mclbm_forward_ckpt(mclbm_ctx* ctx, int64_t ticks, int32_t ckpt_every, void* ckpt_dev,
@@ -331,9 +336,9 @@ mclbm_status mclbm_dissipation(mclbm_ctx* ctx, const double* records_dev, int32_
  * FP32 or 1e-8 in FP64 (at most four), so the records report the exact
  * gamma. The exact mode
  * runs 256-thread blocks only (mclbm_set_launch accepts no other size then,
- * mclbm_autotune returns MCLBM_ERR_UNSUPPORTED) and has no adjoint
- * (mclbm_forward_ckpt and mclbm_backward return MCLBM_ERR_UNSUPPORTED).
- * Captured graphs are dropped. MCLBM_ERR_ARG for any other mode. */
+ * mclbm_autotune returns MCLBM_ERR_UNSUPPORTED); mclbm_forward_ckpt and
+ * mclbm_backward differentiate it in FP64. Captured graphs are dropped.
+ * MCLBM_ERR_ARG for any other mode. */
 mclbm_status mclbm_set_stabiliser(mclbm_ctx* ctx, int32_t mode);
 
 /* Launch shape of the collide-and-stream kernel, one for the whole ensemble

@@ -795,7 +795,10 @@ static mclbm_status check_adjoint(mclbm_ctx* c, int64_t ticks, int32_t ckpt_ever
   if (ticks < 1 || ckpt_every < 1) return fail(MCLBM_ERR_ARG, "ticks and ckpt_every must be >= 1");
   for (int s = 0; s < c->m; ++s)
     if (c->desc[s].stride != 1) return fail(MCLBM_ERR_UNSUPPORTED, "the adjoint needs every stride to be 1");
-  if (c->exact_gamma) return fail(MCLBM_ERR_UNSUPPORTED, "the adjoint is built for the closed-form stabiliser");
+  // The exact minimiser's derivative grows like 1/|dh| near equilibrium (its
+  // change of f* does not vanish with dh), and in FP32 dh is rounding there.
+  if (c->exact_gamma && c->precision != MCLBM_FP64)
+    return fail(MCLBM_ERR_UNSUPPORTED, "the adjoint of the exact stabiliser is built for FP64 states");
   return MCLBM_OK;
 }
 
@@ -878,7 +881,7 @@ mclbm_status mclbm_backward(mclbm_ctx* c, int64_t ticks, int32_t ckpt_every, con
     }
     for (int64_t n = n1 - 1; n >= n0; --n) {
       HIP_TRY(launch_adjoint_step(c->q, c->precision, state_at(n), lam[cur], lam[1 - cur], c->d_samples, table_ptr(c, nat),
-                                  nat->nseg, nat->total_blocks, buffer_ok, c->stream));
+                                  nat->nseg, nat->total_blocks, buffer_ok, c->exact_gamma, c->stream));
       cur = 1 - cur;
     }
   }

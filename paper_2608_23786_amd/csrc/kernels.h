@@ -71,7 +71,7 @@ hipError_t launch_adjoint_seed(int q, int precision, const void* pop, void* lam,
                                const Seg* segs, int32_t nseg, int32_t total_blocks, double inv_m, hipStream_t s);
 hipError_t launch_adjoint_step(int q, int precision, const void* state, const void* lam_in, void* lam_out,
                                const DevSample* samples, const Seg* segs, int32_t nseg, int32_t total_blocks,
-                               int32_t buffer_ok, hipStream_t s);
+                               int32_t buffer_ok, int32_t exact_gamma, hipStream_t s);
 hipError_t launch_init_adjoint(int q, int precision, const void* lam, const DevSample* samples, const Seg* segs,
                                int32_t nseg, int32_t total_blocks, const double* ycoef, double* partials,
                                hipStream_t s);

@@ -230,7 +230,12 @@ __global__ void __launch_bounds__(256) adjoint_seed_kernel(const T* pop, T* lam,
 
 // One reverse step: lambda_n(x) = (d collide / d g_n(x))^T [lambda_{n+1, i}(x + c_i)]_i,
 // the transpose of "collide at x, then move population i to x + c_i".
-template <int QN, typename T, bool BUF>
+// EXACT: the collision with the exact stabiliser of eq. (kbc_entropy), whose
+// t = omega gamma / 2 is the root of F(t) = sum_i dh_i ln(f*_i / w_i) with
+// f*_i = w_i + g_i - omega ds_i - t dh_i; by the implicit function theorem
+// dt = (dF at fixed t) / D, D = sum_i dh_i^2 / f*_i, so the adjoint of t
+// reaches F's inputs (dh, ds and g directly) with weight tbar / D.
+template <int QN, typename T, bool BUF, bool EXACT>
 __global__ void __launch_bounds__(256) adjoint_step_kernel(const T* state, const T* lam_in, T* lam_out,
                                                            const DevSample* samples, const Seg* segs, int nseg) {
   const int b = blockIdx.x;
@@ -290,7 +295,18 @@ __global__ void __launch_bounds__(256) adjoint_step_kernel(const T* state, const
   const bool active = B > T(1e-30);
   T gamma = T(2);
   if (active) gamma = rp.two_over_omega - rp.kappa * (A / B);
-  const T t = T(0.5) * rp.omega * gamma;
+  T t = T(0.5) * rp.omega * gamma;
+  if constexpr (EXACT) {
+    // the forward collision's t, from the same start and with the same steps
+    if (active) {
+      T ge[Q];
+      for_vel<QN>([&](auto ic) {
+        constexpr int i = decltype(ic)::value;
+        ge[i] = geq<QN, i>(m);
+      });
+      t = exact_entropic_t<QN>(ge, fneq, s, rp.omega, t);
+    }
+  }
 
   // reverse sweep. ga: adjoint of g (direct path g* = g - ...)
   T tbar = T(0);
@@ -299,34 +315,68 @@ __global__ void __launch_bounds__(256) adjoint_step_kernel(const T* state, const
     if constexpr (nonzeros(i) == 1 || nonzeros(i) == 2) tbar -= nu[i] * (fneq[i] - shear_part<i>(s));
     else tbar -= nu[i] * fneq[i];
   });
-  T Abar = T(0), Bbar = T(0);
+  T Abar = T(0), Bbar = T(0), Fbar = T(0);
   if (active) {
-    const T gbar = T(0.5) * rp.omega * tbar;
-    Abar = -rp.kappa * gbar / B;
-    Bbar = rp.kappa * gbar * (A / B) / B;  // B * B would underflow in float
+    if constexpr (EXACT) {
+      T d = T(0);
+      for_vel<QN>([&](auto ic) {
+        constexpr int i = decltype(ic)::value;
+        T ds = T(0);
+        if constexpr (nonzeros(i) == 1 || nonzeros(i) == 2) ds = shear_part<i>(s);
+        const T dh = fneq[i] - ds;
+        const T gs = geq<QN, i>(m) + (fneq[i] - rp.omega * ds) - t * dh;  // f*_i - w_i
+        d += dh * dh * recip(T(weight<QN>(i)) + gs);
+      });
+      Fbar = tbar / d;
+    } else {
+      const T gbar = T(0.5) * rp.omega * tbar;
+      Abar = -rp.kappa * gbar / B;
+      Bbar = rp.kappa * gbar * (A / B) / B;  // B * B would underflow in float
+    }
   }
   // adjoints of fneq (through dh and the weights) and of the shear coefficients
   T fbar[Q], geqbar[Q];
   T dsxb = T(0), dsyb = T(0), dszb = T(0), exyb = T(0), exzb = T(0), eyzb = T(0);
   for_vel<QN>([&](auto ic) {
     constexpr int i = decltype(ic)::value;
-    const T r = recip(T(weight<QN>(i)) + geq<QN, i>(m));
-    T dsb, dhb, rbar;
-    T ds = T(0), dh;
-    if constexpr (nonzeros(i) == 1 || nonzeros(i) == 2) {
-      ds = shear_part<i>(s);
-      dh = fneq[i] - ds;
-      dsb = -rp.omega * nu[i] + Abar * dh * r;
-      dhb = -t * nu[i] + Abar * ds * r + T(2) * Bbar * dh * r;
-      rbar = Abar * ds * dh + Bbar * dh * dh;
+    T dsb, dhb;
+    if constexpr (EXACT) {
+      // dF = sum_i [ln(f*_i / w_i) - t dh_i / f*_i] d(dh_i) - omega dh_i / f*_i d(ds_i)
+      //      + dh_i / f*_i d(g_i), with g_i = g^eq_i + fneq_i
+      T ds = T(0);
+      if constexpr (nonzeros(i) == 1 || nonzeros(i) == 2) ds = shear_part<i>(s);
+      const T dh = fneq[i] - ds;
+      T x = T(0), lg = T(0);
+      if (active) {
+        constexpr double w = weight<QN>(i);
+        const T gs = geq<QN, i>(m) + (fneq[i] - rp.omega * ds) - t * dh;
+        x = Fbar * dh * recip(T(w) + gs);
+        lg = Fbar * log1p_acc(gs * T(1.0 / w));
+      }
+      if constexpr (nonzeros(i) == 1 || nonzeros(i) == 2) dsb = -rp.omega * nu[i] - rp.omega * x;
+      else dsb = T(0);
+      dhb = -t * nu[i] + lg - t * x;
+      geqbar[i] = x;
+      fbar[i] = dhb + x;
     } else {
-      dh = fneq[i];
-      dsb = T(0);
-      dhb = -t * nu[i] + T(2) * Bbar * dh * r;
-      rbar = Bbar * dh * dh;
+      const T r = recip(T(weight<QN>(i)) + geq<QN, i>(m));
+      T rbar;
+      T ds = T(0), dh;
+      if constexpr (nonzeros(i) == 1 || nonzeros(i) == 2) {
+        ds = shear_part<i>(s);
+        dh = fneq[i] - ds;
+        dsb = -rp.omega * nu[i] + Abar * dh * r;
+        dhb = -t * nu[i] + Abar * ds * r + T(2) * Bbar * dh * r;
+        rbar = Abar * ds * dh + Bbar * dh * dh;
+      } else {
+        dh = fneq[i];
+        dsb = T(0);
+        dhb = -t * nu[i] + T(2) * Bbar * dh * r;
+        rbar = Bbar * dh * dh;
+      }
+      geqbar[i] = -rbar * r * r;  // through f^eq = w + g^eq
+      fbar[i] = dhb;              // dh = fneq - ds
     }
-    geqbar[i] = -rbar * r * r;  // through f^eq = w + g^eq
-    fbar[i] = dhb;              // dh = fneq - ds
     dsb -= dhb;
     if constexpr (nonzeros(i) == 1) {
       if constexpr (cx(i) != 0) dsxb += dsb;
@@ -609,19 +659,26 @@ hipError_t launch_adjoint_seed(int q, int precision, const void* pop, void* lam,
 
 hipError_t launch_adjoint_step(int q, int precision, const void* state, const void* lam_in, void* lam_out,
                                const DevSample* samples, const Seg* segs, int32_t nseg, int32_t total_blocks,
-                               int32_t buffer_ok, hipStream_t s) {
+                               int32_t buffer_ok, int32_t exact_gamma, hipStream_t s) {
   return dispatch(q, precision, [&](auto qc, auto tc) {
     constexpr int QN = decltype(qc)::value;
     using T = decltype(tc);
     const T* a = static_cast<const T*>(state);
     const T* b = static_cast<const T*>(lam_in);
     T* o = static_cast<T*>(lam_out);
-    if (buffer_ok)
-      hipLaunchKernelGGL((adjoint_step_kernel<QN, T, true>), dim3(total_blocks), dim3(256), 0, s, a, b, o, samples,
-                         segs, nseg);
-    else
-      hipLaunchKernelGGL((adjoint_step_kernel<QN, T, false>), dim3(total_blocks), dim3(256), 0, s, a, b, o, samples,
-                         segs, nseg);
+    const dim3 grid(total_blocks), blk(256);
+    if (exact_gamma) {
+      // FP64 only (the host refuses FP32): see mclbm_backward
+      if constexpr (!std::is_same<T, double>::value) return hipErrorInvalidValue;
+      else if (buffer_ok)
+        hipLaunchKernelGGL((adjoint_step_kernel<QN, T, true, true>), grid, blk, 0, s, a, b, o, samples, segs, nseg);
+      else
+        hipLaunchKernelGGL((adjoint_step_kernel<QN, T, false, true>), grid, blk, 0, s, a, b, o, samples, segs, nseg);
+    } else if (buffer_ok) {
+      hipLaunchKernelGGL((adjoint_step_kernel<QN, T, true, false>), grid, blk, 0, s, a, b, o, samples, segs, nseg);
+    } else {
+      hipLaunchKernelGGL((adjoint_step_kernel<QN, T, false, false>), grid, blk, 0, s, a, b, o, samples, segs, nseg);
+    }
     return hipGetLastError();
   });
 }

@@ -163,7 +163,7 @@ hipError_t launch_step_k(StepKind kind, const StepLaunch& L, hipStream_t s) {
       case kStep: return launch_step_exact<QN, T, kStep>(L, s);
       case kStepRecord: return launch_step_exact<QN, T, kStepRecord>(L, s);
       case kReduceOnly: return launch_step_exact<QN, T, kReduceOnly>(L, s);
-      default: return hipErrorInvalidValue;
+      case kPush: return launch_step_exact<QN, T, kPush>(L, s);
     }
   }
   switch (kind) {

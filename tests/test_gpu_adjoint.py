@@ -24,21 +24,23 @@ mc = pytest.importorskip("paper_2608_23786_amd")
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
 
-def gpu_gradient(samples, precision, y, steps, every):
+def gpu_gradient(samples, precision, y, steps, every, stabiliser="closed_form"):
     ens = mc.Ensemble(samples, precision)
     ens.init(0, torch.from_numpy(y))
+    ens.set_stabiliser(stabiliser)
     ck = ens.forward_ckpt(steps, every)
     dj, ke = ens.backward(steps, every, ck)
     return dj.cpu().numpy(), ke.cpu().numpy(), ens
 
 
-def oracle_gradient(samples, y, steps):
+def oracle_gradient(samples, y, steps, mode=oracle.MODE_KBC, params=None):
     m = len(samples)
     g = np.zeros((m, 24))
     ke = np.zeros(m)
     for s, smp in enumerate(samples):
-        g[s] = oracle.ke_gradient_complex_step(smp.n, smp.u0, smp.re, smp.amp, y[s], smp.project, steps) / m
-        ke[s] = oracle.ke_after(smp.n, smp.u0, smp.re, smp.amp, y[s], smp.project, steps)
+        g[s] = oracle.ke_gradient_complex_step(smp.n, smp.u0, smp.re, smp.amp, y[s], smp.project, steps,
+                                               params=params, mode=mode) / m
+        ke[s] = oracle.ke_after(smp.n, smp.u0, smp.re, smp.amp, y[s], smp.project, steps, mode=mode)
     return g, ke
 
 
@@ -115,6 +117,70 @@ def test_central_differences_at_128_cubed():
         fd = (J(yp) - J(ym)) / (2 * h)
         print(f"p={p}: fd {fd:.6e} adjoint {dj[0, p]:.6e}")
         assert abs(fd - dj[0, p]) <= 1e-6 * np.max(np.abs(dj)), (p, fd, dj[0, p])
+
+
+# ---------------------------------------------------------------- exact stabiliser
+# The reverse step recomputes the forward t (the minimiser of the discrete
+# H-function, eq. (kbc_entropy)) and differentiates it through dH/dt = 0.
+# The oracle's complex step goes through its bisection root and Newton steps
+# in complex arithmetic, a different route to the same derivative.
+
+@pytest.mark.parametrize("steps,every", [(12, 5), (7, 1)])
+def test_exact_stabiliser_fp64_adjoint_matches_complex_step(steps, every):
+    """FP64; tolerance 1e-7 of max|dJ/dY|: the GPU's Newton stops at a
+    step below 1e-8 of t (quadratic convergence leaves the root at rounding
+    level), the rest as for the closed form."""
+    samples = [mc.Sample(8, 0.05, 100.0, 0.5, True), mc.Sample(8, 0.04, 60.0, 0.5, False)]
+    y = mc_inputs.draw_y(41, 2)
+    dj, ke, _ = gpu_gradient(samples, "f64", y, steps, every, "exact")
+    g, ke_o = oracle_gradient(samples, y, steps, oracle.MODE_EXACT)
+    gk, _ = oracle_gradient(samples, y, steps)
+    err = np.max(np.abs(dj - g)) / np.max(np.abs(g))
+    gap = np.max(np.abs(gk - g)) / np.max(np.abs(g))
+    print(f"exact stabiliser, steps {steps} every {every}: adjoint vs complex step {err:.3e} "
+          f"(closed-form gradient differs by {gap:.3e})")
+    assert err < 1e-7 and gap > 100 * err
+    assert np.max(np.abs(ke - ke_o) / ke_o) < 1e-12
+
+
+def test_exact_stabiliser_adjoint_is_fp64_only():
+    """Near equilibrium the exact minimiser's change of f* does not vanish
+    with dh (an oracle pin shows it), so its derivative grows like 1/|dh|;
+    FP32 rounding of dh makes that derivative noise, and the library refuses
+    the FP32 adjoint with the exact stabiliser."""
+    samples = [mc.Sample(16, 0.05, 200.0, 0.2, True)]
+    ens = mc.Ensemble(samples, "f32s")
+    ens.init(0, torch.from_numpy(mc_inputs.draw_y(42, 1)))
+    ens.set_stabiliser("exact")
+    with pytest.raises(mc.MclbmError, match="ERR_UNSUPPORTED"):
+        ens.forward_ckpt(4, 2)
+    ens.set_stabiliser("closed_form")
+    ck = ens.forward_ckpt(4, 2)
+    dj, _ = ens.backward(4, 2, ck)
+    assert torch.isfinite(dj).all()
+
+
+def test_exact_stabiliser_central_differences_of_gpu_forward():
+    """Central differences (h = 1e-3 on Y) of the GPU FP64 forward with the
+    exact stabiliser, over both AA parities and three checkpoint segments."""
+    samples = [mc.Sample(16, 0.05, 200.0, 0.3, True), mc.Sample(16, 0.05, 200.0, 0.3, False)]
+    steps, h = 30, 1e-3
+    y = mc_inputs.draw_y(43, 2)
+    dj, _, _ = gpu_gradient(samples, "f64", y, steps, 10, "exact")
+
+    def J(yy):
+        ens = mc.Ensemble(samples, "f64")
+        ens.init(0, torch.from_numpy(yy))
+        ens.set_stabiliser("exact")
+        ens.step(steps)
+        return float(ens.reduce()[:, 4].mean())
+
+    for s, p in ((0, 2), (0, 13), (1, 7), (1, 20)):
+        yp, ym = y.copy(), y.copy()
+        yp[s, p] += h
+        ym[s, p] -= h
+        fd = (J(yp) - J(ym)) / (2 * h)
+        assert abs(fd - dj[s, p]) <= 1e-6 * np.max(np.abs(dj)), (s, p, fd, dj[s, p])
 
 
 def test_projected_gradient_lies_in_the_range_of_the_projection():

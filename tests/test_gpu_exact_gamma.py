@@ -120,11 +120,19 @@ def test_mode_switch_and_unsupported_combinations():
         ens.set_launch(512, 0, 1, 1)
     with pytest.raises(mc.MclbmError, match="ERR_UNSUPPORTED"):
         ens.autotune(reps=1)
+    # the adjoint follows the stabiliser in FP64 (its parity is in
+    # test_gpu_adjoint) and is refused in FP32
     ens2 = mc.Ensemble(samples, "f32s")
     ens2.init(0, y)
     ens2.set_stabiliser("exact")
     with pytest.raises(mc.MclbmError, match="ERR_UNSUPPORTED"):
         ens2.forward_ckpt(4, 2)
+    e64 = mc.Ensemble(samples, "f64")
+    e64.init(0, y)
+    e64.set_stabiliser("exact")
+    ck = e64.forward_ckpt(4, 2)
+    dj, _ = e64.backward(4, 2, ck)
+    assert torch.isfinite(dj).all() and float(dj.abs().max()) > 0.0
     # back to the closed form: the same kernels as a closed-form ensemble
     ens3 = mc.Ensemble(samples, "f32s")
     ens3.init(0, y)

@@ -612,6 +612,32 @@ def test_complex_step_through_the_exact_stabiliser(q):
     assert np.max(np.abs(g - gk)) > 0.0   # the stabiliser differs from the closed form
 
 
+def test_exact_stabiliser_change_does_not_vanish_near_equilibrium():
+    """With the second-order equilibrium, ln(f^eq_i / w_i) = 3 c_i.u - 1.5 |u|^2
+    + O(u^3) (the quadratic terms cancel), and dh has no mass or momentum, so
+    the root of sum_i dh_i ln(f*_i / w_i) sits where t dh balances the
+    third-order part: along f = f^eq + eps d (d in the hom group) the exact
+    minimiser moves f* away from the closed form by an amount independent of
+    eps, and gamma grows like 1/eps. Its derivative therefore grows without
+    bound near equilibrium."""
+    rng = np.random.default_rng(3)
+    M, Minv, grp = oracle.moment_basis(27)
+    u = np.array([0.04, -0.03, 0.02])
+    feq = oracle.equilibrium(1.0, u, 27)
+    m = M @ rng.normal(size=27)
+    m[grp != 2] = 0.0
+    d = Minv @ m
+    gaps, gammas = [], []
+    for eps in (1e-5, 1e-7, 1e-9, 1e-11):
+        fe, ge, *_ = oracle.collide(feq + eps * d, 1.9, oracle.MODE_EXACT)
+        fk, _, *_ = oracle.collide(feq + eps * d, 1.9, oracle.MODE_KBC)
+        gaps.append(np.max(np.abs(fe - fk)))
+        gammas.append(ge * eps)
+    assert 1e-7 < gaps[0] < 1e-4   # third order in u ~ 0.04
+    assert max(gaps) / min(gaps) < 1.01
+    assert abs(gammas[3] / gammas[2] - 1) < 1e-2   # gamma ~ 1/eps once it dominates the O(1) part
+
+
 # ---------------------------------------------------------------- observables
 def test_spectrum_of_taylor_green_sits_in_shell_two():
     n = 16
