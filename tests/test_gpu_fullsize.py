@@ -103,6 +103,29 @@ def test_rtgv64x64_full_size_sampled_steps_and_invariants():
     assert np.all(allrec[1:, :, 7] > 0.5) and np.all(allrec[1:, :, 7] < 2.5)
 
 
+def test_rtgv64x64_full_size_whole_fields_after_50_steps():
+    """The 64 x 64^3 ensemble as the benchmark runs it (autotuned launch
+    shape, graph-captured ticks, FP64 records fused every 50) over one save
+    interval: the whole velocity field of four samples spread over the batch
+    against the oracle, relative L2 of u <= 1e-5 (the FP32 target)."""
+    wl, ens = full_ensemble("rtgv64x64_f32")
+    g = wl.groups[0]
+    shape = ens.autotune(reps=1)
+    assert ens.ticks == 0
+    rec = ens.step(50, record_every=50)
+    assert rec.shape[0] == 1 and ens.check() == -1
+    y = mc_inputs.draw_y(wl.seed, g.count)
+    om = oracle.omega_shear(oracle.lattice_viscosity(g.n, g.u0, g.re))
+    for s in (0, 21, 42, 63):
+        _, u_g = (t.cpu().numpy() for t in ens.moments(s))
+        f = oracle.init_populations(g.n, g.u0, g.amp, y[s], g.project)
+        oracle.run(f, g.n, 50, om)
+        _, u_o = oracle.moments(f, g.n)
+        err = float(np.linalg.norm(u_g - u_o) / np.linalg.norm(u_o))
+        print(f"launch {shape}, sample {s}, 50 steps: rel L2(u) = {err:.3e}")
+        assert err < 1e-5
+
+
 def test_mixed48_full_size_sampled_steps():
     """32 x 64^3 + 12 x 128^3 + 4 x 256^3 in one launch per tick, strides 16:4:1."""
     wl, ens = full_ensemble("mixed48_f32")
