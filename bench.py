@@ -445,6 +445,26 @@ def observables_probe(mc, torch, reps=3):
         torch.cuda.empty_cache()
 
 
+def adjoint_probe(mc, torch, steps=20, every=10):
+    """A short forward with checkpoints and the backward sweep of the adjoint
+    workload's ensemble (8 x 128^3 FP32, graphs as in the benchmark), timed
+    with HIP events; for kernel-trace and counter passes."""
+    import mc_inputs
+    wl = mc_inputs.WORKLOADS["adjoint128x8_f32"]
+    ens = build_ensemble(wl, mc, torch)
+    ck = ens.forward_ckpt(steps, every)
+    ens.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(ens.stream)
+    dj, _ = ens.backward(steps, every, ck)
+    e1.record(ens.stream)
+    ens.synchronize()
+    sec = e0.elapsed_time(e1) / 1e3
+    lups = sum(s.n ** 3 for s in ens.samples) * steps
+    print(f"[adjoint-probe] {wl.name}: {steps} reverse steps (checkpoints every {every}) in {sec * 1e3:.1f} ms, "
+          f"{lups / sec / 1e6:.0f} MLUPS, |dJ/dY| {float(dj.norm()):.4e}", flush=True)
+
+
 def cpu_baseline(seconds_target=15.0, large=True):
     """The oracle on one 64^3 RTGV sample of the workload, on all host cores
     (and two steps on one core); for context also the 32^3 FP64 TGV
@@ -517,6 +537,8 @@ def main():
     ap.add_argument("--no-capacity", action="store_true", help="skip the 132 GB vanishing-viscosity sequence")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="only run a few ticks of the larger-lattice and D3Q19 ensembles (for counter passes)")
+    ap.add_argument("--adjoint-probe", action="store_true",
+                    help="only run a short forward and backward of the adjoint workload (for counter passes)")
     ap.add_argument("--observables-probe", action="store_true",
                     help="only time the FP64 observables of one group per resolution (for counter passes)")
     args = ap.parse_args()
@@ -531,6 +553,9 @@ def main():
 
     if args.traffic_probe:
         traffic_probe(mc, torch)
+        return
+    if args.adjoint_probe:
+        adjoint_probe(mc, torch)
         return
     if args.observables_probe:
         observables_probe(mc, torch)
