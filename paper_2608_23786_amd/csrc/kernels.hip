@@ -308,7 +308,8 @@ __global__ void __launch_bounds__(256) adjoint_step_kernel(const T* state, const
     }
   }
 
-  // reverse sweep. ga: adjoint of g (direct path g* = g - ...)
+  // reverse sweep (the direct path of g* = g - omega ds - t dh hands nu to g
+  // unchanged; tbar is the adjoint of t)
   T tbar = T(0);
   for_vel<QN>([&](auto ic) {
     constexpr int i = decltype(ic)::value;
