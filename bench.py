@@ -465,6 +465,25 @@ def adjoint_probe(mc, torch, steps=20, every=10):
           f"{lups / sec / 1e6:.0f} MLUPS, |dJ/dY| {float(dj.norm()):.4e}", flush=True)
 
 
+def stabiliser_probe(mc, torch, ticks=8):
+    """A few plain ticks (graphs off, 256-thread blocks) of the default
+    64 x 64^3 ensemble with the closed-form and then the exact stabiliser,
+    timed per launch; for kernel-trace and counter passes."""
+    import mc_inputs
+    ens = build_ensemble(mc_inputs.WORKLOADS["rtgv64x64_f32"], mc, torch)
+    ens.set_launch(256, 0, 1, 1)
+    ens.use_graphs(False)
+    ens.step(2)
+    for mode in ("closed_form", "exact"):
+        ens.set_stabiliser(mode)
+        ens.time_launches(True)
+        ens.step(ticks)
+        avg, n = ens.launch_time()
+        ens.time_launches(False)
+        print(f"[stabiliser-probe] {mode}: {n} launches, {avg:.4f} ms average, "
+              f"{216 * 64 * 64 ** 3 / avg / 1e6:.0f} GB/s algorithmic", flush=True)
+
+
 def cpu_baseline(seconds_target=15.0, large=True):
     """The oracle on one 64^3 RTGV sample of the workload, on all host cores
     (and two steps on one core); for context also the 32^3 FP64 TGV
@@ -537,6 +556,8 @@ def main():
     ap.add_argument("--no-capacity", action="store_true", help="skip the 132 GB vanishing-viscosity sequence")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="only run a few ticks of the larger-lattice and D3Q19 ensembles (for counter passes)")
+    ap.add_argument("--stabiliser-probe", action="store_true",
+                    help="only run a few ticks with each stabiliser (for counter passes)")
     ap.add_argument("--adjoint-probe", action="store_true",
                     help="only run a short forward and backward of the adjoint workload (for counter passes)")
     ap.add_argument("--observables-probe", action="store_true",
@@ -556,6 +577,9 @@ def main():
         return
     if args.adjoint_probe:
         adjoint_probe(mc, torch)
+        return
+    if args.stabiliser_probe:
+        stabiliser_probe(mc, torch)
         return
     if args.observables_probe:
         observables_probe(mc, torch)
