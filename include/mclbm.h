@@ -252,7 +252,9 @@ mclbm_status mclbm_observables_range(mclbm_ctx* ctx, int32_t first, int32_t coun
  * ekc_dev: [count][n/2 + 1] (device, double, as written by
  * mclbm_observables_range); either pair may be NULL, not half of one. The
  * inner-scaled abscissae are kappa eta and r 2 pi / (n eta) with eta from
- * mclbm_dissipation. Runs on the context's stream. */
+ * mclbm_dissipation. Runs on the context's stream. MCLBM_ERR_ARG (nothing
+ * enqueued) for a range outside the ensemble, samples of different n, a NULL
+ * diss_dev or half a pair; both pairs NULL is a no-op. */
 mclbm_status mclbm_compensate(mclbm_ctx* ctx, int32_t first, int32_t count, const double* diss_dev,
                               const double* s2_dev, const double* ek_dev, double* s2c_dev, double* ekc_dev);
 
