@@ -259,6 +259,7 @@ def bench_adjoint(mc, torch):
     bwd = e[1].elapsed_time(e[2]) / 1e3
     out = {"workload": wl.name, "steps": ticks, "ckpt_every": every,
            "forward_seconds": round(fwd, 4), "backward_seconds": round(bwd, 4),
+           "total_seconds": round(fwd + bwd, 4),
            "forward_MLUPS": round(cells * ticks / fwd / 1e6, 1),
            "backward_MLUPS": round(cells * ticks / bwd / 1e6, 1),
            "backward_bytes_per_lup": 324 + 216 * (ticks - (ticks + every - 1) // every) / ticks,
