@@ -304,7 +304,7 @@ __global__ void __launch_bounds__(256) adjoint_step_kernel(const T* state, const
         constexpr int i = decltype(ic)::value;
         ge[i] = geq<QN, i>(m);
       });
-      t = exact_entropic_t<QN>(ge, fneq, s, rp.omega, t);
+      t = exact_entropic_t<QN>(ge, fneq, s, m, rp.omega, t);
     }
   }
 

@@ -263,7 +263,13 @@ struct CellResult {
 // so the result does not depend on its neighbours in the wave.
 // ln(f*_i / w_i) is evaluated as log1p((f*_i - w_i) / w_i) from the shifted
 // values, which keeps its relative accuracy for populations near their
-// weights.
+// weights. dh carries no mass and no momentum, so H'(t) does not change when
+// a + b.c_i is subtracted from every logarithm; the sums subtract
+// drho - 1.5 |u|^2 + 3 c_i.u, the part of ln(f^eq_i / w_i) of first order in
+// drho and second in u. In exact arithmetic that is a no-op; in rounding it
+// keeps the mass and momentum that dh's rounding leaves (near equilibrium,
+// where dh is itself at rounding level) from multiplying an O(u) logarithm
+// and swamping the third-order balance that fixes t there.
 constexpr int kExactNewtonSteps = 4;
 
 template <typename T>
@@ -271,9 +277,27 @@ constexpr T exact_tolerance() {
   return std::is_same<T, float>::value ? T(1.0 / (1 << 12)) : T(1e-8);
 }
 
+// Below which <dh|dh> counts as equilibrium for the exact stabiliser (where
+// gamma = 2). In FP64 the threshold of the closed form, 1e-30. In FP32 the
+// dh of a node at equilibrium is the rounding of its populations (the
+// moments and g^eq of about 27 float terms: a few units in the last place of
+// |g^eq| ~ w |u|), and the exact minimiser acts on any dh, however small, by
+// an amount of third order in u: such a node is taken as at equilibrium,
+// like the FP64 path, when <dh|dh> <= 2^-40 (3 |u|^2 + drho^2), about ten
+// times that rounding level (sum_i (g^eq_i)^2 / f^eq_i = 3 |u|^2 + drho^2 to
+// leading order); resolved flows carry dh far above it.
+template <typename T>
+__device__ __forceinline__ T exact_threshold(const Macro<T>& m) {
+  if constexpr (std::is_same<T, float>::value)
+    return fmaxf(1e-30f, 0x1.0p-40f * (2.0f * m.usq15 + m.drho * m.drho));
+  else
+    return T(1e-30);
+}
+
 template <int QN, typename T>
-__device__ __forceinline__ T exact_entropic_t(const T (&geq)[Q], const T (&fneq)[Q], const Shear<T>& s, T omega,
-                                              T t) {
+__device__ __forceinline__ T exact_entropic_t(const T (&geq)[Q], const T (&fneq)[Q], const Shear<T>& s,
+                                              const Macro<T>& m, T omega, T t) {
+  const T a = m.drho - m.usq15;
   // the interval of t where every f*_i = base_i - t dh_i > 0; in float the
   // quotients use the hardware reciprocal (about one unit in the last place)
   // and are moved inwards by 2^-20 of their size, so that the interval stays
@@ -306,7 +330,7 @@ __device__ __forceinline__ T exact_entropic_t(const T (&geq)[Q], const T (&fneq)
       constexpr double w = weight<QN>(i);
       // f*_i - w_i in shifted form
       const T gs = geq[i] + (fneq[i] - omega * ds) - t * dh;
-      d1 += dh * log1p_acc(gs * T(1.0 / w));
+      d1 += dh * (log1p_acc(gs * T(1.0 / w)) - (a + T(3) * cdot<i>(m.ux, m.uy, m.uz)));
       d2 += dh * dh * recip(T(w) + gs);
     });
     T tn = t + d1 / d2;
@@ -353,8 +377,8 @@ __device__ __forceinline__ CellResult<T> kbc_collide(T (&g)[Q], const Relax<T>& 
   if (B > T(1e-30)) gamma = rp.two_over_omega - rp.kappa * (A / B);
   T t = T(0.5) * rp.omega * gamma;
   if constexpr (EXACT) {
-    if (B > T(1e-30)) {
-      t = exact_entropic_t<QN>(g, fneq, s, rp.omega, t);
+    if (B > exact_threshold<T>(m)) {
+      t = exact_entropic_t<QN>(g, fneq, s, m, rp.omega, t);
       gamma = T(2) * t / rp.omega;
     }
   }
