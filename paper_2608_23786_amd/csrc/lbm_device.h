@@ -380,6 +380,9 @@ __device__ __forceinline__ CellResult<T> kbc_collide(T (&g)[Q], const Relax<T>& 
     if (B > exact_threshold<T>(m)) {
       t = exact_entropic_t<QN>(g, fneq, s, m, rp.omega, t);
       gamma = T(2) * t / rp.omega;
+    } else {
+      gamma = T(2);  // at equilibrium within rounding: t = omega gamma / 2 = omega
+      t = rp.omega;
     }
   }
   // g* = g - omega ds - t dh = (g^eq - ds) + (2 - omega) ds + (1 - t) dh.

@@ -98,7 +98,10 @@ def test_rtgv_fp32_run_from_equilibrium_matches_oracle_exact_mode():
     f = oracle.init_populations(n, u0, amp, y[0], True)
     done = 0
     for steps in (1, 10, 100):
-        ens.step(steps - done)
+        rec = ens.step(steps - done, record_every=steps - done).cpu().numpy()
+        if steps == 1:
+            # the initial equilibrium counts as equilibrium in FP32 too
+            assert np.all(rec[0, 0, 5:8] == 2.0), rec[0, 0, 5:8]
         oracle.run(f, n, steps - done, om, mode=oracle.MODE_EXACT)
         done = steps
         _, u_g = (t.cpu().numpy() for t in ens.moments(0))
