@@ -292,7 +292,7 @@ __global__ void __launch_bounds__(256) adjoint_step_kernel(const T* state, const
       B += fneq[i] * fneq[i] * r;
     }
   });
-  const bool active = B > T(1e-30);
+  const bool active = B > equilibrium_threshold<T>(m);  // as in the forward collision
   T gamma = T(2);
   if (active) gamma = rp.two_over_omega - rp.kappa * (A / B);
   T t = T(0.5) * rp.omega * gamma;

@@ -277,17 +277,18 @@ constexpr T exact_tolerance() {
   return std::is_same<T, float>::value ? T(1.0 / (1 << 12)) : T(1e-8);
 }
 
-// Below which <dh|dh> counts as equilibrium for the exact stabiliser (where
-// gamma = 2). In FP64 the threshold of the closed form, 1e-30. In FP32 the
-// dh of a node at equilibrium is the rounding of its populations (the
-// moments and g^eq of about 27 float terms: a few units in the last place of
-// |g^eq| ~ w |u|), and the exact minimiser acts on any dh, however small, by
-// an amount of third order in u: such a node is taken as at equilibrium,
-// like the FP64 path, when <dh|dh> <= 2^-40 (3 |u|^2 + drho^2), about ten
-// times that rounding level (sum_i (g^eq_i)^2 / f^eq_i = 3 |u|^2 + drho^2 to
-// leading order); resolved flows carry dh far above it.
+// Below which <dh|dh> counts as equilibrium (gamma = 2, for either
+// stabiliser). In FP64 1e-30, where dh vanishes up to rounding. In FP32 the dh
+// of a node at equilibrium is the rounding of its populations (the moments
+// and g^eq of about 27 float terms: a few units in the last place of
+// |g^eq| ~ w |u|): the closed form would report a gamma of that rounding, and
+// the exact minimiser acts on any dh, however small, by an amount of third
+// order in u. Such a node is taken as at equilibrium, like the FP64 path,
+// when <dh|dh> <= 2^-40 (3 |u|^2 + drho^2), about ten times that rounding
+// level (sum_i (g^eq_i)^2 / f^eq_i = 3 |u|^2 + drho^2 to leading order);
+// resolved flows carry dh far above it.
 template <typename T>
-__device__ __forceinline__ T exact_threshold(const Macro<T>& m) {
+__device__ __forceinline__ T equilibrium_threshold(const Macro<T>& m) {
   if constexpr (std::is_same<T, float>::value)
     return fmaxf(1e-30f, 0x1.0p-40f * (2.0f * m.usq15 + m.drho * m.drho));
   else
@@ -373,16 +374,14 @@ __device__ __forceinline__ CellResult<T> kbc_collide(T (&g)[Q], const Relax<T>& 
       B += fneq[i] * fneq[i] * r;
     }
   });
+  const bool resolved = B > equilibrium_threshold<T>(m);
   T gamma = T(2);
-  if (B > T(1e-30)) gamma = rp.two_over_omega - rp.kappa * (A / B);
+  if (resolved) gamma = rp.two_over_omega - rp.kappa * (A / B);
   T t = T(0.5) * rp.omega * gamma;
   if constexpr (EXACT) {
-    if (B > exact_threshold<T>(m)) {
+    if (resolved) {
       t = exact_entropic_t<QN>(g, fneq, s, m, rp.omega, t);
       gamma = T(2) * t / rp.omega;
-    } else {
-      gamma = T(2);  // at equilibrium within rounding: t = omega gamma / 2 = omega
-      t = rp.omega;
     }
   }
   // g* = g - omega ds - t dh = (g^eq - ds) + (2 - omega) ds + (1 - t) dh.

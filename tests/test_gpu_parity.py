@@ -347,6 +347,9 @@ def test_degenerate_rest_and_uniform_states(precision, q):
     uni = ens.get_state(1).cpu().numpy().reshape(q, n ** 3)
     assert np.array_equal(uni, np.repeat(uni[:, :1], n ** 3, axis=1))
     assert np.all(rec[:, 1, 5] == rec[:, 1, 6])
+    # its dh is rounding (FP64: below 1e-30; FP32: within the float
+    # threshold): at equilibrium, gamma = 2 in every record
+    assert np.all(rec[:, 1, 5:8] == 2.0), rec[:, 1, 5:8]
     # rounding only: FP64, or FP32 storage of g ~ 3e-2 (2e-9 per value; the
     # collision of a rounding-level non-equilibrium part moves it by about as
     # much per step)
