@@ -398,6 +398,124 @@ def bench_sequence(mc, torch):
     return out
 
 
+def bench_sequence_to_onset(mc, torch, name, launch=None, rec_every=16):
+    """The vanishing-viscosity sequence in acoustic scaling run to t = 9 (the
+    onset of turbulence of the Taylor-Green vortex): 8 samples per resolution
+    with the same Y at every N, U0 = 0.05 at every N (time step proportional
+    to dx, strides 4:2:1), Re = 12.5 N, FP64 kinetic-energy records every
+    `rec_every` ticks. At every save (t = 1, 2, ..., 9): per resolution the
+    ensemble mean and standard deviation of KE, both dissipation-rate forms
+    (the decay of the records' kinetic energy, and the paper's decay of the
+    summed shell spectrum over the last `rec_every` ticks) with the
+    Kolmogorov length, the mean structure function at common physical lags,
+    the mean spectrum and the mean compensated spectrum; between
+    resolutions, on the 8^3 common nodes in units of U0, W_{1,1} and the
+    relative L1 sample error of each coarser ensemble against the finest, and
+    their orders of convergence (EOWC, EOSC). Prints one line per save."""
+    import mc_inputs
+    import numpy as np
+    wl = mc_inputs.WORKLOADS[name]
+    samples = []
+    for g in wl.groups:
+        samples += [mc.Sample(g.n, g.u0, g.re, g.amp, g.project, g.stride)] * g.count
+    ens = mc.Ensemble(samples, wl.precision, lattice=wl.lattice)
+    per = wl.groups[0].count
+    y = np.tile(mc_inputs.draw_y(wl.seed, per), (len(wl.groups), 1))
+    ens.init(0, torch.from_numpy(y))
+    tuned = launch if launch is not None else ens.autotune(reps=1)
+    ens.set_launch(*tuned)
+    finest = wl.groups[-1]
+    dt = 2 * np.pi / finest.n * finest.u0              # physical time of one tick
+    firsts, first = [], 0
+    for g in wl.groups:
+        firsts.append(first)
+        first += g.count
+    work = ens._dev_empty((max(int(mc.lib().mclbm_observables_range_work_bytes(ens._ctx, a, g.count))
+                               for a, g in zip(firsts, wl.groups)),), torch.uint8)
+    coarse = wl.groups[0].n
+    records, saves = [], []
+    lups, sec = 0, 0.0
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    nsave = wl.ticks // wl.save_every
+    for k in range(1, nsave + 1):
+        t0 = ens.ticks
+        lups += sum(cells_per_tick(ens, t0 + j) for j in range(wl.save_every))
+        ens.synchronize()
+        e0.record(ens.stream)
+        records.append(ens.step(wl.save_every - rec_every, record_every=rec_every))
+        e1.record(ens.stream)
+        ens.synchronize()
+        sec += e0.elapsed_time(e1) / 1e3
+        ek_a = [ens.observables_range(a, g.count, work, structure=False)[1].clone() for a, g in zip(firsts, wl.groups)]
+        e0.record(ens.stream)
+        records.append(ens.step(rec_every, record_every=rec_every))
+        e1.record(ens.stream)
+        ens.synchronize()
+        sec += e0.elapsed_time(e1) / 1e3
+        bad = ens.check()
+        tick = ens.ticks
+        t = tick * dt
+        row = {"tick": tick, "t": round(t, 4), "unstable_sample": bad, "groups": {}}
+        pv = ens.point_values(8, physical=True)
+        ref = pv[firsts[-1]:].contiguous()
+        ns, w1, err = [], [], []
+        for gi, (a, g) in enumerate(zip(firsts, wl.groups)):
+            s2, ek_b = ens.observables_range(a, g.count, work)
+            series = torch.stack([ek_a[gi], ek_b])
+            d_sp, eta_sp = ens.dissipation_spectra(a, series, tick - rec_every, rec_every)
+            ekc = ens.compensate(a, d_sp[1].contiguous(), ek=ek_b)[1]
+            red = ens.reduce()[a:a + g.count]
+            ke_m, ke_s = mc.ensemble_moments(red[:, 4:5].contiguous())
+            u2 = g.u0 ** 2
+            lag = [r * g.n // coarse for r in (1, 2, 4, 8)]
+            s2m = s2.mean(dim=0).cpu().numpy() / u2
+            ekm = ek_b.mean(dim=0).cpu().numpy() / u2
+            ekcm = ekc.mean(dim=0).cpu().numpy()
+            row["groups"][f"{g.count}x{g.n}^3"] = {
+                "E_KE": float(ke_m[0]) / u2, "sigma_KE": float(ke_s[0]) / u2,
+                "E_d_spectral": float(d_sp[1].mean()), "eta_spectral": float(eta_sp[1]),
+                "E_S2_at_lag_dx128_x1_2_4_8": [float(s2m[r - 1]) for r in lag],
+                "E_spectrum_kappa_2_8_32": [float(ekm[kk]) for kk in (2, 8, 32) if kk < len(ekm)],
+                "E_compensated_spectrum_kappa_4_8_16": [float(ekcm[kk]) for kk in (4, 8, 16) if kk < len(ekcm)],
+                "E_kappa_peak": int(np.argmax(ekm))}
+            if gi < len(wl.groups) - 1:
+                cur = pv[a:a + g.count].contiguous()
+                w1.append(float(mc.w1_1pt(cur, ref, 8).sum()))
+                err.append(mc.sample_error(cur, ref, 8).cpu().tolist())
+                ns.append(g.n)
+        row["reference_n"] = finest.n
+        row["W1_1pt_u_over_U0"] = {f"{n}^3": w for n, w in zip(ns, w1)}
+        row["sample_error_L1_vec"] = {f"{n}^3": e[3] for n, e in zip(ns, err)}
+        if all(v > 0 for v in w1) and all(e[3] > 0 for e in err):
+            row["EOWC"] = mc.eoc_slope(ns, w1)
+            row["EOSC"] = mc.eoc_slope(ns, [e[3] for e in err])
+        saves.append(row)
+        print(f"[onset] t = {t:.3f} (tick {tick}): " + "; ".join(
+            f"{key} E[KE] {v['E_KE']:.5f} E[d] {v['E_d_spectral']:.5f}" for key, v in row["groups"].items()) +
+            f"; W1 {[round(v, 5) for v in w1]} EOWC {row.get('EOWC', float('nan')):.3f} "
+            f"EOSC {row.get('EOSC', float('nan')):.3f} ({lups / sec / 1e6:.0f} MLUPS)", flush=True)
+        if bad >= 0:
+            break
+    rec = torch.cat(records)
+    # the kinetic-energy form of the dissipation rate from all records, at
+    # the record nearest each save
+    d_ke, _ = ens.dissipation(rec, 0, rec_every, eta=False)
+    d_ke = d_ke.cpu().numpy()
+    for row in saves:
+        j = min(row["tick"] // rec_every, d_ke.shape[0] - 1)
+        for a, g in zip(firsts, wl.groups):
+            row["groups"][f"{g.count}x{g.n}^3"]["E_d_kinetic_energy"] = float(d_ke[j, a:a + g.count].mean())
+    out = {"workload": wl.name, "ticks": ens.ticks, "t_end": round(ens.ticks * dt, 4),
+           "steps": [ens.steps(a) for a in firsts], "lattice_updates": lups, "seconds": round(sec, 3),
+           "MLUPS": round(lups / sec / 1e6, 1),
+           "launch": dict(zip(("block", "xcd_remap", "buffer_addressing", "nontemporal"), tuned)),
+           "groups": [f"{g.count}x{g.n}^3 U0 {g.u0} Re {g.re} stride {g.stride}" for g in wl.groups],
+           "saves": saves}
+    del ens, work
+    torch.cuda.empty_cache()
+    return out
+
+
 # ensembles for the counter runs of the collide-and-stream kernel beyond the
 # default workload: (lattice, samples, n, block, buffer addressing)
 TRAFFIC_PROBES = ((27, 8, 128, 512, 1), (27, 4, 256, 512, 1), (27, 1, 512, 512, 0), (19, 64, 64, 256, 1))
@@ -506,6 +624,7 @@ def cpu_baseline(seconds_target=15.0, large=True):
     t = time.perf_counter()
     oracle.run(f, g.n, steps, om, threads=threads)
     sec = time.perf_counter() - t
+    _, u_ref = oracle.moments(f, g.n)       # sample 0 after 2 + steps steps
     t = time.perf_counter()
     oracle.run(f, g.n, 2, om, threads=1)
     one = time.perf_counter() - t
@@ -538,7 +657,26 @@ def cpu_baseline(seconds_target=15.0, large=True):
                       f"KBC collision, two-lattice pull streaming ({sec:.1f} s)",
             "single_core_MLUPS": round(g.n ** 3 * 2 / one / 1e6, 3),
             "tgv32_f64_100_steps_MLUPS": round(tgv.n ** 3 * 100 / sec32 / 1e6, 3),
-            "rtgv256_one_sample_one_step_MLUPS": mlups256, "cpu_model": model}
+            "rtgv256_one_sample_one_step_MLUPS": mlups256, "cpu_model": model}, (2 + steps, u_ref)
+
+
+def measured_error(mc, torch, wl, launch, steps, u_ref):
+    """Relative L2 and maximum error of the velocity of sample 0 of the
+    workload after `steps` steps in the benchmark's launch shape
+    (graph-captured ticks, reductions fused as in the timed run) against the
+    oracle's field of the same sample (the CPU baseline's run)."""
+    import numpy as np
+    ens = build_ensemble(wl, mc, torch)
+    if launch is not None:
+        ens.set_launch(*launch)
+    ens.step(steps, record_every=wl.save_every if steps >= wl.save_every else 0)
+    _, u = ens.moments(0)
+    u = u.cpu().numpy().reshape(u_ref.shape)
+    del ens
+    torch.cuda.empty_cache()
+    return {"rel_l2_u_vs_oracle": float(np.linalg.norm(u - u_ref) / np.linalg.norm(u_ref)),
+            "max_abs_u_error_over_max_abs_u": float(np.max(np.abs(u - u_ref)) / np.max(np.abs(u_ref))),
+            "steps": steps, "sample": 0, "target_rel_l2": 1e-5 if wl.precision == "f32s" else 1e-12}
 
 
 def main():
@@ -563,6 +701,8 @@ def main():
                     help="only run a short forward and backward of the adjoint workload (for counter passes)")
     ap.add_argument("--observables-probe", action="store_true",
                     help="only time the FP64 observables of one group per resolution (for counter passes)")
+    ap.add_argument("--onset", default=None, choices=["sequence512x8_acoustic_f32", "sequence256x8_acoustic_f32"],
+                    help="only run this acoustic vanishing-viscosity sequence to t = 9 and print its statistics")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (the library has no multi-GPU path); got --gpus {args.gpus}",
@@ -584,6 +724,13 @@ def main():
         return
     if args.observables_probe:
         observables_probe(mc, torch)
+        return
+    if args.onset:
+        # the finest group of the 512^3 sequence holds 8 samples of 14.5 GB:
+        # plain pointers, block 512, XCD-contiguous blocks (the tuned shape of
+        # the diffusive sequence's 512^3 group)
+        launch = (512, 1, 0, 1) if args.onset.startswith("sequence512") else None
+        print(json.dumps(bench_sequence_to_onset(mc, torch, args.onset, launch)), flush=True)
         return
     wl = mc_inputs.WORKLOADS[args.workload]
     print(f"[bench] workload {wl.name}: {wl.m} samples, precision {wl.precision}", file=sys.stderr, flush=True)
@@ -649,7 +796,7 @@ def main():
                    "precision": "FP32 shifted populations (f - w), FP64 reductions" if wl.precision == "f32s"
                    else "FP64", "reduce_every": rec_every, "launch": dict(zip(("block", "xcd_remap", "buffer_addressing", "nontemporal"),
                                                                           tuned or (256, 0, 1, 1))),
-                   "rel_error_bound_vs_oracle": 1e-5 if wl.precision == "f32s" else 1e-12},
+                   "error_vs_oracle": None},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": counter_traffic(wl.name),
                      "traffic_unit": "bytes per launch", "algorithmic_bytes_per_launch": int(round(bpl)),
@@ -662,7 +809,9 @@ def main():
         **extra,
     }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline()
+        out["cpu_baseline"], (err_steps, u_ref) = cpu_baseline()
+        out["config"]["error_vs_oracle"] = measured_error(mc, torch, wl, tuned, err_steps, u_ref)
+        print(f"[bench] velocity error vs oracle: {out['config']['error_vs_oracle']}", file=sys.stderr, flush=True)
     print(json.dumps(out), flush=True)
 
 

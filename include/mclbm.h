@@ -119,7 +119,7 @@ double mclbm_omega(int32_t n, double u0, double re);
  * small tables. */
 size_t mclbm_workspace_bytes(int32_t m, const mclbm_sample_desc* desc, int32_t precision, int32_t lattice);
 
-/* Create a context for m samples (1 <= m <= 256) on one lattice
+/* Create a context for m samples (1 <= m <= 65536) on one lattice
  * (MCLBM_D3Q27 or MCLBM_D3Q19). `workspace` is device memory of at least
  * mclbm_workspace_bytes() bytes, 256-byte aligned; `hip_stream` is a
  * hipStream_t (NULL for the null stream). The descriptors are copied. */
@@ -198,7 +198,12 @@ mclbm_status mclbm_restore(mclbm_ctx* ctx, const void* src_dev, size_t bytes);
  *     ke_dev[m] = KE_m(T) (device, may be NULL), recomputing each segment
  *     of ckpt_every steps from its checkpoint into work_dev.
  * Sizes come from mclbm_ckpt_bytes / mclbm_backward_work_bytes. The state
- * after backward is the forward state at T. Both stabilisers: with the exact
+ * after backward is the forward state at T. mclbm_backward returns
+ * MCLBM_ERR_STATE (nothing enqueued) when any call changed the state or its
+ * dynamics after the last mclbm_forward_ckpt (init, step, restore,
+ * set_state, set_viscosity, set_stabiliser, poison, autotune), or when
+ * ckpt_dev holds checkpoints of another forward run (each forward writes a
+ * token into the first 256 bytes of its checkpoint buffer). Both stabilisers: with the exact
  * one (mclbm_set_stabiliser) each reverse step recomputes the forward t and
  * differentiates it through its stationarity condition (implicit function
  * theorem), FP64 states only: near equilibrium the exact minimiser moves f*
@@ -212,6 +217,22 @@ mclbm_status mclbm_forward_ckpt(mclbm_ctx* ctx, int64_t ticks, int32_t ckpt_ever
 mclbm_status mclbm_backward(mclbm_ctx* ctx, int64_t ticks, int32_t ckpt_every, const void* ckpt_dev,
                             size_t ckpt_bytes, void* work_dev, size_t work_bytes, double* dJdY_dev,
                             double* ke_dev);
+
+/* Vector-Jacobian product of one step (collide, then stream: eq.
+ * (lbIteration) with the collision of eqs. (kbcCollision),
+ * (entropyControl), or eq. (kbc_entropy) for the exact stabiliser) at the
+ * current state f_n of every sample: out = (d f_{n+1} / d f_n)^T lam, the
+ * reverse step mclbm_backward applies (the state is not advanced). lam_dev,
+ * out_dev: device, double, the samples one after another, each [q][n^3] in
+ * the population order of mclbm_get_state (derivatives with respect to the
+ * unshifted populations f); in FP32 ensembles lam is rounded to float and
+ * the product is computed in float. work_dev: mclbm_step_vjp_work_bytes
+ * bytes of device scratch (three state copies), owned by the caller. The
+ * same restrictions as mclbm_backward: every stride 1 (else
+ * MCLBM_ERR_UNSUPPORTED), the exact stabiliser in FP64 only. */
+size_t mclbm_step_vjp_work_bytes(const mclbm_ctx* ctx);
+mclbm_status mclbm_step_vjp(mclbm_ctx* ctx, const double* lam_dev, double* out_dev, void* work_dev,
+                            size_t work_bytes);
 
 /* Observables of one sample's current velocity field, in double:
  *   s2_dev[n/2]: second-order structure function S2(r), r = 1..n/2, by the
@@ -312,14 +333,21 @@ mclbm_status mclbm_sample_error(const double* a_dev, const double* b_dev, int32_
 mclbm_status mclbm_eoc_slope(const double* n, const double* d, int32_t k, double* slope);
 
 /* Dissipation rate per unit volume and Kolmogorov length from a series of
- * records of mclbm_step (the definition of the sample dissipation rate
- * before eq. (kolmogorov_microscale), and that equation): d_m(t) =
- * -(d/dt) KE_m(t), with KE_m the kinetic energy per unit volume in units of
- * u0^2 (field 4 of the records divided by u0^2) and t the physical time of
- * the record, t = steps * (2 pi / n) * u0 (unit reference velocity, box of
- * side 2 pi); the derivative is a centred difference inside the series and
- * one-sided at its ends. eta(t) = (eps^3 / mean_m d_m(t))^(1/4) with
- * eps = 1 / Re.
+ * records of mclbm_step. The paper defines the sample dissipation rate
+ * (before eq. (kolmogorov_microscale)) as nu ||grad u_m||^2 / |Omega| and
+ * approximates it by the decay of the energy per unit volume; this call
+ * differentiates the kinetic energy per unit volume of the records:
+ * d_m(t) = -(d/dt) KE_m(t), with KE_m in units of u0^2 (field 4 of the
+ * records divided by u0^2; the Parseval sum over every mode) and t the
+ * physical time of the record, t = steps * (2 pi / n) * u0 (unit reference
+ * velocity, box of side 2 pi); the derivative is a centred difference
+ * inside the series and one-sided at its ends. The paper's own
+ * approximation differentiates the summed shell spectrum instead
+ * (mclbm_dissipation_spectra); the two differ by the shell weights of eq.
+ * (energySpecDisc) (a factor 4 pi 3 / 62 = 0.61 for energy in the Taylor-
+ * Green modes, tending to 1 as the energy moves to high shells).
+ * eta(t) = (eps^3 / mean_m d_m(t))^(1/4) with eps = 1 / Re, eq.
+ * (kolmogorov_microscale).
  * records_dev: [nrec][m][8] (device) as written by mclbm_step, the first
  * taken at tick first_tick, the others every record_every ticks (both
  * multiples of every stride; nrec >= 2). diss_dev: [nrec][m] (device).
@@ -327,6 +355,23 @@ mclbm_status mclbm_eoc_slope(const double* n, const double* d, int32_t k, double
  * (MCLBM_ERR_ARG otherwise); a non-positive mean dissipation gives NaN. */
 mclbm_status mclbm_dissipation(mclbm_ctx* ctx, const double* records_dev, int32_t nrec, int64_t first_tick,
                                int32_t record_every, double* diss_dev, double* eta_dev);
+
+/* The paper's approximation of the sample dissipation rate (the sentence
+ * after its definition, before eq. (kolmogorov_microscale)):
+ * d_m(t) = -(d/dt) sum_kappa E_m(kappa, t), with E_m the shell spectrum of
+ * eq. (energySpecDisc) in units of u0^2, for the `count` samples
+ * first..first+count-1 of one resolution, from their spectra at nrec saved
+ * times: ek_dev[nrec][count][n/2+1] (device, lattice units, each row as
+ * written by mclbm_observables_range), the first saved at tick first_tick,
+ * the others every record_every ticks (multiples of the samples' stride).
+ * Time, differences and eta as in mclbm_dissipation; diss_dev[nrec][count]
+ * (device); eta_dev[nrec] (device) or NULL, from the mean over the range
+ * (one Re for the range, else MCLBM_ERR_ARG). MCLBM_ERR_ARG (nothing
+ * enqueued) for a range outside the ensemble or of mixed resolutions,
+ * nrec < 2, or saved ticks where a sample of the range does not step. */
+mclbm_status mclbm_dissipation_spectra(mclbm_ctx* ctx, int32_t first, int32_t count, const double* ek_dev,
+                                       int32_t nrec, int64_t first_tick, int32_t record_every, double* diss_dev,
+                                       double* eta_dev);
 
 /* Stabiliser gamma of the higher-order relaxation omega_hom = omega gamma / 2
  * (Table 1). MCLBM_GAMMA_CLOSED_FORM (default) evaluates eq. (entropyControl).

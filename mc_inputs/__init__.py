@@ -115,6 +115,24 @@ WORKLOADS = {
          SampleGroup(256, 8, diffusive_u0(256), 3200.0, 0.05, True, 4),
          SampleGroup(512, 8, diffusive_u0(512), 6400.0, 0.05, True, 1)],
         "f32s", 256, 2611, 16),
+    # the same sequence in acoustic scaling (the faster variant): U0 = 0.05 at
+    # every N, so the time step is proportional to dx and the strides are
+    # 4:2:1; Re = 12.5 N as above (the lattice viscosity is then the same at
+    # every N). To t = 9: 14,688 ticks of the 512^3 lattice, saves every 1632
+    # ticks (t = 1.0014 per save)
+    "sequence512x8_acoustic_f32": Workload(
+        "sequence512x8_acoustic_f32",
+        [SampleGroup(128, 8, 0.05, 1600.0, 0.05, True, 4),
+         SampleGroup(256, 8, 0.05, 3200.0, 0.05, True, 2),
+         SampleGroup(512, 8, 0.05, 6400.0, 0.05, True, 1)],
+        "f32s", 14688, 2611, 1632),
+    # its rehearsal one resolution lower: 64^3, 128^3, 256^3, 7344 ticks to t = 9
+    "sequence256x8_acoustic_f32": Workload(
+        "sequence256x8_acoustic_f32",
+        [SampleGroup(64, 8, 0.05, 800.0, 0.05, True, 4),
+         SampleGroup(128, 8, 0.05, 1600.0, 0.05, True, 2),
+         SampleGroup(256, 8, 0.05, 3200.0, 0.05, True, 1)],
+        "f32s", 7344, 2611, 816),
     # adjoint workload: 8 x 128^3, FP32 forward, 1000 steps, checkpoints every 50
     "adjoint128x8_f32": Workload(
         "adjoint128x8_f32", [SampleGroup(128, 8, diffusive_u0(128), 1600.0, 0.05, True)], "f32s", 1000, 2610, 50),

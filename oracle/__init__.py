@@ -27,7 +27,13 @@ Contents and the passage each part follows:
     least-squares convergence order of Algorithm (ComputeSlopes); empirical
     ensemble mean and standard deviation, eqs. (spectrum_mean) and
     (spectrum_var); sample-wise compensated spectrum and structure function,
-    eqs. (compensatedE) and (compensatedSF).
+    eqs. (compensatedE) and (compensatedSF);
+  * the sample dissipation rate per unit volume as defined before eq.
+    (kolmogorov_microscale) (viscosity times the mean squared velocity
+    gradient, by spectral derivatives), its approximation the paper uses
+    (minus the time derivative of the summed shell spectrum), the same
+    derivative of the kinetic energy per unit volume, and the Kolmogorov
+    length of eq. (kolmogorov_microscale).
 
 Lattices: D3Q27 (q = 27, the default) and the paper's D3Q19 (q = 19).
 
@@ -444,3 +450,77 @@ def compensated_structure_function(s2, d, u0, n):
             r = (j + 1) * 2.0 * math.pi / n
             out[m, j] = (s2[m, j] / u0[m] ** 2) / np.cbrt((d[m] * r) ** 2)
     return out
+
+
+# ---------------------------------------------------------------- dissipation rate and Kolmogorov length
+def state_time(steps, n, u0):
+    """Physical time after `steps` lattice steps: one step is dt = dx * u0 with
+    dx = 2 pi / n (box of side 2 pi, unit reference velocity), the time step
+    of Tables 2 and 3 for a lattice velocity u0."""
+    return np.asarray(steps, dtype=np.float64) * (2.0 * math.pi / n) * u0
+
+
+def energy_decay_rate(energy, t):
+    """-dE/dt of a series E(t_k), k = 0..K-1 (K >= 2; the first axis is
+    time): centred differences (E_{k+1} - E_{k-1}) / (t_{k+1} - t_{k-1})
+    inside the series, one-sided differences at its two ends."""
+    e = np.asarray(energy, dtype=np.float64)
+    t = np.asarray(t, dtype=np.float64)
+    k_len = e.shape[0]
+    assert k_len >= 2 and t.shape == (k_len,)
+    out = np.zeros_like(e)
+    for k in range(k_len):
+        lo = max(k - 1, 0)
+        hi = min(k + 1, k_len - 1)
+        out[k] = -(e[hi] - e[lo]) / (t[hi] - t[lo])
+    return out
+
+
+def dissipation_from_spectra(ek_series, t, u0):
+    """The paper's approximation of the sample dissipation rate (the
+    definition before eq. (kolmogorov_microscale)): d_m(t) = -d/dt of
+    sum_kappa E_m(kappa, t), the shell spectrum of eq. (energySpecDisc)
+    summed over kappa = 0..N/2, in units of u0^2 (velocities in units of
+    the reference velocity). ek_series[K][M][N/2+1] in lattice units, t[K]
+    physical times, u0[M]. Returns d[K][M]."""
+    ek = np.asarray(ek_series, dtype=np.float64)
+    k_len, m, _ = ek.shape
+    total = np.zeros((k_len, m))
+    for k in range(k_len):
+        for s in range(m):
+            total[k, s] = sum(ek[k, s, kap] for kap in range(ek.shape[2])) / u0[s] ** 2
+    return energy_decay_rate(total, t)
+
+
+def dissipation_from_kinetic_energy(ke_series, t, u0):
+    """-d/dt of the kinetic energy per unit volume, mean |u|^2 / 2 over the
+    nodes (the Parseval sum over every mode, corner modes included), in
+    units of u0^2. ke_series[K][M] in lattice units, t[K], u0[M]."""
+    ke = np.asarray(ke_series, dtype=np.float64)
+    return energy_decay_rate(ke / np.asarray(u0, dtype=np.float64)[None, :] ** 2, t)
+
+
+def dissipation_rate_definition(u, eps, u0):
+    """The sample dissipation rate per unit volume as the paper defines it,
+    d = eps / |Omega| * ||grad u||^2_{L^2(Omega)}, with eps = 1/Re the
+    viscosity in units of the reference length and velocity and u in units
+    of u0 on the box [0, 2 pi)^3; the derivatives of the trigonometric
+    interpolant of the grid field (spectral: d/dx_a of exp(i k.x) is
+    i k_a exp(i k.x), k in {-N/2+1, .., N/2}^3), so that |Omega|^-1
+    ||grad u||^2 = sum_k |k|^2 Phi(k) with Phi of eq. (dftCoeff)."""
+    n = u.shape[1]
+    k = np.fft.fftfreq(n) * n
+    k[k == -n // 2] = n // 2
+    KZ, KY, KX = np.meshgrid(k, k, k, indexing="ij")
+    k2 = KX ** 2 + KY ** 2 + KZ ** 2
+    phi = sum(np.abs(np.fft.fftn(u[a] / u0) / n ** 3) ** 2 for a in range(3))
+    return float(eps * np.sum(k2 * phi))
+
+
+def kolmogorov_length(eps, d):
+    """eq. (kolmogorov_microscale): eta(t) = (eps^3 / E[d(t)])^(1/4) with
+    E[d] the empirical mean of the sample dissipation rates d[..., M] over
+    the last axis."""
+    d = np.asarray(d, dtype=np.float64)
+    mean = np.sum(d, axis=-1) / d.shape[-1]
+    return (eps ** 3 / mean) ** 0.25

@@ -64,6 +64,8 @@ SIGNATURES = {
     "mclbm_backward_work_bytes": (_sz, [_ctxp, _i32]),
     "mclbm_forward_ckpt": (_i32, [_ctxp, _i64, _i32, _vp, _sz]),
     "mclbm_backward": (_i32, [_ctxp, _i64, _i32, _vp, _sz, _vp, _sz, _vp, _vp]),
+    "mclbm_step_vjp_work_bytes": (_sz, [_ctxp]),
+    "mclbm_step_vjp": (_i32, [_ctxp, _vp, _vp, _vp, _sz]),
     "mclbm_observables_work_bytes": (_sz, [_ctxp, _i32]),
     "mclbm_observables": (_i32, [_ctxp, _i32, _vp, _vp, _vp, _sz]),
     "mclbm_observables_range_work_bytes": (_sz, [_ctxp, _i32, _i32]),
@@ -80,6 +82,7 @@ SIGNATURES = {
     "mclbm_get_launch": (_i32, [_ctxp, _ip, _ip, _ip, _ip]),
     "mclbm_autotune": (_i32, [_ctxp, _i32, _vp, _sz, _ip, _ip, _ip, _ip]),
     "mclbm_dissipation": (_i32, [_ctxp, _vp, _i32, _i64, _i32, _vp, _vp]),
+    "mclbm_dissipation_spectra": (_i32, [_ctxp, _i32, _i32, _vp, _i32, _i64, _i32, _vp, _vp]),
     "mclbm_set_stabiliser": (_i32, [_ctxp, _i32]),
     "mclbm_use_graphs": (_i32, [_ctxp, _i32]),
     "mclbm_ticks": (_i64, [_ctxp]),

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -48,6 +49,8 @@ constexpr int kAuxBlock = 256;        // block of the auxiliary kernels
 constexpr int kMaxTables = 128;       // launch tables kept in the workspace
 constexpr size_t kHeaderBytes = 4096; // checkpoint header
 constexpr uint64_t kCkptMagic = 0x4d434c424d434b50ull;
+constexpr size_t kFwdHeaderBytes = 256;  // forward checkpoints: the token of the forward that wrote them
+std::atomic<uint64_t> g_fwd_tokens{0};
 constexpr int kMaxObservablesN = 512;  // the FFT passes are instantiated for n = 8..512
 
 // Leray projection on the 24 perturbation coefficients.
@@ -115,6 +118,12 @@ struct mclbm_ctx {
   std::vector<double> y;     // drawn or given parameters, m x 24
   std::vector<double> pmat;
   bool initialized = false;
+  // bumped by every call that changes the state or its dynamics; a backward
+  // sweep needs the state its forward_ckpt left (fwd_generation) and the
+  // checkpoints that forward wrote (fwd_token, also in their header)
+  uint64_t generation = 0;
+  uint64_t fwd_generation = 0;
+  uint64_t fwd_token = 0;
   int64_t tick = 0;
   std::vector<int64_t> steps;
   int max_stride = 1;
@@ -153,7 +162,7 @@ void drop_graphs(mclbm_ctx* c) {
 }
 
 mclbm_status validate_desc(int32_t m, const mclbm_sample_desc* d, int32_t precision, int32_t lattice) {
-  if (m < 1 || m > kMaxSamples) return fail(MCLBM_ERR_ARG, "m must be in [1, 256]");
+  if (m < 1 || m > kMaxSamples) return fail(MCLBM_ERR_ARG, "m must be in [1, " + std::to_string(kMaxSamples) + "]");
   if (!d) return fail(MCLBM_ERR_ARG, "descriptor array is NULL");
   if (precision != MCLBM_FP64 && precision != MCLBM_FP32_SHIFTED) return fail(MCLBM_ERR_ARG, "unknown precision");
   if (lattice != MCLBM_D3Q27 && lattice != MCLBM_D3Q19) return fail(MCLBM_ERR_ARG, "lattice must be 27 or 19");
@@ -206,15 +215,15 @@ Layout layout_of(int32_t m, const mclbm_sample_desc* d, int32_t precision, int32
   const size_t elem = precision == MCLBM_FP64 ? 8 : 4;
   size_t off = 0;
   L.samples = off;
-  off = align_up(off + sizeof(DevSample) * kMaxSamples);
+  off = align_up(off + sizeof(DevSample) * size_t(m));
   L.flags = off;
-  off = align_up(off + sizeof(int32_t) * kMaxSamples);
+  off = align_up(off + sizeof(int32_t) * size_t(m));
   L.ycoef = off;
-  off = align_up(off + sizeof(double) * 24 * kMaxSamples);
+  off = align_up(off + sizeof(double) * 24 * size_t(m));
   L.pmat = off;
   off = align_up(off + sizeof(double) * 24 * 24);
   L.diss = off;
-  off = align_up(off + sizeof(DissSample) * kMaxSamples);
+  off = align_up(off + sizeof(DissSample) * size_t(m));
   L.tables = off;
   L.table_bytes = size_t(kMaxTables) * align_up(sizeof(Seg) * m);
   off = align_up(off + L.table_bytes);
@@ -540,7 +549,7 @@ mclbm_status mclbm_create(mclbm_ctx** out, int32_t m, const mclbm_sample_desc* d
   }
   hipError_t e = hipMemcpy(c->d_samples, c->h_samples.data(), sizeof(DevSample) * m, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(c->d_pmat, c->pmat.data(), sizeof(double) * 24 * 24, hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = hipMemset(c->d_flags, 0, sizeof(int32_t) * kMaxSamples);
+  if (e == hipSuccess) e = hipMemset(c->d_flags, 0, sizeof(int32_t) * size_t(m));
   if (e == hipSuccess) {
     std::vector<DissSample> ds(m);
     for (int s = 0; s < m; ++s) {
@@ -595,12 +604,13 @@ mclbm_status mclbm_init(mclbm_ctx* c, uint64_t seed, const double* y_host) {
   }
   HIP_TRY(hipStreamSynchronize(c->stream));
   HIP_TRY(hipMemcpy(c->d_ycoef, yc.data(), sizeof(double) * yc.size(), hipMemcpyHostToDevice));
-  HIP_TRY(hipMemset(c->d_flags, 0, sizeof(int32_t) * kMaxSamples));
+  HIP_TRY(hipMemset(c->d_flags, 0, sizeof(int32_t) * size_t(c->m)));
   std::fill(c->steps.begin(), c->steps.end(), 0);
   c->tick = 0;
   const Table* t = nullptr;
   st = get_table(c, 0, true, kAuxBlock, true, &t);
   if (st != MCLBM_OK) return st;
+  c->generation += 1;
   HIP_TRY(launch_init(c->q, c->precision, c->pop, c->d_samples, table_ptr(c, t), t->nseg, t->total_blocks, c->d_ycoef,
                       c->stream));
   c->initialized = true;
@@ -621,6 +631,7 @@ mclbm_status mclbm_set_viscosity(mclbm_ctx* c, const double* eps_host) {
   if (!eps_host) return fail(MCLBM_ERR_ARG, "eps_host is NULL");
   for (int s = 0; s < c->m; ++s)
     if (!(eps_host[s] > 0.0) || !std::isfinite(eps_host[s])) return fail(MCLBM_ERR_ARG, "viscosity must be > 0");
+  c->generation += 1;
   for (int s = 0; s < c->m; ++s) {
     c->desc[s].re = 1.0 / eps_host[s];
     fill_sample(c, s, lattice_nu(c->desc[s]));
@@ -636,6 +647,7 @@ mclbm_status mclbm_step(mclbm_ctx* c, int64_t ticks, int32_t record_every, doubl
   if (st != MCLBM_OK) return st;
   if (ticks < 0) return fail(MCLBM_ERR_ARG, "ticks must be >= 0");
   if (record_every < 0) return fail(MCLBM_ERR_ARG, "record_every must be >= 0");
+  if (ticks > 0) c->generation += 1;
   if (record_every > 0) {
     if (!records_dev) return fail(MCLBM_ERR_ARG, "records_dev is NULL");
     for (int s = 0; s < c->m; ++s)
@@ -701,6 +713,7 @@ mclbm_status mclbm_set_state(mclbm_ctx* c, int32_t sample, const double* f_dev) 
   mclbm_status st = check_ctx(c, true);
   if (st != MCLBM_OK) return st;
   if (sample < 0 || sample >= c->m || !f_dev) return fail(MCLBM_ERR_ARG, "bad sample or NULL buffer");
+  c->generation += 1;
   HIP_TRY(launch_set_state(c->q, c->precision, c->pop, c->d_samples, sample, c->desc[sample].n,
                            int32_t(c->steps[sample] & 1), f_dev, c->stream));
   return MCLBM_OK;
@@ -729,6 +742,7 @@ mclbm_status mclbm_poison(mclbm_ctx* c, int32_t sample, int64_t cell, int32_t i)
   if (sample < 0 || sample >= c->m) return fail(MCLBM_ERR_ARG, "sample out of range");
   if (cell < 0 || cell >= c->cells(sample) || i < 0 || i >= c->q)
     return fail(MCLBM_ERR_ARG, "cell or velocity out of range");
+  c->generation += 1;
   HIP_TRY(launch_poison(c->q, c->precision, c->pop, c->d_samples, sample, int32_t(c->steps[sample] & 1), cell, i, c->stream));
   return MCLBM_OK;
 }
@@ -765,11 +779,12 @@ mclbm_status mclbm_restore(mclbm_ctx* c, const void* src_dev, size_t bytes) {
   HIP_TRY(hipMemcpy(h.data(), src_dev, sizeof(int64_t) * h.size(), hipMemcpyDeviceToHost));
   if (h[0] != int64_t(kCkptMagic) || h[1] != c->m || h[2] != c->precision || h[3] != c->q)
     return fail(MCLBM_ERR_ARG, "checkpoint does not belong to this ensemble");
+  c->generation += 1;
   HIP_TRY(hipMemcpyAsync(c->pop, static_cast<const char*>(src_dev) + kHeaderBytes, c->state_bytes,
                          hipMemcpyDeviceToDevice, c->stream));
   c->tick = h[4];
   for (int s = 0; s < c->m; ++s) c->steps[s] = h[5 + s];
-  HIP_TRY(hipMemsetAsync(c->d_flags, 0, sizeof(int32_t) * kMaxSamples, c->stream));
+  HIP_TRY(hipMemsetAsync(c->d_flags, 0, sizeof(int32_t) * size_t(c->m), c->stream));
   return MCLBM_OK;
 }
 
@@ -777,7 +792,7 @@ mclbm_status mclbm_restore(mclbm_ctx* c, const void* src_dev, size_t bytes) {
 size_t mclbm_ckpt_bytes(const mclbm_ctx* c, int64_t ticks, int32_t ckpt_every) {
   if (!c || ticks < 1 || ckpt_every < 1) return 0;
   const int64_t nck = (ticks + ckpt_every - 1) / ckpt_every;
-  return size_t(nck) * c->state_bytes;
+  return kFwdHeaderBytes + size_t(nck) * c->state_bytes;
 }
 
 size_t mclbm_backward_work_bytes(const mclbm_ctx* c, int32_t ckpt_every) {
@@ -808,15 +823,23 @@ mclbm_status mclbm_forward_ckpt(mclbm_ctx* c, int64_t ticks, int32_t ckpt_every,
   if (c->tick != 0) return fail(MCLBM_ERR_STATE, "forward_ckpt must start from step 0 (call mclbm_init first)");
   if (!ckpt_dev || ckpt_bytes < mclbm_ckpt_bytes(c, ticks, ckpt_every))
     return fail(MCLBM_ERR_OOM, "checkpoint buffer too small");
+  c->generation += 1;
+  c->fwd_generation = 0;
+  char* ck = static_cast<char*>(ckpt_dev) + kFwdHeaderBytes;
   for (int64_t k = 0; k * ckpt_every < ticks; ++k) {
     const Table* t = nullptr;
     st = get_table(c, c->tick, true, kAuxBlock, false, &t);
     if (st != MCLBM_OK) return st;
-    HIP_TRY(launch_canonical_copy(c->q, c->precision, c->pop, static_cast<char*>(ckpt_dev) + size_t(k) * c->state_bytes,
-                                  c->d_samples, table_ptr(c, t), t->nseg, t->total_blocks, c->stream));
+    HIP_TRY(launch_canonical_copy(c->q, c->precision, c->pop, ck + size_t(k) * c->state_bytes, c->d_samples,
+                                  table_ptr(c, t), t->nseg, t->total_blocks, c->stream));
     st = run_plain_ticks(c, std::min<int64_t>(ckpt_every, ticks - k * ckpt_every));
     if (st != MCLBM_OK) return st;
   }
+  const uint64_t token = ++g_fwd_tokens;
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  HIP_TRY(hipMemcpy(ckpt_dev, &token, sizeof(token), hipMemcpyHostToDevice));
+  c->fwd_token = token;
+  c->fwd_generation = c->generation;
   return MCLBM_OK;
 }
 
@@ -831,6 +854,13 @@ mclbm_status mclbm_backward(mclbm_ctx* c, int64_t ticks, int32_t ckpt_every, con
   if (!work_dev || work_bytes < mclbm_backward_work_bytes(c, ckpt_every))
     return fail(MCLBM_ERR_OOM, "backward work buffer too small");
   if (!dJdY_dev) return fail(MCLBM_ERR_ARG, "dJdY_dev is NULL");
+  if (c->fwd_generation == 0 || c->generation != c->fwd_generation)
+    return fail(MCLBM_ERR_STATE, "the state changed since mclbm_forward_ckpt (backward needs the state it left)");
+  uint64_t token = 0;
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  HIP_TRY(hipMemcpy(&token, ckpt_dev, sizeof(token), hipMemcpyDeviceToHost));
+  if (token != c->fwd_token)
+    return fail(MCLBM_ERR_STATE, "the checkpoints were not written by the last mclbm_forward_ckpt of this context");
 
   char* w = static_cast<char*>(work_dev);
   char* seg_states = w;
@@ -871,7 +901,7 @@ mclbm_status mclbm_backward(mclbm_ctx* c, int64_t ticks, int32_t ckpt_every, con
   for (int64_t k = nseg - 1; k >= 0; --k) {
     const int64_t n0 = k * ckpt_every;
     const int64_t n1 = std::min<int64_t>(ticks, n0 + ckpt_every);
-    const char* ck = static_cast<const char*>(ckpt_dev) + size_t(k) * c->state_bytes;
+    const char* ck = static_cast<const char*>(ckpt_dev) + kFwdHeaderBytes + size_t(k) * c->state_bytes;
     auto state_at = [&](int64_t n) -> const char* {
       return n == n0 ? ck : seg_states + size_t(n - n0) * c->state_bytes;
     };
@@ -889,6 +919,43 @@ mclbm_status mclbm_backward(mclbm_ctx* c, int64_t ticks, int32_t ckpt_every, con
                               c->d_ycoef, partials, c->stream));
   HIP_TRY(launch_init_adjoint_finalize(partials, table_ptr(c, nat), nat->nseg, c->d_samples, c->d_pmat, dJdY_dev,
                                        c->stream));
+  return MCLBM_OK;
+}
+
+size_t mclbm_step_vjp_work_bytes(const mclbm_ctx* c) { return c ? 3 * c->state_bytes : 0; }
+
+mclbm_status mclbm_step_vjp(mclbm_ctx* c, const double* lam_dev, double* out_dev, void* work_dev,
+                            size_t work_bytes) {
+  mclbm_status st = check_adjoint(c, 1, 1);
+  if (st != MCLBM_OK) return st;
+  if (!lam_dev || !out_dev) return fail(MCLBM_ERR_ARG, "lam_dev and out_dev must be given");
+  if (!work_dev || work_bytes < mclbm_step_vjp_work_bytes(c)) return fail(MCLBM_ERR_OOM, "work buffer too small");
+  char* state = static_cast<char*>(work_dev);
+  char* lam_in = state + c->state_bytes;
+  char* lam_out = lam_in + c->state_bytes;
+  st = reserve_tables(c, 2);       // the two tables below are held together
+  if (st != MCLBM_OK) return st;
+  const Table* live = nullptr;     // every sample at its own parity
+  st = get_table(c, c->tick, true, kAuxBlock, false, &live);
+  if (st != MCLBM_OK) return st;
+  const Table* nat = nullptr;      // every sample, natural layout
+  st = get_table(c, 0, true, kAuxBlock, true, &nat);
+  if (st != MCLBM_OK) return st;
+  HIP_TRY(launch_canonical_copy(c->q, c->precision, c->pop, state, c->d_samples, table_ptr(c, live), live->nseg,
+                                live->total_blocks, c->stream));
+  size_t off = 0;
+  for (int s = 0; s < c->m; ++s) {
+    HIP_TRY(launch_put_adjoint(c->q, c->precision, lam_in, c->d_samples, s, c->desc[s].n, lam_dev + off, c->stream));
+    off += size_t(c->q) * size_t(c->cells(s));
+  }
+  const int32_t buffer_ok = make_launch(c, nat, c->pop, nullptr).buffer_ok;
+  HIP_TRY(launch_adjoint_step(c->q, c->precision, state, lam_in, lam_out, c->d_samples, table_ptr(c, nat), nat->nseg,
+                              nat->total_blocks, buffer_ok, c->exact_gamma, c->stream));
+  off = 0;
+  for (int s = 0; s < c->m; ++s) {
+    HIP_TRY(launch_get_adjoint(c->q, c->precision, lam_out, c->d_samples, s, c->desc[s].n, out_dev + off, c->stream));
+    off += size_t(c->q) * size_t(c->cells(s));
+  }
   return MCLBM_OK;
 }
 
@@ -1169,12 +1236,36 @@ mclbm_status mclbm_dissipation(mclbm_ctx* c, const double* records_dev, int32_t 
   return MCLBM_OK;
 }
 
+mclbm_status mclbm_dissipation_spectra(mclbm_ctx* c, int32_t first, int32_t count, const double* ek_dev,
+                                       int32_t nrec, int64_t first_tick, int32_t record_every, double* diss_dev,
+                                       double* eta_dev) {
+  mclbm_status st = check_ctx(c, false);
+  if (st != MCLBM_OK) return st;
+  if (!ek_dev || !diss_dev) return fail(MCLBM_ERR_ARG, "ek_dev and diss_dev must be given");
+  if (first < 0 || count < 1 || int64_t(first) + count > c->m)
+    return fail(MCLBM_ERR_ARG, "the sample range leaves the ensemble");
+  if (nrec < 2) return fail(MCLBM_ERR_ARG, "at least two saved spectra are needed");
+  if (first_tick < 0 || record_every < 1) return fail(MCLBM_ERR_ARG, "first_tick >= 0 and record_every >= 1");
+  const int n = c->desc[first].n;
+  for (int s = first; s < first + count; ++s) {
+    if (c->desc[s].n != n) return fail(MCLBM_ERR_ARG, "the samples of the range must share one resolution");
+    if (first_tick % c->desc[s].stride || record_every % c->desc[s].stride)
+      return fail(MCLBM_ERR_ARG, "saved times must fall on ticks where every sample of the range steps");
+    if (eta_dev && c->desc[s].re != c->desc[first].re)
+      return fail(MCLBM_ERR_ARG, "the Kolmogorov length needs one viscosity for the whole range");
+  }
+  HIP_TRY(launch_dissipation_spectra(ek_dev, n, c->d_diss + first, count, nrec, first_tick, record_every,
+                                     1.0 / c->desc[first].re, diss_dev, eta_dev, c->stream));
+  return MCLBM_OK;
+}
+
 mclbm_status mclbm_set_stabiliser(mclbm_ctx* c, int32_t mode) {
   mclbm_status st = check_ctx(c, false);
   if (st != MCLBM_OK) return st;
   if (mode != MCLBM_GAMMA_CLOSED_FORM && mode != MCLBM_GAMMA_EXACT)
     return fail(MCLBM_ERR_ARG, "stabiliser mode must be 0 (closed form) or 1 (exact)");
   HIP_TRY(hipStreamSynchronize(c->stream));
+  c->generation += 1;
   c->exact_gamma = mode == MCLBM_GAMMA_EXACT;
   if (c->exact_gamma) c->block = 256;  // every lattice has at least 512 nodes
   drop_graphs(c);

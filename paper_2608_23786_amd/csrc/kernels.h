@@ -65,6 +65,13 @@ hipError_t launch_poison(int q, int precision, void* pop, const DevSample* sampl
 hipError_t launch_canonical_copy(int q, int precision, const void* pop, void* dst, const DevSample* samples,
                                  const Seg* segs, int32_t nseg, int32_t total_blocks, hipStream_t s);
 
+// Adjoint vectors of one sample, lam[q][n^3] in double, into or out of the
+// natural layout (no weight shift) of a buffer with the state's offsets.
+hipError_t launch_put_adjoint(int q, int precision, void* dst, const DevSample* samples, int32_t sample, int32_t n,
+                              const double* lam, hipStream_t s);
+hipError_t launch_get_adjoint(int q, int precision, const void* src, const DevSample* samples, int32_t sample,
+                              int32_t n, double* lam, hipStream_t s);
+
 // Adjoint: seed lambda_T from the state (parity-aware), one reverse step, and the
 // initial-data adjoint with its per-sample projection onto the 24 parameters.
 hipError_t launch_adjoint_seed(int q, int precision, const void* pop, void* lam, const DevSample* samples,
@@ -89,6 +96,11 @@ struct DissSample {
 hipError_t launch_dissipation(const double* records, const DissSample* smp, int32_t m, int32_t nrec,
                               int64_t first_tick, int32_t record_every, double eps, double* diss, double* eta,
                               hipStream_t s);
+// The same from the spectra ek[nrec][count][n/2+1] of `count` samples of one
+// resolution (smp points at the first of them): E = sum over kappa.
+hipError_t launch_dissipation_spectra(const double* ek, int32_t n, const DissSample* smp, int32_t count,
+                                      int32_t nrec, int64_t first_tick, int32_t record_every, double eps,
+                                      double* diss, double* eta, hipStream_t s);
 
 hipError_t launch_stream_copy(void* dst, const void* src, size_t bytes, hipStream_t s);
 

@@ -193,6 +193,33 @@ __global__ void __launch_bounds__(256)
   write_state<QN>(dst + sp.offset, sp.pstride, c, false, g);
 }
 
+// Adjoint vectors lam[q][n^3] (double, the population order of get_state)
+// into or out of the natural layout of the storage type. No shift: an
+// adjoint is a derivative, which the constant weights do not enter.
+template <int QN, typename T>
+__global__ void __launch_bounds__(256) put_adjoint_kernel(T* dst, const DevSample* samples, int sample,
+                                                          const double* lam) {
+  const DevSample& sp = samples[sample];
+  const uint32_t ncell = 1u << (3 * sp.log2n);
+  const uint32_t cell = blockIdx.x * 256u + threadIdx.x;
+  for_vel<QN>([&](auto ic) {
+    constexpr int k = plane_of<QN>(decltype(ic)::value);
+    dst[sp.offset + size_t(k) * sp.pstride + cell] = T(lam[size_t(k) * ncell + cell]);
+  });
+}
+
+template <int QN, typename T>
+__global__ void __launch_bounds__(256) get_adjoint_kernel(const T* src, const DevSample* samples, int sample,
+                                                          double* lam) {
+  const DevSample& sp = samples[sample];
+  const uint32_t ncell = 1u << (3 * sp.log2n);
+  const uint32_t cell = blockIdx.x * 256u + threadIdx.x;
+  for_vel<QN>([&](auto ic) {
+    constexpr int k = plane_of<QN>(decltype(ic)::value);
+    lam[size_t(k) * ncell + cell] = double(src[sp.offset + size_t(k) * sp.pstride + cell]);
+  });
+}
+
 // ---------------------------------------------------------------- adjoint
 // Seed: J = (1/M) sum_m KE_m with KE = (1/n^3) sum_x |u|^2 / 2, u = j / rho:
 // dJ/dg_i(x) = (1 / (M n^3)) (c_i . u - |u|^2) / rho.
@@ -515,23 +542,44 @@ __global__ void extract_kernel(const double* records, int m, int field, double* 
   if (s < m) out[s] = records[size_t(s) * kRecord + field];
 }
 
-// Dissipation rate per sample and record, d = -dKE/dt in physical units
-// (KE / u0^2 against t = steps * (2 pi / n) * u0): centred differences inside
-// the series, one-sided at its ends; and eta = (eps^3 / mean_s d)^(1/4).
-// One thread per record.
-__global__ void dissipation_kernel(const double* records, const DissSample* smp, int m, int nrec,
-                                   int64_t first_tick, int record_every, double eps, double* diss, double* eta) {
+// Energy per unit volume of sample s at record k, in lattice units: the
+// kinetic energy of a record of the step kernel (field 4, the mean of |u|^2/2
+// over the nodes), or the shell spectrum of eq. (energySpecDisc) summed over
+// kappa = 0..n/2 in fixed order.
+struct RecordEnergy {
+  const double* rec;
+  int m;
+  __device__ double operator()(int k, int s) const { return rec[(size_t(k) * m + s) * kRecord + 4]; }
+};
+struct SpectrumEnergy {
+  const double* ek;
+  int count, len;
+  __device__ double operator()(int k, int s) const {
+    const double* e = ek + (size_t(k) * count + s) * len;
+    double sum = 0.0;
+    for (int j = 0; j < len; ++j) sum += e[j];
+    return sum;
+  }
+};
+
+// Dissipation rate per sample and record, d = -dE/dt in physical units (E /
+// u0^2 against t = steps * (2 pi / n) * u0): centred differences inside the
+// series, one-sided at its ends; and eta = (eps^3 / mean_s d)^(1/4). One
+// thread per record.
+template <class Energy>
+__global__ void dissipation_kernel(Energy energy, const DissSample* smp, int m, int nrec, int64_t first_tick,
+                                   int record_every, double eps, double* diss, double* eta) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= nrec) return;
   const int k0 = k > 0 ? k - 1 : 0, k1 = k + 1 < nrec ? k + 1 : nrec - 1;
   double mean = 0.0;
   for (int s = 0; s < m; ++s) {
     const DissSample& d = smp[s];
-    const double ke0 = records[(size_t(k0) * m + s) * kRecord + 4] * d.inv_u0sq;
-    const double ke1 = records[(size_t(k1) * m + s) * kRecord + 4] * d.inv_u0sq;
+    const double e0 = energy(k0, s) * d.inv_u0sq;
+    const double e1 = energy(k1, s) * d.inv_u0sq;
     const double t0 = double((first_tick + int64_t(k0) * record_every) / d.stride) * d.dt;
     const double t1 = double((first_tick + int64_t(k1) * record_every) / d.stride) * d.dt;
-    const double v = -(ke1 - ke0) / (t1 - t0);
+    const double v = -(e1 - e0) / (t1 - t0);
     diss[size_t(k) * m + s] = v;
     mean += v;
   }
@@ -648,6 +696,28 @@ hipError_t launch_canonical_copy(int q, int precision, const void* pop, void* ds
   });
 }
 
+hipError_t launch_put_adjoint(int q, int precision, void* dst, const DevSample* samples, int32_t sample, int32_t n,
+                              const double* lam, hipStream_t s) {
+  const unsigned blocks = unsigned((uint64_t(n) * n * n) / 256);
+  return dispatch(q, precision, [&](auto qc, auto tc) {
+    using T = decltype(tc);
+    hipLaunchKernelGGL((put_adjoint_kernel<decltype(qc)::value, T>), dim3(blocks), dim3(256), 0, s,
+                       static_cast<T*>(dst), samples, sample, lam);
+    return hipGetLastError();
+  });
+}
+
+hipError_t launch_get_adjoint(int q, int precision, const void* src, const DevSample* samples, int32_t sample,
+                              int32_t n, double* lam, hipStream_t s) {
+  const unsigned blocks = unsigned((uint64_t(n) * n * n) / 256);
+  return dispatch(q, precision, [&](auto qc, auto tc) {
+    using T = decltype(tc);
+    hipLaunchKernelGGL((get_adjoint_kernel<decltype(qc)::value, T>), dim3(blocks), dim3(256), 0, s,
+                       static_cast<const T*>(src), samples, sample, lam);
+    return hipGetLastError();
+  });
+}
+
 hipError_t launch_adjoint_seed(int q, int precision, const void* pop, void* lam, const DevSample* samples,
                                const Seg* segs, int32_t nseg, int32_t total_blocks, double inv_m, hipStream_t s) {
   return dispatch(q, precision, [&](auto qc, auto tc) {
@@ -710,8 +780,17 @@ hipError_t launch_extract(const double* records, int32_t m, int32_t field, doubl
 hipError_t launch_dissipation(const double* records, const DissSample* smp, int32_t m, int32_t nrec,
                               int64_t first_tick, int32_t record_every, double eps, double* diss, double* eta,
                               hipStream_t s) {
-  hipLaunchKernelGGL(dissipation_kernel, dim3((nrec + 63) / 64), dim3(64), 0, s, records, smp, m, nrec, first_tick,
-                     record_every, eps, diss, eta);
+  hipLaunchKernelGGL(dissipation_kernel<RecordEnergy>, dim3((nrec + 63) / 64), dim3(64), 0, s,
+                     RecordEnergy{records, m}, smp, m, nrec, first_tick, record_every, eps, diss, eta);
+  return hipGetLastError();
+}
+
+hipError_t launch_dissipation_spectra(const double* ek, int32_t n, const DissSample* smp, int32_t count,
+                                      int32_t nrec, int64_t first_tick, int32_t record_every, double eps,
+                                      double* diss, double* eta, hipStream_t s) {
+  hipLaunchKernelGGL(dissipation_kernel<SpectrumEnergy>, dim3((nrec + 63) / 64), dim3(64), 0, s,
+                     SpectrumEnergy{ek, count, n / 2 + 1}, smp, count, nrec, first_tick, record_every, eps, diss,
+                     eta);
   return hipGetLastError();
 }
 

@@ -21,7 +21,7 @@
 namespace mclbm {
 
 constexpr int Q = 27;  // size of the velocity numbering (register arrays are indexed by it)
-constexpr int kMaxSamples = 256;
+constexpr int kMaxSamples = 65536;  // samples per ensemble (tables are sized by m)
 
 __host__ __device__ constexpr int cx(int i) { return i / 9 - 1; }
 __host__ __device__ constexpr int cy(int i) { return (i / 3) % 3 - 1; }

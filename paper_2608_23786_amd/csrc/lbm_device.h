@@ -42,7 +42,7 @@ namespace mclbm {
 namespace {
 
 template <int I, int N, typename F>
-__device__ __forceinline__ void static_for(F&& f) {
+__host__ __device__ __forceinline__ void static_for(F&& f) {
   if constexpr (I < N) {
     f(std::integral_constant<int, I>{});
     static_for<I + 1, N>(f);
@@ -51,7 +51,7 @@ __device__ __forceinline__ void static_for(F&& f) {
 
 // f(i) for every velocity i of the lattice (D3Q27 numbering, ascending)
 template <int QN, typename F>
-__device__ __forceinline__ void for_vel(F&& f) {
+__host__ __device__ __forceinline__ void for_vel(F&& f) {
   static_for<0, Q>([&](auto ic) {
     if constexpr (in_lattice<QN>(decltype(ic)::value)) f(ic);
   });
@@ -410,7 +410,7 @@ struct Cell {
   uint32_t ox[3], oy[3], oz[3];  // neighbour coordinates along each axis: -1, 0, +1
 };
 
-__device__ __forceinline__ Cell make_cell(uint32_t cell, int l) {
+__host__ __device__ __forceinline__ Cell make_cell(uint32_t cell, int l) {
   Cell c;
   c.cell = cell;
   const uint32_t msk = (1u << l) - 1u;
@@ -429,17 +429,38 @@ __device__ __forceinline__ Cell make_cell(uint32_t cell, int l) {
 
 // index of the neighbour x + s * c_i
 template <int i, int s>
-__device__ __forceinline__ uint32_t neighbour(const Cell& c) {
+__host__ __device__ __forceinline__ uint32_t neighbour(const Cell& c) {
   return c.oz[1 + s * cz(i)] + c.oy[1 + s * cy(i)] + c.ox[1 + s * cx(i)];
+}
+
+// AA slots of population i (D3Q27 numbering) of the node at c: the slot a
+// step of the given parity reads it from before the collision, and the slot
+// it writes the post-collision value to. A slot is a velocity (whose storage
+// plane holds it) and a node. Even step: read slot i of the node, write slot
+// opposite(i) of the node. Odd step: read slot opposite(i) of x - c_i, write
+// slot i of x + c_i. The odd step's read undoes the even step's write of
+// population i at x - c_i, so the pair streams by c_i twice over two steps,
+// once per step.
+struct Slot {
+  int vel;
+  uint32_t idx;
+};
+template <int i>
+__host__ __device__ __forceinline__ Slot aa_read_slot(const Cell& c, bool odd) {
+  return odd ? Slot{opposite(i), neighbour<i, -1>(c)} : Slot{i, c.cell};
+}
+template <int i>
+__host__ __device__ __forceinline__ Slot aa_write_slot(const Cell& c, bool odd) {
+  return odd ? Slot{i, neighbour<i, +1>(c)} : Slot{opposite(i), c.cell};
 }
 
 // element access with a 32-bit byte offset from a uniform plane base
 template <typename T>
-__device__ __forceinline__ T ld(const T* plane, uint32_t idx) {
+__host__ __device__ __forceinline__ T ld(const T* plane, uint32_t idx) {
   return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(plane) + idx * uint32_t(sizeof(T)));
 }
 template <typename T>
-__device__ __forceinline__ void st(T* plane, uint32_t idx, T v) {
+__host__ __device__ __forceinline__ void st(T* plane, uint32_t idx, T v) {
   *reinterpret_cast<T*>(reinterpret_cast<char*>(plane) + idx * uint32_t(sizeof(T))) = v;
 }
 
@@ -499,36 +520,27 @@ struct PtrPlanes {
   }
 };
 
-// populations of the post-stream state at a node, for either AA parity
+// populations of the post-stream state at a node, for either AA parity: the
+// slots the next step reads them from
 template <int QN, typename T>
-__device__ __forceinline__ void load_state(const T* base, uint32_t pstride, const Cell& c, bool odd, T (&g)[Q]) {
-  if (!odd) {
-    for_vel<QN>([&](auto ic) {
-      constexpr int i = decltype(ic)::value;
-      g[i] = ld(base + size_t(plane_of<QN>(i)) * pstride, c.cell);
-    });
-  } else {
-    for_vel<QN>([&](auto ic) {
-      constexpr int i = decltype(ic)::value;
-      g[i] = ld(base + size_t(plane_of<QN>(opposite(i))) * pstride, neighbour<i, -1>(c));
-    });
-  }
+__host__ __device__ __forceinline__ void load_state(const T* base, uint32_t pstride, const Cell& c, bool odd,
+                                                    T (&g)[Q]) {
+  for_vel<QN>([&](auto ic) {
+    constexpr int i = decltype(ic)::value;
+    const Slot s = aa_read_slot<i>(c, odd);
+    g[i] = ld(base + size_t(plane_of<QN>(s.vel)) * pstride, s.idx);
+  });
 }
 
 // the inverse mapping: write a post-stream state at a node
 template <int QN, typename T>
-__device__ __forceinline__ void write_state(T* base, uint32_t pstride, const Cell& c, bool odd, const T (&g)[Q]) {
-  if (!odd) {
-    for_vel<QN>([&](auto ic) {
-      constexpr int i = decltype(ic)::value;
-      st(base + size_t(plane_of<QN>(i)) * pstride, c.cell, g[i]);
-    });
-  } else {
-    for_vel<QN>([&](auto ic) {
-      constexpr int i = decltype(ic)::value;
-      st(base + size_t(plane_of<QN>(opposite(i))) * pstride, neighbour<i, -1>(c), g[i]);
-    });
-  }
+__host__ __device__ __forceinline__ void write_state(T* base, uint32_t pstride, const Cell& c, bool odd,
+                                                     const T (&g)[Q]) {
+  for_vel<QN>([&](auto ic) {
+    constexpr int i = decltype(ic)::value;
+    const Slot s = aa_read_slot<i>(c, odd);
+    st(base + size_t(plane_of<QN>(s.vel)) * pstride, s.idx, g[i]);
+  });
 }
 
 // ---------------------------------------------------------------- x-shifts without partial cache lines
@@ -608,11 +620,11 @@ __device__ __forceinline__ void row_shift(T (&v)[Q], EdgeLds<T, BLOCK>& edge, ui
 
 // index of x + s * (0, c_i,y, c_i,z): the node of the same x in the shifted row
 template <int i, int s>
-__device__ __forceinline__ uint32_t neighbour_yz(const Cell& c) {
+__host__ __device__ __forceinline__ uint32_t neighbour_yz(const Cell& c) {
   return c.oz[1 + s * cz(i)] + c.oy[1 + s * cy(i)] + c.ox[1];
 }
 
-__device__ __forceinline__ int remap_block(int b, int total, int xcd_remap) {
+__host__ __device__ __forceinline__ int remap_block(int b, int total, int xcd_remap) {
   // hardware dispatches workgroup b to XCD b % 8; give each XCD a contiguous run
   if (xcd_remap) {
     const int g8 = total & ~7;
@@ -621,7 +633,7 @@ __device__ __forceinline__ int remap_block(int b, int total, int xcd_remap) {
   return b;
 }
 
-__device__ __forceinline__ int find_segment(const Seg* segs, int nseg, int b) {
+__host__ __device__ __forceinline__ int find_segment(const Seg* segs, int nseg, int b) {
   int lo = 0, hi = nseg - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;

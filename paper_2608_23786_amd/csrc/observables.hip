@@ -77,10 +77,14 @@ __device__ __forceinline__ int bitrev(int i) {
 // on a few of them.
 __device__ __forceinline__ int lds_pos(int p) { return p + (p >> 4); }
 
-// LDS slots of a line of N complex values
+// LDS slots from one line of N complex values to the next: the padded line
+// plus one slot, an odd number of 16-byte slots, so that the lanes of a wave
+// that touch the same element of consecutive lines (the loads and stores of
+// the y and z passes, where consecutive lanes take consecutive lines to keep
+// their global accesses contiguous) fall on different banks.
 template <int N>
 constexpr int lds_line() {
-  return N + N / 16;
+  return N + N / 16 + 1;
 }
 
 // e^{sign 2 pi i k / N}, k < N/2, at tw[lds_pos(k)]

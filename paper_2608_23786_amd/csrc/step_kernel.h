@@ -43,7 +43,8 @@ __global__ void __launch_bounds__(BLOCK) kbc_step_kernel(StepArgs<T> a) {
   if (!odd) {
     for_vel<QN>([&](auto ic) {
       constexpr int i = decltype(ic)::value;
-      g[i] = src.load(i, c.cell);
+      const Slot s = aa_read_slot<i>(c, false);
+      g[i] = src.load(s.vel, s.idx);
     });
   } else if (rows) {
     for_vel<QN>([&](auto ic) {
@@ -54,7 +55,8 @@ __global__ void __launch_bounds__(BLOCK) kbc_step_kernel(StepArgs<T> a) {
   } else {
     for_vel<QN>([&](auto ic) {
       constexpr int i = decltype(ic)::value;
-      g[i] = src.load(opposite(i), neighbour<i, -1>(c));
+      const Slot s = aa_read_slot<i>(c, true);
+      g[i] = src.load(s.vel, s.idx);
     });
   }
   const CellResult<T> res = kbc_collide<QN, EXACT>(g, relax_of<T>(sp));
@@ -67,7 +69,8 @@ __global__ void __launch_bounds__(BLOCK) kbc_step_kernel(StepArgs<T> a) {
     if (!pushes) {
       for_vel<QN>([&](auto ic) {
         constexpr int i = decltype(ic)::value;
-        dst.store(opposite(i), c.cell, g[i]);
+        const Slot s = aa_write_slot<i>(c, false);
+        dst.store(s.vel, s.idx, g[i]);
       });
     } else if (rows) {
       row_shift<QN, +1, BLOCK>(g, edge_out, n);
@@ -78,7 +81,8 @@ __global__ void __launch_bounds__(BLOCK) kbc_step_kernel(StepArgs<T> a) {
     } else {
       for_vel<QN>([&](auto ic) {
         constexpr int i = decltype(ic)::value;
-        dst.store(i, neighbour<i, +1>(c), g[i]);
+        const Slot s = aa_write_slot<i>(c, true);
+        dst.store(s.vel, s.idx, g[i]);
       });
     }
   }

@@ -289,6 +289,27 @@ class Ensemble:
         self._produce(diss, et)
         return diss, et
 
+    def dissipation_spectra(self, first: int, ek: torch.Tensor, first_tick: int, record_every: int,
+                            eta: bool = True):
+        """The paper's approximation of the dissipation rate, -d/dt of the
+        summed shell spectrum: d[nrec, count] (physical units) and, when eta,
+        the Kolmogorov length eta[nrec] from spectra ek[nrec, count, n/2+1] of
+        samples first..first+count-1 (one n) saved every record_every ticks
+        from first_tick."""
+        _require_cuda(ek, torch.float64, name="ek")
+        if ek.dim() != 3:
+            raise ValueError("ek must be [nrec, count, n/2+1]")
+        nrec, count = ek.shape[0], ek.shape[1]
+        if not 0 <= first < self.m or ek.shape[2] != self.samples[first].n // 2 + 1:
+            raise ValueError("ek rows must hold n/2+1 values of the range's resolution")
+        diss = self._dev_empty((nrec, count))
+        et = self._dev_empty((nrec,)) if eta else None
+        self._consume(ek)
+        check(lib().mclbm_dissipation_spectra(self._ctx, first, count, _ptr(ek), nrec, first_tick, record_every,
+                                              _ptr(diss), _ptr(et) if et is not None else None))
+        self._produce(diss, et)
+        return diss, et
+
     def compensate(self, first: int, diss: torch.Tensor, s2: Optional[torch.Tensor] = None,
                    ek: Optional[torch.Tensor] = None):
         """Sample-wise compensated structure functions [count, n/2] and spectra
@@ -337,6 +358,20 @@ class Ensemble:
         check(lib().mclbm_forward_ckpt(self._ctx, ticks, ckpt_every, _ptr(ck), nb))
         self._produce(ck)
         return ck
+
+    def step_vjp(self, lam: torch.Tensor) -> torch.Tensor:
+        """One step's vector-Jacobian product at the current state of every
+        sample: (d f_{n+1} / d f_n)^T lam. lam: float64 on the device, the
+        samples one after another, each [q, n^3] in the order of get_state."""
+        total = sum(self.q * s.n ** 3 for s in self.samples)
+        _require_cuda(lam, torch.float64, numel=total, name="lam")
+        wb = int(lib().mclbm_step_vjp_work_bytes(self._ctx))
+        work = self._dev_empty((wb,), torch.uint8)
+        out = self._dev_empty((total,))
+        self._consume(lam)
+        check(lib().mclbm_step_vjp(self._ctx, _ptr(lam), _ptr(out), _ptr(work), wb))
+        self._produce(out)
+        return out
 
     def backward(self, ticks: int, ckpt_every: int, ckpt: torch.Tensor):
         wb = int(lib().mclbm_backward_work_bytes(self._ctx, ckpt_every))

@@ -20,8 +20,9 @@ def test_more_than_one_gpu_is_refused():
 def test_cpu_baseline_times_the_oracle():
     sys.path.insert(0, ROOT)
     import bench
-    out = bench.cpu_baseline(seconds_target=0.5, large=False)
+    out, (steps, u_ref) = bench.cpu_baseline(seconds_target=0.5, large=False)
     assert out["kind"] == "oracle" and out["unit"] == "MLUPS" and out["value"] > 0
+    assert steps >= 4 and u_ref.shape == (3, 64, 64, 64)
     assert out["cores"] == len(os.sched_getaffinity(0)) and out["single_core_MLUPS"] > 0
     assert "64^3" in out["sample"] and isinstance(out["cpu_model"], str) and out["tgv32_f64_100_steps_MLUPS"] > 0
 
@@ -48,3 +49,19 @@ def test_short_bench_line(monkeypatch, capsys):
     assert 0 < rf["frac"] < 1 and abs(rf["frac"] - rf["achieved"] / rf["peak"]) < 1e-3
     assert rf["algorithmic_bytes_per_launch"] == 216 * 64 * 64 ** 3
     assert rf["traffic"] is None or abs(rf["traffic"] / rf["algorithmic_bytes_per_launch"] - 1) < 0.01
+
+
+@pytest.mark.gpu
+def test_bench_measures_the_velocity_error_against_the_oracle():
+    """The error field of the bench line: the GPU's sample 0 after the CPU
+    baseline's number of steps against the oracle's field of that run."""
+    sys.path.insert(0, ROOT)
+    import bench
+    import mc_inputs
+    import paper_2608_23786_amd as mc
+    import torch
+    _, (steps, u_ref) = bench.cpu_baseline(seconds_target=0.5, large=False)
+    wl = mc_inputs.WORKLOADS["rtgv64x64_f32"]
+    err = bench.measured_error(mc, torch, wl, (256, 0, 1, 1), steps, u_ref)
+    print(err)
+    assert err["steps"] == steps and 0 < err["rel_l2_u_vs_oracle"] < 1e-5

@@ -250,3 +250,140 @@ def test_gradient_reference_32cubed_1000_steps(precision, tol):
     print(f"{precision}: max |adjoint - reference| / max|reference| = {err:.3e}")
     assert err < tol
     assert np.max(np.abs(ke - np.array(ref["ke"])) / np.array(ref["ke"])) < (1e-12 if precision == "f64" else 1e-5)
+
+
+def _nonequilibrium_state(n, q, seed):
+    """An RTGV equilibrium times (1 + 2e-3 noise), f[n^3][q] (oracle layout):
+    both the shear and the higher-order parts of f^neq are non-zero."""
+    y = mc_inputs.draw_y(seed, 1)[0]
+    f = oracle.init_populations(n, 0.05 * 16 / n, 0.5, y, True, q)
+    return f * (1.0 + mc_inputs.random_populations(seed, f.shape, 2e-3))
+
+
+@pytest.mark.parametrize("n,q,stabiliser,precision,tol", [
+    (8, 27, "closed_form", "f64", 1e-12), (128, 27, "closed_form", "f64", 1e-12),
+    (8, 19, "closed_form", "f64", 1e-12), (128, 19, "closed_form", "f64", 1e-12),
+    (8, 27, "exact", "f64", 1e-11), (16, 19, "exact", "f64", 1e-11),
+    (8, 27, "closed_form", "f32s", 1e-5), (128, 27, "closed_form", "f32s", 1e-5)])
+def test_per_step_adjoint_is_the_transpose_of_the_step(n, q, stabiliser, precision, tol):
+    """Dot-product test of one reverse step: <J v, lam> = <v, J^T lam> for
+    random v and lam, with J the Jacobian of one collide-and-stream step at
+    a non-equilibrium state. J v comes from the oracle's complex step
+    (Im step(f + i h v) / h, h = 1e-30, exact to rounding) on its own copy
+    of the state; J^T lam from the library's reverse-step kernel. n = 128
+    rows span two waves (the row exchange of the forward kernel). The
+    difference of the two dot products is measured against the sum of the
+    absolute values of their terms, the scale of the rounding of either sum
+    (random v and lam make the sums cancel by up to an order of magnitude).
+    FP64: both sides exact to rounding (the closed-form stabiliser's ratio
+    of inner products amplifies per-node rounding to ~1e-13), bound 1e-12
+    (1e-11 for the exact stabiliser, whose Newton iterate is converged to
+    rounding only up to its stopping rule). FP32: the reverse step in
+    float on a float copy of the state, ~30-term sums per output, bound
+    1e-5."""
+    f = _nonequilibrium_state(n, q, 60 + n + q)
+    ncell = n ** 3
+    v = mc_inputs.random_populations(1000 + n, (ncell, q), 1.0)
+    lam = mc_inputs.random_populations(2000 + n, (ncell, q), 1.0)
+    u0, re = 0.05 * 16 / n, 50.0
+    omega = oracle.omega_shear(oracle.lattice_viscosity(n, u0, re))
+    mode = oracle.MODE_EXACT if stabiliser == "exact" else oracle.MODE_KBC
+    h = 1e-30
+    fz = f.astype(np.complex128) + 1j * h * v
+    oracle.run(fz, n, 1, omega, mode=mode)
+    jv = fz.imag / h
+    lhs = float(np.sum(jv * lam))
+    scale = float(np.sum(np.abs(jv * lam)))      # the size of the terms the two sums add
+
+    ens = mc.Ensemble([mc.Sample(n, u0, re, 0.5, True)], precision, lattice=q)
+    ens.init(0)
+    ens.set_stabiliser(stabiliser)
+    ens.set_state(0, torch.from_numpy(np.ascontiguousarray(f.T)).cuda())
+    out = ens.step_vjp(torch.from_numpy(np.ascontiguousarray(lam.T)).reshape(-1).cuda())
+    rhs = float(np.sum(v.T.reshape(-1) * out.cpu().numpy()))
+    rel = abs(lhs - rhs) / scale
+    print(f"n {n} D3Q{q} {stabiliser} {precision}: <Jv, lam> = {lhs:.15e}, <v, J^T lam> = {rhs:.15e}, "
+          f"|difference| / sum |terms| {rel:.2e}, / |<Jv, lam>| {abs(lhs - rhs) / abs(lhs):.2e}")
+    assert rel < tol
+    # the state is not advanced
+    assert ens.ticks == 0
+
+
+@pytest.mark.parametrize("q,stabiliser", [(27, "closed_form"), (19, "closed_form"), (27, "exact")])
+def test_step_vjp_keeps_the_collision_invariants(q, stabiliser):
+    """Mass and momentum summed over the lattice are the same function of the
+    state before and after a step (the collision conserves them per node,
+    streaming moves populations), so the transpose maps the constant
+    adjoints lam_i(x) = 1 and lam_i(x) = c_i,a to themselves, at any state,
+    up to rounding (bound 1e-12: the closed-form stabiliser's ratio of inner
+    products amplifies per-node rounding to ~1e-13)."""
+    n = 16
+    f = _nonequilibrium_state(n, q, 80 + q)
+    c, _ = oracle.velocity_set(q)
+    ens = mc.Ensemble([mc.Sample(n, 0.05, 100.0, 0.5, True)], "f64", lattice=q)
+    ens.init(0)
+    ens.set_stabiliser(stabiliser)
+    ens.set_state(0, torch.from_numpy(np.ascontiguousarray(f.T)).cuda())
+    for a in range(4):
+        col = np.ones(q) if a == 3 else c[:, a].astype(np.float64)
+        lam = np.repeat(col[:, None], n ** 3, axis=1).reshape(-1)
+        out = ens.step_vjp(torch.from_numpy(lam).cuda()).cpu().numpy()
+        assert np.max(np.abs(out - lam)) < 1e-12, a
+
+
+def test_backward_refuses_checkpoints_of_an_earlier_forward():
+    """Two forward passes on one ensemble, then the backward of the first:
+    its checkpoints are not those of the state the ensemble now holds, and
+    the library refuses (MCLBM_ERR_STATE) instead of mixing the two runs.
+    The backward of the latest forward matches a single forward on a fresh
+    ensemble bit for bit; a step after a forward also makes the backward
+    refuse."""
+    samples = [mc.Sample(8, 0.05, 100.0, 0.5, True)] * 2
+    ens = mc.Ensemble(samples, "f64")
+    y1 = torch.from_numpy(mc_inputs.draw_y(71, 2)).requires_grad_(True)
+    y2 = torch.from_numpy(mc_inputs.draw_y(72, 2)).requires_grad_(True)
+    j1 = mc.EnsembleKE.apply(y1, ens, 10, 4)
+    j2 = mc.EnsembleKE.apply(y2, ens, 10, 4)
+    with pytest.raises(Exception, match="ERR_STATE"):
+        j1.backward()
+    j2.backward()
+    ref, _, _ = gpu_gradient(samples, "f64", y2.detach().numpy(), 10, 4)
+    assert np.array_equal(y2.grad.numpy(), ref)
+    ens.init(0, y1.detach())
+    ck = ens.forward_ckpt(10, 4)
+    ens.set_viscosity([1 / 100.0, 1 / 100.0])
+    with pytest.raises(mc.MclbmError, match="state changed"):
+        ens.backward(10, 4, ck)
+
+
+def test_fp32_gradient_of_the_adjoint_workload_against_fp64():
+    """Config 4 in the benchmarked shape: 8 x 128^3, FP32 forward over 1000
+    steps with a checkpoint every 50 and the FP32 reverse sweep, against the
+    FP64 adjoint of two of its samples over the same 1000 steps (the FP64
+    adjoint matches the oracle's complex step to ~1e-12). J is the mean over
+    the ensemble, so dJ/dY_m carries 1/M: the comparison is of M dJ/dY_m.
+    Bound 2e-3 of the largest component, as for the 32^3 reference over 1000
+    steps (linear accumulation of ~2e-6 per reverse step)."""
+    wl = mc_inputs.WORKLOADS["adjoint128x8_f32"]
+    g = wl.groups[0]
+    y = mc_inputs.draw_y(wl.seed, wl.m)
+    ens = mc.Ensemble([mc.Sample(g.n, g.u0, g.re, g.amp, g.project)] * wl.m, "f32s")
+    ens.init(0, torch.from_numpy(y))
+    ck = ens.forward_ckpt(wl.ticks, wl.save_every)
+    dj32, ke32 = ens.backward(wl.ticks, wl.save_every, ck)
+    dj32, ke32 = dj32.cpu().numpy() * wl.m, ke32.cpu().numpy()
+    del ens, ck
+    torch.cuda.empty_cache()
+    pick = [0, wl.m - 1]
+    ens = mc.Ensemble([mc.Sample(g.n, g.u0, g.re, g.amp, g.project)] * len(pick), "f64")
+    ens.init(0, torch.from_numpy(np.ascontiguousarray(y[pick])))
+    ck = ens.forward_ckpt(wl.ticks, wl.save_every)
+    dj64, ke64 = ens.backward(wl.ticks, wl.save_every, ck)
+    dj64, ke64 = dj64.cpu().numpy() * len(pick), ke64.cpu().numpy()
+    del ens, ck
+    torch.cuda.empty_cache()
+    for k, s in enumerate(pick):
+        err = np.max(np.abs(dj32[s] - dj64[k])) / np.max(np.abs(dj64[k]))
+        kerr = abs(ke32[s] / ke64[k] - 1)
+        print(f"sample {s}: FP32 gradient vs FP64 over 1000 steps {err:.2e}; KE {kerr:.2e}")
+        assert err < 2e-3 and kerr < 2e-5

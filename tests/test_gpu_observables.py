@@ -110,29 +110,96 @@ def test_w1_against_sorted_rearrangement(m):
     assert np.max(np.abs(w - ref)) < 1e-13
 
 
+def _oracle_series(n, u0, re, amp, y, project, saves, every, q=27):
+    """Kinetic energy, spectrum and dissipation-rate definition of the
+    oracle's own run of one sample after 0, every, 2 every, ... steps."""
+    om = oracle.omega_shear(oracle.lattice_viscosity(n, u0, re))
+    f = oracle.init_populations(n, u0, amp, y, project, q)
+    ke, ek, ddef = [], [], []
+    for k in range(saves):
+        if k:
+            oracle.run(f, n, every, om)
+        _, u = oracle.moments(f, n)
+        ke.append(oracle.kinetic_energy(u))
+        ek.append(oracle.energy_spectrum(u))
+        ddef.append(oracle.dissipation_rate_definition(u, 1.0 / re, u0))
+    return np.array(ke), np.array(ek), np.array(ddef)
+
+
+def _gpu_series(ens, count, saves, every):
+    """Records and spectra of the library at the same states: the spectra of
+    the state after k * every steps, then the tick that records it."""
+    eks, recs = [], []
+    for _ in range(saves):
+        _, ek = ens.observables_range(0, count, structure=False)
+        eks.append(ek)
+        recs.append(ens.step(every, record_every=every))
+    return torch.cat(recs), torch.stack(eks)
+
+
+@pytest.mark.parametrize("lattice", [27, 19])
+def test_dissipation_rates_and_kolmogorov_length_match_oracle(lattice):
+    """Both dissipation-rate forms and eq. (kolmogorov_microscale) element by
+    element against the oracle. On the library's own records and spectra the
+    oracle's decay-rate functions agree to rounding (1e-13). End to end, the
+    oracle runs the same two samples (FP64, 32^3, Re 100) and takes the same
+    differences of its own kinetic energies and spectra: the FP64 path
+    agrees with the oracle to ~2e-14 relative in KE, and a centred
+    difference over 8 steps divides by a change of ~1 % of KE, so the rates
+    agree to ~1e-12 relative (bound 1e-10)."""
+    n, u0, re, amp, every, saves = 32, 0.05, 100.0, 0.3, 4, 8
+    y = mc_inputs.draw_y(44, 2)
+    ens = mc.Ensemble([mc.Sample(n, u0, re, amp, True)] * 2, "f64", lattice=lattice)
+    ens.init(0, torch.from_numpy(y))
+    rec, ek = _gpu_series(ens, 2, saves, every)
+    d_ke, eta_ke = ens.dissipation(rec, 0, every)
+    d_sp, eta_sp = ens.dissipation_spectra(0, ek, 0, every)
+    rec, ek = rec.cpu().numpy(), ek.cpu().numpy()
+    d_ke, eta_ke, d_sp, eta_sp = (x.cpu().numpy() for x in (d_ke, eta_ke, d_sp, eta_sp))
+    t = oracle.state_time(np.arange(saves) * every, n, u0)
+    # the oracle's functions on the library's own inputs
+    ref_ke = oracle.dissipation_from_kinetic_energy(rec[:, :, 4], t, [u0, u0])
+    ref_sp = oracle.dissipation_from_spectra(ek, t, [u0, u0])
+    assert np.max(np.abs(d_ke - ref_ke)) <= 1e-13 * np.max(np.abs(ref_ke))
+    assert np.max(np.abs(d_sp - ref_sp)) <= 1e-13 * np.max(np.abs(ref_sp))
+    assert np.max(np.abs(eta_ke / oracle.kolmogorov_length(1 / re, ref_ke) - 1)) <= 1e-13
+    assert np.max(np.abs(eta_sp / oracle.kolmogorov_length(1 / re, ref_sp) - 1)) <= 1e-13
+    # end to end against the oracle's own run
+    series = [_oracle_series(n, u0, re, amp, y[s], True, saves, every, lattice) for s in range(2)]
+    o_ke = oracle.dissipation_from_kinetic_energy(np.stack([x[0] for x in series], axis=1), t, [u0, u0])
+    o_sp = oracle.dissipation_from_spectra(np.stack([x[1] for x in series], axis=1), t, [u0, u0])
+    err_ke = np.max(np.abs(d_ke - o_ke)) / np.max(np.abs(o_ke))
+    err_sp = np.max(np.abs(d_sp - o_sp)) / np.max(np.abs(o_sp))
+    print(f"D3Q{lattice}: dissipation vs oracle run, KE form {err_ke:.2e}, spectral form {err_sp:.2e}")
+    assert err_ke <= 1e-10 and err_sp <= 1e-10
+    assert np.max(np.abs(eta_sp / oracle.kolmogorov_length(1 / re, o_sp) - 1)) <= 1e-10
+
+
 def test_dissipation_rate_of_the_viscous_taylor_green_vortex():
-    """The dissipation rate per unit volume, -dKE/dt in physical units, of a
-    Taylor-Green vortex at Re 10: its velocity is a single |k|^2 = 3 mode that
-    decays like exp(-3 eps t), so -dKE/dt = 6 eps KE (eps = 1 / Re) once the
-    initial non-equilibrium layer of the lattice has relaxed (about 20 steps);
-    nonlinear transfer and the lattice error keep the ratio within a few per
-    cent over the next 60 steps. The library's finite differences of the
-    records are also checked against the records themselves, and eta against
-    its definition."""
-    n, u0, re, every, ticks = 32, 0.02, 10.0, 4, 120
+    """Physics of the two forms on a Taylor-Green vortex at Re 10 (FP64,
+    32^3): after the initial non-equilibrium layer of the lattice (about 20
+    steps) the decay of the kinetic energy per unit volume matches the
+    dissipation rate as the paper defines it (viscosity times the mean
+    squared velocity gradient, computed by the oracle on its own fields)
+    within 4 %, and the paper's approximation from the summed shell spectrum
+    is 4 pi 3 / 62 = 0.608 of it, since the energy stays mostly in the
+    |k|^2 = 3 modes of shell 2 (62 modes) at this Reynolds number; the part
+    that the lattice's initial layer and the nonlinear transfer move to other
+    modes carries other shell weights (measured within 2.2 %, bound 4 %)."""
+    n, u0, re, every, saves = 32, 0.02, 10.0, 4, 24
     ens = mc.Ensemble([mc.Sample(n, u0, re, 0.0, False)] * 2, "f64")
     ens.init(0, torch.zeros(2, 24, dtype=torch.float64))
-    rec = ens.step(ticks, record_every=every)
-    diss, eta = ens.dissipation(rec, 0, every)
-    rec, diss, eta = rec.cpu().numpy(), diss.cpu().numpy(), eta.cpu().numpy()
-    ke = rec[:, :, 4] / u0 ** 2
-    t = np.arange(len(ke)) * every * (2 * np.pi / n) * u0
-    ratio = diss[:, 0] / (6.0 / re * ke[:, 0])
-    print("d / (6 eps KE) at records 6..20:", np.round(ratio[6:21], 4))
+    rec, ek = _gpu_series(ens, 2, saves, every)
+    d_ke, _ = ens.dissipation(rec, 0, every)
+    d_sp, _ = ens.dissipation_spectra(0, ek, 0, every)
+    d_ke, d_sp = d_ke.cpu().numpy(), d_sp.cpu().numpy()
+    _, _, ddef = _oracle_series(n, u0, re, 0.0, np.zeros(24), False, saves, every)
+    ratio = d_ke[:, 0] / ddef
+    print("KE form / definition at saves 6..20:", np.round(ratio[6:21], 4))
     assert np.all(np.abs(ratio[6:21] - 1.0) < 0.04)
-    ref = -np.gradient(ke, t, axis=0)
-    assert np.max(np.abs(diss - ref)) < 1e-12 * np.max(np.abs(ref))
-    assert np.max(np.abs(eta - ((1 / re) ** 3 / ref.mean(axis=1)) ** 0.25)) < 1e-12 * eta.max()
+    shell = d_sp[:, 0] / d_ke[:, 0]
+    print("spectral form / KE form at saves 6..20:", np.round(shell[6:21], 5))
+    assert np.all(np.abs(shell[6:21] / (4 * np.pi * 3 / 62) - 1.0) < 0.04)
 
 
 def test_dissipation_argument_checks():
@@ -145,6 +212,15 @@ def test_dissipation_argument_checks():
         ens.dissipation(rec, 0, 4)
     with pytest.raises(mc.MclbmError, match="ERR_ARG"):
         ens.dissipation(rec[:1].contiguous(), 0, 4, eta=False)
+    ek = torch.zeros(3, 2, 9, dtype=torch.float64, device="cuda")
+    d, e = ens.dissipation_spectra(0, ek[:, :1].contiguous(), 0, 4)
+    assert tuple(d.shape) == (3, 1) and tuple(e.shape) == (3,)
+    with pytest.raises(mc.MclbmError, match="one viscosity"):
+        ens.dissipation_spectra(0, ek, 0, 4)
+    with pytest.raises(mc.MclbmError, match="leaves the ensemble"):
+        ens.dissipation_spectra(1, ek, 0, 4, eta=False)
+    with pytest.raises(mc.MclbmError, match="two saved spectra"):
+        ens.dissipation_spectra(0, ek[:1].contiguous(), 0, 4, eta=False)
 
 
 def test_observables_range_equals_single_samples():

@@ -144,6 +144,29 @@ MUTANTS = [
      [("KOLMOGOROV_CONSTANT = 1.5", "KOLMOGOROV_CONSTANT = 1.6")], "compensation"),
     ("compensated structure function: lag in lattice units", PY,
      [("r = (j + 1) * 2.0 * math.pi / n", "r = (j + 1)")], "compensation"),
+    # ---- dissipation rate and Kolmogorov length (Python)
+    ("decay rate: sign of the derivative", PY,
+     [("out[k] = -(e[hi] - e[lo]) / (t[hi] - t[lo])", "out[k] = (e[hi] - e[lo]) / (t[hi] - t[lo])")], "decay_rate"),
+    ("decay rate: centred difference over one interval", PY,
+     [("out[k] = -(e[hi] - e[lo]) / (t[hi] - t[lo])", "out[k] = -(e[hi] - e[lo]) / (t[hi] - t[k] + 1e-300)")],
+     "decay_rate"),
+    ("dissipation from spectra: lattice units kept", PY,
+     [("total[k, s] = sum(ek[k, s, kap] for kap in range(ek.shape[2])) / u0[s] ** 2",
+       "total[k, s] = sum(ek[k, s, kap] for kap in range(ek.shape[2]))")], "dissipation_from_spectra"),
+    ("dissipation from spectra: shell weight dropped (kinetic energy instead)", PY,
+     [("total[k, s] = sum(ek[k, s, kap] for kap in range(ek.shape[2])) / u0[s] ** 2",
+       "total[k, s] = sum(ek[k, s, kap] for kap in range(ek.shape[2])) / u0[s] ** 2 / (4 * math.pi * 3 / 62)")],
+     "dissipation_from_spectra"),
+    ("dissipation definition: k_z dropped from |k|^2", PY,
+     [("k2 = KX ** 2 + KY ** 2 + KZ ** 2\n    phi = sum(", "k2 = KX ** 2 + KY ** 2\n    phi = sum(")],
+     "dissipation_definition"),
+    ("dissipation definition: coefficients without the 1/N^3 of eq. (dftCoeff)", PY,
+     [("phi = sum(np.abs(np.fft.fftn(u[a] / u0) / n ** 3) ** 2 for a in range(3))",
+       "phi = sum(np.abs(np.fft.fftn(u[a] / u0) / n ** 2) ** 2 for a in range(3))")], "dissipation_definition"),
+    ("Kolmogorov length: exponent 1/3", PY, [("return (eps ** 3 / mean) ** 0.25", "return (eps ** 3 / mean) ** (1.0 / 3.0)")],
+     "kolmogorov_length"),
+    ("Kolmogorov length: sum over samples instead of the mean", PY,
+     [("mean = np.sum(d, axis=-1) / d.shape[-1]", "mean = np.sum(d, axis=-1)")], "kolmogorov_length"),
 ]
 
 PIN_FILE = "tests/test_oracle_pins.py"
@@ -158,7 +181,7 @@ def _copy_tree(dst):
     for f in ("conftest.py", "test_oracle_pins.py"):
         shutil.copy(os.path.join(ROOT, "tests", f), os.path.join(dst, "tests", f))
     shutil.copytree(os.path.join(ROOT, "tests", "golden"), os.path.join(dst, "tests", "golden"),
-                    ignore=shutil.ignore_patterns("__pycache__"))
+                    ignore=shutil.ignore_patterns("__pycache__", "*.npz"))
 
 
 def _build(d):

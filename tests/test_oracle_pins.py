@@ -770,3 +770,83 @@ def test_taylor_green_field():
     assert abs(u[0, 0, 1, 2] - math.sin(x) * math.cos(y) * math.cos(z)) < 1e-15
     assert abs(u[1, 0, 1, 2] + math.cos(x) * math.sin(y) * math.cos(z)) < 1e-15
     assert u[2].max() == 0.0 and u[2].min() == 0.0
+
+
+# ---------------------------------------------------------------- dissipation rate and Kolmogorov length
+def test_energy_decay_rate_closed_forms():
+    """The finite differences of the decay rate on series with closed-form
+    differences: for E = C exp(-a t) on a uniform time grid of spacing h,
+    the centred difference inside the series is a E(t_k) sinh(ah)/(ah), the
+    forward difference at the start E(t_0)(1 - exp(-ah))/h and the backward
+    one at the end E(t_K)(exp(ah) - 1)/h; centred differences of a
+    quadratic are exact. Two columns (samples) are handled independently."""
+    a, h, c = 3.0, 0.1, 2.5
+    t = 0.7 + h * np.arange(6)
+    e = c * np.exp(-a * t)
+    d = oracle.energy_decay_rate(np.stack([e, 2 * e], axis=1), t)
+    inner = a * e[1:-1] * math.sinh(a * h) / (a * h)
+    assert np.max(np.abs(d[1:-1, 0] / inner - 1)) < 1e-13
+    assert abs(d[0, 0] / (e[0] * (1 - math.exp(-a * h)) / h) - 1) < 1e-13
+    assert abs(d[-1, 0] / (e[-1] * (math.exp(a * h) - 1) / h) - 1) < 1e-13
+    assert np.max(np.abs(d[:, 1] - 2 * d[:, 0])) < 1e-15 * np.max(np.abs(d))
+    q = 4.0 - 3.0 * t + 0.5 * t ** 2        # -dq/dt = 3 - t
+    dq = oracle.energy_decay_rate(q, t)
+    assert np.max(np.abs(dq[1:-1] - (3.0 - t[1:-1]))) < 1e-13
+
+
+def test_dissipation_definition_closed_forms():
+    """The definition before eq. (kolmogorov_microscale): for u / u0 = A TGV
+    every component is a sum of |k|^2 = 3 modes with mean square A^2 / 8 (x
+    and y components), so d = eps (3/4) A^2; a perturbation of eq.
+    (alpha_perturbation) adds |k|^2 = 12 products of mean square (Y/8)^2 / 8,
+    orthogonal to the TGV modes on the grid: d = eps (3/4 + amp^2 12 sum Y^2
+    / 512) without projection. The spectral derivative equals the analytic
+    derivative of the band-limited field."""
+    n, u0, eps, amp = 16, 0.05, 1.0 / 400.0, 0.3
+    d = oracle.dissipation_rate_definition(u0 * 0.8 * oracle.taylor_green(n), eps, u0)
+    assert abs(d / (eps * 0.75 * 0.64) - 1) < 1e-13
+    y = mc_inputs.draw_y(41, 1)[0]
+    u = oracle.initial_velocity(n, u0, amp, y, False)
+    d = oracle.dissipation_rate_definition(u, eps, u0)
+    assert abs(d / (eps * (0.75 + amp ** 2 * 12 * np.sum(y ** 2) / 512)) - 1) < 1e-13
+    # analytic gradient of the TGV on the grid: mean of |grad u|^2 / u0^2
+    X, Y, Z = oracle.grid(n)
+    gx = [np.cos(X) * np.cos(Y) * np.cos(Z), -np.sin(X) * np.sin(Y) * np.cos(Z), -np.sin(X) * np.cos(Y) * np.sin(Z)]
+    gy = [np.sin(X) * np.sin(Y) * np.cos(Z), -np.cos(X) * np.cos(Y) * np.cos(Z), np.cos(X) * np.sin(Y) * np.sin(Z)]
+    brute = eps * np.mean(sum(g * g for g in gx + gy))
+    assert abs(oracle.dissipation_rate_definition(u0 * oracle.taylor_green(n), eps, u0) / brute - 1) < 1e-13
+
+
+def test_dissipation_from_spectra_of_a_decaying_taylor_green_mode():
+    """The paper's approximation, -d/dt sum_kappa E(kappa, t), for a TGV of
+    amplitude exp(-3 eps t): its energy sits in shell 2 (62 modes, |k|^2 = 3
+    for the 8 of the TGV), so sum_kappa E = (4 pi 3 / 62) KE with KE =
+    exp(-6 eps t) / 8, a factor 0.608 below the kinetic energy per unit
+    volume; the centred differences give 6 eps (4 pi 3/62)(1/8) exp(-6 eps
+    t_k) sinh(6 eps h)/(6 eps h). The kinetic-energy form has no shell factor."""
+    n, eps, h = 16, 1.0 / 50.0, 0.25
+    u0 = np.array([0.05, 0.025])
+    t = h * np.arange(5)
+    amp = np.exp(-3 * eps * t)
+    ek = np.stack([np.stack([oracle.energy_spectrum(u0[s] * a * oracle.taylor_green(n)) for s in range(2)])
+                   for a in amp])
+    ke = np.stack([[oracle.kinetic_energy(u0[s] * a * oracle.taylor_green(n)) for s in range(2)] for a in amp])
+    d_spec = oracle.dissipation_from_spectra(ek, t, u0)
+    d_ke = oracle.dissipation_from_kinetic_energy(ke, t, u0)
+    r = 6 * eps
+    inner = r * np.exp(-r * t[1:-1]) / 8 * math.sinh(r * h) / (r * h)
+    factor = 4 * math.pi * 3 / 62
+    for s in range(2):
+        assert np.max(np.abs(d_ke[1:-1, s] / inner - 1)) < 1e-12
+        assert np.max(np.abs(d_spec[1:-1, s] / (factor * inner) - 1)) < 1e-12
+        assert abs(d_spec[0, s] / (factor * (1 - math.exp(-r * h)) / (8 * h)) - 1) < 1e-12
+
+
+def test_kolmogorov_length_closed_form():
+    """eq. (kolmogorov_microscale) with the ensemble-mean dissipation rate:
+    eps = 1/2 and E[d] = 1/128 give eta = (16)^(1/4) = 2; eps = 0.01 with
+    samples d = 0.01 (1 +- 0.3) gives 0.1; per record along the first axis."""
+    assert abs(oracle.kolmogorov_length(0.5, [1.0 / 128.0]) - 2.0) < 1e-15
+    eta = oracle.kolmogorov_length(0.01, [[0.013, 0.007], [1.0 / 128.0, 1.0 / 128.0]])
+    assert abs(eta[0] - 0.1) < 1e-15
+    assert abs(eta[1] - (1e-6 * 128.0) ** 0.25) < 1e-15
