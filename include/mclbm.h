@@ -325,6 +325,19 @@ size_t mclbm_sample_error_work_bytes(int32_t m);
 mclbm_status mclbm_sample_error(const double* a_dev, const double* b_dev, int32_t m, int32_t q, double* out_dev,
                                 void* work_dev, size_t work_bytes, void* hip_stream);
 
+/* mclbm_sample_error without a caller-provided work buffer, for callers that
+ * cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): the same kernels and the same
+ * result, bit for bit, with the per-sample partial ratios in a device array
+ * of the library (4 doubles per sample, 2 MiB: m <= 65536, else
+ * MCLBM_ERR_ARG before anything is enqueued). Each GPU holds its own copy of
+ * that array until the process ends; the call allocates nothing. Every call
+ * on one GPU shares that GPU's array: calls that overlap on one GPU (on
+ * different streams, or from different threads) race and must be ordered by
+ * the caller. Runs on hip_stream, which must belong to the current device. */
+mclbm_status mclbm_sample_error_noalloc(const double* a_dev, const double* b_dev, int32_t m, int32_t q,
+                                        double* out_dev, void* hip_stream);
+
 /* Experimental order of convergence (Algorithm (ComputeSlopes)): the slope
  * of the least-squares line through (log n[i], log d[i]), i < k, where d[i]
  * is a distance of resolution n[i] to the reference resolution (host

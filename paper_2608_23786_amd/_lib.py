@@ -77,6 +77,7 @@ SIGNATURES = {
     "mclbm_compensate": (_i32, [_vp, _i32, _i32, _vp, _vp, _vp, _vp, _vp]),
     "mclbm_sample_error_work_bytes": (_sz, [_i32]),
     "mclbm_sample_error": (_i32, [_vp, _vp, _i32, _i32, _vp, _vp, _sz, _vp]),
+    "mclbm_sample_error_noalloc": (_i32, [_vp, _vp, _i32, _i32, _vp, _vp]),
     "mclbm_eoc_slope": (_i32, [_vp, _vp, _i32, _vp]),
     "mclbm_set_launch": (_i32, [_ctxp, _i32, _i32, _i32, _i32]),
     "mclbm_get_launch": (_i32, [_ctxp, _ip, _ip, _ip, _ip]),
