@@ -299,44 +299,65 @@ template <int QN, typename T>
 __device__ __forceinline__ T exact_entropic_t(const T (&geq)[Q], const T (&fneq)[Q], const Shear<T>& s,
                                               const Macro<T>& m, T omega, T t) {
   const T a = m.drho - m.usq15;
-  // the interval of t where every f*_i = base_i - t dh_i > 0; in float the
-  // quotients use the hardware reciprocal (about one unit in the last place)
-  // and are moved inwards by 2^-20 of their size, so that the interval stays
-  // inside the exact one
-  T lo = T(-1e30), hi = T(1e30);
+  // dh_i and b_i - w_i = g^eq_i + f^neq_i - omega ds_i once per node, so that
+  // f*_i(t) - w_i = (b_i - w_i) - t dh_i
+  T dh[Q], bs[Q];
   for_vel<QN>([&](auto ic) {
     constexpr int i = decltype(ic)::value;
     T ds = T(0);
     if constexpr (nonzeros(i) == 1 || nonzeros(i) == 2) ds = shear_part<i>(s);
-    const T dh = fneq[i] - ds;
-    const T base = (T(weight<QN>(i)) + geq[i]) + (fneq[i] - omega * ds);
-    T q;
-    if constexpr (std::is_same<T, float>::value) {
-      q = base * __builtin_amdgcn_rcpf(dh);
-      q = dh > T(0) ? q - fabsf(q) * 0x1.0p-20f : q + fabsf(q) * 0x1.0p-20f;
-    } else {
-      q = base / dh;
-    }
-    if (dh > T(0)) hi = vmin(hi, q);
-    if (dh < T(0)) lo = lo > q ? lo : q;
+    dh[i] = fneq[i] - ds;
+    bs[i] = geq[i] + (fneq[i] - omega * ds);
   });
+  // The interval of t where every f*_i = w_i + bs_i - t dh_i > 0 bounds the
+  // Newton iterates; it is formed (27 quotients) only when an iterate leaves
+  // the region where every f*_i is positive, which takes 27 products to
+  // check. In float the quotients use the hardware reciprocal (about one unit
+  // in the last place) and are moved inwards by 2^-20 of their size, so that
+  // the interval stays inside the exact one.
+  bool have_interval = false;
+  T lo = T(-1e30), hi = T(1e30);
+  auto interval = [&]() {
+    for_vel<QN>([&](auto ic) {
+      constexpr int i = decltype(ic)::value;
+      const T base = T(weight<QN>(i)) + bs[i];
+      T q;
+      if constexpr (std::is_same<T, float>::value) {
+        q = base * __builtin_amdgcn_rcpf(dh[i]);
+        q = dh[i] > T(0) ? q - fabsf(q) * 0x1.0p-20f : q + fabsf(q) * 0x1.0p-20f;
+      } else {
+        q = base / dh[i];
+      }
+      if (dh[i] > T(0)) hi = vmin(hi, q);
+      if (dh[i] < T(0)) lo = lo > q ? lo : q;
+    });
+    have_interval = true;
+  };
+  auto positive_at = [&](T tt) {
+    T fmin = T(1);
+    for_vel<QN>([&](auto ic) {
+      constexpr int i = decltype(ic)::value;
+      fmin = vmin(fmin, (T(weight<QN>(i)) + bs[i]) - tt * dh[i]);
+    });
+    return fmin > T(0);
+  };
   bool done = false;
   for (int it = 0; it < kExactNewtonSteps && !done; ++it) {
     T d1 = T(0), d2 = T(0);
     for_vel<QN>([&](auto ic) {
       constexpr int i = decltype(ic)::value;
-      T ds = T(0);
-      if constexpr (nonzeros(i) == 1 || nonzeros(i) == 2) ds = shear_part<i>(s);
-      const T dh = fneq[i] - ds;
       constexpr double w = weight<QN>(i);
       // f*_i - w_i in shifted form
-      const T gs = geq[i] + (fneq[i] - omega * ds) - t * dh;
-      d1 += dh * (log1p_acc(gs * T(1.0 / w)) - (a + T(3) * cdot<i>(m.ux, m.uy, m.uz)));
-      d2 += dh * dh * recip(T(w) + gs);
+      const T gs = bs[i] - t * dh[i];
+      d1 += dh[i] * (log1p_acc(gs * T(1.0 / w)) - (a + T(3) * cdot<i>(m.ux, m.uy, m.uz)));
+      d2 += dh[i] * dh[i] * recip(T(w) + gs);
     });
     T tn = t + d1 / d2;
-    if (!(tn < hi)) tn = T(0.5) * (t + hi);
-    if (!(tn > lo)) tn = T(0.5) * (t + lo);
+    if (!positive_at(tn)) {
+      if (!have_interval) interval();
+      if (!(tn < hi)) tn = T(0.5) * (t + hi);
+      if (!(tn > lo)) tn = T(0.5) * (t + lo);
+    }
     done = fabs(tn - t) <= exact_tolerance<T>() * fabs(t);
     t = tn;
   }

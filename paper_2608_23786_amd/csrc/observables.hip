@@ -14,15 +14,19 @@
 // (the rest follows by conjugate symmetry), fields [z][y][kx], and the
 // pipeline is five passes over HBM:
 //   1. x: velocities from the populations (either AA parity) and the
-//      forward transform along x of the three components, per row in LDS;
+//      forward transform along x of the three components, per row in LDS
+//      (two real components share one complex transform);
 //   2. y: forward transforms along y of the three fields;
 //   3. per z-line: the forward transforms along z of the three fields,
 //      Psi, its shell sums for the spectrum, its total (R_0), and the
 //      inverse transform along z of Psi, written over field 0;
 //   4. inverse along y; 5. per x-row: the inverse along x (conjugate-
-//      symmetric fill, real result R_h) and its shell sums for S2.
+//      symmetric fill, real result R_h, two rows per complex transform) and
+//      its shell sums for S2.
 // Radix-2/4 decimation-in-time transforms of whole lines in LDS (padded
-// against bank conflicts), twiddles by sincospi; each launch hands every XCD
+// against bank conflicts), the first and last stage in registers of the
+// thread that loads or keeps a quartet of the line, twiddles by sincospi;
+// each launch hands every XCD
 // a contiguous run of blocks, so that blocks sharing cache lines share an
 // L2. Shells hold the integer vectors (minimum image, components in
 // {-N/2+1, ..., N/2}) whose length rounds to the shell index. Every shell sum
@@ -47,8 +51,10 @@ namespace {
 // field.
 constexpr int half_lines(int n) { return n >= 512 ? 4 : (n >= 256 ? 8 : (n >= 16 ? 16 : 8)); }
 
-// x-rows per block of the inverse transform along x (at most 1024 values)
-constexpr int inv_rows(int n) { return (n * n < 1024 / n) ? n * n : 1024 / n; }
+// x-rows per block of the inverse transform along x (at most 2048 values;
+// two rows share one complex transform, so a block holds N/4 quartets of
+// ROWS/2 lines, 256 for N >= 16)
+constexpr int inv_rows(int n) { return (n * n < 2048 / n) ? n * n : 2048 / n; }
 
 // rows of the spectrum's and the structure function's shell tables: one
 // per block of the pass that writes them
@@ -97,20 +103,87 @@ __device__ __forceinline__ void make_twiddles(double2* tw, int sign) {
   }
 }
 
-// In-place butterflies of nl lines of length N (element p of line l at
-// sh[l lds_line<N>() + lds_pos(p)]) loaded in
-// bit-reversed order (decimation in time); every thread of the block takes
-// part and the caller synchronises after loading. Two consecutive radix-2
-// stages (spans h and 2h) run as one radix-4 step in registers: a thread
-// takes the four values i0 + {0, 1, 2, 3} h, applies the span-h pairs (one
-// twiddle) and then the span-2h pairs (two twiddles), so LDS is read and
-// written once per two stages. An odd number of stages starts with one
-// radix-2 stage.
+// Transforms of whole lines in LDS, decimation in time (bit-reversed
+// input, radix-4 steps of two radix-2 stages, an odd number of stages
+// starting with one radix-2 stage), with the first and the last stage in
+// registers, for a thread that holds a quartet of a line: the elements r, r + N/4, r + N/2,
+// r + 3N/4 (natural order, r < N/4). The first stage of the
+// decimation-in-time transform combines exactly such a quartet: with an
+// even number of radix-2 stages, the first radix-4 step reads bit-reversed
+// positions 4j..4j+3, which hold elements r, r + N/2, r + N/4, r + 3N/4 for
+// j = bitrev(r) / 4; with an odd number, the first radix-2 stage pairs
+// (r, r + N/2) at positions 2 j1, 2 j1 + 1 (j1 = bitrev(r) / 2) and
+// (r + N/4, r + 3N/4) at 2 j2, 2 j2 + 1 (j2 = bitrev(r + N/4) / 2). The last
+// radix-4 step (span N/4) leaves, for j < N/4, the outputs j, j + N/4,
+// j + N/2, j + 3N/4 in one thread. So a quartet is loaded from memory, put
+// through the first stage and written to LDS once; the middle steps run in
+// LDS as above; the last step reads LDS once and hands the output quartet
+// back in registers. Per transform that saves two of the LDS passes.
+// sign: -1 forward, +1 inverse (the twiddle e^{sign i pi/2} of the first
+// radix-4 step is (0, sign)).
 template <int N>
-__device__ __forceinline__ void butterflies(double2* sh, int nl, const double2* tw) {
+__device__ __forceinline__ void first_stage_to_lds(double2* ln, int r, const double2 (&x)[4], int sign) {
   constexpr int LOG = log2_of<N>();
-  int half = 1;
-  if (LOG & 1) {
+  if constexpr ((LOG & 1) == 0) {
+    const int p = bitrev<N>(r);  // 4j
+    const double2 y0 = make_double2(x[0].x + x[2].x, x[0].y + x[2].y);
+    const double2 y1 = make_double2(x[0].x - x[2].x, x[0].y - x[2].y);
+    const double2 y2 = make_double2(x[1].x + x[3].x, x[1].y + x[3].y);
+    const double2 y3 = make_double2(x[1].x - x[3].x, x[1].y - x[3].y);
+    const double2 u3 = cmul(make_double2(0.0, double(sign)), y3);
+    ln[lds_pos(p)] = make_double2(y0.x + y2.x, y0.y + y2.y);
+    ln[lds_pos(p + 2)] = make_double2(y0.x - y2.x, y0.y - y2.y);
+    ln[lds_pos(p + 1)] = make_double2(y1.x + u3.x, y1.y + u3.y);
+    ln[lds_pos(p + 3)] = make_double2(y1.x - u3.x, y1.y - u3.y);
+  } else {
+    const int p1 = bitrev<N>(r), p2 = bitrev<N>(r + N / 4);  // 2 j1, 2 j2
+    ln[lds_pos(p1)] = make_double2(x[0].x + x[2].x, x[0].y + x[2].y);
+    ln[lds_pos(p1 + 1)] = make_double2(x[0].x - x[2].x, x[0].y - x[2].y);
+    ln[lds_pos(p2)] = make_double2(x[1].x + x[3].x, x[1].y + x[3].y);
+    ln[lds_pos(p2 + 1)] = make_double2(x[1].x - x[3].x, x[1].y - x[3].y);
+  }
+}
+
+// The radix-4 steps between the first stage and the last (spans 4, 16, ...
+// or 2, 8, ... below N/4) over nl lines in LDS; every thread of the block
+// takes part, and the block is synchronised after each step.
+template <int N>
+__device__ __forceinline__ void radix4_steps(double2* sh, int nl, const double2* tw, int half0) {
+  for (int half = half0; half < N / 4; half <<= 2) {
+    const int sa = N / (2 * half), sb = N / (4 * half);
+    for (int b = threadIdx.x; b < nl * (N / 4); b += blockDim.x) {
+      const int l = b / (N / 4), j = b % (N / 4);
+      const int pos = j % half, grp = j / half;
+      double2* ln = sh + l * lds_line<N>();
+      const int i0 = grp * 4 * half + pos;
+      const int p0 = lds_pos(i0), p1 = lds_pos(i0 + half), p2 = lds_pos(i0 + 2 * half), p3 = lds_pos(i0 + 3 * half);
+      const double2 x0 = ln[p0], x1 = ln[p1], x2 = ln[p2], x3 = ln[p3];
+      const double2 wa = tw[lds_pos(pos * sa)];
+      const double2 t1 = cmul(wa, x1), t3 = cmul(wa, x3);
+      const double2 y0 = make_double2(x0.x + t1.x, x0.y + t1.y), y1 = make_double2(x0.x - t1.x, x0.y - t1.y);
+      const double2 y2 = make_double2(x2.x + t3.x, x2.y + t3.y), y3 = make_double2(x2.x - t3.x, x2.y - t3.y);
+      const double2 u2 = cmul(tw[lds_pos(pos * sb)], y2), u3 = cmul(tw[lds_pos((pos + half) * sb)], y3);
+      ln[p0] = make_double2(y0.x + u2.x, y0.y + u2.y);
+      ln[p2] = make_double2(y0.x - u2.x, y0.y - u2.y);
+      ln[p1] = make_double2(y1.x + u3.x, y1.y + u3.y);
+      ln[p3] = make_double2(y1.x - u3.x, y1.y - u3.y);
+    }
+    __syncthreads();
+  }
+}
+
+template <int N>
+__device__ __forceinline__ void middle_steps(double2* sh, int nl, const double2* tw) {
+  radix4_steps<N>(sh, nl, tw, (log2_of<N>() & 1) ? 2 : 4);
+}
+
+// Every stage but the last of nl lines loaded into LDS in bit-reversed order
+// (the first radix-2 stage of an odd number of stages included); the block
+// is synchronised after each step.
+template <int N>
+__device__ __forceinline__ void all_but_last_steps(double2* sh, int nl, const double2* tw) {
+  constexpr int LOG = log2_of<N>();
+  if constexpr (LOG & 1) {
     for (int b = threadIdx.x; b < nl * (N / 2); b += blockDim.x) {
       const int l = b / (N / 2), j = b % (N / 2);
       double2* ln = sh + l * lds_line<N>();
@@ -120,31 +193,26 @@ __device__ __forceinline__ void butterflies(double2* sh, int nl, const double2* 
       ln[p1] = make_double2(a.x - c.x, a.y - c.y);
     }
     __syncthreads();
-    half = 2;
   }
-  for (; half < N; half <<= 2) {
-    const int sa = N / (2 * half), sb = N / (4 * half);  // twiddle strides of the two stages
-    for (int b = threadIdx.x; b < nl * (N / 4); b += blockDim.x) {
-      const int l = b / (N / 4), j = b % (N / 4);
-      const int pos = j % half, grp = j / half;
-      double2* ln = sh + l * lds_line<N>();
-      const int i0 = grp * 4 * half + pos;
-      const int p0 = lds_pos(i0), p1 = lds_pos(i0 + half), p2 = lds_pos(i0 + 2 * half), p3 = lds_pos(i0 + 3 * half);
-      const double2 x0 = ln[p0], x1 = ln[p1], x2 = ln[p2], x3 = ln[p3];
-      // span h: (x0, x1) and (x2, x3), twiddle e^{pos sa}
-      const double2 wa = tw[lds_pos(pos * sa)];
-      const double2 t1 = cmul(wa, x1), t3 = cmul(wa, x3);
-      const double2 y0 = make_double2(x0.x + t1.x, x0.y + t1.y), y1 = make_double2(x0.x - t1.x, x0.y - t1.y);
-      const double2 y2 = make_double2(x2.x + t3.x, x2.y + t3.y), y3 = make_double2(x2.x - t3.x, x2.y - t3.y);
-      // span 2h: (y0, y2) with e^{pos sb}, (y1, y3) with e^{(pos + h) sb}
-      const double2 u2 = cmul(tw[lds_pos(pos * sb)], y2), u3 = cmul(tw[lds_pos((pos + half) * sb)], y3);
-      ln[p0] = make_double2(y0.x + u2.x, y0.y + u2.y);
-      ln[p2] = make_double2(y0.x - u2.x, y0.y - u2.y);
-      ln[p1] = make_double2(y1.x + u3.x, y1.y + u3.y);
-      ln[p3] = make_double2(y1.x - u3.x, y1.y - u3.y);
-    }
-    __syncthreads();
-  }
+  radix4_steps<N>(sh, nl, tw, (LOG & 1) ? 2 : 1);
+}
+
+// The last radix-4 step (span N/4) for outputs j, j + N/4, j + N/2, j + 3N/4
+// of one line (j < N/4): o[m] is output j + m N/4.
+template <int N>
+__device__ __forceinline__ void last_step_from_lds(const double2* ln, int j, const double2* tw, double2 (&o)[4]) {
+  constexpr int Q4 = N / 4;
+  const double2 x0 = ln[lds_pos(j)], x1 = ln[lds_pos(j + Q4)], x2 = ln[lds_pos(j + 2 * Q4)],
+                x3 = ln[lds_pos(j + 3 * Q4)];
+  const double2 wa = tw[lds_pos(2 * j)];
+  const double2 t1 = cmul(wa, x1), t3 = cmul(wa, x3);
+  const double2 y0 = make_double2(x0.x + t1.x, x0.y + t1.y), y1 = make_double2(x0.x - t1.x, x0.y - t1.y);
+  const double2 y2 = make_double2(x2.x + t3.x, x2.y + t3.y), y3 = make_double2(x2.x - t3.x, x2.y - t3.y);
+  const double2 u2 = cmul(tw[lds_pos(j)], y2), u3 = cmul(tw[lds_pos(j + Q4)], y3);
+  o[0] = make_double2(y0.x + u2.x, y0.y + u2.y);
+  o[2] = make_double2(y0.x - u2.x, y0.y - u2.y);
+  o[1] = make_double2(y1.x + u3.x, y1.y + u3.y);
+  o[3] = make_double2(y1.x - u3.x, y1.y - u3.y);
 }
 
 // A batch of samples shares one launch: blockIdx.z is the sample's place in
@@ -191,36 +259,39 @@ __device__ __forceinline__ void shell_range(int half, int s, int r, int& a, int&
 // m = half (the Nyquist value is present once).
 __device__ __forceinline__ double fold_weight(int m, int half) { return (m == 0 || m == half) ? 1.0 : 2.0; }
 
-// v[a] + ... + v[b] (0 for an empty range)
-__device__ __forceinline__ double range_sum(const double* v, int a, int b) {
-  double sum = 0.0;
-  for (int m = a; m <= b; ++m) sum += v[m];
-  return sum;
-}
-
 // Lattice vectors standing behind the folded indices a..b
 __device__ __forceinline__ double range_count(int half, int a, int b) {
   if (a > b) return 0.0;
   return 2.0 * (b - a + 1) - (a == 0 ? 1.0 : 0.0) - (b == half ? 1.0 : 0.0);
 }
 
-// Pass 1: ROWS rows (z, y) per block. Velocities of the row's nodes from
-// the populations (the parity selects the AA slots), forward transform
-// along x of the three components, kx = 0..N/2 written to
-// h[c][(z N + y) NH + kx].
+// x-rows per block of the forward transform along x: two nodes per thread,
+// and an even number of rows (two rows share one transform of uz)
+constexpr int fwd_rows(int n) { return n >= 256 ? 2 : 512 / n; }
+
+// Pass 1: ROWS rows (z, y) per block. Velocities of the rows' nodes from the
+// populations (the parity selects the AA slots; consecutive threads take
+// consecutive nodes of a row, so every population plane is read in
+// contiguous runs), and the forward transform along x of the three
+// components, kx = 0..N/2 written to h[c][(z N + y) NH + kx]. The components
+// are real, so two share one complex transform: ux + i uy of each row, and
+// uz of a pair of rows, loaded into LDS in bit-reversed order; the two
+// spectra of a line are separated afterwards from Z(k) and Z(N - k):
+// A(k) = (Z(k) + conj Z(N - k)) / 2, B(k) = (Z(k) - conj Z(N - k)) / 2i.
 template <int QN, typename T, int N>
 __global__ void __launch_bounds__(256)
     fwd_x_kernel(const T* pop, const DevSample* samples, int sample0, int parity, double2* h0, size_t wstride) {
-  constexpr int ROWS = N >= 512 ? 1 : 512 / N;
-  constexpr int NH = N / 2 + 1;
+  constexpr int ROWS = fwd_rows(N), PAIRS = ROWS / 2, LINES = ROWS + PAIRS;
+  constexpr int NH = N / 2 + 1, Q4 = N / 4;
   constexpr int LS = lds_line<N>();
-  __shared__ double2 sh[3 * ROWS * LS];
+  __shared__ double2 sh[LINES * LS];
   __shared__ double2 tw[lds_line<N / 2>()];
   const DevSample& sp = samples[sample0 + blockIdx.z];
   double2* h = in_batch(h0, wstride);
   const size_t row0 = size_t(remap_block(blockIdx.x, gridDim.x, 1)) * ROWS;
   make_twiddles<N>(tw, -1);
   const T* base = pop + sp.offset;
+  double* shd = reinterpret_cast<double*>(sh);
   for (int e = threadIdx.x; e < ROWS * N; e += 256) {
     const int r = e / N, x = e % N;
     const Cell c = make_cell(uint32_t((row0 + r) * N + x), sp.log2n);
@@ -237,60 +308,87 @@ __global__ void __launch_bounds__(256)
     });
     const double rho = 1.0 + d;
     const int rv = lds_pos(bitrev<N>(x));
-    sh[(0 * ROWS + r) * LS + rv] = make_double2(jx / rho, 0.0);
-    sh[(1 * ROWS + r) * LS + rv] = make_double2(jy / rho, 0.0);
-    sh[(2 * ROWS + r) * LS + rv] = make_double2(jz / rho, 0.0);
+    sh[r * LS + rv] = make_double2(jx / rho, jy / rho);
+    shd[2 * ((ROWS + r / 2) * LS + rv) + (r & 1)] = jz / rho;
   }
   __syncthreads();
-  butterflies<N>(sh, 3 * ROWS, tw);
+  all_but_last_steps<N>(sh, LINES, tw);
+  // the last step, its outputs back into the slots it read (the same thread's)
+  for (int e = threadIdx.x; e < LINES * Q4; e += 256) {
+    const int l = e / Q4, j = e % Q4;
+    double2 o[4];
+    last_step_from_lds<N>(sh + l * LS, j, tw, o);
+#pragma unroll
+    for (int m = 0; m < 4; ++m) sh[l * LS + lds_pos(j + m * Q4)] = o[m];
+  }
+  __syncthreads();
   const size_t field = size_t(N) * N * NH;
-  for (int e = threadIdx.x; e < 3 * ROWS * NH; e += 256) {
-    const int cl = e / NH, kx = e % NH;
-    const int comp = cl / ROWS, r = cl % ROWS;
-    h[comp * field + (row0 + r) * NH + kx] = sh[cl * LS + lds_pos(kx)];
+  for (int e = threadIdx.x; e < LINES * NH; e += 256) {
+    const int l = e / NH, k = e % NH;
+    const double2 z = sh[l * LS + lds_pos(k)];
+    const double2 zn = sh[l * LS + lds_pos((N - k) & (N - 1))];
+    const double2 a = make_double2(0.5 * (z.x + zn.x), 0.5 * (z.y - zn.y));  // (Z(k) + conj Z(N-k)) / 2
+    const double2 b = make_double2(0.5 * (z.y + zn.y), 0.5 * (zn.x - z.x));  // (Z(k) - conj Z(N-k)) / 2i
+    if (l < ROWS) {
+      h[(row0 + l) * NH + k] = a;
+      h[field + (row0 + l) * NH + k] = b;
+    } else {
+      const int p = l - ROWS;
+      h[2 * field + (row0 + 2 * p) * NH + k] = a;
+      h[2 * field + (row0 + 2 * p + 1) * NH + k] = b;
+    }
   }
 }
 
 // Passes 2 and 4: transform along y of the fields h + c * N N NH,
-// c = blockIdx.y; LINES lines (z, kx) per block, consecutive kx. sign -1
-// forward, +1 inverse.
+// c = blockIdx.y; LINES lines (z, kx) per block, consecutive kx, a quartet of
+// a line per thread (consecutive threads take consecutive lines, so their
+// global accesses are contiguous). sign -1 forward, +1 inverse.
 template <int N, int LINES>
 __global__ void __launch_bounds__(256) fft_y_kernel(double2* h0, int sign, size_t wstride) {
-  constexpr int NH = N / 2 + 1, LS = lds_line<N>();
+  constexpr int NH = N / 2 + 1, LS = lds_line<N>(), Q4 = N / 4;
   __shared__ double2 sh[LINES * LS];
   __shared__ double2 tw[lds_line<N / 2>()];
   double2* d = in_batch(h0, wstride) + size_t(blockIdx.y) * N * N * NH;
   make_twiddles<N>(tw, sign);
   const int line0 = remap_block(blockIdx.x, gridDim.x, 1) * LINES;
-  for (int e = threadIdx.x; e < LINES * N; e += 256) {
-    const int i = e / LINES, l = e % LINES;
+  for (int e = threadIdx.x; e < LINES * Q4; e += 256) {
+    const int r = e / LINES, l = e % LINES;
     const int line = line0 + l, z = line / NH, kx = line % NH;
-    sh[l * LS + lds_pos(bitrev<N>(i))] = d[(size_t(z) * N + i) * NH + kx];
+    double2 x[4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) x[m] = d[(size_t(z) * N + r + m * Q4) * NH + kx];
+    first_stage_to_lds<N>(sh + l * LS, r, x, sign);
   }
   __syncthreads();
-  butterflies<N>(sh, LINES, tw);
-  for (int e = threadIdx.x; e < LINES * N; e += 256) {
-    const int i = e / LINES, l = e % LINES;
+  middle_steps<N>(sh, LINES, tw);
+  for (int e = threadIdx.x; e < LINES * Q4; e += 256) {
+    const int j = e / LINES, l = e % LINES;
     const int line = line0 + l, z = line / NH, kx = line % NH;
-    d[(size_t(z) * N + i) * NH + kx] = sh[l * LS + lds_pos(i)];
+    double2 o[4];
+    last_step_from_lds<N>(sh + l * LS, j, tw, o);
+#pragma unroll
+    for (int m = 0; m < 4; ++m) d[(size_t(z) * N + j + m * Q4) * NH + kx] = o[m];
   }
 }
 
-// Pass 3: LINES z-lines (y, kx) per block. The forward
-// transform along z of each of the three fields (already transformed along
-// x and y), one field at a time in LDS, with Psi, the sum of |.|^2 over the
-// fields at every kz, kept in registers (the element to thread map is the
-// same for every field); then the shell sums of |k|^2/2 Psi over the block's
-// lines (each line folded by |kz| and weighted by its kx weight, the lines
-// added in order) into sbins[block][kappa], the sum of Psi into
-// sbins[block][N/2 + 1] (rows of N/2 + 2 values), and the inverse transform
-// of Psi along z, written over field 0.
+// Pass 3: LINES z-lines (y, kx) per block, a quartet of a line per thread
+// (consecutive threads on consecutive lines). The forward transform along z
+// of each of the three fields (already transformed along x and y), one
+// field at a time in LDS, with Psi, the sum of |.|^2 over the fields, kept in
+// registers (the quartets of a thread are the same for every field, and the
+// inverse transform's first stage takes the same quartets); Psi is also kept
+// in LDS in natural order for the shell sums. Then the inverse transform of
+// Psi along z, written over field 0, and the shell sums of |k|^2/2 Psi over
+// the block's lines (each line folded by |kz| and weighted by its kx weight,
+// the lines added in order) into sbins[block][kappa] and the sum of Psi into
+// sbins[block][N/2 + 1] (rows of N/2 + 2 values).
 template <int N, int LINES>
 __global__ void __launch_bounds__(256) z_psd_kernel(double2* h0, double* sbins0, size_t wstride) {
-  constexpr int NH = N / 2 + 1, HALF = N / 2, LS = lds_line<N>();
-  constexpr int PER = (LINES * N + 255) / 256;  // elements of a field per thread
+  constexpr int NH = N / 2 + 1, HALF = N / 2, LS = lds_line<N>(), Q4 = N / 4;
+  constexpr int PER = (LINES * Q4 + 255) / 256;  // quartets per thread
   __shared__ double2 sh[LINES * LS];
-  __shared__ double fold[LINES * (HALF + 1)];
+  __shared__ double psi[LINES * N];
   __shared__ double tot[LINES];
   __shared__ double2 tw[lds_line<N / 2>()];
   const size_t field = size_t(N) * N * NH;
@@ -298,76 +396,96 @@ __global__ void __launch_bounds__(256) z_psd_kernel(double2* h0, double* sbins0,
   double* sbins = in_batch(sbins0, wstride);
   make_twiddles<N>(tw, -1);
   const int line0 = remap_block(blockIdx.x, gridDim.x, 1) * LINES;
-  double psd[PER];
+  double ps[PER][4];
 #pragma unroll
-  for (int j = 0; j < PER; ++j) psd[j] = 0.0;
+  for (int k = 0; k < PER; ++k)
+#pragma unroll
+    for (int m = 0; m < 4; ++m) ps[k][m] = 0.0;
   for (int c = 0; c < 3; ++c) {
     const double2* d = h + c * field;
 #pragma unroll
-    for (int j = 0; j < PER; ++j) {
-      const int e = threadIdx.x + 256 * j;
-      if (e < LINES * N) {
-        const int i = e / LINES, l = e % LINES;
+    for (int k = 0; k < PER; ++k) {
+      const int e = threadIdx.x + 256 * k;
+      if (e < LINES * Q4) {
+        const int r = e / LINES, l = e % LINES;
         const int line = line0 + l, y = line / NH, kx = line % NH;
-        sh[l * LS + lds_pos(bitrev<N>(i))] = d[(size_t(i) * N + y) * NH + kx];
+        double2 x[4];
+#pragma unroll
+        for (int m = 0; m < 4; ++m) x[m] = d[(size_t(r + m * Q4) * N + y) * NH + kx];
+        first_stage_to_lds<N>(sh + l * LS, r, x, -1);
       }
     }
     __syncthreads();
-    butterflies<N>(sh, LINES, tw);
+    middle_steps<N>(sh, LINES, tw);
 #pragma unroll
-    for (int j = 0; j < PER; ++j) {
-      const int e = threadIdx.x + 256 * j;
-      if (e < LINES * N) {
-        const double2 v = sh[(e % LINES) * LS + lds_pos(e / LINES)];
-        psd[j] += v.x * v.x + v.y * v.y;
+    for (int k = 0; k < PER; ++k) {
+      const int e = threadIdx.x + 256 * k;
+      if (e < LINES * Q4) {
+        double2 o[4];
+        last_step_from_lds<N>(sh + (e % LINES) * LS, e / LINES, tw, o);
+#pragma unroll
+        for (int m = 0; m < 4; ++m) ps[k][m] += o[m].x * o[m].x + o[m].y * o[m].y;
       }
     }
     __syncthreads();  // the next field overwrites sh
   }
-  // the twiddles of the inverse transform, and Psi in bit-reversed order
+  // the inverse transform's twiddles; Psi in natural order for the shell
+  // sums; the inverse's first stage from the registers
   make_twiddles<N>(tw, +1);
 #pragma unroll
-  for (int j = 0; j < PER; ++j) {
-    const int e = threadIdx.x + 256 * j;
-    if (e < LINES * N) sh[(e % LINES) * LS + lds_pos(bitrev<N>(e / LINES))] = make_double2(psd[j], 0.0);
+  for (int k = 0; k < PER; ++k) {
+    const int e = threadIdx.x + 256 * k;
+    if (e < LINES * Q4) {
+      const int j = e / LINES, l = e % LINES;
+      double2 x[4];
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        psi[l * N + j + m * Q4] = ps[k][m];
+        x[m] = make_double2(ps[k][m], 0.0);
+      }
+      first_stage_to_lds<N>(sh + l * LS, j, x, +1);
+    }
   }
   __syncthreads();
+  middle_steps<N>(sh, LINES, tw);
+  for (int e = threadIdx.x; e < LINES * Q4; e += 256) {
+    const int j = e / LINES, l = e % LINES;
+    const int line = line0 + l, y = line / NH, kx = line % NH;
+    double2 o[4];
+    last_step_from_lds<N>(sh + l * LS, j, tw, o);
+#pragma unroll
+    for (int m = 0; m < 4; ++m) h[(size_t(j + m * Q4) * N + y) * NH + kx] = o[m];
+  }
+  // the total of Psi per line (R_0), one wave per line
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   for (int l = wave; l < LINES; l += 4) {
-    const int line = line0 + l, y = line / NH, kx = line % NH;
-    const int ky = y <= HALF ? y : y - N;
-    const int64_t s = int64_t(kx) * kx + int64_t(ky) * ky;
-    const double2* ln = sh + l * LS;
+    const int kx = (line0 + l) % NH;
     double total = 0.0;
-    for (int m = lane; m <= HALF; m += 64) {
-      double v = ln[lds_pos(bitrev<N>(m))].x;
-      if (m >= 1 && m <= HALF - 1) v += ln[lds_pos(bitrev<N>(N - m))].x;
-      total += v;
-      fold[l * (HALF + 1) + m] = 0.5 * (double(s) + double(m) * m) * v;
-    }
+    for (int i = lane; i < N; i += 64) total += psi[l * N + i];
     total = wave_sum(total);
     if (lane == 0) tot[l] = fold_weight(kx, HALF) * total;
   }
-  __syncthreads();
-  butterflies<N>(sh, LINES, tw);
-  for (int e = threadIdx.x; e < LINES * N; e += 256) {
-    const int i = e / LINES, l = e % LINES;
-    const int line = line0 + l, y = line / NH, kx = line % NH;
-    h[(size_t(i) * N + y) * NH + kx] = sh[l * LS + lds_pos(i)];
-  }
-  __syncthreads();
+  __syncthreads();  // every read of sh by the transform is done
   // the shell sums of every (line, shell) pair over all threads, in the LDS
-  // the transform no longer needs, then the block's lines added per shell
-  // in line order
+  // the transform no longer needs, each line folded by |kz|; then the
+  // block's lines added per shell in line order
   static_assert(sizeof(double) * LINES * (HALF + 1) <= sizeof(sh), "the line sums fit in the transform's LDS");
   double* part = reinterpret_cast<double*>(sh);
   for (int e = threadIdx.x; e < LINES * (HALF + 1); e += 256) {
     const int l = e / (HALF + 1), r = e % (HALF + 1);
     const int line = line0 + l, y = line / NH, kx = line % NH;
     const int ky = y <= HALF ? y : y - N;
+    const int sxy = kx * kx + ky * ky;
     int a, b;
-    shell_range(HALF, kx * kx + ky * ky, r, a, b);
-    part[e] = fold_weight(kx, HALF) * range_sum(fold + l * (HALF + 1), a, b);
+    shell_range(HALF, sxy, r, a, b);
+    const double* pl = psi + l * N;
+    double sum = 0.0;
+    for (int m = a; m <= b; ++m) {
+      double v = pl[m];
+      if (m >= 1 && m <= HALF - 1) v += pl[N - m];
+      sum += 0.5 * (double(sxy) + double(m) * m) * v;
+    }
+    part[e] = fold_weight(kx, HALF) * sum;
   }
   __syncthreads();
   const size_t blk = size_t(line0 / LINES);
@@ -383,49 +501,61 @@ __global__ void __launch_bounds__(256) z_psd_kernel(double2* h0, double* sbins0,
 // transform along x (R_h times N^6, real), and the shell sums of
 // 2 (R_0 - R_h) over the block's rows (each row folded by |hx|, the rows
 // added in order) into rbins[block][r] (rows of N/2 + 2 values, the last one
-// 0). r0: R_0 times N^6 (the sum of Psi).
+// 0). Both outputs of a pair of rows are real, so the pair shares one
+// complex transform: Z = X_a + i X_b transforms to x_a + i x_b. r0: R_0
+// times N^6 (the sum of Psi).
 template <int N>
 __global__ void __launch_bounds__(256)
     inv_x_rows_kernel(const double2* h0, const double* r00, double* rbins0, size_t wstride) {
-  constexpr int NH = N / 2 + 1, HALF = N / 2;
-  constexpr int ROWS = inv_rows(N);
+  constexpr int NH = N / 2 + 1, HALF = N / 2, Q4 = N / 4;
+  constexpr int ROWS = inv_rows(N), LINES = ROWS / 2;
   constexpr int LS = lds_line<N>();
-  __shared__ double2 sh[ROWS * LS];
-  __shared__ double fold[ROWS * (HALF + 1)];
+  __shared__ double2 sh[LINES * LS];
+  __shared__ double rl[ROWS * N];
   __shared__ double2 tw[lds_line<N / 2>()];
   const double2* h = in_batch(h0, wstride);
   const double* r0 = in_batch(r00, wstride);
   double* rbins = in_batch(rbins0, wstride);
   make_twiddles<N>(tw, +1);
   const int row0 = remap_block(blockIdx.x, gridDim.x, 1) * ROWS;
-  for (int e = threadIdx.x; e < ROWS * N; e += 256) {
-    const int r = e / N, k = e % N;
-    const size_t rowoff = size_t(row0 + r) * NH;
-    double2 v;
-    if (k <= HALF) {
-      v = h[rowoff + k];
-    } else {
-      const double2 c = h[rowoff + (N - k)];
-      v = make_double2(c.x, -c.y);
+  for (int e = threadIdx.x; e < LINES * Q4; e += 256) {
+    const int l = e / Q4, r = e % Q4;
+    const size_t a = size_t(row0 + 2 * l) * NH, b = a + NH;  // the pair of rows
+    double2 x[4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      const int k = r + m * Q4;
+      double2 p, q;
+      if (k <= HALF) {
+        p = h[a + k];
+        q = h[b + k];
+      } else {
+        const double2 cp = h[a + (N - k)], cq = h[b + (N - k)];
+        p = make_double2(cp.x, -cp.y);
+        q = make_double2(cq.x, -cq.y);
+      }
+      x[m] = make_double2(p.x - q.y, p.y + q.x);  // p + i q
     }
-    sh[r * LS + lds_pos(bitrev<N>(k))] = v;
+    first_stage_to_lds<N>(sh + l * LS, r, x, +1);
   }
   __syncthreads();
-  butterflies<N>(sh, ROWS, tw);
-  const double R0 = *r0;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  for (int r = wave; r < ROWS; r += 4) {
-    for (int m = lane; m <= HALF; m += 64) {
-      double v = 2.0 * (R0 - sh[r * LS + lds_pos(m)].x);
-      if (m >= 1 && m <= HALF - 1) v += 2.0 * (R0 - sh[r * LS + lds_pos(N - m)].x);
-      fold[r * (HALF + 1) + m] = v;
+  middle_steps<N>(sh, LINES, tw);
+  for (int e = threadIdx.x; e < LINES * Q4; e += 256) {
+    const int l = e / Q4, j = e % Q4;
+    double2 o[4];
+    last_step_from_lds<N>(sh + l * LS, j, tw, o);
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      rl[(2 * l) * N + j + m * Q4] = o[m].x;
+      rl[(2 * l + 1) * N + j + m * Q4] = o[m].y;
     }
   }
   __syncthreads();
-  // the shell sums of every (row, shell) pair over all threads, in the LDS
-  // the transform no longer needs, then the block's rows added per shell in
-  // row order
+  // the shell sums of every (row, shell) pair over all threads, each row
+  // folded by |hx|, in the LDS the transform no longer needs; then the
+  // block's rows added per shell in row order
   static_assert(sizeof(double) * ROWS * (HALF + 1) <= sizeof(sh), "the row sums fit in the transform's LDS");
+  const double R0 = *r0;
   double* part = reinterpret_cast<double*>(sh);
   for (int e = threadIdx.x; e < ROWS * (HALF + 1); e += 256) {
     const int r = e / (HALF + 1), c = e % (HALF + 1);
@@ -433,7 +563,14 @@ __global__ void __launch_bounds__(256)
     const int hz = iz <= HALF ? iz : iz - N, hy = iy <= HALF ? iy : iy - N;
     int a, b;
     shell_range(HALF, hz * hz + hy * hy, c, a, b);
-    part[e] = range_sum(fold + r * (HALF + 1), a, b);
+    const double* rr = rl + r * N;
+    double sum = 0.0;
+    for (int m = a; m <= b; ++m) {
+      double v = 2.0 * (R0 - rr[m]);
+      if (m >= 1 && m <= HALF - 1) v += 2.0 * (R0 - rr[N - m]);
+      sum += v;
+    }
+    part[e] = sum;
   }
   __syncthreads();
   const size_t blk = size_t(row0 / ROWS);
@@ -780,7 +917,7 @@ template <int QN, typename T, int N>
 hipError_t observables_t(const T* pop, const DevSample* samples, int sample0, int count, int parity, void* work,
                          double* s2, double* ek, hipStream_t s) {
   constexpr int NH = N / 2 + 1, L = half_lines(N);
-  constexpr int ROWS_X = N >= 512 ? 1 : 512 / N;
+  constexpr int ROWS_X = fwd_rows(N);
   constexpr int ROWS_R = inv_rows(N);
   constexpr int W = N / 2 + 2;
   static_assert(N % L == 0 && (N * N) % ROWS_X == 0 && (N * N) % ROWS_R == 0, "launch shapes must tile the field");

@@ -168,6 +168,7 @@ hipError_t launch_step_k(StepKind kind, const StepLaunch& L, hipStream_t s) {
       case kStepRecord: return launch_step_exact<QN, T, kStepRecord>(L, s);
       case kReduceOnly: return launch_step_exact<QN, T, kReduceOnly>(L, s);
       case kPush: return launch_step_exact<QN, T, kPush>(L, s);
+      default: return hipErrorInvalidValue;
     }
   }
   switch (kind) {
@@ -175,8 +176,8 @@ hipError_t launch_step_k(StepKind kind, const StepLaunch& L, hipStream_t s) {
     case kStepRecord: return launch_step_b<QN, T, kStepRecord>(L, s);
     case kReduceOnly: return launch_step_b<QN, T, kReduceOnly>(L, s);
     case kPush: return launch_step_b<QN, T, kPush>(L, s);
+    default: return hipErrorInvalidValue;
   }
-  return hipErrorInvalidValue;
 }
 
 }  // namespace
