@@ -9,7 +9,6 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
-#include <mutex>
 #include <string>
 #include <vector>
 
@@ -53,7 +52,6 @@ constexpr uint64_t kCkptMagic = 0x4d434c424d434b50ull;
 constexpr size_t kFwdHeaderBytes = 256;  // forward checkpoints: the token of the forward that wrote them
 std::atomic<uint64_t> g_fwd_tokens{0};
 constexpr int kMaxObservablesN = 512;  // the FFT passes are instantiated for n = 8..512
-constexpr int kNoAllocMaxSamples = 65536;  // samples of mclbm_sample_error_noalloc (2 MiB of device scratch)
 
 // Leray projection on the 24 perturbation coefficients.
 // Every basis field a_i(2x) a_j(2y) a_k(2z) e_alpha is a Laplacian eigenfunction
@@ -1072,30 +1070,6 @@ mclbm_status mclbm_sample_error(const double* a_dev, const double* b_dev, int32_
   return MCLBM_OK;
 }
 
-// Device scratch of mclbm_sample_error_noalloc: the per-sample ratios, 4
-// doubles per sample. Each GPU holds its own copy for the life of the process;
-// its address is looked up once per device (hipGetSymbolAddress with that
-// device current) and kept, and kernels receive that address, never the
-// array's name, which in host code is only a stand-in.
-static __device__ __align__(256) double scratch[4 * kNoAllocMaxSamples];
-
-static std::mutex g_scratch_mutex;
-static std::vector<double*> g_scratch_ptr;  // per device; nullptr until looked up
-
-static mclbm_status scratch_of_current_device(double** out) {
-  int dev = -1;
-  HIP_TRY(hipGetDevice(&dev));
-  std::lock_guard<std::mutex> lock(g_scratch_mutex);
-  if (size_t(dev) >= g_scratch_ptr.size()) g_scratch_ptr.resize(size_t(dev) + 1, nullptr);
-  if (!g_scratch_ptr[dev]) {
-    void* p = nullptr;
-    HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
-    g_scratch_ptr[dev] = static_cast<double*>(p);
-  }
-  *out = g_scratch_ptr[dev];
-  return MCLBM_OK;
-}
-
 mclbm_status mclbm_sample_error_noalloc(const double* a_dev, const double* b_dev, int32_t m, int32_t q,
                                         double* out_dev, void* hip_stream) {
   if (!a_dev || !b_dev || !out_dev) return fail(MCLBM_ERR_ARG, "NULL buffer");
@@ -1104,8 +1078,7 @@ mclbm_status mclbm_sample_error_noalloc(const double* a_dev, const double* b_dev
                                    "] (the device scratch of the no-allocation variant)");
   if (q < 1 || q > 64) return fail(MCLBM_ERR_ARG, "q must be in [1, 64]");
   double* ratio = nullptr;
-  mclbm_status st = scratch_of_current_device(&ratio);
-  if (st != MCLBM_OK) return st;
+  HIP_TRY(sample_error_scratch(&ratio));
   HIP_TRY(launch_sample_error(a_dev, b_dev, m, q, ratio, out_dev, static_cast<hipStream_t>(hip_stream)));
   return MCLBM_OK;
 }

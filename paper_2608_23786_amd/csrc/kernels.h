@@ -123,5 +123,10 @@ hipError_t launch_compensate(const DevSample* samples, int sample0, int count, i
                              const double* s2, const double* ek, double* s2c, double* ekc, hipStream_t s);
 hipError_t launch_sample_error(const double* a, const double* b, int m, int q, double* ratio, double* out,
                                hipStream_t s);
+// The sample error's per-sample ratios without a caller's buffer: a device
+// array of the library (4 doubles per sample, at most kNoAllocMaxSamples
+// samples) whose address on the current device is looked up once per device.
+constexpr int kNoAllocMaxSamples = 65536;
+hipError_t sample_error_scratch(double** ratio);
 
 }  // namespace mclbm

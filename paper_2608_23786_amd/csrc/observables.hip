@@ -40,6 +40,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <mutex>
+#include <vector>
 
 #include "lbm_device.h"
 
@@ -1008,6 +1010,33 @@ hipError_t launch_w1(const double* a, const double* b, int m, int q, double* col
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(w1_reduce_kernel, dim3(3), dim3(256), 0, s, col, q3, out);
   return hipGetLastError();
+}
+
+// Device scratch of the sample error for callers that cannot allocate: the
+// per-sample ratios, 4 doubles per sample. Each GPU holds its own copy for the
+// life of the process; its address is looked up once per device
+// (hipGetSymbolAddress with that device current) and kept, and kernels
+// receive that address, never the array's name, which in host code is only
+// a stand-in.
+static __device__ __align__(256) double scratch[4 * kNoAllocMaxSamples];
+
+static std::mutex g_scratch_mutex;
+static std::vector<double*> g_scratch_ptr;  // per device; nullptr until looked up
+
+hipError_t sample_error_scratch(double** ratio) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (size_t(dev) >= g_scratch_ptr.size()) g_scratch_ptr.resize(size_t(dev) + 1, nullptr);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = static_cast<double*>(p);
+  }
+  *ratio = g_scratch_ptr[dev];
+  return hipSuccess;
 }
 
 hipError_t launch_sample_error(const double* a, const double* b, int m, int q, double* ratio, double* out,
