@@ -89,18 +89,19 @@ __device__ __forceinline__ T vmin(T a, T b) {
 }
 
 // ln(1 + x) for x > -1. float: the hardware base-2 logarithm of u = 1 + x
-// (rounded to float) times ln 2, corrected by the factor x / (u - 1) that
-// restores the part of x lost in rounding u (the log1p identity in
+// (rounded to float) times ln 2, minus the rounding error e = (u - 1) - x of
+// u (exact in float): ln(1 + x) = ln(u - e) = ln u - e/u + O(e^2), and
+// taking e for e/u errs by e x / u, at most 2^-24 |x|, which is below one
+// unit in the last place of ln(1 + x) for small x and of the logarithm's own
+// rounding for large x (the correction is the one of the log1p identity in
 // Goldberg, "What every computer scientist should know about floating-point
-// arithmetic", 1991, Theorem 4, credited to Kahan); a few units in the last
-// place, and exactly x where u rounds to 1. double: the library log1p.
+// arithmetic", 1991, Theorem 4, to first order, without its division);
+// exactly x where u rounds to 1. double: the library log1p.
 template <typename T>
 __device__ __forceinline__ T log1p_acc(T x) {
   if constexpr (std::is_same<T, float>::value) {
     const float u = 1.0f + x;
-    const float d = u - 1.0f;
-    if (d == 0.0f) return x;
-    return (__builtin_amdgcn_logf(u) * 0.693147180559945309f) * (x * __builtin_amdgcn_rcpf(d));
+    return __builtin_amdgcn_logf(u) * 0.693147180559945309f - ((u - 1.0f) - x);
   } else {
     return log1p(x);
   }
@@ -341,16 +342,25 @@ __device__ __forceinline__ T exact_entropic_t(const T (&geq)[Q], const T (&fneq)
     });
     return fmin > T(0);
   };
+  // In float the curvature H'' of the first step is kept for the later ones
+  // (a chord step: the curvature changes by about |t - t0| |dh| / f* between
+  // steps, so each later step still contracts the error by that factor,
+  // reaching float resolution in the step that meets the stopping rule); in
+  // double every step is a full Newton step.
+  constexpr bool kChord = std::is_same<T, float>::value;
   bool done = false;
+  T d2 = T(0);
   for (int it = 0; it < kExactNewtonSteps && !done; ++it) {
-    T d1 = T(0), d2 = T(0);
+    T d1 = T(0);
+    const bool curvature = !kChord || it == 0;
+    if (curvature) d2 = T(0);
     for_vel<QN>([&](auto ic) {
       constexpr int i = decltype(ic)::value;
       constexpr double w = weight<QN>(i);
       // f*_i - w_i in shifted form
       const T gs = bs[i] - t * dh[i];
       d1 += dh[i] * (log1p_acc(gs * T(1.0 / w)) - (a + T(3) * cdot<i>(m.ux, m.uy, m.uz)));
-      d2 += dh[i] * dh[i] * recip(T(w) + gs);
+      if (curvature) d2 += dh[i] * dh[i] * recip(T(w) + gs);
     });
     T tn = t + d1 / d2;
     if (!positive_at(tn)) {

@@ -53,6 +53,9 @@ namespace {
 // field.
 constexpr int half_lines(int n) { return n >= 512 ? 4 : (n >= 256 ? 8 : (n >= 16 ? 16 : 8)); }
 
+// Lines per block of the z pass (its LDS holds the lines and Psi of each)
+constexpr int z_lines(int n) { return half_lines(n); }
+
 // x-rows per block of the inverse transform along x (at most 2048 values;
 // two rows share one complex transform, so a block holds N/4 quartets of
 // ROWS/2 lines, 256 for N >= 16)
@@ -60,7 +63,7 @@ constexpr int inv_rows(int n) { return (n * n < 2048 / n) ? n * n : 2048 / n; }
 
 // rows of the spectrum's and the structure function's shell tables: one
 // per block of the pass that writes them
-constexpr size_t spectrum_bin_rows(int n) { return size_t(n) * (n / 2 + 1) / half_lines(n); }
+constexpr size_t spectrum_bin_rows(int n) { return size_t(n) * (n / 2 + 1) / z_lines(n); }
 constexpr size_t sf_bin_rows(int n) { return size_t(n) * n / inv_rows(n); }
 
 __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
@@ -932,7 +935,8 @@ hipError_t observables_t(const T* pop, const DevSample* samples, int sample0, in
   hipLaunchKernelGGL((fwd_x_kernel<QN, T, N>), dim3(N * N / ROWS_X, 1, z), dim3(256), 0, s, pop, samples, sample0,
                      parity, w.h, ws);
   hipLaunchKernelGGL((fft_y_kernel<N, L>), dim3(lines / L, 3, z), dim3(256), 0, s, w.h, -1, ws);
-  hipLaunchKernelGGL((z_psd_kernel<N, L>), dim3(lines / L, 1, z), dim3(256), 0, s, w.h, w.sbins, ws);
+  constexpr int LZ = z_lines(N);
+  hipLaunchKernelGGL((z_psd_kernel<N, LZ>), dim3(lines / LZ, 1, z), dim3(256), 0, s, w.h, w.sbins, ws);
   hipLaunchKernelGGL(shell_partial_kernel, dim3(lchunks, 1, z), dim3(256), 0, s, w.sbins, srows, W, w.psum, ws);
   hipLaunchKernelGGL(shell_count_kernel, dim3(NH), dim3(256), 0, s, N, w.cnt);
   hipLaunchKernelGGL(shell_final_kernel, dim3(W, 1, z), dim3(256), 0, s, w.psum, w.cnt, lchunks, W, N, 0, ek, w.r0,
