@@ -54,7 +54,7 @@ namespace {
 constexpr int half_lines(int n) { return n >= 512 ? 4 : (n >= 256 ? 8 : (n >= 16 ? 16 : 8)); }
 
 // Lines per block of the z pass (its LDS holds the lines and Psi of each)
-constexpr int z_lines(int n) { return half_lines(n); }
+constexpr int z_lines(int n) { return n == 128 ? 8 : half_lines(n); }
 
 // x-rows per block of the inverse transform along x (at most 2048 values;
 // two rows share one complex transform, so a block holds N/4 quartets of
