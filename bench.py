@@ -171,8 +171,10 @@ def bench_mixed(mc, torch, with_sf=True):
     ticks, FP64 reductions fused every 16 ticks (all samples at equal physical
     time) and, when with_sf, the FP64 structure function of every sample per
     saved tick (one batch of launches per resolution) with the ensemble mean
-    and standard deviation of KE and S2 per resolution. Returns a dict of
-    throughput figures and the last save's statistics."""
+    and standard deviation of KE and S2 per resolution, both of the state the
+    save's record tick reads (the record tick captures its velocity for the
+    structure functions). Returns a dict of throughput figures and the last
+    save's statistics."""
     import mc_inputs
     wl = mc_inputs.WORKLOADS["mixed48_f32"]
     ens = build_ensemble(wl, mc, torch)
@@ -185,6 +187,8 @@ def bench_mixed(mc, torch, with_sf=True):
         first += g.count
     work = ens._dev_empty((max(int(mc.lib().mclbm_observables_range_work_bytes(ens._ctx, a, c)) for a, c in groups),),
                           torch.uint8)
+    if with_sf:
+        ens.capture_velocity()   # each save's record tick writes the velocity the observables read
     t0 = ens.ticks
     lups = sum(cells_per_tick(ens, t0 + k) for k in range(ticks))
     ens.synchronize()
@@ -201,7 +205,7 @@ def bench_mixed(mc, torch, with_sf=True):
             # mean and standard deviation of KE and of S2
             stats = []
             for a, c in groups:
-                s2, _ = ens.observables_range(a, c, work, structure=True, spectrum=False)
+                s2, _ = ens.observables_velocity_range(a, c, work=work, structure=True, spectrum=False)
                 stats.append((mc.ensemble_moments(rec[0, a:a + c, 4:5], stream=ens.stream),
                                mc.ensemble_moments(s2, stream=ens.stream)))
     e1.record(ens.stream)
@@ -219,8 +223,9 @@ def bench_mixed(mc, torch, with_sf=True):
            "launch": dict(zip(("block", "xcd_remap", "buffer_addressing", "nontemporal"), tuned))}
     if stats:
         out["last_save_statistics_u_over_U0"] = last
-    # the same ticks without the structure functions (first realign to a tick
-    # where every sample steps)
+    # the same ticks without the structure functions and the capture (first
+    # realign to a tick where every sample steps)
+    ens.capture_velocity(False)
     ens.step((-ens.ticks) % every)
     ens.synchronize()
     e0.record(ens.stream)
@@ -543,23 +548,34 @@ OBSERVABLES_PROBES = ((32, 64), (12, 128), (4, 256), (1, 512))
 def observables_probe(mc, torch, reps=3):
     """The FP64 spectrum and structure function of each OBSERVABLES_PROBES
     group (FP32 D3Q27 ensembles a few ticks after initialisation, one set of
-    launches per group), `reps` times, timed with HIP events; for
-    kernel-trace and counter passes. Prints one line per group."""
-    for m, n in OBSERVABLES_PROBES:
-        ens = mc.Ensemble([mc.Sample(n, 0.05 * 32 / n, 25.0 * n, 0.05, True)] * m, "f32s")
-        ens.init(5)
-        ens.step(3)
-        ens.observables_range(0, m)
+    launches per group), `reps` times, timed with HIP events, from the
+    populations and from the velocity a record tick captured, with the
+    record tick timed with and without the capture; for kernel-trace and
+    counter passes. Prints two lines per group."""
+    def timed(ens, fn):
+        fn()
         ens.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(ens.stream)
         for _ in range(reps):
-            ens.observables_range(0, m)
+            fn()
         e1.record(ens.stream)
         ens.synchronize()
-        ms = e0.elapsed_time(e1) / reps
+        return e0.elapsed_time(e1) / reps
+
+    for m, n in OBSERVABLES_PROBES:
+        ens = mc.Ensemble([mc.Sample(n, 0.05 * 32 / n, 25.0 * n, 0.05, True)] * m, "f32s")
+        ens.init(5)
+        ens.step(3)
+        ms = timed(ens, lambda: ens.observables_range(0, m))
         print(f"[observables-probe] {m} x {n}^3: {ms:.3f} ms per set of launches, "
               f"{ms * 1e6 / (m * n ** 3):.4f} ns per node", flush=True)
+        rec = timed(ens, lambda: ens.step(1, record_every=1))
+        ens.capture_velocity()
+        rec_u = timed(ens, lambda: ens.step(1, record_every=1))
+        ms_u = timed(ens, lambda: ens.observables_velocity_range(0, m))
+        print(f"[observables-probe] {m} x {n}^3 from the captured velocity: {ms_u:.3f} ms per set of launches; "
+              f"record tick {rec:.3f} ms, {rec_u:.3f} ms with the capture", flush=True)
         del ens
         torch.cuda.empty_cache()
 

@@ -262,6 +262,32 @@ size_t mclbm_observables_range_work_bytes(const mclbm_ctx* ctx, int32_t first, i
 mclbm_status mclbm_observables_range(mclbm_ctx* ctx, int32_t first, int32_t count, double* s2_dev, double* ek_dev,
                                      void* work_dev, size_t work_bytes);
 
+/* Velocity capture: the record ticks of mclbm_step read every population of
+ * every sample (they fall on ticks where every sample steps), so while a
+ * capture buffer is set each record tick also writes the velocity of the
+ * state it reads -- the state its record describes -- in double, summed
+ * from the populations as eq. (momentDefin) defines it, exactly as the first
+ * pass of mclbm_observables_range computes it (the two fields are bitwise
+ * equal). Layout: u_dev[voff(s) + a n_s^3 + cell], a = 0, 1, 2 the
+ * component, cell = (z n + y) n + x, voff(s) = 3 sum_{s' < s} n_s'^3;
+ * mclbm_velocity_bytes(ctx) bytes in total (24 bytes per node). Setting it
+ * adds 24 bytes of writes per node to each record tick and lets the
+ * observables read 24 bytes per node instead of the populations.
+ * mclbm_capture_velocity: u_dev device, 256-byte aligned, at least
+ * mclbm_velocity_bytes bytes (else MCLBM_ERR_OOM), owned by the caller, who
+ * keeps it alive until the capture is cleared (u_dev NULL) or the context
+ * is destroyed; the kernels write it on the context's stream. */
+size_t mclbm_velocity_bytes(const mclbm_ctx* ctx);
+mclbm_status mclbm_capture_velocity(mclbm_ctx* ctx, double* u_dev, size_t bytes);
+
+/* The observables of mclbm_observables_range (same outputs, work buffer and
+ * errors) of the velocity fields held in u_dev (the layout above, e.g. as
+ * captured by the last record tick), for samples first..first+count-1 that
+ * share one n, in one set of launches. u_dev: device, 256-byte aligned,
+ * read only; the state of the ensemble is not read. */
+mclbm_status mclbm_observables_velocity_range(mclbm_ctx* ctx, int32_t first, int32_t count, const double* u_dev,
+                                              double* s2_dev, double* ek_dev, void* work_dev, size_t work_bytes);
+
 /* Sample-wise compensation (eqs. (compensatedE), (compensatedSF)) of the
  * observables of samples first..first+count-1, which share one n:
  * ekc_dev[s][kappa] = kappa^(5/3) (E_s(kappa) / u0_s^2) / (C_Kol d_s^(2/3)),

@@ -70,6 +70,9 @@ SIGNATURES = {
     "mclbm_observables": (_i32, [_ctxp, _i32, _vp, _vp, _vp, _sz]),
     "mclbm_observables_range_work_bytes": (_sz, [_ctxp, _i32, _i32]),
     "mclbm_observables_range": (_i32, [_ctxp, _i32, _i32, _vp, _vp, _vp, _sz]),
+    "mclbm_velocity_bytes": (_sz, [_ctxp]),
+    "mclbm_capture_velocity": (_i32, [_ctxp, _vp, _sz]),
+    "mclbm_observables_velocity_range": (_i32, [_ctxp, _i32, _i32, _vp, _vp, _vp, _vp, _sz]),
     "mclbm_point_values": (_i32, [_ctxp, _i32, _i32, _vp]),
     "mclbm_w1_work_bytes": (_sz, [_i32]),
     "mclbm_w1_1pt": (_i32, [_vp, _vp, _i32, _i32, _vp, _vp, _sz, _vp]),

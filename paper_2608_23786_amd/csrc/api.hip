@@ -111,6 +111,8 @@ struct mclbm_ctx {
   size_t table_pool_bytes = 0;
   double* d_partials = nullptr;
   size_t partial_blocks = 0;
+  double* d_vel = nullptr;    // velocity capture of the record ticks (the caller's buffer), or NULL
+  size_t vel_doubles = 0;     // 3 sum n^3: the capture buffer's length
   char* pop = nullptr;
   size_t state_bytes = 0;
 
@@ -338,6 +340,7 @@ StepLaunch make_launch(mclbm_ctx* c, const Table* t, void* pop, void* dst) {
   L.buffer_ok = c->buffer_addr;
   L.nontemporal = c->nontemporal;
   L.exact_gamma = c->exact_gamma;
+  L.vel = c->d_vel;
   for (int s = 0; s < c->m; ++s)
     if (uint64_t(c->q) * c->h_samples[s].pstride * c->elem >= (uint64_t(1) << 31)) L.buffer_ok = 0;
   return L;
@@ -543,6 +546,8 @@ mclbm_status mclbm_create(mclbm_ctx** out, int32_t m, const mclbm_sample_desc* d
     h.u0 = desc[s].u0;
     h.amp = desc[s].amp;
     h.project = desc[s].project;
+    h.voffset = c->vel_doubles;
+    c->vel_doubles += 3 * size_t(c->cells(s));
     fill_sample(c, s, lattice_nu(desc[s]));
     off = align_up(off + size_t(c->q) * h.pstride * c->elem);
     c->max_stride = std::max(c->max_stride, desc[s].stride);
@@ -1002,6 +1007,37 @@ mclbm_status mclbm_observables_range(mclbm_ctx* c, int32_t first, int32_t count,
 mclbm_status mclbm_observables(mclbm_ctx* c, int32_t sample, double* s2_dev, double* ek_dev, void* work_dev,
                                size_t work_bytes) {
   return mclbm_observables_range(c, sample, 1, s2_dev, ek_dev, work_dev, work_bytes);
+}
+
+size_t mclbm_velocity_bytes(const mclbm_ctx* c) { return c ? sizeof(double) * c->vel_doubles : 0; }
+
+mclbm_status mclbm_capture_velocity(mclbm_ctx* c, double* u_dev, size_t bytes) {
+  mclbm_status st = check_ctx(c, false);
+  if (st != MCLBM_OK) return st;
+  if (u_dev) {
+    if (bytes < sizeof(double) * c->vel_doubles) return fail(MCLBM_ERR_OOM, "velocity capture buffer too small");
+    if (reinterpret_cast<uintptr_t>(u_dev) % kAlign) return fail(MCLBM_ERR_ARG, "u_dev must be 256-byte aligned");
+  }
+  c->d_vel = u_dev;
+  return MCLBM_OK;
+}
+
+mclbm_status mclbm_observables_velocity_range(mclbm_ctx* c, int32_t first, int32_t count, const double* u_dev,
+                                              double* s2_dev, double* ek_dev, void* work_dev, size_t work_bytes) {
+  mclbm_status st = check_ctx(c, false);
+  if (st != MCLBM_OK) return st;
+  if (!u_dev) return fail(MCLBM_ERR_ARG, "u_dev is NULL");
+  if (reinterpret_cast<uintptr_t>(u_dev) % kAlign) return fail(MCLBM_ERR_ARG, "u_dev must be 256-byte aligned");
+  if (first < 0 || count < 1 || first + count > c->m) return fail(MCLBM_ERR_ARG, "sample range out of bounds");
+  const int n = c->desc[first].n;
+  for (int s = first + 1; s < first + count; ++s)
+    if (c->desc[s].n != n) return fail(MCLBM_ERR_ARG, "the samples of a range must share one n");
+  if (n > kMaxObservablesN) return fail(MCLBM_ERR_UNSUPPORTED, "the observables are built for n <= 512");
+  if (!work_dev || work_bytes < observables_work_bytes(n, count))
+    return fail(MCLBM_ERR_OOM, "observables work buffer too small");
+  if (reinterpret_cast<uintptr_t>(work_dev) % kAlign) return fail(MCLBM_ERR_ARG, "work_dev must be 256-byte aligned");
+  HIP_TRY(launch_observables_velocity(u_dev, c->d_samples, first, count, n, work_dev, s2_dev, ek_dev, c->stream));
+  return MCLBM_OK;
 }
 
 mclbm_status mclbm_compensate(mclbm_ctx* c, int32_t first, int32_t count, const double* diss_dev,

@@ -25,6 +25,7 @@ struct StepLaunch {
   int32_t buffer_ok;         // buffer-resource addressing (every sample's populations span < 2 GiB)
   int32_t nontemporal;       // non-temporal loads and stores of the populations
   int32_t exact_gamma;       // 1: exact minimiser of the H-function (block 256 only)
+  double* vel;               // record mode: velocity capture (DevSample::voffset), or NULL
 };
 
 enum StepKind { kStep = 0, kStepRecord = 1, kReduceOnly = 2, kPush = 3 };
@@ -113,6 +114,10 @@ size_t observables_work_bytes(int n, int count);
 hipError_t launch_observables(int q, int precision, const void* pop, const DevSample* samples, int32_t sample0,
                               int32_t count, int32_t n, int32_t parity, void* work, double* s2, double* ek,
                               hipStream_t s);
+// The same observables from captured velocities (u: the capture buffer, each
+// sample's three planes at its voffset).
+hipError_t launch_observables_velocity(const double* u, const DevSample* samples, int32_t sample0, int32_t count,
+                                       int32_t n, void* work, double* s2, double* ek, hipStream_t s);
 // lattice: 27 or 19; q: common nodes per axis
 hipError_t launch_point_values(int lattice, int precision, const void* pop, const DevSample* samples,
                                const Seg* segs, int32_t nseg, int q, int physical, double* out, hipStream_t s);

@@ -81,6 +81,7 @@ struct DevSample {
   int32_t project;        // 1: the perturbation coefficients were Leray-projected
   double u0;              // Taylor-Green amplitude
   double amp;             // perturbation amplitude relative to u0
+  uint64_t voffset;       // double offset of this sample's captured velocity (three planes of n^3)
 };
 
 // One run of consecutive blocks of a launch that belong to one sample.

@@ -147,6 +147,28 @@ __device__ __forceinline__ Macro<T> macroscopic(const T (&g)[Q]) {
   return m;
 }
 
+// Velocity of a node (eq. (momentDefin)) from its shifted populations, summed
+// in double in velocity order whatever the storage precision: the field the
+// FP64 observables transform. The collide-and-stream kernel writes it on
+// record ticks and the first pass of the observables computes it from a
+// stored state with this same code, so the two fields are bitwise equal.
+template <int QN, typename T>
+__device__ __forceinline__ void node_velocity(const T (&g)[Q], double& ux, double& uy, double& uz) {
+  double d = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
+  for_vel<QN>([&](auto ic) {
+    constexpr int i = decltype(ic)::value;
+    const double v = double(g[i]);
+    d += v;
+    if constexpr (cx(i) != 0) jx += cx(i) * v;
+    if constexpr (cy(i) != 0) jy += cy(i) * v;
+    if constexpr (cz(i) != 0) jz += cz(i) * v;
+  });
+  const double rho = 1.0 + d;
+  ux = jx / rho;
+  uy = jy / rho;
+  uz = jz / rho;
+}
+
 // shifted equilibrium g^eq_i = f^eq_i - w_i
 template <int QN, int i, typename T>
 __device__ __forceinline__ T geq(const Macro<T>& m) {

@@ -277,15 +277,17 @@ constexpr int fwd_rows(int n) { return n >= 256 ? 2 : 512 / n; }
 // Pass 1: ROWS rows (z, y) per block. Velocities of the rows' nodes from the
 // populations (the parity selects the AA slots; consecutive threads take
 // consecutive nodes of a row, so every population plane is read in
-// contiguous runs), and the forward transform along x of the three
+// contiguous runs), or, with FROM_U, read from the velocity a record tick
+// captured (u + voffset, three planes of N^3; pop and parity unused), and
+// the forward transform along x of the three
 // components, kx = 0..N/2 written to h[c][(z N + y) NH + kx]. The components
 // are real, so two share one complex transform: ux + i uy of each row, and
 // uz of a pair of rows, loaded into LDS in bit-reversed order; the two
 // spectra of a line are separated afterwards from Z(k) and Z(N - k):
 // A(k) = (Z(k) + conj Z(N - k)) / 2, B(k) = (Z(k) - conj Z(N - k)) / 2i.
-template <int QN, typename T, int N>
-__global__ void __launch_bounds__(256)
-    fwd_x_kernel(const T* pop, const DevSample* samples, int sample0, int parity, double2* h0, size_t wstride) {
+template <int QN, typename T, int N, bool FROM_U>
+__global__ void __launch_bounds__(256) fwd_x_kernel(const T* pop, const double* u, const DevSample* samples,
+                                                    int sample0, int parity, double2* h0, size_t wstride) {
   constexpr int ROWS = fwd_rows(N), PAIRS = ROWS / 2, LINES = ROWS + PAIRS;
   constexpr int NH = N / 2 + 1, Q4 = N / 4;
   constexpr int LS = lds_line<N>();
@@ -295,26 +297,25 @@ __global__ void __launch_bounds__(256)
   double2* h = in_batch(h0, wstride);
   const size_t row0 = size_t(remap_block(blockIdx.x, gridDim.x, 1)) * ROWS;
   make_twiddles<N>(tw, -1);
-  const T* base = pop + sp.offset;
   double* shd = reinterpret_cast<double*>(sh);
   for (int e = threadIdx.x; e < ROWS * N; e += 256) {
     const int r = e / N, x = e % N;
-    const Cell c = make_cell(uint32_t((row0 + r) * N + x), sp.log2n);
-    T g[Q];
-    load_state<QN>(base, sp.pstride, c, parity & 1, g);
-    double d = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
-    for_vel<QN>([&](auto ic) {
-      constexpr int i = decltype(ic)::value;
-      const double v = double(g[i]);
-      d += v;
-      if constexpr (cx(i) != 0) jx += cx(i) * v;
-      if constexpr (cy(i) != 0) jy += cy(i) * v;
-      if constexpr (cz(i) != 0) jz += cz(i) * v;
-    });
-    const double rho = 1.0 + d;
+    const uint32_t cell = uint32_t((row0 + r) * N + x);
+    double ux, uy, uz;
+    if constexpr (FROM_U) {
+      constexpr size_t plane = size_t(N) * N * N;
+      const double* ub = u + sp.voffset;
+      ux = ub[cell];
+      uy = ub[plane + cell];
+      uz = ub[2 * plane + cell];
+    } else {
+      T g[Q];
+      load_state<QN>(pop + sp.offset, sp.pstride, make_cell(cell, sp.log2n), parity & 1, g);
+      node_velocity<QN>(g, ux, uy, uz);
+    }
     const int rv = lds_pos(bitrev<N>(x));
-    sh[r * LS + rv] = make_double2(jx / rho, jy / rho);
-    shd[2 * ((ROWS + r / 2) * LS + rv) + (r & 1)] = jz / rho;
+    sh[r * LS + rv] = make_double2(ux, uy);
+    shd[2 * ((ROWS + r / 2) * LS + rv) + (r & 1)] = uz;
   }
   __syncthreads();
   all_but_last_steps<N>(sh, LINES, tw);
@@ -918,9 +919,9 @@ ObsWork carve(void* work, int n) {
   return w;
 }
 
-template <int QN, typename T, int N>
-hipError_t observables_t(const T* pop, const DevSample* samples, int sample0, int count, int parity, void* work,
-                         double* s2, double* ek, hipStream_t s) {
+template <int QN, typename T, int N, bool FROM_U>
+hipError_t observables_t(const T* pop, const double* u, const DevSample* samples, int sample0, int count, int parity,
+                         void* work, double* s2, double* ek, hipStream_t s) {
   constexpr int NH = N / 2 + 1, L = half_lines(N);
   constexpr int ROWS_X = fwd_rows(N);
   constexpr int ROWS_R = inv_rows(N);
@@ -932,8 +933,8 @@ hipError_t observables_t(const T* pop, const DevSample* samples, int sample0, in
   const int lines = N * NH, rows = N * N;
   const int srows = int(spectrum_bin_rows(N)), rrows = int(sf_bin_rows(N));
   const int lchunks = int(chunks_of(srows)), rchunks = int(chunks_of(rrows));
-  hipLaunchKernelGGL((fwd_x_kernel<QN, T, N>), dim3(N * N / ROWS_X, 1, z), dim3(256), 0, s, pop, samples, sample0,
-                     parity, w.h, ws);
+  hipLaunchKernelGGL((fwd_x_kernel<QN, T, N, FROM_U>), dim3(N * N / ROWS_X, 1, z), dim3(256), 0, s, pop, u, samples,
+                     sample0, parity, w.h, ws);
   hipLaunchKernelGGL((fft_y_kernel<N, L>), dim3(lines / L, 3, z), dim3(256), 0, s, w.h, -1, ws);
   constexpr int LZ = z_lines(N);
   hipLaunchKernelGGL((z_psd_kernel<N, LZ>), dim3(lines / LZ, 1, z), dim3(256), 0, s, w.h, w.sbins, ws);
@@ -951,18 +952,18 @@ hipError_t observables_t(const T* pop, const DevSample* samples, int sample0, in
   return hipGetLastError();
 }
 
-template <int QN, typename T>
-hipError_t observables_n(int n, const void* pop, const DevSample* samples, int sample0, int count, int parity,
-                         void* work, double* s2, double* ek, hipStream_t s) {
+template <int QN, typename T, bool FROM_U>
+hipError_t observables_n(int n, const void* pop, const double* u, const DevSample* samples, int sample0, int count,
+                         int parity, void* work, double* s2, double* ek, hipStream_t s) {
   const T* p = static_cast<const T*>(pop);
   switch (n) {
-    case 8: return observables_t<QN, T, 8>(p, samples, sample0, count, parity, work, s2, ek, s);
-    case 16: return observables_t<QN, T, 16>(p, samples, sample0, count, parity, work, s2, ek, s);
-    case 32: return observables_t<QN, T, 32>(p, samples, sample0, count, parity, work, s2, ek, s);
-    case 64: return observables_t<QN, T, 64>(p, samples, sample0, count, parity, work, s2, ek, s);
-    case 128: return observables_t<QN, T, 128>(p, samples, sample0, count, parity, work, s2, ek, s);
-    case 256: return observables_t<QN, T, 256>(p, samples, sample0, count, parity, work, s2, ek, s);
-    case 512: return observables_t<QN, T, 512>(p, samples, sample0, count, parity, work, s2, ek, s);
+    case 8: return observables_t<QN, T, 8, FROM_U>(p, u, samples, sample0, count, parity, work, s2, ek, s);
+    case 16: return observables_t<QN, T, 16, FROM_U>(p, u, samples, sample0, count, parity, work, s2, ek, s);
+    case 32: return observables_t<QN, T, 32, FROM_U>(p, u, samples, sample0, count, parity, work, s2, ek, s);
+    case 64: return observables_t<QN, T, 64, FROM_U>(p, u, samples, sample0, count, parity, work, s2, ek, s);
+    case 128: return observables_t<QN, T, 128, FROM_U>(p, u, samples, sample0, count, parity, work, s2, ek, s);
+    case 256: return observables_t<QN, T, 256, FROM_U>(p, u, samples, sample0, count, parity, work, s2, ek, s);
+    case 512: return observables_t<QN, T, 512, FROM_U>(p, u, samples, sample0, count, parity, work, s2, ek, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -975,14 +976,21 @@ hipError_t launch_observables(int q, int precision, const void* pop, const DevSa
                               int32_t count, int32_t n, int32_t parity, void* work, double* s2, double* ek,
                               hipStream_t s) {
   if (q == 27) {
-    return precision == 0 ? observables_n<27, double>(n, pop, samples, sample0, count, parity, work, s2, ek, s)
-                          : observables_n<27, float>(n, pop, samples, sample0, count, parity, work, s2, ek, s);
+    return precision == 0
+               ? observables_n<27, double, false>(n, pop, nullptr, samples, sample0, count, parity, work, s2, ek, s)
+               : observables_n<27, float, false>(n, pop, nullptr, samples, sample0, count, parity, work, s2, ek, s);
   }
   if (q == 19) {
-    return precision == 0 ? observables_n<19, double>(n, pop, samples, sample0, count, parity, work, s2, ek, s)
-                          : observables_n<19, float>(n, pop, samples, sample0, count, parity, work, s2, ek, s);
+    return precision == 0
+               ? observables_n<19, double, false>(n, pop, nullptr, samples, sample0, count, parity, work, s2, ek, s)
+               : observables_n<19, float, false>(n, pop, nullptr, samples, sample0, count, parity, work, s2, ek, s);
   }
   return hipErrorInvalidValue;
+}
+
+hipError_t launch_observables_velocity(const double* u, const DevSample* samples, int32_t sample0, int32_t count,
+                                       int32_t n, void* work, double* s2, double* ek, hipStream_t s) {
+  return observables_n<27, double, true>(n, nullptr, u, samples, sample0, count, 0, work, s2, ek, s);
 }
 
 hipError_t launch_point_values(int lattice, int precision, const void* pop, const DevSample* samples,

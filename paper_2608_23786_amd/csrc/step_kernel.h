@@ -21,6 +21,7 @@ struct StepArgs {
   int32_t xcd_remap;
   int32_t* flags;
   double* partials;
+  double* vel;  // record ticks: the velocity of the state read, per sample at voffset (NULL: none)
 };
 
 template <int QN, typename T, int BLOCK, StepKind KIND, bool BUF, bool NT, bool EXACT = false>
@@ -58,6 +59,17 @@ __global__ void __launch_bounds__(BLOCK) kbc_step_kernel(StepArgs<T> a) {
       const Slot s = aa_read_slot<i>(c, true);
       g[i] = src.load(s.vel, s.idx);
     });
+  }
+  if constexpr (KIND == kStepRecord) {
+    if (a.vel) {
+      double ux, uy, uz;
+      node_velocity<QN>(g, ux, uy, uz);
+      double* u = a.vel + sp.voffset;
+      const size_t plane = size_t(n) * n * n;
+      __builtin_nontemporal_store(ux, u + c.cell);
+      __builtin_nontemporal_store(uy, u + plane + c.cell);
+      __builtin_nontemporal_store(uz, u + 2 * plane + c.cell);
+    }
   }
   const CellResult<T> res = kbc_collide<QN, EXACT>(g, relax_of<T>(sp));
   if (res.bad) a.flags[sg.sample] = 1;
@@ -112,6 +124,7 @@ hipError_t launch_step_t(const StepLaunch& L, hipStream_t s) {
   a.xcd_remap = L.xcd_remap;
   a.flags = L.flags;
   a.partials = L.partials;
+  a.vel = L.vel;
   const dim3 grid(L.total_blocks), blk(BLOCK);
   if (buf && L.nontemporal)
     hipLaunchKernelGGL((kbc_step_kernel<QN, T, BLOCK, KIND, true, true>), grid, blk, 0, s, a);
@@ -151,6 +164,7 @@ hipError_t launch_step_exact(const StepLaunch& L, hipStream_t s) {
   a.xcd_remap = L.xcd_remap;
   a.flags = L.flags;
   a.partials = L.partials;
+  a.vel = L.vel;
   if (L.block != 256) return hipErrorInvalidValue;
   if (L.buffer_ok)
     hipLaunchKernelGGL((kbc_step_kernel<QN, T, 256, KIND, true, true, true>), dim3(L.total_blocks), dim3(256), 0, s, a);

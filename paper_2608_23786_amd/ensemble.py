@@ -223,6 +223,57 @@ class Ensemble:
         self._produce(s2, ek)
         return s2, ek
 
+    def capture_velocity(self, enable: bool = True) -> Optional[torch.Tensor]:
+        """While enabled, every record tick of step() also writes the float64
+        velocity of the state it reads (the state its record describes) into a
+        buffer the ensemble owns, which is returned: per sample three planes of
+        n^3 one after another (velocity() gives one sample's view). Disabling
+        clears the library's pointer before the buffer is released."""
+        if not enable:
+            check(lib().mclbm_capture_velocity(self._ctx, None, 0))
+            self._vel = None
+            return None
+        nbytes = int(lib().mclbm_velocity_bytes(self._ctx))
+        buf = self._dev_empty((nbytes // 8,))
+        if buf.data_ptr() % 256:
+            raise MclbmError(_lib.ERR_ARG, "the capture buffer is not 256-byte aligned")
+        check(lib().mclbm_capture_velocity(self._ctx, _ptr(buf), nbytes))
+        self._vel = buf
+        return buf
+
+    def velocity(self, sample: int) -> torch.Tensor:
+        """[3, n, n, n] float64 view of one sample's captured velocity."""
+        self._check_sample(sample)
+        if getattr(self, "_vel", None) is None:
+            raise MclbmError(_lib.ERR_STATE, "no velocity capture is set")
+        off = sum(3 * s.n ** 3 for s in self.samples[:sample])
+        n = self.samples[sample].n
+        return self._vel[off:off + 3 * n ** 3].view(3, n, n, n)
+
+    def observables_velocity_range(self, first: int, count: int, u: Optional[torch.Tensor] = None,
+                                   work: Optional[torch.Tensor] = None, structure: bool = True,
+                                   spectrum: bool = True):
+        """observables_range() of the velocity fields in u (the capture layout;
+        by default the capture buffer, i.e. the state the last record tick read)."""
+        wb = int(lib().mclbm_observables_range_work_bytes(self._ctx, first, count))
+        if wb == 0:
+            raise MclbmError(_lib.ERR_ARG, "invalid sample range (out of bounds, mixed resolutions or n above 512)")
+        if u is None:
+            u = getattr(self, "_vel", None)
+            if u is None:
+                raise MclbmError(_lib.ERR_STATE, "no velocity capture is set")
+        _require_cuda(u, torch.float64, sum(3 * s.n ** 3 for s in self.samples), "u")
+        n = self.samples[first].n
+        if work is None or work.numel() < wb:
+            work = self._dev_empty((wb,), torch.uint8)
+        s2 = self._dev_empty((count, n // 2)) if structure else None
+        ek = self._dev_empty((count, n // 2 + 1)) if spectrum else None
+        self._consume(work, u)
+        check(lib().mclbm_observables_velocity_range(self._ctx, first, count, _ptr(u), _ptr(s2), _ptr(ek), _ptr(work),
+                                                     work.numel()))
+        self._produce(s2, ek)
+        return s2, ek
+
     def point_values(self, q: int = 8, physical: bool = False) -> torch.Tensor:
         """Velocity at the q^3 nodes common to all resolutions: [m, 3, q^3] float64,
         in lattice units or, with physical, as u / u0."""

@@ -352,3 +352,77 @@ def test_compensated_observables_match_oracle(lattice):
     assert none is None and torch.equal(only, s2c)
     with pytest.raises(mc.MclbmError, match="ERR_ARG"):
         ens.compensate(2, d, s2=s2)       # past the ensemble
+
+
+@pytest.mark.parametrize("precision,lattice,stabiliser", [("f32s", 27, "closed_form"), ("f64", 27, "closed_form"),
+                                                          ("f32s", 19, "closed_form"), ("f32s", 27, "exact")])
+@pytest.mark.parametrize("layout", ["strides", "row_exchange"])
+def test_captured_velocity_gives_the_observables_of_the_recorded_state(precision, lattice, stabiliser, layout):
+    """A record tick with velocity capture writes, for every sample, the
+    velocity of the state it reads: bitwise the library's read-out of that
+    state, and its observables are bitwise those of the state (which the
+    tests above tie to the oracle at 1e-12). Both AA parities: a stride-2
+    group recorded at odd and even step counts, and a 128^3 sample whose odd
+    ticks exchange row edges between waves."""
+    if layout == "strides":
+        samples = [mc.Sample(16, 0.05, 200.0, 0.3, True, 2)] * 2 + [mc.Sample(32, 0.05, 200.0, 0.3, True, 1)] * 2
+        groups, first_ticks = [(0, 2), (2, 2)], (6, 2)     # records at ticks 6 and 8
+    else:
+        samples = [mc.Sample(16, 0.05, 200.0, 0.3, True, 1), mc.Sample(128, 0.0125, 3200.0, 0.3, True, 1)]
+        groups, first_ticks = [(0, 1), (1, 1)], (5, 1)     # records at ticks 5 and 6
+    y = mc_inputs.draw_y(34, len(samples))
+    ens = mc.Ensemble(samples, precision, lattice=lattice)
+    ens.init(0, torch.from_numpy(y))
+    ens.set_stabiliser(stabiliser)
+    ens.capture_velocity()
+    for ticks_before in first_ticks:
+        ens.step(ticks_before)
+        parities = {s: ens.steps(s) % 2 for s in range(len(samples))}
+        ref_u = [ens.moments(s)[1].clone() for s in range(len(samples))]
+        ref_obs = [ens.observables_range(a, c) for a, c in groups]
+        ens.step(2, record_every=2)
+        ens.synchronize()
+        for s in range(len(samples)):
+            assert torch.equal(ens.velocity(s), ref_u[s]), (s, parities[s])
+        for (a, c), (s2r, ekr) in zip(groups, ref_obs):
+            s2, ek = ens.observables_velocity_range(a, c)
+            assert torch.equal(s2, s2r) and torch.equal(ek, ekr), (a, parities[a])
+    assert {p for p in parities.values()} <= {0, 1}
+    # plain ticks leave the capture alone; clearing it stops the writes
+    snap = ens.velocity(0).clone()
+    ens.step(4)
+    assert torch.equal(ens.velocity(0), snap)
+    ens.capture_velocity(False)
+    ens.step(2, record_every=2)
+    with pytest.raises(mc.MclbmError, match="ERR_STATE"):
+        ens.velocity(0)
+
+
+def test_velocity_capture_argument_checks():
+    ens = mc.Ensemble([mc.Sample(16, 0.05, 200.0, 0.3, True)], "f32s")
+    ens.init(0, torch.from_numpy(mc_inputs.draw_y(35, 1)))
+    lib = mc.lib()
+    nbytes = int(lib.mclbm_velocity_bytes(ens._ctx))
+    assert nbytes == 24 * 16 ** 3
+    buf = torch.zeros(nbytes // 8 + 64, dtype=torch.float64, device="cuda")
+    assert lib.mclbm_capture_velocity(ens._ctx, buf.data_ptr(), nbytes - 8) == mc._lib.ERR_OOM
+    assert lib.mclbm_capture_velocity(ens._ctx, buf.data_ptr() + 8, nbytes) == mc._lib.ERR_ARG
+    work = torch.empty(int(lib.mclbm_observables_range_work_bytes(ens._ctx, 0, 1)), dtype=torch.uint8, device="cuda")
+    assert lib.mclbm_observables_velocity_range(ens._ctx, 0, 1, None, None, None, work.data_ptr(),
+                                                work.numel()) == mc._lib.ERR_ARG
+    assert lib.mclbm_observables_velocity_range(ens._ctx, 0, 2, buf.data_ptr(), None, None, work.data_ptr(),
+                                                work.numel()) == mc._lib.ERR_ARG
+    assert lib.mclbm_observables_velocity_range(ens._ctx, 0, 1, buf.data_ptr(), None, None, work.data_ptr(),
+                                                16) == mc._lib.ERR_OOM
+    # the observables of a field written by hand: the Taylor-Green velocity
+    n = 16
+    x = torch.arange(n, dtype=torch.float64, device="cuda") * (2 * np.pi / n)
+    X, Y, Z = torch.meshgrid(x, x, x, indexing="ij")
+    u = torch.stack([torch.sin(X) * torch.cos(Y) * torch.cos(Z), -torch.cos(X) * torch.sin(Y) * torch.cos(Z),
+                     torch.zeros_like(X)]).permute(0, 3, 2, 1).contiguous()   # [c][z][y][x]
+    buf[:3 * n ** 3] = u.flatten()
+    s2, ek = ens.observables_velocity_range(0, 1, u=buf[:3 * n ** 3].contiguous())
+    eko = oracle.energy_spectrum(u.cpu().numpy())
+    s2o = oracle.structure_function(u.cpu().numpy())
+    assert np.max(np.abs(ek.cpu().numpy()[0] - eko)) <= 1e-12 * eko.max()
+    assert np.max(np.abs(s2.cpu().numpy()[0] - s2o)) <= 1e-12 * s2o.max()
