@@ -244,7 +244,7 @@ mclbm_status mclbm_step_vjp(mclbm_ctx* ctx, const double* lam_dev, double* out_d
  *     (energySpecDisc) with the coefficients of eq. (dftCoeff); modes whose
  *     length rounds above n/2 are not counted.
  * Either output may be NULL. work_dev: device scratch of
- * mclbm_observables_work_bytes(ctx, sample) bytes (about 25 n^3 bytes),
+ * mclbm_observables_work_bytes(ctx, sample) bytes (about 27 n^3 bytes),
  * 256-byte aligned, owned by the caller. Supported n: 8..512 (a sample
  * of n = 1024 gives MCLBM_ERR_UNSUPPORTED and 0 work bytes). Lattice
  * units (divide by u0^2 for physical units). */

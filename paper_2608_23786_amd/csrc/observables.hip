@@ -11,18 +11,27 @@
 //     ensembles by sorting (Algorithm 2, eq. (wassersteinPermutations)).
 //
 // The velocity is real, so its transform is stored for kx = 0..N/2 only
-// (the rest follows by conjugate symmetry), fields [z][y][kx], and the
-// pipeline is five passes over HBM:
-//   1. x: velocities from the populations (either AA parity) and the
-//      forward transform along x of the three components, per row in LDS
-//      (two real components share one complex transform);
+// (the rest follows by conjugate symmetry), fields [z][y][kx]. A shell C_r
+// is closed under a change of sign of any lag component, so S2 needs R only
+// summed over the lags that fold to f = (|hx|, |hy|, |hz|), f_a = 0..N/2:
+// X(f) = sum_{h -> f} R_h = N^-6 sum_k Psi(k) prod_a mu(f_a) cos(2 pi k_a f_a / N)
+// with mu(0) = mu(N/2) = 1 and mu = 2 otherwise (the lags behind f_a). The
+// inverse transforms therefore run as cosine sums that keep f_a = 0..N/2,
+// which shrinks each axis' output to about half. The pipeline is five
+// passes over HBM:
+//   1. x: velocities from the populations (either AA parity), or from the
+//      velocity a record tick captured, and the forward transform along x
+//      of the three components, per row in LDS (two real components share
+//      one complex transform);
 //   2. y: forward transforms along y of the three fields;
 //   3. per z-line: the forward transforms along z of the three fields,
 //      Psi, its shell sums for the spectrum, its total (R_0), and the
-//      inverse transform along z of Psi, written over field 0;
-//   4. inverse along y; 5. per x-row: the inverse along x (conjugate-
-//      symmetric fill, real result R_h, two rows per complex transform) and
-//      its shell sums for S2.
+//      folded inverse along z, G[ky][kx][f_z] (real);
+//   4. y: the folded inverse along y of G, H[f_y][kx][f_z] (two real lines
+//      per complex transform);
+//   5. per row (f_y, f_z): the folded inverse along x (H is even in kx once
+//      y and z are folded, so its transform is real; two rows per complex
+//      transform), X(f), and the shell sums for S2.
 // Radix-2/4 decimation-in-time transforms of whole lines in LDS (padded
 // against bank conflicts), the first and last stage in registers of the
 // thread that loads or keeps a quartet of the line, twiddles by sincospi;
@@ -56,15 +65,17 @@ constexpr int half_lines(int n) { return n >= 512 ? 4 : (n >= 256 ? 8 : (n >= 16
 // Lines per block of the z pass (its LDS holds the lines and Psi of each)
 constexpr int z_lines(int n) { return n == 128 ? 8 : half_lines(n); }
 
-// x-rows per block of the inverse transform along x (at most 2048 values;
-// two rows share one complex transform, so a block holds N/4 quartets of
-// ROWS/2 lines, 256 for N >= 16)
-constexpr int inv_rows(int n) { return (n * n < 2048 / n) ? n * n : 2048 / n; }
+// Pairs of real lines per block of the folded inverse passes along y and x
+// (one complex transform per pair; LDS: about PAIRS * N complex doubles)
+constexpr int cos_pairs(int n) { return n >= 512 ? 4 : (n >= 128 ? 8 : 16); }
+
+// Lines of the folded passes: (N/2 + 1)^2 per value of the other index
+constexpr size_t folded_lines(int n) { return size_t(n / 2 + 1) * (n / 2 + 1); }
 
 // rows of the spectrum's and the structure function's shell tables: one
 // per block of the pass that writes them
 constexpr size_t spectrum_bin_rows(int n) { return size_t(n) * (n / 2 + 1) / z_lines(n); }
-constexpr size_t sf_bin_rows(int n) { return size_t(n) * n / inv_rows(n); }
+constexpr size_t sf_bin_rows(int n) { return (folded_lines(n) + 2 * cos_pairs(n) - 1) / (2 * cos_pairs(n)); }
 
 __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
   return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
@@ -346,7 +357,7 @@ __global__ void __launch_bounds__(256) fwd_x_kernel(const T* pop, const double* 
   }
 }
 
-// Passes 2 and 4: transform along y of the fields h + c * N N NH,
+// Pass 2: transform along y of the fields h + c * N N NH,
 // c = blockIdx.y; LINES lines (z, kx) per block, consecutive kx, a quartet of
 // a line per thread (consecutive threads take consecutive lines, so their
 // global accesses are contiguous). sign -1 forward, +1 inverse.
@@ -383,22 +394,31 @@ __global__ void __launch_bounds__(256) fft_y_kernel(double2* h0, int sign, size_
 // of each of the three fields (already transformed along x and y), one
 // field at a time in LDS, with Psi, the sum of |.|^2 over the fields, kept in
 // registers (the quartets of a thread are the same for every field, and the
-// inverse transform's first stage takes the same quartets); Psi is also kept
-// in LDS in natural order for the shell sums. Then the inverse transform of
-// Psi along z, written over field 0, and the shell sums of |k|^2/2 Psi over
-// the block's lines (each line folded by |kz| and weighted by its kx weight,
-// the lines added in order) into sbins[block][kappa] and the sum of Psi into
-// sbins[block][N/2 + 1] (rows of N/2 + 2 values).
+// inverse transform's first stage takes the same quartets). Psi then goes to
+// the transform's LDS in natural order for the shell sums of |k|^2/2 Psi
+// over the block's lines (each line folded by |kz| and weighted by its kx
+// weight, the lines added in order) into sbins[block][kappa] and the sum of
+// Psi into sbins[block][N/2 + 1] (rows of N/2 + 2 values); last, the folded
+// inverse transform of Psi along z, G(f_z) = mu(f_z) Re F^-1(Psi)(f_z) for
+// f_z = 0..N/2 (Psi is real, so that real part is even), written to
+// g[(ky NH + kx)(N/2 + 1) + f_z]: the block's lines are consecutive (ky, kx),
+// so it writes one contiguous run. One LDS area serves all three, which
+// keeps a block at the transform's LDS.
 template <int N, int LINES>
-__global__ void __launch_bounds__(256) z_psd_kernel(double2* h0, double* sbins0, size_t wstride) {
+__global__ void __launch_bounds__(256) z_psd_kernel(const double2* h0, double* g0, double* sbins0, size_t wstride) {
   constexpr int NH = N / 2 + 1, HALF = N / 2, LS = lds_line<N>(), Q4 = N / 4;
   constexpr int PER = (LINES * Q4 + 255) / 256;  // quartets per thread
   __shared__ double2 sh[LINES * LS];
-  __shared__ double psi[LINES * N];
   __shared__ double tot[LINES];
   __shared__ double2 tw[lds_line<N / 2>()];
+  // Psi of every line and the (line, shell) sums live in the transform's LDS
+  // between the forward and the inverse transforms
+  static_assert(sizeof(double) * LINES * (N + HALF + 1) <= sizeof(sh), "Psi and the line sums fit in the LDS");
+  double* psi = reinterpret_cast<double*>(sh);
+  double* part = psi + LINES * N;
   const size_t field = size_t(N) * N * NH;
-  double2* h = in_batch(h0, wstride);
+  const double2* h = in_batch(h0, wstride);
+  double* g = in_batch(g0, wstride);
   double* sbins = in_batch(sbins0, wstride);
   make_twiddles<N>(tw, -1);
   const int line0 = remap_block(blockIdx.x, gridDim.x, 1) * LINES;
@@ -433,35 +453,21 @@ __global__ void __launch_bounds__(256) z_psd_kernel(double2* h0, double* sbins0,
         for (int m = 0; m < 4; ++m) ps[k][m] += o[m].x * o[m].x + o[m].y * o[m].y;
       }
     }
-    __syncthreads();  // the next field overwrites sh
+    __syncthreads();  // the next field (or Psi) overwrites sh
   }
-  // the inverse transform's twiddles; Psi in natural order for the shell
-  // sums; the inverse's first stage from the registers
-  make_twiddles<N>(tw, +1);
+  // Psi in natural order; the inverse transform's twiddles are the
+  // conjugates of the forward ones
 #pragma unroll
   for (int k = 0; k < PER; ++k) {
     const int e = threadIdx.x + 256 * k;
     if (e < LINES * Q4) {
       const int j = e / LINES, l = e % LINES;
-      double2 x[4];
 #pragma unroll
-      for (int m = 0; m < 4; ++m) {
-        psi[l * N + j + m * Q4] = ps[k][m];
-        x[m] = make_double2(ps[k][m], 0.0);
-      }
-      first_stage_to_lds<N>(sh + l * LS, j, x, +1);
+      for (int m = 0; m < 4; ++m) psi[l * N + j + m * Q4] = ps[k][m];
     }
   }
+  for (int k = threadIdx.x; k < N / 2; k += 256) tw[lds_pos(k)].y = -tw[lds_pos(k)].y;
   __syncthreads();
-  middle_steps<N>(sh, LINES, tw);
-  for (int e = threadIdx.x; e < LINES * Q4; e += 256) {
-    const int j = e / LINES, l = e % LINES;
-    const int line = line0 + l, y = line / NH, kx = line % NH;
-    double2 o[4];
-    last_step_from_lds<N>(sh + l * LS, j, tw, o);
-#pragma unroll
-    for (int m = 0; m < 4; ++m) h[(size_t(j + m * Q4) * N + y) * NH + kx] = o[m];
-  }
   // the total of Psi per line (R_0), one wave per line
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   for (int l = wave; l < LINES; l += 4) {
@@ -471,12 +477,8 @@ __global__ void __launch_bounds__(256) z_psd_kernel(double2* h0, double* sbins0,
     total = wave_sum(total);
     if (lane == 0) tot[l] = fold_weight(kx, HALF) * total;
   }
-  __syncthreads();  // every read of sh by the transform is done
-  // the shell sums of every (line, shell) pair over all threads, in the LDS
-  // the transform no longer needs, each line folded by |kz|; then the
-  // block's lines added per shell in line order
-  static_assert(sizeof(double) * LINES * (HALF + 1) <= sizeof(sh), "the line sums fit in the transform's LDS");
-  double* part = reinterpret_cast<double*>(sh);
+  // the shell sums of every (line, shell) pair over all threads, each line
+  // folded by |kz|; then the block's lines added per shell in line order
   for (int e = threadIdx.x; e < LINES * (HALF + 1); e += 256) {
     const int l = e / (HALF + 1), r = e % (HALF + 1);
     const int line = line0 + l, y = line / NH, kx = line % NH;
@@ -500,89 +502,216 @@ __global__ void __launch_bounds__(256) z_psd_kernel(double2* h0, double* sbins0,
     for (int l = 0; l < LINES; ++l) sum += r == HALF + 1 ? tot[l] : part[l * (HALF + 1) + r];
     sbins[blk * (HALF + 2) + r] = sum;
   }
-}
-
-// Pass 5: ROWS x-rows (z, y) per block of field 0 (Psi transformed back along
-// z and y): the conjugate-symmetric fill of kx = N/2+1..N-1, the inverse
-// transform along x (R_h times N^6, real), and the shell sums of
-// 2 (R_0 - R_h) over the block's rows (each row folded by |hx|, the rows
-// added in order) into rbins[block][r] (rows of N/2 + 2 values, the last one
-// 0). Both outputs of a pair of rows are real, so the pair shares one
-// complex transform: Z = X_a + i X_b transforms to x_a + i x_b. r0: R_0
-// times N^6 (the sum of Psi).
-template <int N>
-__global__ void __launch_bounds__(256)
-    inv_x_rows_kernel(const double2* h0, const double* r00, double* rbins0, size_t wstride) {
-  constexpr int NH = N / 2 + 1, HALF = N / 2, Q4 = N / 4;
-  constexpr int ROWS = inv_rows(N), LINES = ROWS / 2;
-  constexpr int LS = lds_line<N>();
-  __shared__ double2 sh[LINES * LS];
-  __shared__ double rl[ROWS * N];
-  __shared__ double2 tw[lds_line<N / 2>()];
-  const double2* h = in_batch(h0, wstride);
-  const double* r0 = in_batch(r00, wstride);
-  double* rbins = in_batch(rbins0, wstride);
-  make_twiddles<N>(tw, +1);
-  const int row0 = remap_block(blockIdx.x, gridDim.x, 1) * ROWS;
-  for (int e = threadIdx.x; e < LINES * Q4; e += 256) {
-    const int l = e / Q4, r = e % Q4;
-    const size_t a = size_t(row0 + 2 * l) * NH, b = a + NH;  // the pair of rows
-    double2 x[4];
+  __syncthreads();  // Psi and the sums are read; the inverse overwrites sh
+  // the inverse transform of Psi along z, its first stage from the registers
 #pragma unroll
-    for (int m = 0; m < 4; ++m) {
-      const int k = r + m * Q4;
-      double2 p, q;
-      if (k <= HALF) {
-        p = h[a + k];
-        q = h[b + k];
-      } else {
-        const double2 cp = h[a + (N - k)], cq = h[b + (N - k)];
-        p = make_double2(cp.x, -cp.y);
-        q = make_double2(cq.x, -cq.y);
-      }
-      x[m] = make_double2(p.x - q.y, p.y + q.x);  // p + i q
+  for (int k = 0; k < PER; ++k) {
+    const int e = threadIdx.x + 256 * k;
+    if (e < LINES * Q4) {
+      const int j = e / LINES, l = e % LINES;
+      double2 x[4];
+#pragma unroll
+      for (int m = 0; m < 4; ++m) x[m] = make_double2(ps[k][m], 0.0);
+      first_stage_to_lds<N>(sh + l * LS, j, x, +1);
     }
-    first_stage_to_lds<N>(sh + l * LS, r, x, +1);
   }
   __syncthreads();
   middle_steps<N>(sh, LINES, tw);
-  for (int e = threadIdx.x; e < LINES * Q4; e += 256) {
-    const int l = e / Q4, j = e % Q4;
-    double2 o[4];
-    last_step_from_lds<N>(sh + l * LS, j, tw, o);
+  // outputs j and j + N/4 of a quartet lie in 0..N/2 - 1, and j + N/2 is N/2
+  // for j = 0; mu is 2 except at 0 and N/2
+  double gv[PER][3];
 #pragma unroll
-    for (int m = 0; m < 4; ++m) {
-      rl[(2 * l) * N + j + m * Q4] = o[m].x;
-      rl[(2 * l + 1) * N + j + m * Q4] = o[m].y;
+  for (int k = 0; k < PER; ++k) {
+    const int e = threadIdx.x + 256 * k;
+    if (e < LINES * Q4) {
+      const int j = e / LINES, l = e % LINES;
+      double2 o[4];
+      last_step_from_lds<N>(sh + l * LS, j, tw, o);
+      gv[k][0] = (j == 0 ? 1.0 : 2.0) * o[0].x;
+      gv[k][1] = 2.0 * o[1].x;
+      gv[k][2] = o[2].x;
+    }
+  }
+  __syncthreads();  // the transform's reads are done; sh stages the output
+  constexpr int HP = HALF + 1;
+  double* stage = reinterpret_cast<double*>(sh);
+  static_assert(sizeof(double) * LINES * HP <= sizeof(sh), "the folded lines fit in the LDS");
+#pragma unroll
+  for (int k = 0; k < PER; ++k) {
+    const int e = threadIdx.x + 256 * k;
+    if (e < LINES * Q4) {
+      const int j = e / LINES, l = e % LINES;
+      stage[l * HP + j] = gv[k][0];
+      stage[l * HP + j + Q4] = gv[k][1];
+      if (j == 0) stage[l * HP + HALF] = gv[k][2];
     }
   }
   __syncthreads();
-  // the shell sums of every (row, shell) pair over all threads, each row
-  // folded by |hx|, in the LDS the transform no longer needs; then the
-  // block's rows added per shell in row order
-  static_assert(sizeof(double) * ROWS * (HALF + 1) <= sizeof(sh), "the row sums fit in the transform's LDS");
+  double* out = g + size_t(line0) * HP;
+  for (int i = threadIdx.x; i < LINES * HP; i += 256) out[i] = stage[i];
+}
+
+// Pass 4: the folded inverse transform along y. Lines j = kx (N/2 + 1) + f_z
+// of G[ky][j] (J = (N/2 + 1)^2 of them), 2 PAIRS consecutive lines per block
+// (consecutive threads take consecutive lines, so each ky is read in one
+// contiguous run); two real lines share one complex transform,
+// Z = G_a + i G_b, and H[f_y][j] = mu(f_y) sum_ky G[ky][j] cos(2 pi ky f_y / N)
+// is mu(f_y) Re of their transforms: Re A(f) = (Re Z(f) + Re Z(N - f)) / 2,
+// Re B(f) = (Im Z(f) + Im Z(N - f)) / 2, for f_y = 0..N/2. Lines past J
+// transform zeros and are not written.
+template <int N, int PAIRS>
+__global__ void __launch_bounds__(256) cos_y_kernel(const double* g0, double* hout0, size_t wstride) {
+  constexpr int HALF = N / 2, HP = HALF + 1, J = HP * HP, LS = lds_line<N>(), Q4 = N / 4;
+  constexpr int PER = (PAIRS * Q4 + 255) / 256;
+  __shared__ double2 sh[PAIRS * LS];
+  __shared__ double2 tw[lds_line<N / 2>()];
+  const double* g = in_batch(g0, wstride);
+  double* ho = in_batch(hout0, wstride);
+  make_twiddles<N>(tw, +1);
+  const int j0 = remap_block(blockIdx.x, gridDim.x, 1) * 2 * PAIRS;
+#pragma unroll
+  for (int k = 0; k < PER; ++k) {
+    const int e = threadIdx.x + 256 * k;
+    if (e < PAIRS * Q4) {
+      const int r = e / PAIRS, p = e % PAIRS;
+      const int ja = j0 + 2 * p, jb = ja + 1;
+      double2 x[4];
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        const size_t row = size_t(r + m * Q4) * J;
+        x[m] = make_double2(ja < J ? g[row + ja] : 0.0, jb < J ? g[row + jb] : 0.0);
+      }
+      first_stage_to_lds<N>(sh + p * LS, r, x, +1);
+    }
+  }
+  __syncthreads();
+  middle_steps<N>(sh, PAIRS, tw);
+  // the last step, its outputs back into the slots it read (the same thread's)
+#pragma unroll
+  for (int k = 0; k < PER; ++k) {
+    const int e = threadIdx.x + 256 * k;
+    if (e < PAIRS * Q4) {
+      const int j = e / PAIRS, p = e % PAIRS;
+      double2 o[4];
+      last_step_from_lds<N>(sh + p * LS, j, tw, o);
+#pragma unroll
+      for (int m = 0; m < 4; ++m) sh[p * LS + lds_pos(j + m * Q4)] = o[m];
+    }
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < HP * PAIRS; e += 256) {
+    const int f = e / PAIRS, p = e % PAIRS;
+    const int ja = j0 + 2 * p;
+    if (ja >= J) continue;
+    const double2 z = sh[p * LS + lds_pos(f)], zn = sh[p * LS + lds_pos((N - f) & (N - 1))];
+    const bool edge = f == 0 || f == HALF;  // mu = 1 and Z(N - f) = Z(f)
+    ho[size_t(f) * J + ja] = edge ? z.x : z.x + zn.x;
+    if (ja + 1 < J) ho[size_t(f) * J + ja + 1] = edge ? z.y : z.y + zn.y;
+  }
+}
+
+// Pass 5: the folded inverse transform along x and the shell sums of S2.
+// Rows q = f_y (N/2 + 1) + f_z of H[f_y][kx][f_z] (lines along kx =
+// 0..N/2), 2 PAIRS consecutive rows per block. With y and z folded, H is
+// even in kx (a mode at -kx is the conjugate partner of one at kx with ky,
+// kz negated, and the folds are even in those), so the transform of its
+// even extension is real: two rows share one complex transform, Z = E_a +
+// i E_b giving x_a + i x_b, and X(f) = mu(f_x) x(f_x) is N^6 times the sum
+// of R_h over the lags that fold to f. The shell sums of
+// 2 (mu(f) R_0 - X(f)) (mu(f) the number of those lags) over the block's
+// rows (each row folded by f_x, the rows added in order) go to
+// rbins[block][r] (rows of N/2 + 2 values, the last one 0). r0: R_0 times
+// N^6 (the sum of Psi). Rows past (N/2 + 1)^2 transform zeros and add
+// nothing.
+template <int N, int PAIRS>
+__global__ void __launch_bounds__(256)
+    cos_x_kernel(const double* hin0, const double* r00, double* rbins0, size_t wstride) {
+  constexpr int HALF = N / 2, HP = HALF + 1, J = HP * HP, LS = lds_line<N>(), Q4 = N / 4, ROWS = 2 * PAIRS;
+  constexpr int PER = (PAIRS * Q4 + 255) / 256;
+  // the transforms, then (as doubles) the rows' X values and their shell sums
+  constexpr int SH = PAIRS * LS > ROWS * HP ? PAIRS * LS : ROWS * HP;
+  __shared__ double2 sh[SH];
+  __shared__ double2 tw[lds_line<N / 2>()];
+  const double* hin = in_batch(hin0, wstride);
+  const double* r0 = in_batch(r00, wstride);
+  double* rbins = in_batch(rbins0, wstride);
+  make_twiddles<N>(tw, +1);
+  const int q0 = remap_block(blockIdx.x, gridDim.x, 1) * ROWS;
+#pragma unroll
+  for (int k = 0; k < PER; ++k) {
+    const int e = threadIdx.x + 256 * k;
+    if (e < PAIRS * Q4) {
+      const int r = e / PAIRS, p = e % PAIRS;
+      const int qa = q0 + 2 * p, qb = qa + 1;
+      const size_t ba = size_t(qa / HP) * J + qa % HP, bb = size_t(qb / HP) * J + qb % HP;
+      double2 x[4];
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        const int kx = r + m * Q4, kf = kx <= HALF ? kx : N - kx;  // the even extension
+        x[m] = make_double2(qa < J ? hin[ba + size_t(kf) * HP] : 0.0, qb < J ? hin[bb + size_t(kf) * HP] : 0.0);
+      }
+      first_stage_to_lds<N>(sh + p * LS, r, x, +1);
+    }
+  }
+  __syncthreads();
+  middle_steps<N>(sh, PAIRS, tw);
+  // outputs j and j + N/4 of a quartet lie in 0..N/2 - 1, and j + N/2 is N/2
+  // for j = 0
+  double xv[PER][3][2];
+#pragma unroll
+  for (int k = 0; k < PER; ++k) {
+    const int e = threadIdx.x + 256 * k;
+    if (e < PAIRS * Q4) {
+      const int j = e / PAIRS, p = e % PAIRS;
+      double2 o[4];
+      last_step_from_lds<N>(sh + p * LS, j, tw, o);
+      const double w0 = j == 0 ? 1.0 : 2.0;
+      xv[k][0][0] = w0 * o[0].x;
+      xv[k][0][1] = w0 * o[0].y;
+      xv[k][1][0] = 2.0 * o[1].x;
+      xv[k][1][1] = 2.0 * o[1].y;
+      xv[k][2][0] = o[2].x;
+      xv[k][2][1] = o[2].y;
+    }
+  }
+  __syncthreads();  // the transform's reads are done; sh holds the rows next
+  double* xr = reinterpret_cast<double*>(sh);  // [ROWS][HP]
+  double* part = xr + ROWS * HP;                // [ROWS][HP]
+#pragma unroll
+  for (int k = 0; k < PER; ++k) {
+    const int e = threadIdx.x + 256 * k;
+    if (e < PAIRS * Q4) {
+      const int j = e / PAIRS, p = e % PAIRS;
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        double* row = xr + (2 * p + b) * HP;
+        row[j] = xv[k][0][b];
+        row[j + Q4] = xv[k][1][b];
+        if (j == 0) row[HALF] = xv[k][2][b];
+      }
+    }
+  }
+  __syncthreads();
   const double R0 = *r0;
-  double* part = reinterpret_cast<double*>(sh);
-  for (int e = threadIdx.x; e < ROWS * (HALF + 1); e += 256) {
-    const int r = e / (HALF + 1), c = e % (HALF + 1);
-    const int row = row0 + r, iz = row / N, iy = row % N;
-    const int hz = iz <= HALF ? iz : iz - N, hy = iy <= HALF ? iy : iy - N;
-    int a, b;
-    shell_range(HALF, hz * hz + hy * hy, c, a, b);
-    const double* rr = rl + r * N;
+  for (int e = threadIdx.x; e < ROWS * HP; e += 256) {
+    const int rho = e / HP, c = e % HP;
+    const int q = q0 + rho;
     double sum = 0.0;
-    for (int m = a; m <= b; ++m) {
-      double v = 2.0 * (R0 - rr[m]);
-      if (m >= 1 && m <= HALF - 1) v += 2.0 * (R0 - rr[N - m]);
-      sum += v;
+    if (q < J) {
+      const int fy = q / HP, fz = q % HP;
+      const double myz = fold_weight(fy, HALF) * fold_weight(fz, HALF);
+      int a, b;
+      shell_range(HALF, fy * fy + fz * fz, c, a, b);
+      const double* row = xr + rho * HP;
+      for (int m = a; m <= b; ++m) sum += 2.0 * (myz * fold_weight(m, HALF) * R0 - row[m]);
     }
     part[e] = sum;
   }
   __syncthreads();
-  const size_t blk = size_t(row0 / ROWS);
+  const size_t blk = size_t(q0 / ROWS);
   for (int c = threadIdx.x; c <= HALF + 1; c += 256) {
     double sum = 0.0;
-    for (int r = 0; r < ROWS && c <= HALF; ++r) sum += part[r * (HALF + 1) + c];
+    for (int r = 0; r < ROWS && c <= HALF; ++r) sum += part[r * HP + c];
     rbins[blk * (HALF + 2) + c] = sum;
   }
 }
@@ -872,7 +1001,8 @@ __global__ void __launch_bounds__(256) compensate_kernel(const DevSample* sample
 
 
 struct ObsWork {
-  double2* h;       // 3 fields of N * N * NH complex
+  double2* h;       // 3 fields of N * N * NH complex; after pass 3, H
+  double* g;        // N (N/2 + 1)^2: the folded z-transform G
   double* sbins;    // spectrum_bin_rows(N) rows of N/2 + 2
   double* rbins;    // sf_bin_rows(N) rows of N/2 + 2
   double* psum;     // one row of N/2 + 2 per chunk of either table
@@ -886,8 +1016,8 @@ size_t chunks_of(size_t rows) { return (rows + kShellChunk - 1) / kShellChunk; }
 
 // Byte sizes of the parts of one sample's work area (each a multiple of 256)
 struct WorkSizes {
-  size_t h, sbins, rbins, psum, r0, cnt;
-  size_t total() const { return h + sbins + rbins + psum + r0 + cnt; }
+  size_t h, g, sbins, rbins, psum, r0, cnt;
+  size_t total() const { return h + g + sbins + rbins + psum + r0 + cnt; }
 };
 
 WorkSizes work_sizes(int n) {
@@ -895,6 +1025,7 @@ WorkSizes work_sizes(int n) {
   const size_t srows = spectrum_bin_rows(n), rrows = sf_bin_rows(n);
   WorkSizes z;
   z.h = align256(3 * size_t(n) * n * nh * sizeof(double2));
+  z.g = align256(size_t(n) * folded_lines(n) * sizeof(double));
   z.sbins = align256(srows * width * sizeof(double));
   z.rbins = align256(rrows * width * sizeof(double));
   z.psum = align256(chunks_of(std::max(srows, rrows)) * width * sizeof(double));
@@ -911,7 +1042,8 @@ ObsWork carve(void* work, int n) {
   char* p = static_cast<char*>(work);
   ObsWork w;
   w.h = reinterpret_cast<double2*>(p);
-  w.sbins = reinterpret_cast<double*>(p += z.h);
+  w.g = reinterpret_cast<double*>(p += z.h);
+  w.sbins = reinterpret_cast<double*>(p += z.g);
   w.rbins = reinterpret_cast<double*>(p += z.sbins);
   w.psum = reinterpret_cast<double*>(p += z.rbins);
   w.r0 = reinterpret_cast<double*>(p += z.psum);
@@ -924,27 +1056,28 @@ hipError_t observables_t(const T* pop, const double* u, const DevSample* samples
                          void* work, double* s2, double* ek, hipStream_t s) {
   constexpr int NH = N / 2 + 1, L = half_lines(N);
   constexpr int ROWS_X = fwd_rows(N);
-  constexpr int ROWS_R = inv_rows(N);
+  constexpr int PC = cos_pairs(N);
   constexpr int W = N / 2 + 2;
-  static_assert(N % L == 0 && (N * N) % ROWS_X == 0 && (N * N) % ROWS_R == 0, "launch shapes must tile the field");
+  static_assert(N % L == 0 && (N * N) % ROWS_X == 0, "launch shapes must tile the field");
   const ObsWork w = carve(work, N);
   const size_t ws = sample_work_bytes(N);
   const unsigned z = unsigned(count);
-  const int lines = N * NH, rows = N * N;
+  const int lines = N * NH;
   const int srows = int(spectrum_bin_rows(N)), rrows = int(sf_bin_rows(N));
   const int lchunks = int(chunks_of(srows)), rchunks = int(chunks_of(rrows));
   hipLaunchKernelGGL((fwd_x_kernel<QN, T, N, FROM_U>), dim3(N * N / ROWS_X, 1, z), dim3(256), 0, s, pop, u, samples,
                      sample0, parity, w.h, ws);
   hipLaunchKernelGGL((fft_y_kernel<N, L>), dim3(lines / L, 3, z), dim3(256), 0, s, w.h, -1, ws);
   constexpr int LZ = z_lines(N);
-  hipLaunchKernelGGL((z_psd_kernel<N, LZ>), dim3(lines / LZ, 1, z), dim3(256), 0, s, w.h, w.sbins, ws);
+  hipLaunchKernelGGL((z_psd_kernel<N, LZ>), dim3(lines / LZ, 1, z), dim3(256), 0, s, w.h, w.g, w.sbins, ws);
   hipLaunchKernelGGL(shell_partial_kernel, dim3(lchunks, 1, z), dim3(256), 0, s, w.sbins, srows, W, w.psum, ws);
   hipLaunchKernelGGL(shell_count_kernel, dim3(NH), dim3(256), 0, s, N, w.cnt);
   hipLaunchKernelGGL(shell_final_kernel, dim3(W, 1, z), dim3(256), 0, s, w.psum, w.cnt, lchunks, W, N, 0, ek, w.r0,
                      ws);
   if (s2) {
-    hipLaunchKernelGGL((fft_y_kernel<N, L>), dim3(lines / L, 1, z), dim3(256), 0, s, w.h, +1, ws);
-    hipLaunchKernelGGL((inv_x_rows_kernel<N>), dim3(rows / ROWS_R, 1, z), dim3(256), 0, s, w.h, w.r0, w.rbins, ws);
+    double* hr = reinterpret_cast<double*>(w.h);
+    hipLaunchKernelGGL((cos_y_kernel<N, PC>), dim3(rrows, 1, z), dim3(256), 0, s, w.g, hr, ws);
+    hipLaunchKernelGGL((cos_x_kernel<N, PC>), dim3(rrows, 1, z), dim3(256), 0, s, hr, w.r0, w.rbins, ws);
     hipLaunchKernelGGL(shell_partial_kernel, dim3(rchunks, 1, z), dim3(256), 0, s, w.rbins, rrows, W, w.psum, ws);
     hipLaunchKernelGGL(shell_final_kernel, dim3(W, 1, z), dim3(256), 0, s, w.psum, w.cnt, rchunks, W, N, 1, s2,
                        nullptr, ws);

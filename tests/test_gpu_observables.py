@@ -19,6 +19,7 @@ mc = pytest.importorskip("paper_2608_23786_amd")
 
 @pytest.mark.parametrize("n,steps,precision,lattice", [(8, 4, "f64", 27), (16, 8, "f64", 27), (32, 16, "f64", 27),
                                                         (64, 32, "f64", 27), (128, 7, "f64", 27),
+                                                        (256, 3, "f32s", 27),
                                                         (32, 5, "f32s", 27), (32, 3, "f32s", 19),
                                                         (16, 6, "f64", 19)])
 def test_structure_function_and_spectrum_match_oracle_on_the_same_field(n, steps, precision, lattice):
@@ -66,6 +67,43 @@ def test_taylor_green_spectrum_closed_form():
     # sum of Phi = mean |u|^2 = U0^2 / 4
     assert abs(ek[2] - 4 * np.pi / 62 * 0.5 * 3 * 0.05 ** 2 / 4) < 1e-16
     assert np.max(np.abs(np.delete(ek, 2))) < 1e-18
+
+
+@pytest.mark.parametrize("n", [16, 256, 512])
+def test_taylor_green_observables_closed_form_from_a_written_velocity(n):
+    """The velocity u = (sin x cos y cos z, -cos x sin y cos z, 0) written into
+    the capture layout: E is 4 pi / 62 * 3 / 8 in shell 2 and zero elsewhere,
+    and R_h = cos(t hx) cos(t hy) cos(t hz) / 4 (t = 2 pi / n), so
+    S2(r) = (1 - mean over the shell C_r of that product) / 2, the mean taken
+    over every lag of the shell (minimum image, the product is even in each
+    component). Covers the launch shapes of the largest resolutions."""
+    ens = mc.Ensemble([mc.Sample(n, 0.05, 100.0)], "f32s")
+    t = 2 * np.pi / n
+    x = torch.arange(n, dtype=torch.float64, device="cuda") * t
+    u = torch.empty(3, n, n, n, dtype=torch.float64, device="cuda")   # [c][z][y][x]
+    sx, cx = torch.sin(x)[None, None, :], torch.cos(x)[None, None, :]
+    sy, cy = torch.sin(x)[None, :, None], torch.cos(x)[None, :, None]
+    cz = torch.cos(x)[:, None, None]
+    u[0] = sx * cy * cz
+    u[1] = -cx * sy * cz
+    u[2] = 0.0
+    s2, ek = ens.observables_velocity_range(0, 1, u=u.reshape(-1))
+    del u
+    ek, s2 = ek.cpu().numpy()[0], s2.cpu().numpy()[0]
+    assert abs(ek[2] - 4 * np.pi / 62 * 3 / 8) < 1e-15
+    assert np.max(np.abs(np.delete(ek, 2))) < 1e-15
+    # the shell means of the cosine product, over all lags (sign classes counted)
+    f = np.arange(n // 2 + 1)
+    mult = np.where((f == 0) | (f == n // 2), 1.0, 2.0)
+    c = np.cos(t * f)
+    r2 = f[:, None, None] ** 2 + f[None, :, None] ** 2 + f[None, None, :] ** 2
+    shell = np.floor(np.sqrt(r2) + 0.5).astype(np.int64).ravel()
+    w = (mult[:, None, None] * mult[None, :, None] * mult[None, None, :]).ravel()
+    prod = (c[:, None, None] * c[None, :, None] * c[None, None, :]).ravel()
+    num = np.bincount(shell, weights=w * prod)[1:n // 2 + 1]
+    cnt = np.bincount(shell, weights=w)[1:n // 2 + 1]
+    s2o = 0.5 * (1.0 - num / cnt)
+    assert np.max(np.abs(s2 - s2o)) <= 1e-12 * np.max(s2o)
 
 
 def test_mixed_resolutions_point_values_and_w1():
