@@ -326,12 +326,13 @@ __global__ void __launch_bounds__(256) adjoint_step_kernel(const T* state, const
   if constexpr (EXACT) {
     // the forward collision's t, from the same start and with the same steps
     if (active) {
-      T ge[Q];
+      T ge[Q], dh[Q], bs[Q];
       for_vel<QN>([&](auto ic) {
         constexpr int i = decltype(ic)::value;
         ge[i] = geq<QN, i>(m);
       });
-      t = exact_entropic_t<QN>(ge, fneq, s, m, rp.omega, t);
+      exact_terms<QN>(ge, fneq, s, rp.eps, dh, bs);
+      t = exact_entropic_t<QN>(dh, bs, m, t);
     }
   }
 
@@ -352,7 +353,7 @@ __global__ void __launch_bounds__(256) adjoint_step_kernel(const T* state, const
         T ds = T(0);
         if constexpr (nonzeros(i) == 1 || nonzeros(i) == 2) ds = shear_part<i>(s);
         const T dh = fneq[i] - ds;
-        const T gs = geq<QN, i>(m) + (fneq[i] - rp.omega * ds) - t * dh;  // f*_i - w_i
+        const T gs = (((geq<QN, i>(m) - ds) + rp.eps * ds) + dh) - t * dh;  // f*_i - w_i
         d += dh * dh * recip(T(weight<QN>(i)) + gs);
       });
       Fbar = tbar / d;

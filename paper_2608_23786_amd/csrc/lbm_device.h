@@ -318,20 +318,28 @@ __device__ __forceinline__ T equilibrium_threshold(const Macro<T>& m) {
     return T(1e-30);
 }
 
+// The terms of the exact stabiliser, once per node: dh_i = f^neq_i - ds_i and
+// bs_i = b_i - w_i = f_i - omega ds_i - w_i, so that f*_i(t) - w_i = bs_i - t dh_i.
+// bs is formed as the closed-form update forms the post-collision state,
+// (g^eq_i - ds_i) + eps ds_i + dh_i with eps = 2 - omega, which keeps the
+// shear relaxation at full relative precision for omega near 2 (a float
+// omega alone would carry eps to about 1e-4); the post-collision state is
+// then bs_i - t dh_i, and g^eq and f^neq are no longer needed.
 template <int QN, typename T>
-__device__ __forceinline__ T exact_entropic_t(const T (&geq)[Q], const T (&fneq)[Q], const Shear<T>& s,
-                                              const Macro<T>& m, T omega, T t) {
-  const T a = m.drho - m.usq15;
-  // dh_i and b_i - w_i = g^eq_i + f^neq_i - omega ds_i once per node, so that
-  // f*_i(t) - w_i = (b_i - w_i) - t dh_i
-  T dh[Q], bs[Q];
+__device__ __forceinline__ void exact_terms(const T (&geq)[Q], const T (&fneq)[Q], const Shear<T>& s, T eps,
+                                            T (&dh)[Q], T (&bs)[Q]) {
   for_vel<QN>([&](auto ic) {
     constexpr int i = decltype(ic)::value;
     T ds = T(0);
     if constexpr (nonzeros(i) == 1 || nonzeros(i) == 2) ds = shear_part<i>(s);
     dh[i] = fneq[i] - ds;
-    bs[i] = geq[i] + (fneq[i] - omega * ds);
+    bs[i] = ((geq[i] - ds) + eps * ds) + dh[i];
   });
+}
+
+template <int QN, typename T>
+__device__ __forceinline__ T exact_entropic_t(const T (&dh)[Q], const T (&bs)[Q], const Macro<T>& m, T t) {
+  const T a = m.drho - m.usq15;
   // The interval of t where every f*_i = w_i + bs_i - t dh_i > 0 bounds the
   // Newton iterates; it is formed (27 quotients) only when an iterate leaves
   // the region where every f*_i is positive, which takes 27 products to
@@ -432,25 +440,34 @@ __device__ __forceinline__ CellResult<T> kbc_collide(T (&g)[Q], const Relax<T>& 
   if (resolved) gamma = rp.two_over_omega - rp.kappa * (A / B);
   T t = T(0.5) * rp.omega * gamma;
   if constexpr (EXACT) {
+    // g* = bs - t dh (the same update as below, in the terms of the exact
+    // minimiser, which are all it keeps through its iteration)
+    T dh[Q], bs[Q];
+    exact_terms<QN>(g, fneq, s, rp.eps, dh, bs);
     if (resolved) {
-      t = exact_entropic_t<QN>(g, fneq, s, m, rp.omega, t);
+      t = exact_entropic_t<QN>(dh, bs, m, t);
       gamma = T(2) * t / rp.omega;
     }
+    for_vel<QN>([&](auto ic) {
+      constexpr int i = decltype(ic)::value;
+      g[i] = bs[i] - t * dh[i];
+    });
+  } else {
+    // g* = g - omega ds - t dh = (g^eq - ds) + (2 - omega) ds + (1 - t) dh.
+    // The shear relaxation enters through eps = 2 - omega, which keeps the
+    // viscosity (proportional to eps for omega near 2) at full relative
+    // precision even in float.
+    const T one_t = T(1) - t;
+    for_vel<QN>([&](auto ic) {
+      constexpr int i = decltype(ic)::value;
+      if constexpr (nonzeros(i) == 1 || nonzeros(i) == 2) {
+        const T ds = shear_part<i>(s);
+        g[i] = (g[i] - ds) + rp.eps * ds + one_t * (fneq[i] - ds);
+      } else {
+        g[i] = g[i] + one_t * fneq[i];
+      }
+    });
   }
-  // g* = g - omega ds - t dh = (g^eq - ds) + (2 - omega) ds + (1 - t) dh.
-  // The shear relaxation enters through eps = 2 - omega, which keeps the
-  // viscosity (proportional to eps for omega near 2) at full relative
-  // precision even in float.
-  const T one_t = T(1) - t;
-  for_vel<QN>([&](auto ic) {
-    constexpr int i = decltype(ic)::value;
-    if constexpr (nonzeros(i) == 1 || nonzeros(i) == 2) {
-      const T ds = shear_part<i>(s);
-      g[i] = (g[i] - ds) + rp.eps * ds + one_t * (fneq[i] - ds);
-    } else {
-      g[i] = g[i] + one_t * fneq[i];
-    }
-  });
   res.gamma = gamma;
   res.bad = !(m.rho > T(0)) || !(m.usq15 < T(1.5)) || !(fmin > T(0));
   if constexpr (EXACT) res.bad = res.bad || !(t == t);
