@@ -1,6 +1,7 @@
 """The package's usage example runs as written and its results hang
 together (GPU): the statistics of the records agree with the records, the
-last record sits at the tick of the observables, and the gradient of the
+last record sits at the tick of the observables (also when they are taken
+from the velocity that record tick captured), and the gradient of the
 ensemble-mean kinetic energy has the shape of Y."""
 import numpy as np
 import pytest
@@ -19,7 +20,12 @@ def test_usage_example():
     assert tuple(rec.shape) == (10, 16, 8)
     s2, ek = ens.observables_range(0, 16)
     assert ens.ticks == 500
-    rec = torch.cat([rec, ens.step(50, record_every=50)])
+    ens.capture_velocity()
+    rec_u = ens.step(50, record_every=50)
+    s2u, eku = ens.observables_velocity_range(0, 16)
+    # the capture is the velocity of tick 500, the state of the observables above
+    assert torch.equal(s2u, s2) and torch.equal(eku, ek)
+    rec = torch.cat([rec, rec_u])
     ke_mean, ke_std = mc.ensemble_moments(rec[-1, :, 4:5])
     ke = rec[-1, :, 4].cpu().numpy()
     assert abs(float(ke_mean[0]) - ke.mean()) <= 1e-14 * ke.mean()
