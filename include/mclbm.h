@@ -442,7 +442,8 @@ mclbm_status mclbm_get_launch(const mclbm_ctx* ctx, int32_t* block_threads, int3
                               int32_t* buffer_addressing, int32_t* nontemporal);
 
 /* Time every launch shape on the current state (`reps` periods of
- * 2 * max stride ticks each, after one warm-up period), keep the fastest,
+ * 2 * max stride ticks each, after one warm-up period), time the three
+ * fastest twice more, keep the one with the best time,
  * and restore the state from a checkpoint written to scratch_dev
  * (mclbm_checkpoint_bytes). best_* (may be NULL) receive the choice. On an
  * error the launch shape and the state are put back as they were and the
