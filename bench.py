@@ -386,8 +386,14 @@ def bench_sequence(mc, torch):
         w1.append(float(mc.w1_1pt(cur, ref, 8).sum()))          # on the current stream, like pv
         err.append(mc.sample_error(cur, ref, 8).cpu().tolist())
         ns.append(g.n)
+    # and between consecutive resolutions
+    w1c = {}
+    for k in range(len(wl.groups) - 1):
+        lo, hi = pv[k * per:(k + 1) * per].contiguous(), pv[(k + 1) * per:(k + 2) * per].contiguous()
+        w1c[f"{wl.groups[k].n}^3-{wl.groups[k + 1].n}^3"] = round(float(mc.w1_1pt(lo, hi, 8).sum()), 8)
     conv = {"reference_n": nref,
             "W1_1pt_u_over_U0": {f"{n}^3": round(v, 8) for n, v in zip(ns, w1)},
+            "W1_1pt_consecutive_u_over_U0": w1c,
             "sample_error_L1_xyz_vec": {f"{n}^3": [round(v, 6) for v in e] for n, e in zip(ns, err)},
             "EOWC_W1_1pt": round(mc.eoc_slope(ns, w1), 4),
             "EOSC_vec": round(mc.eoc_slope(ns, [e[3] for e in err]), 4)}
@@ -490,6 +496,10 @@ def bench_sequence_to_onset(mc, torch, name, launch=None, rec_every=16):
                 ns.append(g.n)
         row["reference_n"] = finest.n
         row["W1_1pt_u_over_U0"] = {f"{n}^3": w for n, w in zip(ns, w1)}
+        row["W1_1pt_consecutive_u_over_U0"] = {
+            f"{lo.n}^3-{hi.n}^3": float(mc.w1_1pt(pv[a:a + lo.count].contiguous(), pv[b:b + hi.count].contiguous(),
+                                                  8).sum())
+            for (a, lo), (b, hi) in zip(zip(firsts, wl.groups), zip(firsts[1:], wl.groups[1:]))}
         row["sample_error_L1_vec"] = {f"{n}^3": e[3] for n, e in zip(ns, err)}
         if all(v > 0 for v in w1) and all(e[3] > 0 for e in err):
             row["EOWC"] = mc.eoc_slope(ns, w1)
