@@ -69,7 +69,7 @@ def test_taylor_green_spectrum_closed_form():
     assert np.max(np.abs(np.delete(ek, 2))) < 1e-18
 
 
-@pytest.mark.parametrize("n", [16, 256, 512])
+@pytest.mark.parametrize("n", [8, 16, 256, 512])
 def test_taylor_green_observables_closed_form_from_a_written_velocity(n):
     """The velocity u = (sin x cos y cos z, -cos x sin y cos z, 0) written into
     the capture layout: E is 4 pi / 62 * 3 / 8 in shell 2 and zero elsewhere,
@@ -104,6 +104,16 @@ def test_taylor_green_observables_closed_form_from_a_written_velocity(n):
     cnt = np.bincount(shell, weights=w)[1:n // 2 + 1]
     s2o = 0.5 * (1.0 - num / cnt)
     assert np.max(np.abs(s2 - s2o)) <= 1e-12 * np.max(s2o)
+
+
+def test_observables_of_a_velocity_at_rest_are_zero():
+    """u = 0 everywhere (R_0 = 0): every shell of both observables is exactly
+    zero, at the smallest and a multi-tile size."""
+    for n in (8, 64):
+        ens = mc.Ensemble([mc.Sample(n, 0.05, 100.0)] * 2, "f32s")
+        u = torch.zeros(2 * 3 * n ** 3, dtype=torch.float64, device="cuda")
+        s2, ek = ens.observables_velocity_range(0, 2, u=u)
+        assert torch.count_nonzero(s2).item() == 0 and torch.count_nonzero(ek).item() == 0, n
 
 
 def test_mixed_resolutions_point_values_and_w1():
