@@ -88,6 +88,11 @@ __device__ __forceinline__ T vmin(T a, T b) {
   return a < b ? a : b;
 }
 
+template <typename T>
+__device__ __forceinline__ T vmax(T a, T b) {
+  return a > b ? a : b;
+}
+
 // ln(1 + x) for x > -1. float: the hardware base-2 logarithm of u = 1 + x
 // (rounded to float) times ln 2, minus the rounding error e = (u - 1) - x of
 // u (exact in float): ln(1 + x) = ln(u - e) = ln u - e/u + O(e^2), and
@@ -377,9 +382,15 @@ __device__ __forceinline__ T exact_entropic_t(const T (&dh)[Q], const T (&bs)[Q]
   // steps, so each later step still contracts the error by that factor,
   // reaching float resolution in the step that meets the stopping rule); in
   // double every step is a full Newton step.
+  // In float the first step also bounds its own error: with q_i = dh_i / f*_i,
+  // |d3H/dt3| = |sum dh_i q_i^2| <= max|q| H'', so Newton's error after a
+  // step D from t is below (|d3H/dt3| / (2 H'')) D^2 <= max|q| D^2 / 2 to
+  // first order in D max|q|; while D max|q| <= 1/16 a node stops once that
+  // is below 2^-22 of t, about two units in the last place, without taking
+  // the logarithms again to see the next step fall below the tolerance.
   constexpr bool kChord = std::is_same<T, float>::value;
   bool done = false;
-  T d2 = T(0);
+  T d2 = T(0), qmax = T(0);
   for (int it = 0; it < kExactNewtonSteps && !done; ++it) {
     T d1 = T(0);
     const bool curvature = !kChord || it == 0;
@@ -390,15 +401,30 @@ __device__ __forceinline__ T exact_entropic_t(const T (&dh)[Q], const T (&bs)[Q]
       // f*_i - w_i in shifted form
       const T gs = bs[i] - t * dh[i];
       d1 += dh[i] * (log1p_acc(gs * T(1.0 / w)) - (a + T(3) * cdot<i>(m.ux, m.uy, m.uz)));
-      if (curvature) d2 += dh[i] * dh[i] * recip(T(w) + gs);
+      if (curvature) {
+        const T qi = dh[i] * recip(T(w) + gs);
+        d2 += dh[i] * qi;
+        if constexpr (kChord) qmax = vmax(qmax, qi < T(0) ? -qi : qi);
+      }
     });
     T tn = t + d1 / d2;
+    bool newton = true;
     if (!positive_at(tn)) {
       if (!have_interval) interval();
-      if (!(tn < hi)) tn = T(0.5) * (t + hi);
-      if (!(tn > lo)) tn = T(0.5) * (t + lo);
+      if (!(tn < hi)) {
+        tn = T(0.5) * (t + hi);
+        newton = false;
+      }
+      if (!(tn > lo)) {
+        tn = T(0.5) * (t + lo);
+        newton = false;
+      }
     }
-    done = fabs(tn - t) <= exact_tolerance<T>() * fabs(t);
+    const T step = tn - t, astep = step < T(0) ? -step : step;
+    done = astep <= exact_tolerance<T>() * fabs(t);
+    if constexpr (kChord)
+      if (it == 0 && newton && qmax * astep <= T(0.0625))
+        done = done || qmax * astep * astep <= T(0x1.0p-22) * fabs(tn);
     t = tn;
   }
   return t;
