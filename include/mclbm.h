@@ -284,7 +284,10 @@ mclbm_status mclbm_capture_velocity(mclbm_ctx* ctx, double* u_dev, size_t bytes)
  * errors) of the velocity fields held in u_dev (the layout above, e.g. as
  * captured by the last record tick), for samples first..first+count-1 that
  * share one n, in one set of launches. u_dev: device, 256-byte aligned,
- * read only; the state of the ensemble is not read. */
+ * read only, holding at least the planes of those samples at their offsets
+ * (mclbm_velocity_bytes(ctx) bytes for the whole layout; the library cannot
+ * check the length of a raw pointer); the state of the ensemble is not
+ * read. */
 mclbm_status mclbm_observables_velocity_range(mclbm_ctx* ctx, int32_t first, int32_t count, const double* u_dev,
                                               double* s2_dev, double* ek_dev, void* work_dev, size_t work_bytes);
 
